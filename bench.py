@@ -1,0 +1,249 @@
+"""Benchmark: BDDC-PCG solves/s on one MI355X.
+
+Workload (default): 3D Q1 diffusion on a 64^3 element grid, 4x4x4 = 64 box
+subdomains of 16^3 elements, lognormal(0,1) per-element conductivity, corner +
+edge + face constraints, uniform[-1,1] right-hand side, solved to relative
+residual 1e-8.  A step is one warm BDDC-PCG solve (the preconditioner is set up
+once beforehand, as when the matrix is reused across time steps); inputs are
+resident in HBM when the timed region starts.
+
+Prints one JSON line with the FP64 solve rate as `value`, the FP32-local rate
+beside it, the roofline of the dominant kernel (achieved bytes per launch over
+its HIP-event-timed average duration) and a CPU-oracle baseline on a bounded
+sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRSV_FAMILIES = ["trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii", "trsv_bwd_ii"]
+NB = 64
+
+
+def sub_sizes(w):
+    """Per-subdomain sizes of a tensor box partition: n_R (interior + non-corner
+    interface rows of the local factor), n_I (interior rows), n_ci (constraints)."""
+    from paper_2410_14786_amd.workloads import CORNERS, EDGES, FACES
+    dim = w.dim
+    out = []
+    nsub = [len(c) - 1 for c in w.cuts]
+    for bidx in range(int(np.prod(nsub))):
+        b, r = [], bidx
+        for a in range(dim):
+            b.append(r % nsub[a])
+            r //= nsub[a]
+        cnt, inner, ends = [], [], []
+        for a in range(dim):
+            lo, hi = int(w.cuts[a][b[a]]), int(w.cuts[a][b[a] + 1])
+            n = w.nel[a]
+            cnt.append(min(hi, n - 1) - max(lo, 1) + 1)
+            inner.append(hi - lo - 1)
+            ends.append(int(lo > 0) + int(hi < n))
+        n_i = int(np.prod(cnt))
+        n_I = int(np.prod(inner))
+        corners = int(np.prod(ends)) if w.constraints & CORNERS else 0
+        if dim == 3:
+            edges = sum(ends[(c + 1) % 3] * ends[(c + 2) % 3] for c in range(3))
+            faces = sum(ends)
+        else:
+            edges, faces = sum(ends), 0
+        n_A = (edges if w.constraints & EDGES else 0) + (faces if w.constraints & FACES else 0)
+        out.append((n_i - corners, n_I, n_A + corners))
+    return out
+
+
+def algorithmic_bytes(w, local_bytes):
+    """Bytes each triangular-solve family must stream per launch: the lower
+    triangle of the factor it uses plus the border rows where they are read,
+    plus its vectors (FP64 input/output)."""
+    fam = {}
+    s = sub_sizes(w)
+    tri = lambda n: n * (n + 1) // 2
+    fam["trsv_fwd_rr"] = sum(tri(nR) * local_bytes + nci * nR * local_bytes + nR * (8 + 8 + 4 + local_bytes)
+                             for nR, nI, nci in s)
+    fam["trsv_bwd_rr"] = sum(tri(nR) * local_bytes + nci * nR * local_bytes + nR * (8 + 2 * local_bytes)
+                             for nR, nI, nci in s)
+    fam["trsv_fwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 4 + local_bytes) for nR, nI, nci in s)
+    fam["trsv_bwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 8 + 4 + local_bytes) for nR, nI, nci in s)
+    return fam
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2410_14786_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload, local_bits):
+    """HBM traffic per launch measured by rocprofv3 counters, if the record in
+    profiles/ was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    key = f"{workload}/{local_bits}/{kernel}"
+    ent = rec.get(key)
+    if not ent or ent.get("kernel_sha") != kernel_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def run_gpu(w, steps, warmup, local_bits, use_graph=False):
+    import torch
+    from paper_2410_14786_amd import bddc
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = bddc.solver_for(w, local_bits=local_bits, use_graph=use_graph)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    b = torch.as_tensor(w.b, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(b)
+    info = None
+    for _ in range(warmup):
+        _, info = S.solve(b, w.rtol, out=x)
+    S.set_timing(True)
+    for f in TRSV_FAMILIES + ["apply"]:
+        S.kernel_time(f)   # reset counters
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for _ in range(steps):
+        _, info = S.solve(b, w.rtol, out=x)
+        iters.append(info["iters"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fam = {f: S.kernel_time(f) for f in TRSV_FAMILIES + ["apply"]}
+    S.set_timing(False)
+    res = {"setup_s": setup_s, "elapsed_s": elapsed, "iters": iters, "info": info, "kernels": fam,
+           "dev_bytes": S.dev_bytes}
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(full_iters):
+    """The oracle on a bounded sample: the same 16^3 boxes and coefficient law,
+    2x2x2 boxes (32^3 elements) instead of 4x4x4; its solve time is scaled by
+    the subdomain count (64/8) and by the iteration ratio to give solves/s for
+    the full workload.  Setup is excluded, as for the GPU rate."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:
+        threadpool_limits = None
+    from oracle import bddc_oracle as O
+    from paper_2410_14786_amd import workloads as W
+    w = W.make_workload("sample_3d_32cubed_2x2x2_lognormal", 3, (32, 32, 32), (2, 2, 2), theta="lognormal",
+                        rtol=1e-8, seed=0)
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        P = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints)
+        t0 = time.perf_counter()
+        res = O.bddc_pcg(P, w.b, w.rtol)
+        t = time.perf_counter() - t0
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    scale = (64 / 8) * (full_iters / max(res.iters, 1))
+    return {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle BDDC-PCG on 32^3 elements, 2x2x2 boxes of 16^3 (8 of the 64 subdomains), "
+                      f"{res.iters} iterations in {t:.2f} s, scaled x8 for subdomains and x{full_iters}/{res.iters} "
+                      f"for iterations; setup excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="3d_64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--local-bits", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the whole problem lives on one MI355X); --gpus {args.gpus} "
+              f"is not supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2410_14786_amd import workloads as W
+    w = W.WORKLOADS[args.workload]()
+    print(f"[bench] workload {w.name}: n_free {w.n_free}, {int(np.prod(w.nsub))} subdomains", file=sys.stderr,
+          flush=True)
+    main_bits = args.local_bits
+    r64 = run_gpu(w, args.steps, args.warmup, main_bits)
+    ms = 1000.0 * r64["elapsed_s"] / args.steps
+    print(f"[bench] fp{main_bits}-local: {ms:.2f} ms/solve, iters {r64['iters'][-1]}, setup {r64['setup_s']:.2f} s",
+          file=sys.stderr, flush=True)
+    r32 = None
+    if not args.no_fp32 and main_bits == 64:
+        r32 = run_gpu(w, args.steps, args.warmup, 32)
+        print(f"[bench] fp32-local: {1000 * r32['elapsed_s'] / args.steps:.2f} ms/solve, iters {r32['iters'][-1]}",
+              file=sys.stderr, flush=True)
+    # roofline of the dominant kernel family
+    lb = 8 if main_bits == 64 else 4
+    algo = algorithmic_bytes(w, lb)
+    fams = {f: r64["kernels"][f] for f in TRSV_FAMILIES}
+    dom = max(fams, key=lambda f: fams[f][1])
+    n_l, tot_ms = fams[dom]
+    avg_s = tot_ms / 1000.0 / max(n_l, 1)
+    achieved = algo[dom] / avg_s / 1e9
+    traffic = load_traffic(dom, args.workload, main_bits)
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "bytes_per_launch": algo[dom], "avg_launch_ms": round(avg_s * 1e3, 4), "launches": n_l}
+    apply_n, apply_ms = r64["kernels"]["apply"]
+    apply_bytes = sum(algo.values())
+    out = {
+        "metric": "BDDC-PCG solves/s to rtol 1e-8 (FP64 vs FP32-local) + % HBM/MFMA peak",
+        "value": round(args.steps / r64["elapsed_s"], 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_bits == 64 else "f64-outer/f32-local",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_free": w.n_free, "subdomains": int(np.prod(w.nsub)),
+                   "rtol": w.rtol, "local_bits": main_bits},
+        "iters": r64["iters"][-1],
+        "relres_true": r64["info"]["relres_true"],
+        "cond_est": r64["info"]["cond_est"],
+        "setup_s": round(r64["setup_s"], 3),
+        "applies_per_s": round(apply_n / (apply_ms / 1e3), 2) if apply_n else None,
+        "apply_hbm_frac": round(apply_bytes / (apply_ms / 1e3 / max(apply_n, 1)) / 1e9 / HBM_PEAK_GBS, 4)
+        if apply_n else None,
+        "kernel_ms": {f: round(fams[f][1] / max(fams[f][0], 1), 4) for f in fams},
+        "roofline": roof,
+        "dev_bytes": r64["dev_bytes"],
+    }
+    if r32 is not None:
+        a32 = algorithmic_bytes(w, 4)
+        n32, ms32 = r32["kernels"]["apply"]
+        out["fp32_local"] = {"value": round(args.steps / r32["elapsed_s"], 3), "unit": "solves/s",
+                             "ms_per_step": round(1000 * r32["elapsed_s"] / args.steps, 3),
+                             "iters": r32["iters"][-1], "relres_true": r32["info"]["relres_true"],
+                             "setup_s": round(r32["setup_s"], 3),
+                             "apply_hbm_frac": round(sum(a32.values()) / (ms32 / 1e3 / max(n32, 1)) / 1e9
+                                                     / HBM_PEAK_GBS, 4) if n32 else None}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(r64["iters"][-1])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,820 @@
+// C ABI of libbddc.so: context management and the orchestration of setup, apply
+// and preconditioned CG.  Every step of the numerical path runs in the HIP
+// kernels of kernels.hip; this file only allocates, uploads the host plan,
+// launches and reads back status words.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "bddc_internal.h"
+#include "kernels.h"
+
+using namespace bddc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(BDDC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Extreme eigenvalues of a symmetric tridiagonal matrix by Sturm bisection.
+int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (size_t i = 0; i < d.size(); ++i) {
+    double off = i ? e[i - 1] * e[i - 1] : 0.0;
+    q = d[i] - x - (i ? off / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+double tridiag_eig(const std::vector<double>& d, const std::vector<double>& e, int k) {
+  double lo = 1e300, hi = -1e300;
+  for (size_t i = 0; i < d.size(); ++i) {
+    double r = (i ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < d.size() ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (sturm_count(d, e, mid) > k) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// CG-Lanczos tridiagonal from the CG coefficients: T[k,k] = 1/alpha_k +
+// beta_{k-1}/alpha_{k-1}, T[k,k+1] = sqrt(beta_k)/alpha_k.
+double lanczos_cond(const std::vector<double>& alpha, const std::vector<double>& beta) {
+  const size_t m = alpha.size();
+  if (m == 0) return 1.0;
+  std::vector<double> d(m), e(m ? m - 1 : 0);
+  for (size_t k = 0; k < m; ++k) {
+    d[k] = 1.0 / alpha[k] + (k ? beta[k - 1] / alpha[k - 1] : 0.0);
+    if (k + 1 < m) e[k] = std::sqrt(std::max(beta[k], 0.0)) / alpha[k];
+  }
+  double lmin = tridiag_eig(d, e, 0), lmax = tridiag_eig(d, e, int(m) - 1);
+  return lmin > 0 ? lmax / lmin : INFINITY;
+}
+
+struct TimedFamily {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  int64_t launches = 0;
+  double total_ms = 0.0;
+};
+
+}  // namespace
+
+struct bddc_ctx {
+  Plan plan;
+  hipStream_t st = nullptr;
+  bool fp32 = false;
+  bool use_graph = false;
+  MeshDevHost mesh{};
+  std::vector<void*> allocs;
+  int64_t dev_bytes = 0;
+  int cus = 256;
+  int grid_trsv = 1024;
+
+  double* theta = nullptr;
+  int32_t *rowptr = nullptr, *col = nullptr;
+  double* val = nullptr;
+  uint8_t* kappa = nullptr;
+  MatDesc* mats = nullptr;
+  int32_t *gmap = nullptr, *lmap = nullptr, *avg_of = nullptr;
+  double *wgt = nullptr, *avg_coef = nullptr, *dsc = nullptr, *wd = nullptr;
+  void* tiles = nullptr;
+  void* dinv = nullptr;
+  double *app = nullptr, *sainv = nullptr, *sainve = nullptr, *aci = nullptr;
+  int32_t *rc = nullptr, *cinv_ptr = nullptr, *cinv = nullptr, *inv_ptr = nullptr, *inv = nullptr;
+  int32_t *ac_src_ptr = nullptr, *ac_src = nullptr, *ac_row = nullptr, *ac_col = nullptr, *ac_diag = nullptr;
+  double *ac_val = nullptr, *dc = nullptr;
+  double *ctiles = nullptr, *cdinv = nullptr;
+  MatDesc* cmat = nullptr;
+  MatDesc cmat_host{};
+  int32_t *ctask_fwd = nullptr, *ctask_bwd = nullptr;
+  int Tc = 0;
+  int32_t *t_fwd_rr = nullptr, *t_bwd_rr = nullptr, *t_fwd_ii = nullptr, *t_bwd_ii = nullptr;
+  void* pub_local = nullptr;   // 4 * n_vec entries of the local precision
+  double* pub_coarse = nullptr;
+  unsigned* tickets = nullptr;
+  double *part = nullptr, *gbuf = nullptr, *mu = nullptr, *coef = nullptr, *ww = nullptr, *v12 = nullptr,
+         *uc = nullptr;
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *tmp = nullptr;
+  double *part_a = nullptr, *part_b = nullptr, *part_c = nullptr, *scal = nullptr;
+  PcgScalars* sc = nullptr;
+  int* err = nullptr;
+  double t_setup_ms = 0.0;
+
+  bool timing = false;
+  std::map<std::string, TimedFamily> fam;
+  std::vector<hipEvent_t> event_pool;
+
+  ~bddc_ctx() {
+    for (auto& kv : fam)
+      for (auto& pr : kv.second.pending) {
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+      }
+    for (hipEvent_t e : event_pool) hipEventDestroy(e);
+    for (void* a : allocs) hipFree(a);
+  }
+
+  template <typename T>
+  int alloc(T*& ptr, int64_t count) {
+    ptr = nullptr;
+    if (count <= 0) count = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, size_t(count) * sizeof(T));
+    if (e != hipSuccess) return fail(BDDC_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    allocs.push_back(p);
+    dev_bytes += count * int64_t(sizeof(T));
+    ptr = static_cast<T*>(p);
+    return BDDC_OK;
+  }
+  template <typename T>
+  int upload(T*& ptr, const std::vector<T>& host) {
+    int rc_ = alloc(ptr, int64_t(host.size()));
+    if (rc_) return rc_;
+    if (!host.empty()) HIP_TRY(hipMemcpyAsync(ptr, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return BDDC_OK;
+  }
+
+  hipEvent_t get_event() {
+    if (!event_pool.empty()) {
+      hipEvent_t e = event_pool.back();
+      event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    hipEventCreate(&e);
+    return e;
+  }
+  // event pair around a launch of a named family when timing is on
+  hipEvent_t begin(const char* name) {
+    if (!timing) return nullptr;
+    hipEvent_t e = get_event();
+    hipEventRecord(e, st);
+    return e;
+  }
+  void end(const char* name, hipEvent_t b) {
+    if (!timing || !b) return;
+    hipEvent_t e = get_event();
+    hipEventRecord(e, st);
+    fam[name].pending.push_back({b, e});
+  }
+  void collect() {
+    hipStreamSynchronize(st);
+    for (auto& kv : fam) {
+      for (auto& pr : kv.second.pending) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, pr.first, pr.second);
+        kv.second.total_ms += ms;
+        kv.second.launches += 1;
+        event_pool.push_back(pr.first);
+        event_pool.push_back(pr.second);
+      }
+      kv.second.pending.clear();
+    }
+  }
+};
+
+namespace {
+
+TrsvArgs base_args(bddc_ctx* c) {
+  TrsvArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.mats = c->mats;
+  a.tiles = c->tiles;
+  a.dinv = c->dinv;
+  a.gmap = c->gmap;
+  a.wd = c->wd;
+  a.dsc = c->dsc;
+  a.rowptr = c->rowptr;
+  a.colind = c->col;
+  a.vals = c->val;
+  return a;
+}
+
+void* pub_slot(bddc_ctx* c, int i) {
+  const size_t es = c->fp32 ? sizeof(float) : sizeof(double);
+  return static_cast<char*>(c->pub_local) + size_t(i) * size_t(c->plan.n_vec) * es;
+}
+
+int trsv_grid(bddc_ctx* c, int ntasks) { return std::max(1, std::min(ntasks, c->grid_trsv)); }
+
+// z = M^{-1} r (paper Sec. 2): v1 + v2 through the forward solve, the coarse
+// problem and the backward solve, then v3 on subdomain interiors.
+void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
+  const Plan& P = c->plan;
+  hipStream_t st = c->st;
+  hipEvent_t ea = c->begin("apply");
+  if (c->fp32) launch_fill_sentinel<float>(static_cast<float*>(c->pub_local), 4 * P.n_vec, st);
+  else launch_fill_sentinel<double>(static_cast<double*>(c->pub_local), 4 * P.n_vec, st);
+  if (c->Tc > 0) launch_fill_sentinel<double>(c->pub_coarse, 2 * int64_t(c->Tc) * NB, st);
+  launch_fill<unsigned>(c->tickets, 0u, 8, st);
+
+  // forward solve with A_RR: t = L^{-1} D W_i R_i r, border partials W^T t
+  TrsvArgs a = base_args(c);
+  a.done = done;
+  a.tasks = c->t_fwd_rr;
+  a.ntasks = int(P.fwd_rr.size() / 2);
+  a.ticket = c->tickets + 0;
+  a.sol = pub_slot(c, 0);
+  a.rin = r;
+  a.part = c->part;
+  hipEvent_t e = c->begin("trsv_fwd_rr");
+  launch_trsv(TRSV_FWD_RR, c->fp32, a, trsv_grid(c, a.ntasks), st);
+  c->end("trsv_fwd_rr", e);
+
+  if (P.n_coarse > 0) {
+    launch_coarse_prep(c->mats, P.nsubs, c->part, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done, st);
+    TrsvArgs cf;
+    std::memset(&cf, 0, sizeof(cf));
+    cf.mats = c->cmat;
+    cf.tiles = c->ctiles;
+    cf.dinv = c->cdinv;
+    cf.done = done;
+    cf.tasks = c->ctask_fwd;
+    cf.ntasks = c->Tc;
+    cf.ticket = c->tickets + 4;
+    cf.sol = c->pub_coarse;
+    cf.cinv_ptr = c->cinv_ptr;
+    cf.cinv = c->cinv;
+    cf.gbuf = c->gbuf;
+    cf.dc = c->dc;
+    launch_trsv(TRSV_FWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
+    cf.tasks = c->ctask_bwd;
+    cf.ticket = c->tickets + 5;
+    cf.src = c->pub_coarse;
+    cf.sol = c->pub_coarse + int64_t(c->Tc) * NB;
+    cf.uc = c->uc;
+    launch_trsv(TRSV_BWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
+    launch_coarse_coef(c->mats, P.nsubs, c->rc, c->uc, c->mu, c->sainv, c->sainve, c->wgt, c->coef, c->ww, done,
+                       st);
+  }
+  // backward solve: D L^{-T} (t + W coef) = z_R + Phi_R u (weighted)
+  a = base_args(c);
+  a.done = done;
+  a.tasks = c->t_bwd_rr;
+  a.ntasks = int(P.bwd_rr.size() / 2);
+  a.ticket = c->tickets + 1;
+  a.sol = pub_slot(c, 1);
+  a.src = pub_slot(c, 0);
+  a.coef = c->coef;
+  a.ww = c->ww;
+  e = c->begin("trsv_bwd_rr");
+  launch_trsv(TRSV_BWD_RR, c->fp32, a, trsv_grid(c, a.ntasks), st);
+  c->end("trsv_bwd_rr", e);
+  // v1 + v2 = sum_i R_i^T W_i w_i
+  launch_gather_v12(c->inv_ptr, c->inv, c->ww, c->kappa, c->v12, z, P.n_free, done, st);
+  // v3: interior solves of r1 = r - A (v1 + v2)
+  a = base_args(c);
+  a.done = done;
+  a.tasks = c->t_fwd_ii;
+  a.ntasks = int(P.fwd_ii.size() / 2);
+  a.ticket = c->tickets + 2;
+  a.sol = pub_slot(c, 2);
+  a.rin = r;
+  a.v12 = c->v12;
+  e = c->begin("trsv_fwd_ii");
+  launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
+  c->end("trsv_fwd_ii", e);
+  a = base_args(c);
+  a.done = done;
+  a.tasks = c->t_bwd_ii;
+  a.ntasks = int(P.bwd_ii.size() / 2);
+  a.ticket = c->tickets + 3;
+  a.sol = pub_slot(c, 3);
+  a.src = pub_slot(c, 2);
+  a.zout = z;
+  a.base = c->v12;
+  e = c->begin("trsv_bwd_ii");
+  launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
+  c->end("trsv_bwd_ii", e);
+  c->end("apply", ea);
+}
+
+// x = P_I b: interior solves of b, zero on the interface
+void enqueue_interior_guess(bddc_ctx* c, const double* b, double* x) {
+  const Plan& P = c->plan;
+  hipStream_t st = c->st;
+  if (c->fp32) launch_fill_sentinel<float>(static_cast<float*>(pub_slot(c, 2)), 2 * P.n_vec, st);
+  else launch_fill_sentinel<double>(static_cast<double*>(pub_slot(c, 2)), 2 * P.n_vec, st);
+  launch_fill<unsigned>(c->tickets, 0u, 8, st);
+  launch_zero_interface(c->kappa, x, P.n_free, st);
+  TrsvArgs a = base_args(c);
+  a.tasks = c->t_fwd_ii;
+  a.ntasks = int(P.fwd_ii.size() / 2);
+  a.ticket = c->tickets + 2;
+  a.sol = pub_slot(c, 2);
+  a.rin = b;
+  launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
+  a = base_args(c);
+  a.tasks = c->t_bwd_ii;
+  a.ntasks = int(P.bwd_ii.size() / 2);
+  a.ticket = c->tickets + 3;
+  a.sol = pub_slot(c, 3);
+  a.src = pub_slot(c, 2);
+  a.zout = x;
+  launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
+}
+
+int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
+  Plan& P = c->plan;
+  hipStream_t st = c->st;
+  int rc_;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  c->cus = prop.multiProcessorCount;
+  c->grid_trsv = std::max(64, c->cus * 4);
+
+  // coefficients
+  if ((rc_ = c->alloc(c->theta, P.n_el))) return rc_;
+  HIP_TRY(hipMemcpyAsync(c->theta, coef->theta, size_t(P.n_el) * sizeof(double),
+                         coef->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  if ((rc_ = c->alloc(c->err, 4))) return rc_;
+  launch_fill<int>(c->err, 0, 4, st);
+  launch_check_theta(c->theta, P.n_el, c->err, st);
+
+  // plan arrays
+  if ((rc_ = c->upload(c->rowptr, P.rowptr))) return rc_;
+  if ((rc_ = c->alloc(c->col, P.nnz))) return rc_;
+  if ((rc_ = c->alloc(c->val, P.nnz))) return rc_;
+  if ((rc_ = c->upload(c->kappa, P.kappa))) return rc_;
+  if ((rc_ = c->upload(c->mats, P.subs))) return rc_;
+  if ((rc_ = c->upload(c->gmap, P.gmap))) return rc_;
+  if ((rc_ = c->upload(c->lmap, P.lmap))) return rc_;
+  if ((rc_ = c->upload(c->avg_of, P.avg_of))) return rc_;
+  if ((rc_ = c->upload(c->wgt, P.weight))) return rc_;
+  if ((rc_ = c->upload(c->avg_coef, P.avg_coef))) return rc_;
+  if ((rc_ = c->alloc(c->dsc, P.n_loc))) return rc_;
+  if ((rc_ = c->alloc(c->wd, P.n_loc))) return rc_;
+  if ((rc_ = c->upload(c->rc, P.rc))) return rc_;
+  if ((rc_ = c->upload(c->cinv_ptr, P.cinv_ptr))) return rc_;
+  if ((rc_ = c->upload(c->cinv, P.cinv))) return rc_;
+  if ((rc_ = c->upload(c->inv_ptr, P.inv_ptr))) return rc_;
+  if ((rc_ = c->upload(c->inv, P.inv))) return rc_;
+  if ((rc_ = c->upload(c->ac_src_ptr, P.ac_src_ptr))) return rc_;
+  if ((rc_ = c->upload(c->ac_src, P.ac_src))) return rc_;
+  if ((rc_ = c->upload(c->ac_row, P.ac_row))) return rc_;
+  if ((rc_ = c->upload(c->ac_col, P.ac_col))) return rc_;
+  if ((rc_ = c->upload(c->ac_diag, P.ac_diag))) return rc_;
+  if ((rc_ = c->upload(c->t_fwd_rr, P.fwd_rr))) return rc_;
+  if ((rc_ = c->upload(c->t_bwd_rr, P.bwd_rr))) return rc_;
+  if ((rc_ = c->upload(c->t_fwd_ii, P.fwd_ii))) return rc_;
+  if ((rc_ = c->upload(c->t_bwd_ii, P.bwd_ii))) return rc_;
+
+  // global matrix
+  launch_assemble_csr(c->mesh, c->theta, c->rowptr, c->col, c->val, P.n_free, c->err, st);
+
+  // local matrices, tiles zero-filled first
+  const int64_t tile_elems = P.n_tiles * NB * NB;
+  const int64_t dinv_elems = P.n_dinv * NB * NB;
+  if (c->fp32) {
+    float *t, *d;
+    if ((rc_ = c->alloc(t, tile_elems))) return rc_;
+    if ((rc_ = c->alloc(d, dinv_elems))) return rc_;
+    launch_fill<float>(t, 0.f, tile_elems, st);
+    c->tiles = t;
+    c->dinv = d;
+    float* pl;
+    if ((rc_ = c->alloc(pl, 4 * P.n_vec))) return rc_;
+    c->pub_local = pl;
+  } else {
+    double *t, *d;
+    if ((rc_ = c->alloc(t, tile_elems))) return rc_;
+    if ((rc_ = c->alloc(d, dinv_elems))) return rc_;
+    launch_fill<double>(t, 0.0, tile_elems, st);
+    c->tiles = t;
+    c->dinv = d;
+    double* pl;
+    if ((rc_ = c->alloc(pl, 4 * P.n_vec))) return rc_;
+    c->pub_local = pl;
+  }
+  const int64_t small = int64_t(P.nsubs) * MAX_NCI * MAX_NCI;
+  if ((rc_ = c->alloc(c->app, small))) return rc_;
+  if ((rc_ = c->alloc(c->sainv, small))) return rc_;
+  if ((rc_ = c->alloc(c->sainve, small))) return rc_;
+  if ((rc_ = c->alloc(c->aci, small))) return rc_;
+  launch_fill<double>(c->app, 0.0, small, st);
+  launch_fill<double>(c->aci, 0.0, small, st);
+  int max_ni = 1;
+  for (auto& D : P.subs) max_ni = std::max(max_ni, int(D.n_i));
+  launch_local_assembly(c->mesh, c->theta, c->mats, P.nsubs, max_ni, c->gmap, c->lmap, c->wgt, c->dsc, c->wd,
+                        c->avg_of, c->avg_coef, c->tiles, c->fp32, c->app, c->err + 1, st);
+  launch_factor(c->mats, P.nsubs, P.maxT, P.maxTx, c->tiles, c->dinv, c->fp32, c->err + 1, st);
+  launch_local_small(c->mats, P.nsubs, c->tiles, c->fp32, c->app, c->sainv, c->sainve, c->aci, c->err + 1, st);
+
+  // coarse problem
+  const int nc = P.n_coarse;
+  c->Tc = (nc + NB - 1) / NB;
+  std::memset(&c->cmat_host, 0, sizeof(MatDesc));
+  c->cmat_host.T = c->Tc;
+  c->cmat_host.Tx = c->Tc;
+  c->cmat_host.n_R = nc;
+  std::vector<MatDesc> cm(1, c->cmat_host);
+  if ((rc_ = c->upload(c->cmat, cm))) return rc_;
+  if ((rc_ = c->alloc(c->ac_val, int64_t(P.ac_row.size())))) return rc_;
+  if ((rc_ = c->alloc(c->dc, nc))) return rc_;
+  if ((rc_ = c->alloc(c->ctiles, tri_tile(c->Tc, 0) * NB * NB))) return rc_;
+  if ((rc_ = c->alloc(c->cdinv, int64_t(c->Tc) * NB * NB))) return rc_;
+  if ((rc_ = c->alloc(c->pub_coarse, 2 * int64_t(c->Tc) * NB))) return rc_;
+  std::vector<int32_t> cf, cb;
+  for (int k = 0; k < c->Tc; ++k) {
+    cf.push_back(0);
+    cf.push_back(k);
+    cb.push_back(0);
+    cb.push_back(c->Tc - 1 - k);
+  }
+  if ((rc_ = c->upload(c->ctask_fwd, cf))) return rc_;
+  if ((rc_ = c->upload(c->ctask_bwd, cb))) return rc_;
+  if (nc > 0) {
+    launch_fill<double>(c->ctiles, 0.0, tri_tile(c->Tc, 0) * NB * NB, st);
+    launch_pad_identity(c->cmat, 1, c->ctiles, false, st);
+    launch_coarse_assembly(c->ac_src_ptr, c->ac_src, c->ac_row, c->ac_col, c->ac_diag, int(P.ac_row.size()), nc,
+                           c->aci, c->ac_val, c->dc, c->ctiles, c->err + 2, st);
+    launch_factor(c->cmat, 1, c->Tc, c->Tc, c->ctiles, c->cdinv, false, c->err + 2, st);
+  }
+
+  // apply and PCG work space
+  if ((rc_ = c->alloc(c->tickets, 8))) return rc_;
+  if ((rc_ = c->alloc(c->part, (P.n_vec / NB + 1) * MAX_NCI))) return rc_;
+  if ((rc_ = c->alloc(c->gbuf, int64_t(P.rc.size()) + 1))) return rc_;
+  if ((rc_ = c->alloc(c->mu, int64_t(P.nsubs) * MAX_NCI))) return rc_;
+  if ((rc_ = c->alloc(c->coef, int64_t(P.nsubs) * MAX_NCI))) return rc_;
+  if ((rc_ = c->alloc(c->ww, P.n_loc))) return rc_;
+  if ((rc_ = c->alloc(c->v12, P.n_free))) return rc_;
+  if ((rc_ = c->alloc(c->uc, nc + 1))) return rc_;
+  launch_fill<double>(c->coef, 0.0, int64_t(P.nsubs) * MAX_NCI, st);
+  if ((rc_ = c->alloc(c->r, P.n_free))) return rc_;
+  if ((rc_ = c->alloc(c->z, P.n_free))) return rc_;
+  if ((rc_ = c->alloc(c->p, P.n_free))) return rc_;
+  if ((rc_ = c->alloc(c->q, P.n_free))) return rc_;
+  if ((rc_ = c->alloc(c->tmp, P.n_free))) return rc_;
+  if ((rc_ = c->alloc(c->part_a, VEC_GRID))) return rc_;
+  if ((rc_ = c->alloc(c->part_b, VEC_GRID))) return rc_;
+  if ((rc_ = c->alloc(c->part_c, VEC_GRID))) return rc_;
+  if ((rc_ = c->alloc(c->sc, 1))) return rc_;
+  if ((rc_ = c->alloc(c->scal, 8))) return rc_;
+
+  HIP_TRY(hipGetLastError());
+  int herr[4] = {0, 0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(herr, c->err, sizeof(herr), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (herr[0] & 1) return fail(BDDC_ENOTSPD, "conductivity must be positive and finite");
+  if (herr[0] & 4) return fail(BDDC_EINVAL, "internal: CSR row count mismatch");
+  if (herr[1]) return fail(BDDC_ENOTSPD, "a local factorisation met a non-positive pivot (flags " +
+                                            std::to_string(herr[1]) + ")");
+  if (herr[2]) return fail(BDDC_ENOTSPD, "the coarse matrix is not positive definite (flags " +
+                                            std::to_string(herr[2]) + ")");
+  return BDDC_OK;
+}
+
+int check_ctx(bddc_ctx* c) {
+  if (!c) return fail(BDDC_EINVAL, "ctx is NULL");
+  return BDDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bddc_plan_stats(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constraints, int64_t stats[8]) {
+  if (!stats) return fail(BDDC_EINVAL, "stats is NULL");
+  Plan P;
+  std::string err;
+  int rc_ = make_plan(mesh, part, constraints, P, err);
+  if (rc_) return fail(rc_, err);
+  int64_t sum_ni = 0;
+  for (auto& D : P.subs) sum_ni += D.n_i;
+  stats[0] = P.n_free;
+  stats[1] = P.nsubs;
+  stats[2] = P.n_coarse;
+  stats[3] = P.n_corner_classes;
+  stats[4] = P.n_edge_classes;
+  stats[5] = P.n_face_classes;
+  stats[6] = sum_ni;
+  stats[7] = P.max_nci;
+  return BDDC_OK;
+}
+
+int bddc_setup(const bddc_mesh* mesh, const bddc_partition* part, const bddc_coefficients* coef,
+               uint32_t constraints, const bddc_options* opts, bddc_ctx** out) {
+  const double t0 = now_ms();
+  if (!out) return fail(BDDC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!coef || !coef->theta) return fail(BDDC_EINVAL, "coefficients are NULL");
+  if (!opts) return fail(BDDC_EINVAL, "options are NULL");
+  if (opts->local_bits != 32 && opts->local_bits != 64) return fail(BDDC_EINVAL, "local_bits must be 32 or 64");
+  if (opts->nb_override != 0 && opts->nb_override != NB) return fail(BDDC_ENOTIMPL, "only 64-wide tiles are built");
+  if (opts->flags & ~BDDC_SETUP_KEEP_ON_ERROR) return fail(BDDC_EINVAL, "unknown options.flags bits");
+  bddc_ctx* c = new (std::nothrow) bddc_ctx();
+  if (!c) return fail(BDDC_ENOMEM, "host allocation failed");
+  std::string err;
+  int rc_ = make_plan(mesh, part, constraints, c->plan, err);
+  if (rc_) {
+    delete c;
+    return fail(rc_, err);
+  }
+  if (coef->on_device != 0 && coef->on_device != 1) {
+    delete c;
+    return fail(BDDC_EINVAL, "coefficients.on_device must be 0 or 1");
+  }
+  if (!coef->on_device) {
+    for (int64_t e = 0; e < c->plan.n_el; ++e)
+      if (!(coef->theta[e] > 0.0) || !std::isfinite(coef->theta[e])) {
+        delete c;
+        return fail(BDDC_ENOTSPD, "conductivity must be positive and finite (element " + std::to_string(e) + ")");
+      }
+  }
+  c->st = static_cast<hipStream_t>(opts->stream);
+  c->fp32 = opts->local_bits == 32;
+  c->use_graph = opts->use_graph != 0;
+  c->mesh.dim = c->plan.dim;
+  for (int a = 0; a < 3; ++a) {
+    c->mesh.nel[a] = int(c->plan.nel[a]);
+    c->mesh.h[a] = 1.0 / double(c->plan.nel[a]);
+  }
+  rc_ = do_setup(c, coef);
+  if (rc_) {
+    hipStreamSynchronize(c->st);
+    if ((opts->flags & BDDC_SETUP_KEEP_ON_ERROR) && rc_ == BDDC_ENOTSPD) {
+      *out = c;
+      return rc_;
+    }
+    delete c;
+    return rc_;
+  }
+  c->t_setup_ms = now_ms() - t0;
+  *out = c;
+  return BDDC_OK;
+}
+
+int bddc_apply(bddc_ctx* c, const double* r, double* z) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  if (!r || !z || r == z) return fail(BDDC_EINVAL, "r and z must be distinct non-NULL device pointers");
+  enqueue_apply(c, r, z, nullptr);
+  HIP_TRY(hipGetLastError());
+  return BDDC_OK;
+}
+
+int bddc_spmv(bddc_ctx* c, const double* x, double* y) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  if (!x || !y || x == y) return fail(BDDC_EINVAL, "x and y must be distinct non-NULL device pointers");
+  hipEvent_t e = c->begin("spmv");
+  launch_spmv(c->rowptr, c->col, c->val, x, y, c->plan.n_free, c->st);
+  c->end("spmv", e);
+  HIP_TRY(hipGetLastError());
+  return BDDC_OK;
+}
+
+int bddc_elem_grad(bddc_ctx* c, const double* lam, const double* u, double* g) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  if (!lam || !u || !g) return fail(BDDC_EINVAL, "NULL pointer");
+  launch_elem_grad(c->mesh, lam, u, g, c->plan.n_el, c->st);
+  HIP_TRY(hipGetLastError());
+  return BDDC_OK;
+}
+
+int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t maxit, int32_t flags,
+                   bddc_pcg_info* info) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  if (!b || !x || b == x) return fail(BDDC_EINVAL, "b and x must be distinct non-NULL device pointers");
+  if (!(rtol > 0.0) || !(rtol < 1.0)) return fail(BDDC_EINVAL, "rtol must be in (0, 1)");
+  if (maxit < 0 || maxit > MAX_PCG_IT) return fail(BDDC_EINVAL, "maxit must be in [0, 8192]");
+  if (flags & ~BDDC_X0_GIVEN) return fail(BDDC_EINVAL, "unknown solve flags");
+  const double t0 = now_ms();
+  const Plan& P = c->plan;
+  hipStream_t st = c->st;
+  const int64_t n = P.n_free;
+  int* done = &c->sc->done;
+  if (!(flags & BDDC_X0_GIVEN)) enqueue_interior_guess(c, b, x);
+  launch_residual(c->rowptr, c->col, c->val, x, b, c->r, c->part_a, c->part_b, n, st);
+  launch_pcg_init(c->part_a, c->part_b, c->sc, rtol * rtol, st);
+
+  struct HostScalars { double tol2, bb, rr0; int done, iters; } hs{};
+  std::vector<double> alphas, betas;
+  int it = 0;            // iteration slot
+  int restarts = 0;
+  int status = BDDC_OK;
+  double relres_true = 0.0, relres_rec = 0.0;
+  const int chunk = 4;
+  bool fresh = true;
+  int seg_start = 0;
+  for (;;) {
+    // (re)start: z = M^{-1} r, rz
+    enqueue_apply(c, c->r, c->z, done);
+    launch_dot(c->r, c->z, c->part_c, n, done, st);
+    while (it < maxit) {
+      const int end = std::min(maxit, it + chunk);
+      for (; it < end; ++it) {
+        hipEvent_t e = c->begin("spmv");
+        launch_pcg_dir(c->rowptr, c->col, c->val, c->z, c->p, c->q, c->part_c, c->part_a, c->sc, it, fresh ? 1 : 0,
+                       n, st);
+        c->end("spmv", e);
+        fresh = false;
+        launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st);
+        launch_pcg_check(c->part_b, c->sc, it, st);
+        enqueue_apply(c, c->r, c->z, done);
+        launch_dot(c->r, c->z, c->part_c, n, done, st);
+      }
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(&hs, c->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (hs.done) break;
+    }
+    HIP_TRY(hipMemcpyAsync(&hs, c->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int iters = hs.iters;
+    // CG coefficients of this segment
+    if (iters > seg_start) {
+      std::vector<double> al(iters - seg_start), be(iters - seg_start);
+      HIP_TRY(hipMemcpy(al.data(), c->sc->alpha + seg_start, al.size() * sizeof(double), hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(be.data(), c->sc->beta + seg_start, be.size() * sizeof(double), hipMemcpyDeviceToHost));
+      if (restarts == 0) {
+        alphas = al;
+        betas.assign(be.begin(), be.end() - 1);
+      }
+    }
+    double rr = 0.0;
+    if (iters > 0) HIP_TRY(hipMemcpy(&rr, c->sc->rr + iters - 1, sizeof(double), hipMemcpyDeviceToHost));
+    else rr = hs.rr0;
+    relres_rec = hs.bb > 0 ? std::sqrt(rr / hs.bb) : 0.0;
+    // true residual
+    launch_residual(c->rowptr, c->col, c->val, x, b, c->tmp, c->part_a, c->part_b, n, st);
+    launch_finish_dot(c->part_a, c->scal, st);
+    double rr_true = 0.0;
+    HIP_TRY(hipMemcpyAsync(&rr_true, c->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    relres_true = hs.bb > 0 ? std::sqrt(rr_true / hs.bb) : 0.0;
+    if (hs.done == 2) { status = BDDC_EBREAKDOWN; break; }
+    if (hs.done == 1 && relres_true <= rtol) { status = BDDC_OK; break; }
+    if (it >= maxit) { status = BDDC_ENOCONV; break; }
+    if (restarts >= 3) { status = BDDC_ENOCONV; break; }
+    // residual replacement: r = b - A x, restart the directions
+    ++restarts;
+    launch_residual(c->rowptr, c->col, c->val, x, b, c->r, c->part_a, c->part_b, n, st);
+    launch_pcg_init(c->part_a, c->part_b, c->sc, rtol * rtol, st);
+    // keep the iteration count across the restart
+    fresh = true;
+    seg_start = it;
+    launch_fill<int>(&c->sc->iters, it, 1, st);
+  }
+  if (info) {
+    info->iters = hs.iters;
+    info->relres_true = relres_true;
+    info->relres_rec = relres_rec;
+    info->cond_est = lanczos_cond(alphas, betas);
+    info->t_setup_ms = c->t_setup_ms;
+    info->t_solve_ms = now_ms() - t0;
+  }
+  if (status == BDDC_EBREAKDOWN) return fail(status, "CG breakdown: (p, A p) <= 0, (r, z) <= 0 or NaN");
+  if (status == BDDC_ENOCONV) return fail(status, "maximum iterations reached");
+  return BDDC_OK;
+}
+
+int bddc_query(bddc_ctx* c, int64_t* n_free, int32_t* n_sub, int32_t* n_coarse, int64_t* dev_bytes) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  if (n_free) *n_free = c->plan.n_free;
+  if (n_sub) *n_sub = c->plan.nsubs;
+  if (n_coarse) *n_coarse = c->plan.n_coarse;
+  if (dev_bytes) *dev_bytes = c->dev_bytes;
+  return BDDC_OK;
+}
+
+int bddc_set_timing(bddc_ctx* c, int32_t enabled) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  c->collect();
+  c->timing = enabled != 0;
+  return BDDC_OK;
+}
+
+int bddc_kernel_time(bddc_ctx* c, const char* family, int64_t* launches, double* total_ms) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  static const char* known[] = {"trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii", "trsv_bwd_ii", "spmv", "apply"};
+  bool ok = false;
+  for (const char* k : known) ok |= family && std::strcmp(family, k) == 0;
+  if (!ok) return fail(BDDC_EINVAL, "unknown kernel family");
+  c->collect();
+  auto it = c->fam.find(family);
+  if (launches) *launches = it == c->fam.end() ? 0 : it->second.launches;
+  if (total_ms) *total_ms = it == c->fam.end() ? 0.0 : it->second.total_ms;
+  if (it != c->fam.end()) {
+    it->second.launches = 0;
+    it->second.total_ms = 0.0;
+  }
+  return BDDC_OK;
+}
+
+int64_t bddc_debug_read(bddc_ctx* c, const char* what, int32_t sub, double* out, int64_t cap) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  if (!what || !out || sub < 0 || sub >= c->plan.nsubs) return fail(BDDC_EINVAL, "bad debug_read arguments");
+  HIP_TRY(hipStreamSynchronize(c->st));
+  const MatDesc& D = c->plan.subs[sub];
+  const std::string w(what);
+  const int64_t es = c->fp32 ? 4 : 8;
+  auto tile_to_double = [&](int64_t tile_index, std::vector<double>& buf) -> int {
+    buf.resize(NB * NB);
+    if (c->fp32) {
+      std::vector<float> f(NB * NB);
+      HIP_TRY(hipMemcpy(f.data(), static_cast<char*>(c->tiles) + tile_index * NB * NB * es, NB * NB * es,
+                        hipMemcpyDeviceToHost));
+      for (int i = 0; i < NB * NB; ++i) buf[i] = f[i];
+    } else {
+      HIP_TRY(hipMemcpy(buf.data(), static_cast<char*>(c->tiles) + tile_index * NB * NB * es, NB * NB * es,
+                        hipMemcpyDeviceToHost));
+    }
+    return BDDC_OK;
+  };
+  std::vector<double> res;
+  if (w == "sizes") {
+    res = {double(D.n_R), double(D.n_I), double(D.n_A), double(D.n_P), double(D.T), double(D.n_i)};
+  } else if (w == "factor") {
+    const int64_t n = int64_t(D.T) * NB;
+    res.assign(n * n, 0.0);
+    std::vector<double> t;
+    for (int i = 0; i < D.T; ++i)
+      for (int j = 0; j <= i; ++j) {
+        if (int rc_ = tile_to_double(D.tile_off + tri_tile(i, j), t)) return rc_;
+        for (int r = 0; r < NB; ++r)
+          for (int q = 0; q < NB; ++q) res[(i * NB + r) * n + j * NB + q] = t[r * NB + q];
+      }
+  } else if (w == "border" || w == "schur") {
+    if (D.n_ci == 0) return 0;
+    std::vector<double> t;
+    if (w == "schur") {
+      if (int rc_ = tile_to_double(D.tile_off + tri_tile(D.T, D.T), t)) return rc_;
+      res = t;
+    } else {
+      const int64_t n = int64_t(D.T) * NB;
+      res.assign(NB * n, 0.0);
+      for (int j = 0; j < D.T; ++j) {
+        if (int rc_ = tile_to_double(D.tile_off + tri_tile(D.T, j), t)) return rc_;
+        for (int r = 0; r < NB; ++r)
+          for (int q = 0; q < NB; ++q) res[r * n + j * NB + q] = t[r * NB + q];
+      }
+    }
+  } else if (w == "aci") {
+    res.resize(MAX_NCI * MAX_NCI);
+    HIP_TRY(hipMemcpy(res.data(), c->aci + int64_t(sub) * MAX_NCI * MAX_NCI, res.size() * 8, hipMemcpyDeviceToHost));
+  } else if (w == "gmap") {
+    res.resize(D.n_i);
+    for (int a = 0; a < D.n_i; ++a) res[a] = c->plan.gmap[D.loc_off + a];
+  } else if (w == "dscale") {
+    res.resize(D.n_i);
+    HIP_TRY(hipMemcpy(res.data(), c->dsc + D.loc_off, res.size() * 8, hipMemcpyDeviceToHost));
+  } else {
+    return fail(BDDC_EINVAL, "unknown debug_read item");
+  }
+  const int64_t m = std::min<int64_t>(cap, int64_t(res.size()));
+  std::memcpy(out, res.data(), size_t(m) * sizeof(double));
+  return m;
+}
+
+void bddc_destroy(bddc_ctx* c) {
+  if (!c) return;
+  hipStreamSynchronize(c->st);
+  delete c;
+}
+
+const char* bddc_strerror(int code) {
+  switch (code) {
+    case BDDC_OK: return "success";
+    case BDDC_EINVAL: return "invalid argument";
+    case BDDC_ENOTSPD: return "matrix not symmetric positive definite";
+    case BDDC_ENOMEM: return "out of memory";
+    case BDDC_EHIP: return "HIP runtime error";
+    case BDDC_ENOCONV: return "no convergence within maxit";
+    case BDDC_EBREAKDOWN: return "CG breakdown";
+    case BDDC_ENOTIMPL: return "not implemented";
+    default: return "unknown status";
+  }
+}
+
+const char* bddc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Internal declarations shared by the host planner, the kernels and the ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bddc.h"
+
+namespace bddc {
+
+constexpr int NB = 64;        // tile edge (rows and columns) of every dense factor
+constexpr int MAX_NCI = 64;   // constraints per subdomain (one extra tile row)
+
+// Per-matrix descriptor used by the factorisation and the triangular solves.
+// A "matrix" is a subdomain's equilibrated A_RR bordered by one extra tile row
+// holding (D B)^T with B = [C_AR^T | A_RPi], or the coarse matrix A_c.
+struct MatDesc {
+  int64_t tile_off;   // first tile of this matrix in the tile array
+  int64_t dinv_off;   // first inverse-diagonal tile
+  int64_t vec_off;    // offset of this matrix's padded vectors (T*NB entries)
+  int64_t loc_off;    // offset of its local dof arrays (n_i entries)
+  int32_t T;          // factored tile rows: ceil(n_R / NB)
+  int32_t Tx;         // stored tile rows: T + 1 with the border row, else T
+  int32_t TI;         // tile rows covering the interior block: ceil(n_I / NB)
+  int32_t n_R;        // rows of A_RR (interior + non-corner interface)
+  int32_t n_I;        // interior rows (the leading block)
+  int32_t n_i;        // all local dofs (n_R + corners)
+  int32_t n_A;        // average constraints
+  int32_t n_P;        // corner (primal point) constraints
+  int32_t n_ci;       // n_A + n_P
+  int32_t coarse_off; // offset into the per-subdomain coarse arrays
+  int32_t box_lo[3];  // first element of the box along each axis
+  int32_t box_len[3]; // box length in elements
+  int32_t lmap_off;   // offset of the box-node -> local index table
+  int32_t pad;
+};
+
+// Host-side plan: everything bddc_setup derives from the mesh and partition
+// before any device work.
+struct Plan {
+  int dim = 0;
+  int64_t nel[3] = {1, 1, 1};
+  int nsub[3] = {1, 1, 1};
+  std::vector<int64_t> cuts[3];
+  uint32_t constraints = 0;
+  int64_t n_free = 0;
+  int64_t n_el = 0;
+  int nsubs = 0;
+
+  // global CSR pattern (values come from the device assembly)
+  std::vector<int32_t> rowptr;   // n_free + 1
+  int64_t nnz = 0;
+  std::vector<uint8_t> kappa;    // multiplicity of each free dof
+
+  std::vector<MatDesc> subs;
+  // concatenated local arrays (sum n_i): order [interior | interface R | corners]
+  std::vector<int32_t> gmap;     // local dof -> global free dof
+  std::vector<double> weight;    // 1/kappa
+  std::vector<int32_t> avg_of;   // local average-constraint index, or -1
+  std::vector<double> avg_coef;  // 1/(nodes in the class) for constrained dofs
+  std::vector<int32_t> lmap;     // box node -> local index, -1 on the Dirichlet boundary
+
+  // coarse space
+  int n_coarse = 0;
+  int n_corner_classes = 0, n_edge_classes = 0, n_face_classes = 0;
+  std::vector<int32_t> rc;        // per subdomain local coarse index -> global (sum n_ci)
+  std::vector<int32_t> cinv_ptr;  // global coarse dof -> slots in rc
+  std::vector<int32_t> cinv;
+  std::vector<int32_t> inv_ptr;   // global dof -> slots in the local arrays
+  std::vector<int32_t> inv;
+
+  // coarse matrix assembly: unique lower entries (p >= q) and their sources
+  std::vector<int32_t> ac_row, ac_col;   // per unique entry
+  std::vector<int32_t> ac_src_ptr;       // per unique entry -> sources
+  std::vector<int32_t> ac_src;           // source = s * MAX_NCI*MAX_NCI + a*MAX_NCI + b
+  std::vector<int32_t> ac_diag;          // entry index of (p, p)
+
+  // ticket-ordered task lists of the triangular solves, (matrix, tile row)
+  std::vector<int32_t> fwd_rr, bwd_rr, fwd_ii, bwd_ii;
+
+  int maxT = 0, maxTx = 0, maxTI = 0;
+  int64_t n_tiles = 0, n_dinv = 0, n_vec = 0, n_loc = 0, n_lmap = 0;
+  int max_nci = 0;
+};
+
+// Validates and plans; returns a bddc_status, with a message in err.
+int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constraints,
+              Plan& plan, std::string& err);
+
+#if defined(__HIPCC__)
+#define BDDC_HD __host__ __device__
+#else
+#define BDDC_HD
+#endif
+
+// Tile index of tile (i, j), j <= i, inside a matrix's packed lower storage.
+BDDC_HD inline int64_t tri_tile(int64_t i, int64_t j) { return i * (i + 1) / 2 + j; }
+
+}  // namespace bddc

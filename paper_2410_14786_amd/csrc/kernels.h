@@ -1,0 +1,118 @@
+// Launch wrappers of the HIP kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bddc_internal.h"
+
+namespace bddc {
+
+constexpr int MAX_PCG_IT = 8192;
+
+struct MeshDevHost {
+  int dim;
+  int nel[3];
+  double h[3];
+};
+
+enum {
+  TRSV_FWD_RR = 0,  // L y = D W_i R_i r on the whole A_RR factor (+ border partials)
+  TRSV_BWD_RR = 1,  // L^T x = y + W coef on the whole factor (-> weighted local output)
+  TRSV_FWD_II = 2,  // interior block, rhs = D (r - A v12) on interior rows
+  TRSV_BWD_II = 3,  // interior block, z = v12 + D x on interior rows
+  TRSV_FWD_C = 4,   // coarse factor, rhs gathered from the subdomain coarse residuals
+  TRSV_BWD_C = 5    // coarse factor, u_c = D x
+};
+
+struct TrsvArgs {
+  const MatDesc* mats;
+  const void* tiles;
+  const void* dinv;
+  const int32_t* tasks;
+  int ntasks;
+  unsigned* ticket;
+  void* sol;             // published solution, sentinel-initialised
+  const void* src;       // backward passes: the forward solution
+  const int* done;       // optional early exit (converged PCG)
+  const int32_t* gmap;
+  const double* wd;      // weight * equilibration per local dof
+  const double* dsc;     // equilibration per local dof
+  const double* rin;     // forward input vector (global)
+  const double* v12;     // FWD_II: subtract A v12 (may be null)
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const double* vals;
+  double* part;          // FWD_RR border partial products
+  const double* coef;    // BWD_RR per-matrix coefficients of the border columns
+  double* ww;            // BWD_RR weighted local output
+  double* zout;          // BWD_II output
+  const double* base;    // BWD_II: added to the output (may be null)
+  const int32_t* cinv_ptr;
+  const int32_t* cinv;
+  const double* gbuf;
+  const double* dc;
+  double* uc;
+};
+
+struct PcgScalars {
+  double tol2;
+  double bb;
+  double rr0;
+  int done;    // 0 running, 1 converged, 2 breakdown
+  int iters;
+  double rz[MAX_PCG_IT + 1];
+  double pq[MAX_PCG_IT + 1];
+  double rr[MAX_PCG_IT + 1];
+  double alpha[MAX_PCG_IT + 1];
+  double beta[MAX_PCG_IT + 1];
+};
+
+template <typename T> void launch_fill(T* p, T v, int64_t n, hipStream_t st);
+template <typename T> void launch_fill_sentinel(T* p, int64_t n, hipStream_t st);
+
+void launch_check_theta(const double* theta, int64_t n, int* err, hipStream_t st);
+void launch_assemble_csr(const MeshDevHost& m, const double* theta, const int32_t* rowptr, int32_t* col,
+                         double* val, int64_t n, int* err, hipStream_t st);
+void launch_local_assembly(const MeshDevHost& m, const double* theta, const MatDesc* mats, int nmats, int max_ni,
+                           const int32_t* gmap, const int32_t* lmap, const double* wgt, double* dsc, double* wd,
+                           const int32_t* avg_of, const double* avg_coef, void* tiles, bool fp32, double* app,
+                           int* err, hipStream_t st);
+void launch_pad_identity(const MatDesc* mats, int nmats, void* tiles, bool fp32, hipStream_t st);
+void launch_factor(const MatDesc* mats, int nmats, int maxT, int maxTx, void* tiles, void* dinv, bool fp32,
+                   int* err, hipStream_t st);
+void launch_local_small(const MatDesc* mats, int nmats, const void* tiles, bool fp32, const double* app,
+                        double* sainv, double* sainve, double* aci, int* err, hipStream_t st);
+void launch_coarse_assembly(const int32_t* src_ptr, const int32_t* src, const int32_t* row, const int32_t* col,
+                            const int32_t* diag, int nentries, int nc, const double* aci, double* val, double* dc,
+                            double* tiles, int* err, hipStream_t st);
+void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st);
+void launch_coarse_prep(const MatDesc* mats, int nmats, const double* part, const double* sainv,
+                        const double* sainve, const int32_t* gmap, const double* wgt, const double* r,
+                        double* gbuf, double* mu, const int* done, hipStream_t st);
+void launch_coarse_coef(const MatDesc* mats, int nmats, const int32_t* rc, const double* uc, const double* mu,
+                        const double* sainv, const double* sainve, const double* wgt, double* coef, double* ww,
+                        const int* done, hipStream_t st);
+void launch_gather_v12(const int32_t* inv_ptr, const int32_t* inv, const double* ww, const uint8_t* kappa,
+                       double* v12, double* z, int64_t n, const int* done, hipStream_t st);
+void launch_zero_interface(const uint8_t* kappa, double* x, int64_t n, hipStream_t st);
+void launch_spmv(const int32_t* rowptr, const int32_t* col, const double* val, const double* x, double* y, int64_t n,
+                 hipStream_t st);
+void launch_residual(const int32_t* rowptr, const int32_t* col, const double* val, const double* x, const double* b,
+                     double* r, double* part_rr, double* part_bb, int64_t n, hipStream_t st);
+void launch_pcg_init(const double* part_rr, const double* part_bb, PcgScalars* sc, double rtol2, hipStream_t st);
+void launch_pcg_dir(const int32_t* rowptr, const int32_t* col, const double* val, const double* z, double* p,
+                    double* q, const double* part_rz, double* part_pq, PcgScalars* sc, int it, int fresh, int64_t n,
+                    hipStream_t st);
+void launch_pcg_update(double* x, double* r, const double* p, const double* q, const double* part_pq,
+                       double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st);
+void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, hipStream_t st);
+void launch_dot(const double* a, const double* b, double* part, int64_t n, const int* done, hipStream_t st);
+void launch_finish_dot(const double* part, double* out, hipStream_t st);
+void launch_elem_grad(const MeshDevHost& m, const double* lam, const double* u, double* g, int64_t nel,
+                      hipStream_t st);
+
+constexpr int VEC_GRID = 1024;   // partial-sum count of the vector kernels
+
+}  // namespace bddc

@@ -1,0 +1,1286 @@
+// HIP kernels for gfx950: assembly, batched tiled Cholesky on MFMA, persistent
+// sync-free triangular solves, the coarse problem and the PCG vector kernels.
+//
+// Paper Sec. 2 defines what every kernel computes (eqs. (1)-(5)); the way it is
+// computed here is this library's own:
+//  * each subdomain's A_RR (interior first, then non-corner interface dofs) is
+//    equilibrated to unit diagonal and stored as NB x NB lower tiles; one more
+//    tile row holds (D B)^T with B = [C_AR^T | A_RPi], so the right-looking
+//    factorisation also produces W = L^{-1} D B and, in the bordering diagonal
+//    tile, -W^T W (the constraint Schur complement and its coupling blocks);
+//  * the leading interior block of L is chol(A_II), reused for eq. (5);
+//  * triangular solves are persistent kernels that take (matrix, tile row)
+//    tasks from a ticket counter in dependency order; each published solution
+//    value doubles as its own ready flag (a signalling-NaN sentinel until it
+//    is written), read and written with device-scope atomics.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bddc_internal.h"
+#include "kernels.h"
+
+namespace bddc {
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Traits;
+template <> struct Traits<double> {
+  using U = unsigned long long;
+  using V = d2v;
+  static constexpr int VEC = 2;
+  static constexpr U SENT = 0x7FF4A5A5A5A5A5A5ull;   // signalling NaN, never produced by arithmetic
+};
+template <> struct Traits<float> {
+  using U = unsigned int;
+  using V = f4v;
+  static constexpr int VEC = 4;
+  static constexpr U SENT = 0x7F85A5A5u;
+};
+
+template <typename T>
+__device__ __forceinline__ T load_published(const T* p) {
+  using U = typename Traits<T>::U;
+  U v = __hip_atomic_load(reinterpret_cast<const U*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_bit_cast(T, v);
+}
+
+template <typename T>
+__device__ __forceinline__ bool is_sentinel(T v) {
+  using U = typename Traits<T>::U;
+  return __builtin_bit_cast(U, v) == Traits<T>::SENT;
+}
+
+template <typename T>
+__device__ __forceinline__ T poll_published(const T* p) {
+  T v = load_published(p);
+  while (is_sentinel(v)) {
+    __builtin_amdgcn_s_sleep(2);
+    v = load_published(p);
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_published(T* p, T v) {
+  using U = typename Traits<T>::U;
+  __hip_atomic_store(reinterpret_cast<U*>(p), __builtin_bit_cast(U, v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// Q1 element matrix entries (closed form of the tensor-product integrals)
+// ---------------------------------------------------------------------------
+
+struct MeshDev {
+  int dim;
+  int nel[3];
+  double h[3];
+};
+
+// integral of grad N_a . grad N_b over one element; a, b are local node numbers
+// (bit d = offset along axis d)
+__device__ __forceinline__ double kref(const MeshDev& M, int a, int b) {
+  double val = 0.0;
+  for (int d = 0; d < M.dim; ++d) {
+    double t = (((a >> d) & 1) == ((b >> d) & 1)) ? 1.0 / M.h[d] : -1.0 / M.h[d];
+    for (int o = 0; o < M.dim; ++o)
+      if (o != d) t *= M.h[o] * ((((a >> o) & 1) == ((b >> o) & 1)) ? 2.0 : 1.0) / 6.0;
+    val += t;
+  }
+  return val;
+}
+
+// Stiffness entry between nodes n1 and n2 (integer coordinates), summed over the
+// elements of the box [lo, lo+len) that contain both.
+__device__ double stiff_entry(const MeshDev& M, const double* theta, const int n1[3], const int n2[3],
+                              const int lo[3], const int len[3]) {
+  int e0[3], e1[3];
+  for (int d = 0; d < 3; ++d) {
+    if (d >= M.dim) { e0[d] = 0; e1[d] = 0; continue; }
+    int a = max(max(n1[d], n2[d]) - 1, lo[d]);
+    int b = min(min(n1[d], n2[d]), lo[d] + len[d] - 1);
+    e0[d] = a;
+    e1[d] = b;
+    if (a > b) return 0.0;
+  }
+  double v = 0.0;
+  for (int ez = e0[2]; ez <= e1[2]; ++ez)
+    for (int ey = e0[1]; ey <= e1[1]; ++ey)
+      for (int ex = e0[0]; ex <= e1[0]; ++ex) {
+        int e[3] = {ex, ey, ez};
+        int la = 0, lb = 0;
+        for (int d = 0; d < M.dim; ++d) {
+          la |= (n1[d] - e[d]) << d;
+          lb |= (n2[d] - e[d]) << d;
+        }
+        int64_t eid = ex + int64_t(M.nel[0]) * (ey + int64_t(M.nel[1]) * ez);
+        v += theta[eid] * kref(M, la, lb);
+      }
+  return v;
+}
+
+__device__ __forceinline__ void free_coords(const MeshDev& M, int64_t g, int c[3]) {
+  int nx1 = M.nel[0] - 1, ny1 = M.nel[1] - 1;
+  c[0] = int(g % nx1) + 1;
+  g /= nx1;
+  if (M.dim == 3) {
+    c[1] = int(g % ny1) + 1;
+    c[2] = int(g / ny1) + 1;
+  } else {
+    c[1] = int(g) + 1;
+    c[2] = 0;
+  }
+}
+
+__device__ __forceinline__ int64_t free_of(const MeshDev& M, const int c[3]) {
+  for (int d = 0; d < M.dim; ++d)
+    if (c[d] < 1 || c[d] > M.nel[d] - 1) return -1;
+  int64_t g = c[0] - 1;
+  g += int64_t(M.nel[0] - 1) * (c[1] - 1);
+  if (M.dim == 3) g += int64_t(M.nel[0] - 1) * (M.nel[1] - 1) * (c[2] - 1);
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// Simple fills
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void fill_kernel(T* p, T v, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+template <typename T>
+__global__ void fill_bits_kernel(T* p, int64_t n) {
+  using U = typename Traits<T>::U;
+  U* q = reinterpret_cast<U*>(p);
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    q[i] = Traits<T>::SENT;
+}
+
+static int grid_for(int64_t n, int block = 256, int cap = 8192) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return int(g);
+}
+
+template <typename T>
+void launch_fill(T* p, T v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel<T>, dim3(grid_for(n)), dim3(256), 0, st, p, v, n);
+}
+template void launch_fill<double>(double*, double, int64_t, hipStream_t);
+template void launch_fill<float>(float*, float, int64_t, hipStream_t);
+template void launch_fill<int>(int*, int, int64_t, hipStream_t);
+template void launch_fill<unsigned>(unsigned*, unsigned, int64_t, hipStream_t);
+
+template <typename T>
+void launch_fill_sentinel(T* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_bits_kernel<T>, dim3(grid_for(n)), dim3(256), 0, st, p, n);
+}
+template void launch_fill_sentinel<double>(double*, int64_t, hipStream_t);
+template void launch_fill_sentinel<float>(float*, int64_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Global CSR assembly (paper Sec. 2: A from all elements)
+// ---------------------------------------------------------------------------
+
+__global__ void assemble_csr_kernel(MeshDev M, const double* theta, const int32_t* rowptr, int32_t* col,
+                                    double* val, int64_t n, int* err) {
+  int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (g >= n) return;
+  int c[3];
+  free_coords(M, g, c);
+  int lo[3] = {0, 0, 0}, len[3] = {M.nel[0], M.nel[1], M.dim == 3 ? M.nel[2] : 1};
+  int64_t j = rowptr[g];
+  const int zr = M.dim == 3 ? 1 : 0;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int nb[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+        int64_t q = free_of(M, nb);
+        if (q < 0) continue;
+        col[j] = int32_t(q);
+        val[j] = stiff_entry(M, theta, c, nb, lo, len);
+        ++j;
+      }
+  if (j != rowptr[g + 1]) atomicOr(err, 4);
+}
+
+void launch_assemble_csr(const MeshDevHost& mh, const double* theta, const int32_t* rowptr, int32_t* col,
+                         double* val, int64_t n, int* err, hipStream_t st) {
+  MeshDev M{mh.dim, {mh.nel[0], mh.nel[1], mh.nel[2]}, {mh.h[0], mh.h[1], mh.h[2]}};
+  hipLaunchKernelGGL(assemble_csr_kernel, dim3((n + 255) / 256), dim3(256), 0, st, M, theta, rowptr, col, val,
+                     n, err);
+}
+
+__global__ void check_theta_kernel(const double* theta, int64_t n, int* err) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    if (!(theta[i] > 0.0) || !(theta[i] < 1e300)) atomicOr(err, 1);
+}
+
+void launch_check_theta(const double* theta, int64_t n, int* err, hipStream_t st) {
+  hipLaunchKernelGGL(check_theta_kernel, dim3(grid_for(n)), dim3(256), 0, st, theta, n, err);
+}
+
+// ---------------------------------------------------------------------------
+// Local (subdomain) assembly into equilibrated tiles
+// ---------------------------------------------------------------------------
+
+// local dof a of matrix s -> box-local node coordinates
+__device__ __forceinline__ void local_node(const MeshDev& M, const MatDesc& D, const int32_t* gmap, int a,
+                                           int c[3]) {
+  free_coords(M, gmap[D.loc_off + a], c);
+}
+
+// d_a = 1 / sqrt(A_aa) for a < n_R (diagonal of the box-restricted Neumann matrix)
+__global__ void local_diag_kernel(MeshDev M, const double* theta, const MatDesc* mats, const int32_t* gmap,
+                                  const double* wgt, double* dsc, double* wd, int* err) {
+  const MatDesc D = mats[blockIdx.y];
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.n_i) return;
+  if (a >= D.n_R) {
+    dsc[D.loc_off + a] = 1.0;
+    wd[D.loc_off + a] = wgt[D.loc_off + a];
+    return;
+  }
+  int c[3];
+  local_node(M, D, gmap, a, c);
+  int lo[3] = {D.box_lo[0], D.box_lo[1], D.box_lo[2]};
+  int len[3] = {D.box_len[0], D.box_len[1], M.dim == 3 ? D.box_len[2] : 1};
+  double v = stiff_entry(M, theta, c, c, lo, len);
+  if (!(v > 0.0)) { atomicOr(err, 1); v = 1.0; }
+  const double d = 1.0 / sqrt(v);
+  dsc[D.loc_off + a] = d;
+  wd[D.loc_off + a] = wgt[D.loc_off + a] * d;
+}
+
+template <typename T>
+__global__ void local_assemble_kernel(MeshDev M, const double* theta, const MatDesc* mats, const int32_t* gmap,
+                                      const int32_t* lmap, const double* dsc, const int32_t* avg_of,
+                                      const double* avg_coef, T* tiles, double* app) {
+  const int s = blockIdx.y;
+  const MatDesc D = mats[s];
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.n_i) return;
+  int c[3];
+  local_node(M, D, gmap, a, c);
+  int lo[3] = {D.box_lo[0], D.box_lo[1], D.box_lo[2]};
+  int len[3] = {D.box_len[0], D.box_len[1], M.dim == 3 ? D.box_len[2] : 1};
+  const int n1x = D.box_len[0] + 1, n1y = D.box_len[1] + 1;
+  T* mt = tiles + D.tile_off * int64_t(NB * NB);
+  const double da = dsc[D.loc_off + a];
+  const int zr = M.dim == 3 ? 1 : 0;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int nb[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+        int bl[3] = {nb[0] - lo[0], nb[1] - lo[1], nb[2] - lo[2]};
+        if (bl[0] < 0 || bl[0] > D.box_len[0] || bl[1] < 0 || bl[1] > D.box_len[1]) continue;
+        if (M.dim == 3 && (bl[2] < 0 || bl[2] > D.box_len[2])) continue;
+        int q = bl[0] + n1x * (bl[1] + n1y * (M.dim == 3 ? bl[2] : 0));
+        int b = lmap[D.lmap_off + q];
+        if (b < 0) continue;
+        if (a < D.n_R && b < D.n_R) {
+          if (b > a) continue;
+          double v = stiff_entry(M, theta, c, nb, lo, len) * da * dsc[D.loc_off + b];
+          int64_t t = tri_tile(a / NB, b / NB);
+          mt[t * NB * NB + (a % NB) * NB + (b % NB)] = T(v);
+        } else if (a < D.n_R && b >= D.n_R) {
+          // border row: (D A_R,Pi)^T, constraint row n_A + corner index
+          double v = stiff_entry(M, theta, c, nb, lo, len) * da;
+          int row = D.n_A + (b - D.n_R);
+          int64_t t = tri_tile(D.T, a / NB);
+          mt[t * NB * NB + row * NB + (a % NB)] = T(v);
+        } else if (a >= D.n_R && b >= D.n_R) {
+          double v = stiff_entry(M, theta, c, nb, lo, len);
+          app[int64_t(s) * MAX_NCI * MAX_NCI + (a - D.n_R) * MAX_NCI + (b - D.n_R)] = v;
+        }
+      }
+  if (a < D.n_R) {
+    int k = avg_of[D.loc_off + a];
+    if (k >= 0) {
+      int64_t t = tri_tile(D.T, a / NB);
+      mt[t * NB * NB + k * NB + (a % NB)] = T(avg_coef[D.loc_off + a] * da);
+    }
+  }
+}
+
+// identity on the padding rows of the last tile row
+template <typename T>
+__global__ void pad_identity_kernel(const MatDesc* mats, T* tiles) {
+  const MatDesc D = mats[blockIdx.x];
+  int r = D.n_R + threadIdx.x;
+  if (D.T == 0 || r >= D.T * NB) return;
+  int64_t t = D.tile_off + tri_tile(D.T - 1, D.T - 1);
+  tiles[t * NB * NB + (r % NB) * NB + (r % NB)] = T(1);
+}
+
+void launch_local_assembly(const MeshDevHost& mh, const double* theta, const MatDesc* mats, int nmats,
+                           int max_ni, const int32_t* gmap, const int32_t* lmap, const double* wgt, double* dsc,
+                           double* wd, const int32_t* avg_of, const double* avg_coef, void* tiles, bool fp32,
+                           double* app, int* err, hipStream_t st) {
+  MeshDev M{mh.dim, {mh.nel[0], mh.nel[1], mh.nel[2]}, {mh.h[0], mh.h[1], mh.h[2]}};
+  dim3 grid((max_ni + 127) / 128, nmats);
+  hipLaunchKernelGGL(local_diag_kernel, grid, dim3(128), 0, st, M, theta, mats, gmap, wgt, dsc, wd, err);
+  if (fp32) {
+    hipLaunchKernelGGL(local_assemble_kernel<float>, grid, dim3(128), 0, st, M, theta, mats, gmap, lmap, dsc,
+                       avg_of, avg_coef, (float*)tiles, app);
+  } else {
+    hipLaunchKernelGGL(local_assemble_kernel<double>, grid, dim3(128), 0, st, M, theta, mats, gmap, lmap, dsc,
+                       avg_of, avg_coef, (double*)tiles, app);
+  }
+  launch_pad_identity(mats, nmats, tiles, fp32, st);
+}
+
+void launch_pad_identity(const MatDesc* mats, int nmats, void* tiles, bool fp32, hipStream_t st) {
+  if (fp32)
+    hipLaunchKernelGGL(pad_identity_kernel<float>, dim3(nmats), dim3(NB), 0, st, mats, (float*)tiles);
+  else
+    hipLaunchKernelGGL(pad_identity_kernel<double>, dim3(nmats), dim3(NB), 0, st, mats, (double*)tiles);
+}
+
+// ---------------------------------------------------------------------------
+// Batched right-looking tile Cholesky
+// ---------------------------------------------------------------------------
+
+constexpr int LDT = NB + 1;   // padded LDS row stride
+
+// Factor the diagonal tile (k, k) of every matrix with T > k in LDS, write L_kk and
+// its inverse (the inverse-diagonal tile used by the panel step and the solves).
+template <typename T>
+__global__ __launch_bounds__(256) void potrf_diag_kernel(const MatDesc* mats, T* tiles, T* dinv, int k,
+                                                         int* err) {
+  const MatDesc D = mats[blockIdx.x];
+  if (k >= D.T) return;
+  __shared__ T a[NB * LDT];
+  __shared__ T x[NB * LDT];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  T* tile = tiles + (D.tile_off + tri_tile(k, k)) * int64_t(NB * NB);
+  for (int i = tid; i < NB * NB; i += 256) a[(i / NB) * LDT + (i % NB)] = tile[i];
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < NB; ++j) {
+    if (tid == 0) {
+      T p = a[j * LDT + j];
+      if (!(p > T(0)) || !(p < T(3e38))) { bad = 1; p = T(1); }
+      a[j * LDT + j] = sqrt(p);
+    }
+    __syncthreads();
+    const T ljj = a[j * LDT + j];
+    for (int i = j + 1 + tid; i < NB; i += 256) a[i * LDT + j] /= ljj;
+    __syncthreads();
+    const int m = NB - 1 - j;
+    for (int idx = tid; idx < m * m; idx += 256) {
+      int i = j + 1 + idx / m, c = j + 1 + idx % m;
+      if (c <= i) a[i * LDT + c] -= a[i * LDT + j] * a[c * LDT + j];
+    }
+    __syncthreads();
+  }
+  // inverse of the lower-triangular factor, one column per thread
+  if (tid < NB) {
+    const int c = tid;
+    for (int i = 0; i < c; ++i) x[i * LDT + c] = T(0);
+    for (int i = c; i < NB; ++i) {
+      T s = (i == c) ? T(1) : T(0);
+      for (int j = c; j < i; ++j) s -= a[i * LDT + j] * x[j * LDT + c];
+      x[i * LDT + c] = s / a[i * LDT + i];
+    }
+  }
+  __syncthreads();
+  T* dt = dinv + (D.dinv_off + k) * int64_t(NB * NB);
+  for (int i = tid; i < NB * NB; i += 256) {
+    int r = i / NB, c = i % NB;
+    tile[i] = (c <= r) ? a[r * LDT + c] : T(0);
+    dt[i] = (c <= r) ? x[r * LDT + c] : T(0);
+  }
+  if (tid == 0 && bad) atomicOr(err, 2);
+}
+
+// MFMA 16x16x4 wrappers: a operand = A[row0 + lane%16][k + lane/16], b operand =
+// B[col0 + lane%16][k + lane/16].  Accumulator item i of lane l holds column
+// l%16 of the 16x16 block, row 4*i + l/16 for the FP64 instruction and row
+// 4*(l/16) + i for the FP32 one (acc_row below).
+__device__ __forceinline__ d4v mfma16(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4v mfma16(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T> struct Acc4;
+template <> struct Acc4<double> {
+  using type = d4v;
+  static __device__ __forceinline__ int row(int lane, int i) { return 4 * i + (lane >> 4); }
+};
+template <> struct Acc4<float> {
+  using type = f4v;
+  static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
+// acc(64x64, distributed over 4 waves as 32x32 quadrants) = A * B^T with A, B
+// 64x64 row-major tiles in LDS (stride LDT).
+template <typename T>
+__device__ __forceinline__ void gemm_nt_tile(const T* A, const T* B, typename Acc4<T>::type acc[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  const int li = lane & 15, lk = lane >> 4;
+  for (int kk = 0; kk < NB; kk += 4) {
+    T a0 = A[(r0 + li) * LDT + kk + lk];
+    T a1 = A[(r0 + 16 + li) * LDT + kk + lk];
+    T b0 = B[(c0 + li) * LDT + kk + lk];
+    T b1 = B[(c0 + 16 + li) * LDT + kk + lk];
+    acc[0][0] = mfma16(a0, b0, acc[0][0]);
+    acc[0][1] = mfma16(a0, b1, acc[0][1]);
+    acc[1][0] = mfma16(a1, b0, acc[1][0]);
+    acc[1][1] = mfma16(a1, b1, acc[1][1]);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_tile_lds(T* dst, const T* src) {
+  for (int i = threadIdx.x; i < NB * NB; i += 256) dst[(i / NB) * LDT + (i % NB)] = src[i];
+}
+
+// L_ik = A_ik * Dinv_k^T for tile rows i in (k, Tx) (the border row included).
+template <typename T>
+__global__ __launch_bounds__(256) void trsm_panel_kernel(const MatDesc* mats, T* tiles, const T* dinv, int k) {
+  const MatDesc D = mats[blockIdx.y];
+  const int i = k + 1 + blockIdx.x;
+  if (k >= D.T || i >= D.Tx) return;
+  __shared__ T sa[NB * LDT];
+  __shared__ T sb[NB * LDT];
+  T* tik = tiles + (D.tile_off + tri_tile(i, k)) * int64_t(NB * NB);
+  load_tile_lds(sa, tik);
+  load_tile_lds(sb, dinv + (D.dinv_off + k) * int64_t(NB * NB));
+  __syncthreads();
+  typename Acc4<T>::type acc[2][2];
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q) acc[p][q] = typename Acc4<T>::type(0);
+  gemm_nt_tile<T>(sa, sb, acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q)
+      for (int it = 0; it < 4; ++it) {
+        int r = r0 + 16 * p + Acc4<T>::row(lane, it), c = c0 + 16 * q + (lane & 15);
+        tik[r * NB + c] = acc[p][q][it];
+      }
+}
+
+// A_ij -= L_ik L_jk^T for k < j <= i < Tx (pairs enumerated row by row).
+template <typename T>
+__global__ __launch_bounds__(256) void syrk_update_kernel(const MatDesc* mats, T* tiles, int k) {
+  const MatDesc D = mats[blockIdx.y];
+  if (k >= D.T) return;
+  const int m = D.Tx - k - 1;                 // tile rows below k
+  const int64_t pidx = blockIdx.x;
+  if (pidx >= int64_t(m) * (m + 1) / 2) return;
+  int ii = int((sqrt(8.0 * double(pidx) + 1.0) - 1.0) * 0.5);
+  while (int64_t(ii) * (ii + 1) / 2 > pidx) --ii;
+  while (int64_t(ii + 1) * (ii + 2) / 2 <= pidx) ++ii;
+  const int jj = int(pidx - int64_t(ii) * (ii + 1) / 2);
+  const int i = k + 1 + ii, j = k + 1 + jj;
+  __shared__ T sa[NB * LDT];
+  __shared__ T sb[NB * LDT];
+  const T* lik = tiles + (D.tile_off + tri_tile(i, k)) * int64_t(NB * NB);
+  const T* ljk = tiles + (D.tile_off + tri_tile(j, k)) * int64_t(NB * NB);
+  T* aij = tiles + (D.tile_off + tri_tile(i, j)) * int64_t(NB * NB);
+  load_tile_lds(sa, lik);
+  if (i != j) load_tile_lds(sb, ljk);
+  __syncthreads();
+  typename Acc4<T>::type acc[2][2];
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q) acc[p][q] = typename Acc4<T>::type(0);
+  gemm_nt_tile<T>(sa, i != j ? sb : sa, acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q)
+      for (int it = 0; it < 4; ++it) {
+        int r = r0 + 16 * p + Acc4<T>::row(lane, it), c = c0 + 16 * q + (lane & 15);
+        aij[r * NB + c] -= acc[p][q][it];
+      }
+}
+
+void launch_factor(const MatDesc* mats, int nmats, int maxT, int maxTx, void* tiles, void* dinv, bool fp32,
+                   int* err, hipStream_t st) {
+  for (int k = 0; k < maxT; ++k) {
+    const int below = maxTx - k - 1;
+    if (fp32) {
+      hipLaunchKernelGGL(potrf_diag_kernel<float>, dim3(nmats), dim3(256), 0, st, mats, (float*)tiles,
+                         (float*)dinv, k, err);
+      if (below > 0) {
+        hipLaunchKernelGGL(trsm_panel_kernel<float>, dim3(below, nmats), dim3(256), 0, st, mats, (float*)tiles,
+                           (const float*)dinv, k);
+        hipLaunchKernelGGL(syrk_update_kernel<float>, dim3(int64_t(below) * (below + 1) / 2, nmats), dim3(256),
+                           0, st, mats, (float*)tiles, k);
+      }
+    } else {
+      hipLaunchKernelGGL(potrf_diag_kernel<double>, dim3(nmats), dim3(256), 0, st, mats, (double*)tiles,
+                         (double*)dinv, k, err);
+      if (below > 0) {
+        hipLaunchKernelGGL(trsm_panel_kernel<double>, dim3(below, nmats), dim3(256), 0, st, mats,
+                           (double*)tiles, (const double*)dinv, k);
+        hipLaunchKernelGGL(syrk_update_kernel<double>, dim3(int64_t(below) * (below + 1) / 2, nmats),
+                           dim3(256), 0, st, mats, (double*)tiles, k);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-subdomain small dense algebra after the factorisation
+// ---------------------------------------------------------------------------
+// The bordering diagonal tile holds -G with G = W^T W, W = L^{-1} D [C_AR^T | A_RPi]
+// (constraint order: averages then corners).  With S_A = G_AA and E = G_A,Pi:
+//   A_ci = [[S_A^{-1}, S_A^{-1} E], [E^T S_A^{-1}, A_PiPi - G_PiPi + E^T S_A^{-1} E]]
+// which equals Phi_i^T A_i Phi_i = -Lambda_i of eq. (1).
+template <typename T>
+__global__ __launch_bounds__(256) void local_small_kernel(const MatDesc* mats, const T* tiles,
+                                                          const double* app, double* sainv, double* sainve,
+                                                          double* aci, int* err) {
+  const int s = blockIdx.x;
+  const MatDesc D = mats[s];
+  const int nA = D.n_A, nP = D.n_P, nc = D.n_ci;
+  if (nc == 0) return;
+  __shared__ double G[MAX_NCI * MAX_NCI];
+  __shared__ double L[MAX_NCI * MAX_NCI];
+  __shared__ double X[MAX_NCI * MAX_NCI];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const T* bt = tiles + (D.tile_off + tri_tile(D.T, D.T)) * int64_t(NB * NB);
+  for (int i = tid; i < MAX_NCI * MAX_NCI; i += 256) {
+    int r = i / MAX_NCI, c = i % MAX_NCI;
+    // the tile holds the lower triangle reliably; symmetrise from it
+    double v = (r < nc && c < nc) ? -double(r >= c ? bt[r * NB + c] : bt[c * NB + r]) : 0.0;
+    G[i] = v;
+    L[i] = 0.0;
+    X[i] = 0.0;
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  // Cholesky of S_A (one thread, n_A <= 64)
+  if (tid == 0 && nA > 0) {
+    for (int j = 0; j < nA; ++j) {
+      double sdiag = G[j * MAX_NCI + j];
+      for (int p = 0; p < j; ++p) sdiag -= L[j * MAX_NCI + p] * L[j * MAX_NCI + p];
+      if (!(sdiag > 0.0)) { bad = 1; sdiag = 1.0; }
+      L[j * MAX_NCI + j] = sqrt(sdiag);
+      for (int i = j + 1; i < nA; ++i) {
+        double v = G[i * MAX_NCI + j];
+        for (int p = 0; p < j; ++p) v -= L[i * MAX_NCI + p] * L[j * MAX_NCI + p];
+        L[i * MAX_NCI + j] = v / L[j * MAX_NCI + j];
+      }
+    }
+  }
+  __syncthreads();
+  // X = S_A^{-1} [I | E]: columns solved in parallel
+  if (tid < nc && nA > 0) {
+    const int c = tid;
+    double y[MAX_NCI];
+    for (int i = 0; i < nA; ++i) {
+      double v = (c < nA) ? (i == c ? 1.0 : 0.0) : G[i * MAX_NCI + c];
+      for (int p = 0; p < i; ++p) v -= L[i * MAX_NCI + p] * y[p];
+      y[i] = v / L[i * MAX_NCI + i];
+    }
+    for (int i = nA - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int p = i + 1; p < nA; ++p) v -= L[p * MAX_NCI + i] * y[p];
+      y[i] = v / L[i * MAX_NCI + i];
+    }
+    for (int i = 0; i < nA; ++i) X[i * MAX_NCI + c] = y[i];
+  }
+  __syncthreads();
+  double* so = sainv + int64_t(s) * MAX_NCI * MAX_NCI;
+  double* se = sainve + int64_t(s) * MAX_NCI * MAX_NCI;
+  double* ao = aci + int64_t(s) * MAX_NCI * MAX_NCI;
+  const double* ap = app + int64_t(s) * MAX_NCI * MAX_NCI;
+  for (int i = tid; i < MAX_NCI * MAX_NCI; i += 256) {
+    int r = i / MAX_NCI, c = i % MAX_NCI;
+    so[i] = (r < nA && c < nA) ? X[r * MAX_NCI + c] : 0.0;
+    se[i] = (r < nA && c < nP) ? X[r * MAX_NCI + nA + c] : 0.0;
+    double v = 0.0;
+    if (r < nc && c < nc) {
+      if (r < nA) {
+        v = X[r * MAX_NCI + c];                       // S_A^{-1} [I | E]
+      } else if (c < nA) {
+        v = X[c * MAX_NCI + r];                       // (S_A^{-1} E)^T
+      } else {
+        const int p = r - nA, q = c - nA;
+        v = ap[p * MAX_NCI + q] - G[r * MAX_NCI + c];
+        for (int t = 0; t < nA; ++t) v += G[t * MAX_NCI + r] * X[t * MAX_NCI + c];
+      }
+    }
+    ao[i] = v;
+  }
+  if (tid == 0 && bad) atomicOr(err, 8);
+}
+
+void launch_local_small(const MatDesc* mats, int nmats, const void* tiles, bool fp32, const double* app,
+                        double* sainv, double* sainve, double* aci, int* err, hipStream_t st) {
+  if (fp32)
+    hipLaunchKernelGGL(local_small_kernel<float>, dim3(nmats), dim3(256), 0, st, mats, (const float*)tiles, app,
+                       sainv, sainve, aci, err);
+  else
+    hipLaunchKernelGGL(local_small_kernel<double>, dim3(nmats), dim3(256), 0, st, mats, (const double*)tiles,
+                       app, sainv, sainve, aci, err);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse matrix assembly (A_c = sum_i R_ci^T A_ci R_ci) into equilibrated tiles
+// ---------------------------------------------------------------------------
+
+__global__ void coarse_entries_kernel(const int32_t* src_ptr, const int32_t* src, const double* aci, double* val,
+                                      int n) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double v = 0.0;
+  for (int j = src_ptr[e]; j < src_ptr[e + 1]; ++j) v += aci[src[j]];
+  val[e] = v;
+}
+
+__global__ void coarse_scale_kernel(const int32_t* diag, const double* val, double* dc, int nc, int* err) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nc) return;
+  double d = val[diag[p]];
+  if (!(d > 0.0)) { atomicOr(err, 16); d = 1.0; }
+  dc[p] = 1.0 / sqrt(d);
+}
+
+__global__ void coarse_write_kernel(const int32_t* row, const int32_t* col, const double* val, const double* dc,
+                                    double* tiles, int n) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  int p = row[e], q = col[e];
+  tiles[tri_tile(p / NB, q / NB) * NB * NB + (p % NB) * NB + (q % NB)] = dc[p] * val[e] * dc[q];
+}
+
+void launch_coarse_assembly(const int32_t* src_ptr, const int32_t* src, const int32_t* row, const int32_t* col,
+                            const int32_t* diag, int nentries, int nc, const double* aci, double* val, double* dc,
+                            double* tiles, int* err, hipStream_t st) {
+  if (nentries == 0) return;
+  hipLaunchKernelGGL(coarse_entries_kernel, dim3((nentries + 255) / 256), dim3(256), 0, st, src_ptr, src, aci,
+                     val, nentries);
+  hipLaunchKernelGGL(coarse_scale_kernel, dim3((nc + 255) / 256), dim3(256), 0, st, diag, val, dc, nc, err);
+  hipLaunchKernelGGL(coarse_write_kernel, dim3((nentries + 255) / 256), dim3(256), 0, st, row, col, val, dc,
+                     tiles, nentries);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent sync-free blocked triangular solves
+// ---------------------------------------------------------------------------
+// Task (s, k): tile row k of matrix s.  Forward: y_k = Dinv_k (rhs_k - sum_{j<k}
+// L_kj y_j); backward: x_k = Dinv_k^T (rhs_k - sum_{j>k} L_jk^T x_j).  Tiles are
+// row-major; a wave owns 16 rows of a tile and every load instruction of a wave
+// covers 1 KB of contiguous tile memory.
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
+  using V = typename Traits<T>::V;
+  constexpr int VEC = Traits<T>::VEC;
+  constexpr int LPR = NB / VEC;      // lanes per tile row
+  constexpr int RPI = 64 / LPR;      // tile rows per wave instruction
+  constexpr int NI = 16 / RPI;       // instructions per 16-row slab
+  constexpr bool FWD = (MODE == TRSV_FWD_RR || MODE == TRSV_FWD_II || MODE == TRSV_FWD_C);
+
+  __shared__ T s_rhs[NB];
+  __shared__ T s_v[NB];
+  __shared__ T s_out[NB];
+  __shared__ T s_red[4][NB];
+  __shared__ int s_task;
+
+  if (A.done && *A.done) return;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int lr = lane / LPR, lc = lane % LPR;
+  const T* tiles = reinterpret_cast<const T*>(A.tiles);
+  const T* dinv = reinterpret_cast<const T*>(A.dinv);
+  T* sol = reinterpret_cast<T*>(A.sol);
+  const T* src = reinterpret_cast<const T*>(A.src);
+
+  for (;;) {
+    if (tid == 0) s_task = atomicAdd(A.ticket, 1u);
+    __syncthreads();
+    const int task = s_task;
+    __syncthreads();
+    if (task >= A.ntasks) return;
+    const int s = A.tasks[2 * task], k = A.tasks[2 * task + 1];
+    const MatDesc D = A.mats[s];
+    const int T_rows = (MODE == TRSV_FWD_II || MODE == TRSV_BWD_II) ? D.TI : D.T;
+    const int nlim = (MODE == TRSV_FWD_II || MODE == TRSV_BWD_II) ? D.n_I : D.n_R;
+    const int64_t tbase = D.tile_off;
+    T* my_sol = sol + D.vec_off;
+
+    // ---------------- prologue: right-hand side of tile row k ----------------
+    if (tid < NB) {
+      const int a = k * NB + tid;
+      double rhs = 0.0;
+      if (a < nlim) {
+        if (MODE == TRSV_FWD_RR) {
+          const int64_t l = D.loc_off + a;
+          rhs = A.wd[l] * A.rin[A.gmap[l]];
+        } else if (MODE == TRSV_FWD_II) {
+          const int64_t l = D.loc_off + a;
+          const int g = A.gmap[l];
+          double v = A.rin[g];
+          if (A.v12) {
+            for (int j = A.rowptr[g]; j < A.rowptr[g + 1]; ++j) v -= A.vals[j] * A.v12[A.colind[j]];
+          }
+          rhs = A.dsc[l] * v;
+        } else if (MODE == TRSV_FWD_C) {
+          double v = 0.0;
+          for (int j = A.cinv_ptr[a]; j < A.cinv_ptr[a + 1]; ++j) v += A.gbuf[A.cinv[j]];
+          rhs = A.dc[a] * v;
+        } else {
+          rhs = double(src[D.vec_off + a]);   // backward: the forward solution
+        }
+      }
+      s_rhs[tid] = T(rhs);
+    }
+    if (MODE == TRSV_BWD_RR && D.n_ci > 0) {
+      // rhs_k += W_k coef, W_k^T stored in the bordering tile row (rows = constraints)
+      __syncthreads();
+      const T* bt = tiles + (tbase + tri_tile(D.T, k)) * int64_t(NB * NB);
+      const double* cf = A.coef + int64_t(s) * MAX_NCI;
+      if (tid < NB) {
+        double v = 0.0;
+        for (int c = 0; c < D.n_ci; ++c) v += double(bt[c * NB + tid]) * cf[c];
+        if (k * NB + tid < nlim) s_rhs[tid] += T(v);
+      }
+    }
+
+    // ---------------- main loop over off-diagonal tiles ----------------
+    T acc[FWD ? NI : VEC];
+    for (int i = 0; i < (FWD ? NI : VEC); ++i) acc[i] = T(0);
+    const int nt = FWD ? k : (T_rows - 1 - k);
+    if (nt > 0) {
+      auto tile_ptr = [&](int jj) -> const T* {
+        // forward: tile (k, jj) for jj = 0..k-1; backward: tile (j, k) for j = T_rows-1 .. k+1
+        int64_t t = FWD ? tri_tile(k, jj) : tri_tile(T_rows - 1 - jj, k);
+        return tiles + (tbase + t) * int64_t(NB * NB) + (16 * w + lr) * NB + VEC * lc;
+      };
+      auto sol_row = [&](int jj) -> int { return FWD ? jj : (T_rows - 1 - jj); };
+      V cur[NI], nxt[NI];
+      {
+        const T* p = tile_ptr(0);
+        for (int i = 0; i < NI; ++i) cur[i] = *reinterpret_cast<const V*>(p + i * RPI * NB);
+      }
+      for (int jj = 0; jj < nt; ++jj) {
+        const T* ys = my_sol + sol_row(jj) * NB;
+        T xv[FWD ? VEC : NI];
+        if (FWD) {
+          for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + VEC * lc + e);
+        } else {
+          for (int i = 0; i < NI; ++i) xv[i] = poll_published(ys + 16 * w + RPI * i + lr);
+        }
+        if (jj + 1 < nt) {
+          const T* p = tile_ptr(jj + 1);
+          for (int i = 0; i < NI; ++i) nxt[i] = *reinterpret_cast<const V*>(p + i * RPI * NB);
+        }
+        if (FWD) {
+          for (int i = 0; i < NI; ++i)
+            for (int e = 0; e < VEC; ++e) acc[i] += cur[i][e] * xv[e];
+        } else {
+          for (int i = 0; i < NI; ++i)
+            for (int e = 0; e < VEC; ++e) acc[e] += cur[i][e] * xv[i];
+        }
+        for (int i = 0; i < NI; ++i) cur[i] = nxt[i];
+      }
+    }
+    // reduce partial sums into s_red
+    if (FWD) {
+      for (int i = 0; i < NI; ++i) {
+        T v = acc[i];
+        for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lc == 0) s_red[0][16 * w + RPI * i + lr] = v;
+      }
+    } else {
+      for (int e = 0; e < VEC; ++e) {
+        T v = acc[e];
+        for (int off = LPR; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+        if (lr == 0) s_red[w][VEC * lc + e] = v;
+      }
+    }
+    __syncthreads();
+    if (tid < NB) {
+      T red = FWD ? s_red[0][tid] : (s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid]);
+      s_v[tid] = (k * NB + tid < nlim) ? (s_rhs[tid] - red) : T(0);
+    }
+    __syncthreads();
+
+    // ---------------- diagonal block: multiply by the inverse tile ----------------
+    {
+      const T* dt = dinv + (D.dinv_off + k) * int64_t(NB * NB) + (16 * w + lr) * NB + VEC * lc;
+      V dv[NI];
+      for (int i = 0; i < NI; ++i) dv[i] = *reinterpret_cast<const V*>(dt + i * RPI * NB);
+      if (FWD) {
+        for (int i = 0; i < NI; ++i) {
+          T v = T(0);
+          for (int e = 0; e < VEC; ++e) v += dv[i][e] * s_v[VEC * lc + e];
+          for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+          if (lc == 0) s_red[0][16 * w + RPI * i + lr] = v;
+        }
+      } else {
+        T a2[VEC];
+        for (int e = 0; e < VEC; ++e) a2[e] = T(0);
+        for (int i = 0; i < NI; ++i)
+          for (int e = 0; e < VEC; ++e) a2[e] += dv[i][e] * s_v[16 * w + RPI * i + lr];
+        for (int e = 0; e < VEC; ++e) {
+          T v = a2[e];
+          for (int off = LPR; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+          if (lr == 0) s_red[w][VEC * lc + e] = v;
+        }
+      }
+      __syncthreads();
+      if (tid < NB) {
+        T o = FWD ? s_red[0][tid] : (s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid]);
+        if (k * NB + tid >= nlim) o = T(0);
+        s_out[tid] = o;
+        store_published(my_sol + k * NB + tid, o);
+      }
+    }
+    __syncthreads();
+
+    // ---------------- epilogue ----------------
+    if (MODE == TRSV_FWD_RR && D.n_ci > 0) {
+      // partial border products h_c = sum_r W^T[c][r] y_k[r] for this tile row
+      const T* bt = tiles + (tbase + tri_tile(D.T, k)) * int64_t(NB * NB);
+      if (tid < D.n_ci) {
+        double v = 0.0;
+        for (int r = 0; r < NB; ++r) v += double(bt[tid * NB + r]) * double(s_out[r]);
+        A.part[(D.vec_off / NB + k) * MAX_NCI + tid] = v;
+      }
+    } else if (MODE == TRSV_BWD_RR) {
+      if (tid < NB) {
+        const int a = k * NB + tid;
+        if (a < D.n_R) {
+          const int64_t l = D.loc_off + a;
+          A.ww[l] = A.wd[l] * double(s_out[tid]);
+        }
+      }
+    } else if (MODE == TRSV_BWD_II) {
+      if (tid < NB) {
+        const int a = k * NB + tid;
+        if (a < D.n_I) {
+          const int64_t l = D.loc_off + a;
+          const int g = A.gmap[l];
+          A.zout[g] = (A.base ? A.base[g] : 0.0) + A.dsc[l] * double(s_out[tid]);
+        }
+      }
+    } else if (MODE == TRSV_BWD_C) {
+      if (tid < NB) {
+        const int a = k * NB + tid;
+        if (a < D.n_R) A.uc[a] = A.dc[a] * double(s_out[tid]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+static void launch_trsv_t(int mode, const TrsvArgs& a, int grid, hipStream_t st) {
+  switch (mode) {
+    case TRSV_FWD_RR: hipLaunchKernelGGL((trsv_kernel<T, TRSV_FWD_RR>), dim3(grid), dim3(256), 0, st, a); break;
+    case TRSV_BWD_RR: hipLaunchKernelGGL((trsv_kernel<T, TRSV_BWD_RR>), dim3(grid), dim3(256), 0, st, a); break;
+    case TRSV_FWD_II: hipLaunchKernelGGL((trsv_kernel<T, TRSV_FWD_II>), dim3(grid), dim3(256), 0, st, a); break;
+    case TRSV_BWD_II: hipLaunchKernelGGL((trsv_kernel<T, TRSV_BWD_II>), dim3(grid), dim3(256), 0, st, a); break;
+    case TRSV_FWD_C: hipLaunchKernelGGL((trsv_kernel<T, TRSV_FWD_C>), dim3(grid), dim3(256), 0, st, a); break;
+    case TRSV_BWD_C: hipLaunchKernelGGL((trsv_kernel<T, TRSV_BWD_C>), dim3(grid), dim3(256), 0, st, a); break;
+  }
+}
+
+void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st) {
+  if (a.ntasks <= 0) return;
+  if (fp32 && mode != TRSV_FWD_C && mode != TRSV_BWD_C)
+    launch_trsv_t<float>(mode, a, grid, st);
+  else
+    launch_trsv_t<double>(mode, a, grid, st);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-level glue of the apply
+// ---------------------------------------------------------------------------
+// h = sum_k part[s][k] = W^T t (W = L^{-1} D B, t = L^{-1} D W_i f_R), then
+//   g[A]  = S_A^{-1} h_A                        (also mu, the average multipliers)
+//   g[Pi] = -h_Pi + (S_A^{-1} E)^T h_A + W_Pi r_Pi
+// g = Phi_i^T W_i R_i r, the subdomain's share of the coarse residual r_c.
+__global__ __launch_bounds__(64) void coarse_prep_kernel(const MatDesc* mats, const double* part,
+                                                         const double* sainv, const double* sainve,
+                                                         const int32_t* gmap, const double* wgt, const double* r,
+                                                         double* gbuf, double* mu, const int* done) {
+  if (done && *done) return;
+  const int s = blockIdx.x;
+  const MatDesc D = mats[s];
+  const int tid = threadIdx.x;
+  __shared__ double h[MAX_NCI];
+  if (D.n_ci == 0) return;
+  if (tid < D.n_ci) {
+    double v = 0.0;
+    const int64_t base = (D.vec_off / NB) * MAX_NCI;
+    for (int k = 0; k < D.T; ++k) v += part[base + int64_t(k) * MAX_NCI + tid];
+    h[tid] = v;
+  }
+  __syncthreads();
+  const double* so = sainv + int64_t(s) * MAX_NCI * MAX_NCI;
+  const double* se = sainve + int64_t(s) * MAX_NCI * MAX_NCI;
+  const int nA = D.n_A;
+  if (tid < D.n_ci) {
+    double v;
+    if (tid < nA) {
+      v = 0.0;
+      for (int t = 0; t < nA; ++t) v += so[tid * MAX_NCI + t] * h[t];
+      mu[int64_t(s) * MAX_NCI + tid] = v;
+    } else {
+      const int p = tid - nA;
+      v = -h[tid];
+      for (int t = 0; t < nA; ++t) v += se[t * MAX_NCI + p] * h[t];
+      const int64_t l = D.loc_off + D.n_R + p;
+      v += wgt[l] * r[gmap[l]];
+    }
+    gbuf[D.coarse_off + tid] = v;
+  }
+}
+
+// per subdomain: u = R_ci u_c; coef_A = -mu + S_A^{-1} u_A + S_A^{-1} E u_Pi;
+// coef_Pi = -u_Pi; corner outputs w_Pi = u_Pi (weighted)
+__global__ __launch_bounds__(64) void coarse_coef_kernel(const MatDesc* mats, const int32_t* rc, const double* uc,
+                                                         const double* mu, const double* sainv,
+                                                         const double* sainve, const double* wgt, double* coef,
+                                                         double* ww, const int* done) {
+  if (done && *done) return;
+  const int s = blockIdx.x;
+  const MatDesc D = mats[s];
+  const int tid = threadIdx.x;
+  __shared__ double u[MAX_NCI];
+  if (D.n_ci == 0) return;
+  if (tid < D.n_ci) u[tid] = uc[rc[D.coarse_off + tid]];
+  __syncthreads();
+  const double* so = sainv + int64_t(s) * MAX_NCI * MAX_NCI;
+  const double* se = sainve + int64_t(s) * MAX_NCI * MAX_NCI;
+  const int nA = D.n_A, nP = D.n_P;
+  if (tid < D.n_ci) {
+    double v;
+    if (tid < nA) {
+      v = -mu[int64_t(s) * MAX_NCI + tid];
+      for (int t = 0; t < nA; ++t) v += so[tid * MAX_NCI + t] * u[t];
+      for (int p = 0; p < nP; ++p) v += se[tid * MAX_NCI + p] * u[nA + p];
+    } else {
+      v = -u[tid];
+      const int64_t l = D.loc_off + D.n_R + (tid - nA);
+      ww[l] = wgt[l] * u[tid];
+    }
+    coef[int64_t(s) * MAX_NCI + tid] = v;
+  }
+}
+
+void launch_coarse_prep(const MatDesc* mats, int nmats, const double* part, const double* sainv,
+                        const double* sainve, const int32_t* gmap, const double* wgt, const double* r,
+                        double* gbuf, double* mu, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(coarse_prep_kernel, dim3(nmats), dim3(64), 0, st, mats, part, sainv, sainve, gmap, wgt, r,
+                     gbuf, mu, done);
+}
+
+void launch_coarse_coef(const MatDesc* mats, int nmats, const int32_t* rc, const double* uc, const double* mu,
+                        const double* sainv, const double* sainve, const double* wgt, double* coef, double* ww,
+                        const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(coarse_coef_kernel, dim3(nmats), dim3(64), 0, st, mats, rc, uc, mu, sainv, sainve, wgt, coef,
+                     ww, done);
+}
+
+// v12[g] = sum over the subdomains holding g of W_i w_i (gather through the inverse
+// map, fixed order); interface entries of z get v12 directly (their v3 is 0).
+__global__ void gather_v12_kernel(const int32_t* inv_ptr, const int32_t* inv, const double* ww,
+                                  const uint8_t* kappa, double* v12, double* z, int64_t n, const int* done) {
+  if (done && *done) return;
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x) {
+    double v = 0.0;
+    for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) v += ww[inv[j]];
+    v12[g] = v;
+    if (kappa[g] > 1) z[g] = v;
+  }
+}
+
+void launch_gather_v12(const int32_t* inv_ptr, const int32_t* inv, const double* ww, const uint8_t* kappa,
+                       double* v12, double* z, int64_t n, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(gather_v12_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, inv_ptr, inv, ww, kappa,
+                     v12, z, n, done);
+}
+
+// zero the interface entries (the static-condensation guess is zero there)
+__global__ void zero_interface_kernel(const uint8_t* kappa, double* x, int64_t n) {
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x)
+    if (kappa[g] > 1) x[g] = 0.0;
+}
+
+void launch_zero_interface(const uint8_t* kappa, double* x, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_interface_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, kappa, x, n);
+}
+
+// ---------------------------------------------------------------------------
+// CSR SpMV and the PCG vector kernels (FP64, deterministic reductions)
+// ---------------------------------------------------------------------------
+// A half-wave (32 lanes) per row: a 27-point row fits one pass.
+
+constexpr int VBLK = 256;
+constexpr int VGRID = 1024;   // fixed grid for the vector kernels: <= 1024 partial sums
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < VBLK / 64; ++i) t += sh[i];
+  return t;
+}
+
+// every block re-reduces the partials of the previous kernel in the same order, so
+// all blocks obtain the same bits
+__device__ __forceinline__ double reduce_partials(const double* part, int np, double* sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += VBLK) v += part[i];
+  return block_sum(v, sh);
+}
+
+__device__ __forceinline__ double row_dot(const int32_t* rowptr, const int32_t* col, const double* val,
+                                          const double* x, int64_t row, int sl) {
+  const int b = rowptr[row], e = rowptr[row + 1];
+  double v = 0.0;
+  for (int j = b + sl; j < e; j += 32) v += val[j] * x[col[j]];
+  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 32);
+  return v;
+}
+
+__global__ __launch_bounds__(VBLK) void spmv_kernel(const int32_t* rowptr, const int32_t* col, const double* val,
+                                                    const double* x, double* y, int64_t n) {
+  const int sl = threadIdx.x & 31;
+  const int64_t hw = (blockIdx.x * int64_t(VBLK) + threadIdx.x) >> 5;
+  const int64_t nhw = (int64_t(gridDim.x) * VBLK) >> 5;
+  for (int64_t row = hw; row < n; row += nhw) {
+    double v = row_dot(rowptr, col, val, x, row, sl);
+    if (sl == 0) y[row] = v;
+  }
+}
+
+void launch_spmv(const int32_t* rowptr, const int32_t* col, const double* val, const double* x, double* y, int64_t n,
+                 hipStream_t st) {
+  int64_t g = (n * 32 + VBLK - 1) / VBLK;
+  if (g > 16384) g = 16384;
+  hipLaunchKernelGGL(spmv_kernel, dim3(g), dim3(VBLK), 0, st, rowptr, col, val, x, y, n);
+}
+
+// r = b - A x, partial sums of r.r and b.b
+__global__ __launch_bounds__(VBLK) void residual_kernel(const int32_t* rowptr, const int32_t* col,
+                                                        const double* val, const double* x, const double* b,
+                                                        double* r, double* part_rr, double* part_bb, int64_t n) {
+  __shared__ double sh[VBLK / 64];
+  const int sl = threadIdx.x & 31;
+  const int64_t hw = (blockIdx.x * int64_t(VBLK) + threadIdx.x) >> 5;
+  const int64_t nhw = (int64_t(gridDim.x) * VBLK) >> 5;
+  double rr = 0.0, bb = 0.0;
+  for (int64_t row = hw; row < n; row += nhw) {
+    double v = row_dot(rowptr, col, val, x, row, sl);
+    if (sl == 0) {
+      double rv = b[row] - v;
+      r[row] = rv;
+      rr += rv * rv;
+      bb += b[row] * b[row];
+    }
+  }
+  double t = block_sum(rr, sh);
+  double u = block_sum(bb, sh);
+  if (threadIdx.x == 0) {
+    part_rr[blockIdx.x] = t;
+    part_bb[blockIdx.x] = u;
+  }
+}
+
+void launch_residual(const int32_t* rowptr, const int32_t* col, const double* val, const double* x, const double* b,
+                     double* r, double* part_rr, double* part_bb, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(residual_kernel, dim3(VGRID), dim3(VBLK), 0, st, rowptr, col, val, x, b, r, part_rr, part_bb,
+                     n);
+}
+
+// scalars: per-iteration slots (rz[it], pq[it], rr[it], alpha[it], beta[it])
+// p = z + beta p, q = A z + beta q (beta = rz[it]/rz[it-1]; it == 0: p = z, q = A z),
+// partial sums of p.q
+__global__ __launch_bounds__(VBLK) void pcg_dir_kernel(const int32_t* rowptr, const int32_t* col, const double* val,
+                                                       const double* z, double* p, double* q, const double* part_rz,
+                                                       double* part_pq, PcgScalars* sc, int it, int fresh,
+                                                       int64_t n) {
+  __shared__ double sh[VBLK / 64];
+  if (sc->done) return;
+  const double rz = reduce_partials(part_rz, VGRID, sh);
+  double beta = 0.0;
+  if (!fresh) beta = rz / sc->rz[it - 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rz[it] = rz;
+    if (!fresh) sc->beta[it - 1] = beta;
+  }
+  const int sl = threadIdx.x & 31;
+  const int64_t hw = (blockIdx.x * int64_t(VBLK) + threadIdx.x) >> 5;
+  const int64_t nhw = (int64_t(gridDim.x) * VBLK) >> 5;
+  double pq = 0.0;
+  for (int64_t row = hw; row < n; row += nhw) {
+    double az = row_dot(rowptr, col, val, z, row, sl);
+    if (sl == 0) {
+      double pv = z[row] + (fresh ? 0.0 : beta * p[row]);
+      double qv = az + (fresh ? 0.0 : beta * q[row]);
+      p[row] = pv;
+      q[row] = qv;
+      pq += pv * qv;
+    }
+  }
+  double t = block_sum(pq, sh);
+  if (threadIdx.x == 0) part_pq[blockIdx.x] = t;
+}
+
+// alpha = rz/pq; x += alpha p; r -= alpha q; partial sums of r.r
+__global__ __launch_bounds__(VBLK) void pcg_update_kernel(double* x, double* r, const double* p, const double* q,
+                                                          const double* part_pq, double* part_rr, PcgScalars* sc,
+                                                          int it, int64_t n) {
+  __shared__ double sh[VBLK / 64];
+  if (sc->done) return;
+  const double pq = reduce_partials(part_pq, VGRID, sh);
+  const double rz = sc->rz[it];
+  const double alpha = rz / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->pq[it] = pq;
+    sc->alpha[it] = alpha;
+  }
+  double rr = 0.0;
+  if (pq > 0.0 && rz > 0.0) {
+    for (int64_t i = blockIdx.x * int64_t(VBLK) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VBLK) {
+      x[i] += alpha * p[i];
+      double rv = r[i] - alpha * q[i];
+      r[i] = rv;
+      rr += rv * rv;
+    }
+  }
+  double t = block_sum(rr, sh);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = t;
+}
+
+// finalise rr (convergence / breakdown decision) in a single block; later kernels
+// of the iteration see sc->done
+__global__ __launch_bounds__(VBLK) void pcg_check_kernel(const double* part_rr, PcgScalars* sc, int it) {
+  __shared__ double sh[VBLK / 64];
+  if (sc->done) return;
+  const double rr = reduce_partials(part_rr, VGRID, sh);
+  if (threadIdx.x == 0) {
+    sc->rr[it] = rr;
+    const double pq = sc->pq[it], rz = sc->rz[it];
+    sc->iters = it + 1;
+    if (!(pq > 0.0) || !(rz > 0.0) || !(rr == rr)) {
+      sc->done = 2;
+      sc->iters = it;     // the update of this iteration was not applied
+    } else if (rr <= sc->tol2) {
+      sc->done = 1;
+    }
+  }
+}
+
+// partial sums of r.z (it == 0: also stores rz[0])
+__global__ __launch_bounds__(VBLK) void dot_kernel(const double* a, const double* b, double* part, int64_t n,
+                                                   const int* done) {
+  __shared__ double sh[VBLK / 64];
+  if (done && *done) return;
+  double v = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(VBLK) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VBLK) v += a[i] * b[i];
+  double t = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(VBLK) void finish_dot_kernel(const double* part, double* out) {
+  __shared__ double sh[VBLK / 64];
+  const double v = reduce_partials(part, VGRID, sh);
+  if (threadIdx.x == 0) *out = v;
+}
+
+void launch_pcg_dir(const int32_t* rowptr, const int32_t* col, const double* val, const double* z, double* p,
+                    double* q, const double* part_rz, double* part_pq, PcgScalars* sc, int it, int fresh, int64_t n,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(pcg_dir_kernel, dim3(VGRID), dim3(VBLK), 0, st, rowptr, col, val, z, p, q, part_rz, part_pq,
+                     sc, it, fresh, n);
+}
+
+// tolerance from ||b||^2, initial residual check
+__global__ __launch_bounds__(VBLK) void pcg_init_kernel(const double* part_rr, const double* part_bb, PcgScalars* sc,
+                                                        double rtol2) {
+  __shared__ double sh[VBLK / 64];
+  const double rr = reduce_partials(part_rr, VGRID, sh);
+  const double bb = reduce_partials(part_bb, VGRID, sh);
+  if (threadIdx.x == 0) {
+    sc->bb = bb;
+    sc->rr0 = rr;
+    sc->tol2 = rtol2 * bb;
+    sc->iters = 0;
+    sc->done = (rr <= rtol2 * bb) ? 1 : 0;
+  }
+}
+
+void launch_pcg_init(const double* part_rr, const double* part_bb, PcgScalars* sc, double rtol2, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(VBLK), 0, st, part_rr, part_bb, sc, rtol2);
+}
+void launch_pcg_update(double* x, double* r, const double* p, const double* q, const double* part_pq,
+                       double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_update_kernel, dim3(VGRID), dim3(VBLK), 0, st, x, r, p, q, part_pq, part_rr, sc, it, n);
+}
+void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_check_kernel, dim3(1), dim3(VBLK), 0, st, part_rr, sc, it);
+}
+void launch_dot(const double* a, const double* b, double* part, int64_t n, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(dot_kernel, dim3(VGRID), dim3(VBLK), 0, st, a, b, part, n, done);
+}
+void launch_finish_dot(const double* part, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(finish_dot_kernel, dim3(1), dim3(VBLK), 0, st, part, out);
+}
+
+// ---------------------------------------------------------------------------
+// Per-element gradient g_e = -lam_e^T K_ref u_e
+// ---------------------------------------------------------------------------
+__global__ void elem_grad_kernel(MeshDev M, const double* lam, const double* u, double* g, int64_t nel) {
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < nel; e += int64_t(gridDim.x) * blockDim.x) {
+    int ec[3];
+    int64_t r = e;
+    ec[0] = int(r % M.nel[0]);
+    r /= M.nel[0];
+    if (M.dim == 3) {
+      ec[1] = int(r % M.nel[1]);
+      ec[2] = int(r / M.nel[1]);
+    } else {
+      ec[1] = int(r);
+      ec[2] = 0;
+    }
+    const int nn = 1 << M.dim;
+    double lv[8], uv[8];
+    for (int a = 0; a < nn; ++a) {
+      int c[3] = {ec[0] + (a & 1), ec[1] + ((a >> 1) & 1), M.dim == 3 ? ec[2] + ((a >> 2) & 1) : 0};
+      int64_t q = free_of(M, c);
+      lv[a] = q >= 0 ? lam[q] : 0.0;
+      uv[a] = q >= 0 ? u[q] : 0.0;
+    }
+    double s = 0.0;
+    for (int a = 0; a < nn; ++a) {
+      double t = 0.0;
+      for (int b = 0; b < nn; ++b) t += kref(M, a, b) * uv[b];
+      s += lv[a] * t;
+    }
+    g[e] = -s;
+  }
+}
+
+void launch_elem_grad(const MeshDevHost& mh, const double* lam, const double* u, double* g, int64_t nel,
+                      hipStream_t st) {
+  MeshDev M{mh.dim, {mh.nel[0], mh.nel[1], mh.nel[2]}, {mh.h[0], mh.h[1], mh.h[2]}};
+  hipLaunchKernelGGL(elem_grad_kernel, dim3(grid_for(nel)), dim3(256), 0, st, M, lam, u, g, nel);
+}
+
+}  // namespace bddc

@@ -1,0 +1,240 @@
+"""Parity of the HIP library (through the C ABI) with the CPU oracle.
+
+Tolerances: FP64 local solves must match the oracle's preconditioner and PCG
+iterates to 1e-10 relative (norm-wise); the FP32-local form has no exact
+counterpart and is checked by the true residual it reaches and by its error
+against the oracle's solution, reported and bounded.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import bddc_oracle as O
+from paper_2410_14786_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def bd():
+    from paper_2410_14786_amd import bddc
+    return bddc
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    "2d_64_4x4_theta1": lambda: W.cfg_2d_64(),
+    "2d_20x24_uneven": lambda: W.make_workload("t", 2, (20, 24), cuts=[[0, 7, 13, 20], [0, 9, 24]],
+                                               theta="lognormal", seed=3),
+    "3d_16_2x2x2": lambda: W.make_workload("t", 3, (16, 16, 16), (2, 2, 2), theta="lognormal", seed=4),
+    "3d_12x10x14_uneven": lambda: W.make_workload("t", 3, (12, 10, 14),
+                                                  cuts=[[0, 5, 12], [0, 4, 7, 10], [0, 3, 9, 14]],
+                                                  theta="lognormal", seed=5),
+    "3d_24_3x3x3_inclusions": lambda: W.make_workload("t", 3, (24, 24, 24), (3, 3, 3), theta="inclusions",
+                                                      seed=6),
+    "3d_8_corners_edges": lambda: W.make_workload("t", 3, (8, 8, 8), (2, 2, 2), theta="lognormal", seed=7,
+                                                  constraints=W.CORNERS | W.EDGES),
+    "3d_8_corners_only": lambda: W.make_workload("t", 3, (8, 8, 8), (2, 2, 2), theta="lognormal", seed=8,
+                                                 constraints=W.CORNERS),
+}
+
+_oracles = {}
+
+
+def oracle_for(name):
+    if name not in _oracles:
+        w = CASES[name]()
+        _oracles[name] = (w, O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints))
+    return _oracles[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_parity_fp64(name):
+    w, P = oracle_for(name)
+    say("case", name, "n", P.n, "subs", len(P.subs), "n_c", P.n_coarse)
+    S = bd().solver_for(w)
+    rng = np.random.default_rng(0)
+    r = rng.standard_normal(P.n)
+    rf = r.copy()
+    rf[P.kappa == 1] = 0.0
+    for vec in (r, rf, w.b):
+        z = host(S.apply(dev(vec)))
+        zo = P.apply(vec)
+        e = rel(z, zo)
+        say("  apply rel err", e)
+        assert e <= 1e-10
+    S.close()
+
+
+@pytest.mark.parametrize("name", ["2d_20x24_uneven", "3d_12x10x14_uneven"])
+def test_spmv_parity(name):
+    w, P = oracle_for(name)
+    S = bd().solver_for(w)
+    x = np.random.default_rng(1).standard_normal(P.n)
+    y = host(S.spmv(dev(x)))
+    assert rel(y, P.A @ x) <= 1e-14
+    S.close()
+
+
+@pytest.mark.parametrize("name", ["2d_64_4x4_theta1", "3d_12x10x14_uneven", "3d_24_3x3x3_inclusions"])
+def test_pcg_iterates_match_oracle(name):
+    """Same number K of iterations from the same x0 = P_I b: iterates agree."""
+    w, P = oracle_for(name)
+    ref = O.bddc_pcg(P, w.b, w.rtol)
+    S = bd().solver_for(w)
+    K = max(ref.iters - 2, 1)
+    refK = O.bddc_pcg(P, w.b, 1e-300, maxit=K)
+    xK, info = S.solve(dev(w.b), 1e-15, maxit=K, raise_on_noconv=False)
+    e = rel(host(xK), refK.x)
+    say(name, "K", K, "iterate rel err", e, "status", info["status"])
+    assert info["iters"] == K
+    assert e <= 1e-10
+    x, info = S.solve(dev(w.b), w.rtol)
+    say(name, "iters gpu", info["iters"], "oracle", ref.iters, "relres", info["relres_true"],
+        "cond", info["cond_est"], ref.cond_est)
+    assert abs(info["iters"] - ref.iters) <= 1
+    assert info["relres_true"] <= w.rtol
+    assert abs(info["cond_est"] - ref.cond_est) <= 1e-6 * ref.cond_est + 1e-8
+    S.close()
+
+
+@pytest.mark.parametrize("name", ["2d_20x24_uneven", "3d_16_2x2x2"])
+def test_solution_matches_sparse_direct(name):
+    import scipy.sparse.linalg as spla
+    w, P = oracle_for(name)
+    S = bd().solver_for(w)
+    x, info = S.solve(dev(w.b), 1e-13)
+    xs = spla.spsolve(P.A.tocsc(), w.b)
+    assert rel(host(x), xs) <= 1e-10
+    S.close()
+
+
+def test_single_subdomain_is_direct():
+    w = W.make_workload("t", 3, (9, 10, 11), (1, 1, 1), theta="lognormal", seed=9)
+    S = bd().solver_for(w)
+    assert S.n_coarse == 0
+    x, info = S.solve(dev(w.b), 1e-12)
+    P = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints)
+    import scipy.sparse.linalg as spla
+    assert info["iters"] == 0
+    assert rel(host(x), spla.spsolve(P.A.tocsc(), w.b)) <= 1e-12
+    S.close()
+
+
+def test_all_primal_converges_in_one_iteration():
+    w = W.make_workload("t", 2, (8, 8), (2, 2), theta="lognormal", constraints=W.ALL_PRIMAL, seed=10)
+    S = bd().solver_for(w)
+    x, info = S.solve(dev(w.b), 1e-12)
+    assert info["iters"] == 1
+    S.close()
+
+
+def test_apply_and_solve_are_deterministic():
+    w, P = oracle_for("3d_24_3x3x3_inclusions")
+    S = bd().solver_for(w)
+    r = dev(np.random.default_rng(2).standard_normal(P.n))
+    z1, z2 = host(S.apply(r)), host(S.apply(r))
+    assert np.array_equal(z1, z2)
+    x1, i1 = S.solve(dev(w.b), 1e-9)
+    x2, i2 = S.solve(dev(w.b), 1e-9)
+    assert np.array_equal(host(x1), host(x2)) and i1["iters"] == i2["iters"]
+    S.close()
+
+
+def test_warm_start_flag():
+    w, P = oracle_for("3d_12x10x14_uneven")
+    S = bd().solver_for(w)
+    x, info = S.solve(dev(w.b), 1e-10)
+    x2, info2 = S.solve(dev(w.b), 1e-10, x0=x)
+    assert info2["iters"] <= 1 and info2["relres_true"] <= 1e-10
+    S.close()
+
+
+@pytest.mark.parametrize("name", ["3d_16_2x2x2", "3d_24_3x3x3_inclusions", "2d_20x24_uneven"])
+def test_fp32_local_reaches_true_residual(name):
+    w, P = oracle_for(name)
+    ref = O.bddc_pcg(P, w.b, 1e-12)
+    S = bd().solver_for(w, local_bits=32)
+    x, info = S.solve(dev(w.b), 1e-8)
+    e = rel(host(x), ref.x)
+    say(name, "fp32-local iters", info["iters"], "relres_true", info["relres_true"], "err vs oracle", e)
+    assert info["relres_true"] <= 1e-8
+    assert e <= 1e-6
+    S.close()
+
+
+def test_fp32_local_apply_close_to_oracle():
+    w, P = oracle_for("3d_16_2x2x2")
+    S = bd().solver_for(w, local_bits=32)
+    r = np.random.default_rng(3).standard_normal(P.n)
+    e = rel(host(S.apply(dev(r))), P.apply(r))
+    say("fp32-local apply rel err", e)
+    assert e <= 1e-3
+    S.close()
+
+
+def test_element_gradient_kernel():
+    w, P = oracle_for("3d_12x10x14_uneven")
+    S = bd().solver_for(w)
+    rng = np.random.default_rng(4)
+    lam, u = rng.standard_normal(P.n), rng.standard_normal(P.n)
+    g = host(S.elem_grad(dev(lam), dev(u)))
+    assert rel(g, O.element_gradient(P.mesh, lam, u)) <= 1e-13
+    S.close()
+
+
+def test_autograd_matches_oracle_adjoint():
+    w = W.make_workload("t", 3, (8, 8, 8), (2, 2, 2), theta="lognormal", seed=11)
+    W.add_adjoint_data(w, 4)
+    mesh = O.Mesh(3, w.nel)
+    import scipy.sparse.linalg as spla
+    u_obs = spla.spsolve(O.assemble(mesh, w.theta_obs).tocsc(), w.b)
+    J, u, lam, g = O.adjoint_gradient(mesh, w.theta, w.b, u_obs)
+    th = dev(w.theta).requires_grad_(True)
+    b = dev(w.b).requires_grad_(True)
+    uu = bd().bddc_solve(th, b, 3, w.nel, w.cuts, w.constraints, rtol=1e-12)
+    loss = 0.5 * torch.sum((uu - dev(u_obs)) ** 2)
+    loss.backward()
+    assert rel(host(th.grad), g) <= 1e-8
+    assert rel(host(b.grad), lam) <= 1e-8
+
+
+def test_kernel_timing_api():
+    w, P = oracle_for("3d_16_2x2x2")
+    S = bd().solver_for(w)
+    S.set_timing(True)
+    r = dev(w.b)
+    for _ in range(3):
+        S.apply(r)
+    n, ms = S.kernel_time("trsv_fwd_rr")
+    assert n == 3 and ms > 0
+    n, ms = S.kernel_time("apply")
+    assert n == 3 and ms > 0
+    S.set_timing(False)
+    S.close()

@@ -1,0 +1,87 @@
+"""Setup-stage parity on the GPU, read back through bddc_debug_read.
+
+For one subdomain at a time:
+  * the batched Cholesky factor satisfies ||L L^T - D A_RR D||_F <= c n eps ||.||_F
+    (backward-error bound of Cholesky), with A_RR built from the oracle's A_i;
+  * the bordering rows W^T satisfy L W = D B with B = [C_AR^T | A_RPi]: the corner
+    columns equal D A_RPi, and every average column is a constant 1/m on the m
+    nodes of one interface class (paper Sec. 2: averages over edges and faces);
+  * the bordering diagonal tile equals -W^T W;
+  * A_ci = Phi_i^T A_i Phi_i has the oracle's spectrum (the constraint order of
+    the two sides differs, the matrices agree up to that permutation).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import bddc_oracle as O
+from paper_2410_14786_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+CASES = [
+    ("3d_12_2x2x2", lambda: W.make_workload("t", 3, (12, 12, 12), (2, 2, 2), theta="lognormal", seed=0)),
+    ("3d_12x10x14_uneven", lambda: W.make_workload("t", 3, (12, 10, 14),
+                                                   cuts=[[0, 5, 12], [0, 4, 7, 10], [0, 3, 9, 14]],
+                                                   theta="inclusions", seed=5)),
+    ("2d_40_2x2", lambda: W.make_workload("t", 2, (40, 40), (2, 2), theta="lognormal", seed=2)),
+]
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_local_setup_against_numpy(case, bits):
+    from paper_2410_14786_amd import bddc
+    name, make = case
+    w = make()
+    P = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints)
+    S = bddc.Solver(w.dim, w.nel, w.cuts, w.theta, w.constraints, local_bits=bits)
+    eps = np.finfo(np.float64 if bits == 64 else np.float32).eps
+    for sub in range(min(S.n_sub, 4)):
+        s = P.subs[sub]
+        nR, nI, nA, nP, T, ni = S.debug_read("sizes", sub).astype(int)
+        gmap = S.debug_read("gmap", sub).astype(int)
+        loc = np.searchsorted(s.R, gmap)
+        assert np.array_equal(s.R[loc], gmap) and ni == len(s.R)
+        A = s.A.toarray()[np.ix_(loc, loc)]
+        d = S.debug_read("dscale", sub)
+        assert np.allclose(d[:nR], 1 / np.sqrt(np.diag(A)[:nR]), rtol=1e-14)
+        At = d[:nR, None] * A[:nR, :nR] * d[None, :nR]
+        L = S.debug_read("factor", sub).reshape(T * 64, T * 64)[:nR, :nR]
+        assert np.array_equal(L, np.tril(L))
+        berr = np.linalg.norm(L @ L.T - At) / np.linalg.norm(At)
+        print(name, bits, "sub", sub, "n_R", nR, "backward error", berr, flush=True)
+        assert berr <= 4 * nR * eps
+        nci = nA + nP
+        if nci == 0:
+            continue
+        Wt = S.debug_read("border", sub).reshape(64, T * 64)[:nci, :nR]
+        LW = L @ Wt.T
+        tol = 50 * nR * eps
+        corner = d[:nR, None] * A[:nR, nR:]
+        assert np.abs(LW[:, nA:] - corner).max() <= tol * max(1.0, np.abs(corner).max())
+        for k in range(nA):
+            col = LW[:, k] / d[:nR]
+            nz = np.abs(col) > 1e-3 * np.abs(col).max()
+            m = int(nz.sum())
+            assert m >= 1 and np.allclose(col[nz], 1.0 / m, rtol=1e3 * eps * nR)
+            assert np.abs(col[~nz]).max(initial=0) <= 1e3 * nR * eps
+        schur = S.debug_read("schur", sub).reshape(64, 64)[:nci, :nci]
+        G = Wt @ Wt.T
+        assert np.abs(-schur - G).max() <= 1e3 * nR * eps * max(1.0, np.abs(G).max())
+        aci = S.debug_read("aci", sub).reshape(64, 64)[:nci, :nci]
+        ev_gpu = np.sort(np.linalg.eigvalsh(0.5 * (aci + aci.T)))
+        ev_orc = np.sort(np.linalg.eigvalsh(s.Ac))
+        rtol = 1e-10 if bits == 64 else 1e-4
+        assert np.allclose(ev_gpu, ev_orc, rtol=rtol, atol=rtol * ev_orc.max())
+    S.close()

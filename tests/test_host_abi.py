@@ -1,0 +1,139 @@
+"""Host-side checks of libbddc.so that need no GPU: the library loads, exports
+every entry point its header declares, validates arguments before touching the
+device, and its host planner (dof numbering, multiplicities, interface classes)
+agrees with the oracle's independent classification."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import bddc_oracle as O
+from paper_2410_14786_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bddc.h")
+
+bddc = pytest.importorskip("paper_2410_14786_amd.bddc")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(bddc.LIB_PATH):
+        pytest.fail("libbddc.so is not built (run __graft_entry__.build())")
+    return bddc.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bddc_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_exports():
+    assert declared_functions() == sorted(bddc.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_covers_every_status(lib):
+    for code in range(0, -8, -1):
+        assert lib.bddc_strerror(code).decode() not in ("", "unknown status")
+    assert lib.bddc_strerror(-99).decode() == "unknown status"
+
+
+@pytest.mark.parametrize("case", [
+    (2, (64, 64), (4, 4), W.CORNERS | W.EDGES),
+    (3, (16, 16, 16), (2, 2, 2), 7),
+    (3, (12, 10, 14), None, 7),
+    (3, (8, 8, 8), (4, 4, 4), W.CORNERS | W.EDGES),
+    (2, (8, 8), (2, 2), W.ALL_PRIMAL),
+])
+def test_plan_matches_oracle_classification(lib, case):
+    dim, nel, nsub, cons = case
+    if nsub is None:
+        cuts = [[0, 5, 12], [0, 4, 7, 10], [0, 3, 9, 14]]
+    else:
+        cuts = [W.uniform_cuts(nel[a], nsub[a]) for a in range(dim)]
+    st = bddc.plan_stats(dim, nel, cuts, cons)
+    P = O.BDDC(dim, nel, cuts, np.ones(int(np.prod(nel))), cons)
+    kinds = [c.kind for c in P.classes]
+    assert st["n_free"] == P.n
+    assert st["n_sub"] == len(P.subs)
+    assert st["n_coarse"] == P.n_coarse
+    assert st["corners"] == kinds.count("corner")
+    assert st["edges"] == kinds.count("edge")
+    assert st["faces"] == kinds.count("face")
+    assert st["sum_ni"] == sum(len(s.R) for s in P.subs)
+    assert st["max_nci"] == max(s.C.shape[0] for s in P.subs)
+
+
+def test_plan_full_size_workloads(lib):
+    # sizes of the 3D workloads (closed forms: K boxes per axis)
+    st = bddc.plan_stats(3, (64, 64, 64), [W.uniform_cuts(64, 4)] * 3, 7)
+    assert st["n_free"] == 63 ** 3 and st["n_coarse"] == 27 + 108 + 144
+    st = bddc.plan_stats(3, (96, 96, 96), [W.uniform_cuts(96, 6)] * 3, 7)
+    assert st["n_coarse"] == 125 + 3 * 6 * 25 + 3 * 36 * 5
+    w = W.cfg_3d_128_uneven()
+    st = bddc.plan_stats(3, w.nel, w.cuts, 7)
+    assert st["n_sub"] == 512 and st["n_coarse"] == 343 + 3 * 8 * 49 + 3 * 64 * 7
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dim=4), dict(cuts=[[0, 4, 7], [0, 8]]), dict(cuts=[[0, 1, 8], [0, 8]]),
+    dict(cuts=[[0, 8, 8], [0, 8]]), dict(nel=(1, 8)), dict(cuts=[[1, 8], [0, 8]]),
+])
+def test_plan_rejects_bad_input(lib, bad):
+    args = dict(dim=2, nel=(8, 8), cuts=[[0, 4, 8], [0, 8]])
+    args.update(bad)
+    with pytest.raises(bddc.BDDCError) as e:
+        bddc.plan_stats(args["dim"], args["nel"], args["cuts"], 3)
+    assert e.value.code == bddc.EINVAL
+
+
+def _setup_raw(lib, theta, cuts=((0, 4, 8), (0, 8)), local_bits=64, nb=0, flags=0, on_device=0):
+    m, p, keep = bddc._mesh_partition(2, (8, 8), cuts)
+    co = bddc.Coefficients()
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    co.theta = th.ctypes.data
+    co.on_device = on_device
+    opt = bddc.Options()
+    opt.local_bits, opt.use_graph, opt.nb_override, opt.stream, opt.flags = local_bits, 0, nb, None, flags
+    ctx = ctypes.c_void_p()
+    code = lib.bddc_setup(ctypes.byref(m), ctypes.byref(p), ctypes.byref(co), 3, ctypes.byref(opt),
+                          ctypes.byref(ctx))
+    return code, ctx
+
+
+def test_setup_validates_before_any_device_work(lib):
+    th = np.ones(64)
+    assert _setup_raw(lib, th, local_bits=16)[0] == bddc.EINVAL
+    assert _setup_raw(lib, th, nb=32)[0] == bddc.ENOTIMPL
+    assert _setup_raw(lib, th, flags=2)[0] == bddc.EINVAL
+    assert _setup_raw(lib, th, on_device=2)[0] == bddc.EINVAL
+    assert _setup_raw(lib, th, cuts=((0, 7, 8), (0, 8)))[0] == bddc.EINVAL
+    bad = th.copy()
+    bad[17] = 0.0
+    code, ctx = _setup_raw(lib, bad)
+    assert code == bddc.ENOTSPD and not ctx.value
+    assert "element 17" in lib.bddc_last_error().decode()
+    bad[17] = np.nan
+    assert _setup_raw(lib, bad)[0] == bddc.ENOTSPD
+
+
+def test_null_context_is_rejected(lib):
+    assert lib.bddc_apply(None, None, None) == bddc.EINVAL
+    assert lib.bddc_spmv(None, None, None) == bddc.EINVAL
+    assert lib.bddc_query(None, None, None, None, None) == bddc.EINVAL
+    lib.bddc_destroy(None)
+
+
+def test_too_many_constraints_not_implemented(lib):
+    # all-primal on large boxes exceeds 64 constraints per subdomain
+    with pytest.raises(bddc.BDDCError) as e:
+        bddc.plan_stats(3, (16, 16, 16), [[0, 8, 16]] * 3, W.ALL_PRIMAL)
+    assert e.value.code == bddc.ENOTIMPL
