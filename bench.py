@@ -171,6 +171,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--local-bits", type=int, default=64)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 512 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the whole problem lives on one MI355X); --gpus {args.gpus} "
@@ -178,6 +180,14 @@ def main():
         sys.exit(2)
     import torch
     from paper_2410_14786_amd import workloads as W
+    if args.copy_calibration:
+        n = 512 * 1024 * 1024 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = W.WORKLOADS[args.workload]()
     print(f"[bench] workload {w.name}: n_free {w.n_free}, {int(np.prod(w.nsub))} subdomains", file=sys.stderr,
           flush=True)
