@@ -86,17 +86,19 @@ def kernel_hash():
 
 def load_traffic(kernel, workload, local_bits):
     """HBM traffic per launch measured by rocprofv3 counters, if the record in
-    profiles/ was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    profiles/traffic.txt was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
     try:
-        rec = json.load(open(path))
-    except Exception:
+        lines = open(path).read().splitlines()
+    except OSError:
         return None
     key = f"{workload}/{local_bits}/{kernel}"
-    ent = rec.get(key)
-    if not ent or ent.get("kernel_sha") != kernel_hash():
-        return None
-    return ent.get("bytes_per_launch")
+    for ln in lines:
+        parts = ln.split()
+        if ln.startswith("#") or len(parts) < 3 or parts[0] != key:
+            continue
+        return int(parts[2]) if parts[1] == kernel_hash() else None
+    return None
 
 
 def run_gpu(w, steps, warmup, local_bits, use_graph=False):
