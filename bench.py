@@ -7,10 +7,12 @@ residual 1e-8.  A step is one warm BDDC-PCG solve (the preconditioner is set up
 once beforehand, as when the matrix is reused across time steps); inputs are
 resident in HBM when the timed region starts.
 
-Prints one JSON line with the FP64 solve rate as `value`, the FP32-local rate
-beside it, the roofline of the dominant kernel (achieved bytes per launch over
-its HIP-event-timed average duration) and a CPU-oracle baseline on a bounded
-sample of the same workload.
+Prints one JSON line with the FP64 solve rate as `value` (CG restricted to the
+interface dofs, the default of bddc_pcg_solve), the same solve with CG on the
+whole space (the three-part preconditioner applied as written) and the
+FP32-local rate beside it, the roofline of the dominant kernel (algorithmic
+bytes per launch over its HIP-event-timed average duration) and a CPU-oracle
+baseline on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -25,7 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRSV_FAMILIES = ["trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii", "trsv_bwd_ii"]
+FULL_FAMILIES = ["trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii", "trsv_bwd_ii"]
+IFACE_FAMILIES = ["trsv_fwd_g", "trsv_bwd_g", "mv_t", "mv"]
 NB = 64
 
 
@@ -74,6 +77,14 @@ def algorithmic_bytes(w, local_bytes):
                              for nR, nI, nci in s)
     fam["trsv_fwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 4 + local_bytes) for nR, nI, nci in s)
     fam["trsv_bwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 8 + 4 + local_bytes) for nR, nI, nci in s)
+    # interface form: the trailing block L_GG (n_G = n_R - n_I rows) and its border rows
+    fam["trsv_fwd_g"] = sum(tri(nR - nI) * local_bytes + nci * (nR - nI) * local_bytes
+                            + (nR - nI) * (8 + 8 + 4 + local_bytes) for nR, nI, nci in s)
+    fam["trsv_bwd_g"] = sum(tri(nR - nI) * local_bytes + nci * (nR - nI) * local_bytes
+                            + (nR - nI) * (8 + 2 * local_bytes) for nR, nI, nci in s)
+    fam["mv_t"] = sum(tri(nR - nI) * local_bytes + 8 * (nR - nI) * local_bytes + 2 * (nR - nI) * local_bytes
+                      for nR, nI, nci in s)
+    fam["mv"] = sum(tri(nR - nI) * local_bytes + (nR - nI) * (local_bytes + 16) for nR, nI, nci in s)
     return fam
 
 
@@ -101,12 +112,13 @@ def load_traffic(kernel, workload, local_bits):
     return None
 
 
-def run_gpu(w, steps, warmup, local_bits, use_graph=False):
+def run_gpu(w, steps, warmup, local_bits, use_graph=False, full_space=False):
     import torch
     from paper_2410_14786_amd import bddc
+    families = FULL_FAMILIES if full_space else IFACE_FAMILIES
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    S = bddc.solver_for(w, local_bits=local_bits, use_graph=use_graph)
+    S = bddc.solver_for(w, local_bits=local_bits, use_graph=use_graph, full_space=full_space)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     b = torch.as_tensor(w.b, dtype=torch.float64, device="cuda")
@@ -115,7 +127,7 @@ def run_gpu(w, steps, warmup, local_bits, use_graph=False):
     for _ in range(warmup):
         _, info = S.solve(b, w.rtol, out=x)
     S.set_timing(True)
-    for f in TRSV_FAMILIES + ["apply"]:
+    for f in families + ["apply"]:
         S.kernel_time(f)   # reset counters
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -125,10 +137,10 @@ def run_gpu(w, steps, warmup, local_bits, use_graph=False):
         iters.append(info["iters"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    fam = {f: S.kernel_time(f) for f in TRSV_FAMILIES + ["apply"]}
+    fam = {f: S.kernel_time(f) for f in families + ["apply"]}
     S.set_timing(False)
     res = {"setup_s": setup_s, "elapsed_s": elapsed, "iters": iters, "info": info, "kernels": fam,
-           "dev_bytes": S.dev_bytes}
+           "dev_bytes": S.dev_bytes, "families": families}
     S.close()
     del S
     torch.cuda.empty_cache()
@@ -172,6 +184,7 @@ def main():
     ap.add_argument("--workload", default="3d_64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-full-space", action="store_true")
     ap.add_argument("--local-bits", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 512 MiB device copy first (reference for HBM byte counters)")
@@ -194,66 +207,67 @@ def main():
     print(f"[bench] workload {w.name}: n_free {w.n_free}, {int(np.prod(w.nsub))} subdomains", file=sys.stderr,
           flush=True)
     main_bits = args.local_bits
-    r64 = run_gpu(w, args.steps, args.warmup, main_bits)
-    ms = 1000.0 * r64["elapsed_s"] / args.steps
-    print(f"[bench] fp{main_bits}-local: {ms:.2f} ms/solve, iters {r64['iters'][-1]}, setup {r64['setup_s']:.2f} s",
-          file=sys.stderr, flush=True)
-    r32 = None
+    runs = {}
+    runs["main"] = run_gpu(w, args.steps, args.warmup, main_bits)
+    if not args.no_full_space:
+        runs["full_space"] = run_gpu(w, args.steps, args.warmup, main_bits, full_space=True)
     if not args.no_fp32 and main_bits == 64:
-        r32 = run_gpu(w, args.steps, args.warmup, 32)
-        print(f"[bench] fp32-local: {1000 * r32['elapsed_s'] / args.steps:.2f} ms/solve, iters {r32['iters'][-1]}",
-              file=sys.stderr, flush=True)
-    # roofline of the dominant kernel family
-    lb = 8 if main_bits == 64 else 4
-    algo = algorithmic_bytes(w, lb)
-    fams = {f: r64["kernels"][f] for f in TRSV_FAMILIES}
-    dom = max(fams, key=lambda f: fams[f][1])
-    n_l, tot_ms = fams[dom]
-    avg_s = tot_ms / 1000.0 / max(n_l, 1)
-    achieved = algo[dom] / avg_s / 1e9
-    traffic = load_traffic(dom, args.workload, main_bits)
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "bytes_per_launch": algo[dom], "avg_launch_ms": round(avg_s * 1e3, 4), "launches": n_l}
-    apply_n, apply_ms = r64["kernels"]["apply"]
-    apply_bytes = sum(algo.values())
+        runs["fp32_local"] = run_gpu(w, args.steps, args.warmup, 32)
+    for name, r in runs.items():
+        print(f"[bench] {name}: {1000 * r['elapsed_s'] / args.steps:.2f} ms/solve, iters {r['iters'][-1]}, "
+              f"setup {r['setup_s']:.2f} s", file=sys.stderr, flush=True)
+
+    def summarize(r, bits):
+        lb = 8 if bits == 64 else 4
+        algo = algorithmic_bytes(w, lb)
+        fams = {f: r["kernels"][f] for f in r["families"]}
+        dom = max(fams, key=lambda f: fams[f][1])
+        n_l, tot_ms = fams[dom]
+        avg_s = tot_ms / 1000.0 / max(n_l, 1)
+        achieved = algo[dom] / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": load_traffic(dom, args.workload, bits),
+                "bytes_per_launch": algo[dom], "avg_launch_ms": round(avg_s * 1e3, 4), "launches": n_l}
+        fam_bytes = sum(algo[f] for f in r["families"])
+        fam_ms = sum(fams[f][1] / max(fams[f][0], 1) for f in r["families"])
+        n_a, ms_a = r["kernels"]["apply"]
+        return {"value": round(args.steps / r["elapsed_s"], 3), "unit": "solves/s",
+                "ms_per_step": round(1000 * r["elapsed_s"] / args.steps, 3), "iters": r["iters"][-1],
+                "relres_true": r["info"]["relres_true"], "cond_est": r["info"]["cond_est"],
+                "setup_s": round(r["setup_s"], 3),
+                "applies_per_s": round(n_a / (ms_a / 1e3), 2) if n_a else None,
+                "kernel_ms": {f: round(fams[f][1] / max(fams[f][0], 1), 4) for f in fams},
+                "streamed_hbm_frac": round(fam_bytes / (fam_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if fam_ms else None,
+                "roofline": roof, "dev_bytes": r["dev_bytes"]}
+
+    m = summarize(runs["main"], main_bits)
     out = {
         "metric": "BDDC-PCG solves/s to rtol 1e-8 (FP64 vs FP32-local) + % HBM/MFMA peak",
-        "value": round(args.steps / r64["elapsed_s"], 3),
+        "value": m["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 3),
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if main_bits == 64 else "f64-outer/f32-local",
         "data": "synthetic",
         "config": {"workload": w.name, "n_free": w.n_free, "subdomains": int(np.prod(w.nsub)),
-                   "rtol": w.rtol, "local_bits": main_bits},
-        "iters": r64["iters"][-1],
-        "relres_true": r64["info"]["relres_true"],
-        "cond_est": r64["info"]["cond_est"],
-        "setup_s": round(r64["setup_s"], 3),
-        "applies_per_s": round(apply_n / (apply_ms / 1e3), 2) if apply_n else None,
-        "apply_hbm_frac": round(apply_bytes / (apply_ms / 1e3 / max(apply_n, 1)) / 1e9 / HBM_PEAK_GBS, 4)
-        if apply_n else None,
-        "kernel_ms": {f: round(fams[f][1] / max(fams[f][0], 1), 4) for f in fams},
-        "roofline": roof,
-        "dev_bytes": r64["dev_bytes"],
+                   "rtol": w.rtol, "local_bits": main_bits, "cg_space": "interface"},
     }
-    if r32 is not None:
-        a32 = algorithmic_bytes(w, 4)
-        n32, ms32 = r32["kernels"]["apply"]
-        out["fp32_local"] = {"value": round(args.steps / r32["elapsed_s"], 3), "unit": "solves/s",
-                             "ms_per_step": round(1000 * r32["elapsed_s"] / args.steps, 3),
-                             "iters": r32["iters"][-1], "relres_true": r32["info"]["relres_true"],
-                             "setup_s": round(r32["setup_s"], 3),
-                             "apply_hbm_frac": round(sum(a32.values()) / (ms32 / 1e3 / max(n32, 1)) / 1e9
-                                                     / HBM_PEAK_GBS, 4) if n32 else None}
+    for k in ["iters", "relres_true", "cond_est", "setup_s", "applies_per_s", "kernel_ms", "streamed_hbm_frac",
+              "dev_bytes"]:
+        out[k] = m[k]
+    out["roofline"] = m["roofline"]
+    if "full_space" in runs:
+        out["full_space"] = summarize(runs["full_space"], main_bits)
+    if "fp32_local" in runs:
+        out["fp32_local"] = summarize(runs["fp32_local"], 32)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(r64["iters"][-1])
+        out["cpu_baseline"] = cpu_baseline(m["iters"])
     print(json.dumps(out), flush=True)
 
 

@@ -64,6 +64,19 @@ enum { BDDC_CORNERS = 1, BDDC_EDGES = 2, BDDC_FACES = 4, BDDC_ALL_PRIMAL = 8 };
  * can be inspected with bddc_debug_read; it must then be destroyed. */
 enum { BDDC_SETUP_KEEP_ON_ERROR = 1 };
 
+/* Setup option flag: iterate CG on the whole space with the three-part
+ * preconditioner exactly as written in the paper (Sec. 2: M^{-1} r = v1 + v2 + v3
+ * applied every iteration, r1 and v3 included).  Without it, bddc_pcg_solve runs
+ * the same preconditioned CG restricted to interface dofs: from x0 = P_I b every
+ * residual vanishes on subdomain interiors and every search direction is
+ * discrete-harmonic, so CG with A on those vectors is CG with the assembled
+ * Schur complement S = sum_i R_i^T (A_BB - A_BI A_II^{-1} A_IB)_i R_i, and the
+ * preconditioned residual restricted to the interface is v1 + v2 (v3 only
+ * changes interior values).  Both give the same iterates in exact arithmetic;
+ * the interior values of x are recovered once at the end by the interior
+ * solves of eq. (5).  bddc_apply always applies the full three-part operator. */
+enum { BDDC_SETUP_FULL_SPACE = 2 };
+
 /* Solve flags. */
 enum { BDDC_X0_GIVEN = 1 /* use x on entry as the initial guess */ };
 
@@ -97,7 +110,7 @@ typedef struct {
   int32_t use_graph;    /* 1: replay PCG iterations from a captured HIP graph   */
   int32_t nb_override;  /* 0 = default tile size (64); other values: ENOTIMPL   */
   void* stream;         /* hipStream_t for all work of this ctx                 */
-  int32_t flags;        /* 0, or BDDC_SETUP_KEEP_ON_ERROR (tests only)           */
+  int32_t flags;        /* BDDC_SETUP_FULL_SPACE and/or BDDC_SETUP_KEEP_ON_ERROR */
 } bddc_options;
 
 typedef struct {
@@ -158,7 +171,10 @@ int bddc_plan_stats(const bddc_mesh* mesh, const bddc_partition* part,
  * bracketed by HIP events on the ctx stream; bddc_kernel_time returns the
  * number of timed launches and their summed duration in ms (synchronising
  * the stream).  Families: "trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii",
- * "trsv_bwd_ii", "spmv", "apply".  Unknown names give EINVAL. */
+ * "trsv_bwd_ii" (full-space solves), "trsv_fwd_g", "trsv_bwd_g" (interface
+ * block solves), "mv_t", "mv" (the two triangular mat-vecs of the Schur
+ * operator), "schur" (the whole operator), "spmv", "apply".  Unknown names
+ * give EINVAL. */
 int bddc_set_timing(bddc_ctx* ctx, int32_t enabled);
 int bddc_kernel_time(bddc_ctx* ctx, const char* family, int64_t* launches,
                      double* total_ms);

@@ -38,7 +38,7 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
         if src.endswith(".hip"):
             cmd = [cc, "-x", "hip"] + common + gpu + ["-c", os.path.join(CSRC, src), "-o", obj]
         else:
-            cmd = [cc] + common + ["-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [cc] + common + gpu + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))

@@ -91,6 +91,7 @@ struct bddc_ctx {
   hipStream_t st = nullptr;
   bool fp32 = false;
   bool use_graph = false;
+  bool iface = true;                // interface-restricted CG (see bddc.h)
   MeshDevHost mesh{};
   std::vector<void*> allocs;
   int64_t dev_bytes = 0;
@@ -116,6 +117,10 @@ struct bddc_ctx {
   int32_t *ctask_fwd = nullptr, *ctask_bwd = nullptr;
   int Tc = 0;
   int32_t *t_fwd_rr = nullptr, *t_bwd_rr = nullptr, *t_fwd_ii = nullptr, *t_bwd_ii = nullptr;
+  int32_t *t_fwd_g = nullptr, *t_bwd_g = nullptr;
+  void *vloc = nullptr, *qloc = nullptr;      // interface operator: local v and q (local precision)
+  double *ppi = nullptr, *sploc = nullptr, *cpp = nullptr;
+  int max_loclen = 1;
   void* pub_local = nullptr;   // 4 * n_vec entries of the local precision
   double* pub_coarse = nullptr;
   unsigned* tickets = nullptr;
@@ -249,7 +254,8 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   c->end("trsv_fwd_rr", e);
 
   if (P.n_coarse > 0) {
-    launch_coarse_prep(c->mats, P.nsubs, c->part, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done, st);
+    launch_coarse_prep(c->mats, P.nsubs, c->part, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done, 0,
+                       st);
     TrsvArgs cf;
     std::memset(&cf, 0, sizeof(cf));
     cf.mats = c->cmat;
@@ -316,6 +322,106 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   c->end("apply", ea);
 }
 
+// Interface preconditioner (v1 + v2 restricted to interface dofs) on an
+// interface residual r: forward solve with the trailing block L_GG, coarse
+// problem, backward solve, weighted gather into z (interface entries), and the
+// partial sums of r.z for the next direction.
+void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_rz, const int* done) {
+  const Plan& P = c->plan;
+  hipStream_t st = c->st;
+  hipEvent_t ea = c->begin("apply");
+  launch_reset(c->fp32, c->pub_local, 2 * P.n_vec, c->pub_coarse, 2 * int64_t(c->Tc) * NB, c->tickets, done, st);
+  TrsvArgs a = base_args(c);
+  a.done = done;
+  a.tasks = c->t_fwd_g;
+  a.ntasks = int(P.fwd_g.size() / 2);
+  a.ticket = c->tickets + 0;
+  a.sol = pub_slot(c, 0);
+  a.rin = r;
+  a.part = c->part;
+  hipEvent_t e = c->begin("trsv_fwd_g");
+  launch_trsv(TRSV_FWD_G, c->fp32, a, trsv_grid(c, a.ntasks), st);
+  c->end("trsv_fwd_g", e);
+  if (P.n_coarse > 0) {
+    launch_coarse_prep(c->mats, P.nsubs, c->part, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done, 1,
+                       st);
+    TrsvArgs cf;
+    std::memset(&cf, 0, sizeof(cf));
+    cf.mats = c->cmat;
+    cf.tiles = c->ctiles;
+    cf.dinv = c->cdinv;
+    cf.done = done;
+    cf.tasks = c->ctask_fwd;
+    cf.ntasks = c->Tc;
+    cf.ticket = c->tickets + 4;
+    cf.sol = c->pub_coarse;
+    cf.cinv_ptr = c->cinv_ptr;
+    cf.cinv = c->cinv;
+    cf.gbuf = c->gbuf;
+    cf.dc = c->dc;
+    launch_trsv(TRSV_FWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
+    cf.tasks = c->ctask_bwd;
+    cf.ticket = c->tickets + 5;
+    cf.src = c->pub_coarse;
+    cf.sol = c->pub_coarse + int64_t(c->Tc) * NB;
+    cf.uc = c->uc;
+    launch_trsv(TRSV_BWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
+    launch_coarse_coef(c->mats, P.nsubs, c->rc, c->uc, c->mu, c->sainv, c->sainve, c->wgt, c->coef, c->ww, done,
+                       st);
+  }
+  a = base_args(c);
+  a.done = done;
+  a.tasks = c->t_bwd_g;
+  a.ntasks = int(P.bwd_g.size() / 2);
+  a.ticket = c->tickets + 1;
+  a.sol = pub_slot(c, 1);
+  a.src = pub_slot(c, 0);
+  a.coef = c->coef;
+  a.ww = c->ww;
+  e = c->begin("trsv_bwd_g");
+  launch_trsv(TRSV_BWD_G, c->fp32, a, trsv_grid(c, a.ntasks), st);
+  c->end("trsv_bwd_g", e);
+  launch_gather_z(c->inv_ptr, c->inv, c->ww, c->kappa, r, z, part_rz, P.n_free, done, st);
+  c->end("apply", ea);
+}
+
+// q = S p with p = z + beta p (iteration it), partial sums of p.q into part_pq
+void enqueue_schur(bddc_ctx* c, int it, bool fresh, const double* part_rz, double* part_pq) {
+  const Plan& P = c->plan;
+  hipStream_t st = c->st;
+  const int* done = &c->sc->done;
+  hipEvent_t e = c->begin("schur");
+  launch_iface_local(c->mats, P.nsubs, c->max_loclen, c->gmap, c->dsc, c->z, c->p, part_rz, c->sc, it, fresh ? 1 : 0,
+                     c->vloc, c->fp32, c->ppi, st);
+  MvArgs m;
+  std::memset(&m, 0, sizeof(m));
+  m.mats = c->mats;
+  m.tiles = c->tiles;
+  m.tasks = c->t_fwd_g;
+  m.ntasks = int(P.fwd_g.size() / 2);
+  m.done = done;
+  m.ppi = c->ppi;
+  m.part = c->part;
+  m.dsc = c->dsc;
+  m.sploc = c->sploc;
+  m.ticket = c->tickets + 2;
+  m.xin = c->vloc;
+  m.xout = c->qloc;
+  hipEvent_t e1 = c->begin("mv_t");
+  launch_tile_mv(true, c->fp32, m, trsv_grid(c, m.ntasks), st);
+  c->end("mv_t", e1);
+  m.ticket = c->tickets + 3;
+  m.xin = c->qloc;
+  m.xout = nullptr;
+  e1 = c->begin("mv");
+  launch_tile_mv(false, c->fp32, m, trsv_grid(c, m.ntasks), st);
+  c->end("mv", e1);
+  launch_corner_sp(c->mats, P.nsubs, c->part, c->cpp, c->ppi, c->sploc, done, st);
+  launch_gather_sp(c->inv_ptr, c->inv, c->sploc, c->kappa, c->z, c->p, c->q, part_rz, part_pq, c->sc, it,
+                   fresh ? 1 : 0, P.n_free, st);
+  c->end("schur", e);
+}
+
 // x = P_I b: interior solves of b, zero on the interface
 void enqueue_interior_guess(bddc_ctx* c, const double* b, double* x) {
   const Plan& P = c->plan;
@@ -338,6 +444,31 @@ void enqueue_interior_guess(bddc_ctx* c, const double* b, double* x) {
   a.sol = pub_slot(c, 3);
   a.src = pub_slot(c, 2);
   a.zout = x;
+  launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
+}
+
+// out = xt + P_I (b - A xt) on interior dofs, xt on the interface (xt is zero on
+// interior dofs); out may be xt itself
+void enqueue_interior_complete(bddc_ctx* c, const double* b, const double* xt, double* out) {
+  const Plan& P = c->plan;
+  hipStream_t st = c->st;
+  launch_reset(c->fp32, pub_slot(c, 2), 2 * P.n_vec, nullptr, 0, c->tickets, nullptr, st);
+  TrsvArgs a = base_args(c);
+  a.tasks = c->t_fwd_ii;
+  a.ntasks = int(P.fwd_ii.size() / 2);
+  a.ticket = c->tickets + 2;
+  a.sol = pub_slot(c, 2);
+  a.rin = b;
+  a.v12 = xt;
+  launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
+  a = base_args(c);
+  a.tasks = c->t_bwd_ii;
+  a.ntasks = int(P.bwd_ii.size() / 2);
+  a.ticket = c->tickets + 3;
+  a.sol = pub_slot(c, 3);
+  a.src = pub_slot(c, 2);
+  a.zout = out;
+  a.base = xt;
   launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
 }
 
@@ -387,6 +518,8 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->upload(c->t_bwd_rr, P.bwd_rr))) return rc_;
   if ((rc_ = c->upload(c->t_fwd_ii, P.fwd_ii))) return rc_;
   if ((rc_ = c->upload(c->t_bwd_ii, P.bwd_ii))) return rc_;
+  if ((rc_ = c->upload(c->t_fwd_g, P.fwd_g))) return rc_;
+  if ((rc_ = c->upload(c->t_bwd_g, P.bwd_g))) return rc_;
 
   // global matrix
   launch_assemble_csr(c->mesh, c->theta, c->rowptr, c->col, c->val, P.n_free, c->err, st);
@@ -427,7 +560,9 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   launch_local_assembly(c->mesh, c->theta, c->mats, P.nsubs, max_ni, c->gmap, c->lmap, c->wgt, c->dsc, c->wd,
                         c->avg_of, c->avg_coef, c->tiles, c->fp32, c->app, c->err + 1, st);
   launch_factor(c->mats, P.nsubs, P.maxT, P.maxTx, c->tiles, c->dinv, c->fp32, c->err + 1, st);
-  launch_local_small(c->mats, P.nsubs, c->tiles, c->fp32, c->app, c->sainv, c->sainve, c->aci, c->err + 1, st);
+  if ((rc_ = c->alloc(c->cpp, small))) return rc_;
+  launch_local_small(c->mats, P.nsubs, c->tiles, c->fp32, c->app, c->sainv, c->sainve, c->aci, c->cpp, c->err + 1,
+                     st);
 
   // coarse problem
   const int nc = P.n_coarse;
@@ -479,6 +614,22 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->alloc(c->part_b, VEC_GRID))) return rc_;
   if ((rc_ = c->alloc(c->part_c, VEC_GRID))) return rc_;
   if ((rc_ = c->alloc(c->sc, 1))) return rc_;
+  if ((rc_ = c->alloc(c->ppi, int64_t(P.nsubs) * MAX_NCI))) return rc_;
+  if ((rc_ = c->alloc(c->sploc, P.n_loc))) return rc_;
+  if (c->fp32) {
+    float *v, *q;
+    if ((rc_ = c->alloc(v, P.n_vec))) return rc_;
+    if ((rc_ = c->alloc(q, P.n_vec))) return rc_;
+    c->vloc = v;
+    c->qloc = q;
+  } else {
+    double *v, *q;
+    if ((rc_ = c->alloc(v, P.n_vec))) return rc_;
+    if ((rc_ = c->alloc(q, P.n_vec))) return rc_;
+    c->vloc = v;
+    c->qloc = q;
+  }
+  for (auto& D : P.subs) c->max_loclen = std::max(c->max_loclen, int(D.T * NB + D.n_P));
   if ((rc_ = c->alloc(c->scal, 8))) return rc_;
 
   HIP_TRY(hipGetLastError());
@@ -531,7 +682,8 @@ int bddc_setup(const bddc_mesh* mesh, const bddc_partition* part, const bddc_coe
   if (!opts) return fail(BDDC_EINVAL, "options are NULL");
   if (opts->local_bits != 32 && opts->local_bits != 64) return fail(BDDC_EINVAL, "local_bits must be 32 or 64");
   if (opts->nb_override != 0 && opts->nb_override != NB) return fail(BDDC_ENOTIMPL, "only 64-wide tiles are built");
-  if (opts->flags & ~BDDC_SETUP_KEEP_ON_ERROR) return fail(BDDC_EINVAL, "unknown options.flags bits");
+  if (opts->flags & ~(BDDC_SETUP_KEEP_ON_ERROR | BDDC_SETUP_FULL_SPACE))
+    return fail(BDDC_EINVAL, "unknown options.flags bits");
   bddc_ctx* c = new (std::nothrow) bddc_ctx();
   if (!c) return fail(BDDC_ENOMEM, "host allocation failed");
   std::string err;
@@ -554,6 +706,7 @@ int bddc_setup(const bddc_mesh* mesh, const bddc_partition* part, const bddc_coe
   c->st = static_cast<hipStream_t>(opts->stream);
   c->fp32 = opts->local_bits == 32;
   c->use_graph = opts->use_graph != 0;
+  c->iface = !(opts->flags & BDDC_SETUP_FULL_SPACE);
   c->mesh.dim = c->plan.dim;
   for (int a = 0; a < 3; ++a) {
     c->mesh.nel[a] = int(c->plan.nel[a]);
@@ -612,8 +765,25 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
   hipStream_t st = c->st;
   const int64_t n = P.n_free;
   int* done = &c->sc->done;
-  if (!(flags & BDDC_X0_GIVEN)) enqueue_interior_guess(c, b, x);
-  launch_residual(c->rowptr, c->col, c->val, x, b, c->r, c->part_a, c->part_b, n, st);
+  const bool iface = c->iface;
+  if (iface) {
+    // interface unknowns: x holds the interface part (interior zero) during the
+    // iteration; the residual lives on interface dofs
+    launch_fill<double>(c->z, 0.0, n, st);
+    launch_fill<double>(c->p, 0.0, n, st);
+    launch_fill<double>(c->q, 0.0, n, st);
+    if (flags & BDDC_X0_GIVEN) {
+      launch_zero_interior(c->kappa, x, n, st);
+      enqueue_interior_complete(c, b, x, c->tmp);
+    } else {
+      launch_fill<double>(x, 0.0, n, st);
+      enqueue_interior_guess(c, b, c->tmp);
+    }
+    launch_residual(c->rowptr, c->col, c->val, c->tmp, b, c->r, c->part_a, c->part_b, n, st, c->kappa);
+  } else {
+    if (!(flags & BDDC_X0_GIVEN)) enqueue_interior_guess(c, b, x);
+    launch_residual(c->rowptr, c->col, c->val, x, b, c->r, c->part_a, c->part_b, n, st);
+  }
   launch_pcg_init(c->part_a, c->part_b, c->sc, rtol * rtol, st);
 
   struct HostScalars { double tol2, bb, rr0; int done, iters; } hs{};
@@ -627,20 +797,32 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
   int seg_start = 0;
   for (;;) {
     // (re)start: z = M^{-1} r, rz
-    enqueue_apply(c, c->r, c->z, done);
-    launch_dot(c->r, c->z, c->part_c, n, done, st);
+    if (iface) {
+      enqueue_apply_iface(c, c->r, c->z, c->part_c, done);
+    } else {
+      enqueue_apply(c, c->r, c->z, done);
+      launch_dot(c->r, c->z, c->part_c, n, done, st);
+    }
     while (it < maxit) {
       const int end = std::min(maxit, it + chunk);
       for (; it < end; ++it) {
-        hipEvent_t e = c->begin("spmv");
-        launch_pcg_dir(c->rowptr, c->col, c->val, c->z, c->p, c->q, c->part_c, c->part_a, c->sc, it, fresh ? 1 : 0,
-                       n, st);
-        c->end("spmv", e);
+        if (iface) {
+          enqueue_schur(c, it, fresh, c->part_c, c->part_a);
+        } else {
+          hipEvent_t e = c->begin("spmv");
+          launch_pcg_dir(c->rowptr, c->col, c->val, c->z, c->p, c->q, c->part_c, c->part_a, c->sc, it,
+                         fresh ? 1 : 0, n, st);
+          c->end("spmv", e);
+        }
         fresh = false;
         launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st);
         launch_pcg_check(c->part_b, c->sc, it, st);
-        enqueue_apply(c, c->r, c->z, done);
-        launch_dot(c->r, c->z, c->part_c, n, done, st);
+        if (iface) {
+          enqueue_apply_iface(c, c->r, c->z, c->part_c, done);
+        } else {
+          enqueue_apply(c, c->r, c->z, done);
+          launch_dot(c->r, c->z, c->part_c, n, done, st);
+        }
       }
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipMemcpyAsync(&hs, c->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
@@ -664,7 +846,8 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
     if (iters > 0) HIP_TRY(hipMemcpy(&rr, c->sc->rr + iters - 1, sizeof(double), hipMemcpyDeviceToHost));
     else rr = hs.rr0;
     relres_rec = hs.bb > 0 ? std::sqrt(rr / hs.bb) : 0.0;
-    // true residual
+    // interior values of x (interface form), then the true residual
+    if (iface) enqueue_interior_complete(c, b, x, x);
     launch_residual(c->rowptr, c->col, c->val, x, b, c->tmp, c->part_a, c->part_b, n, st);
     launch_finish_dot(c->part_a, c->scal, st);
     double rr_true = 0.0;
@@ -677,7 +860,12 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
     if (restarts >= 3) { status = BDDC_ENOCONV; break; }
     // residual replacement: r = b - A x, restart the directions
     ++restarts;
-    launch_residual(c->rowptr, c->col, c->val, x, b, c->r, c->part_a, c->part_b, n, st);
+    launch_residual(c->rowptr, c->col, c->val, x, b, c->r, c->part_a, c->part_b, n, st,
+                    iface ? c->kappa : nullptr);
+    if (iface) {
+      launch_zero_interior(c->kappa, x, n, st);
+      launch_fill<double>(c->p, 0.0, n, st);
+    }
     launch_pcg_init(c->part_a, c->part_b, c->sc, rtol * rtol, st);
     // keep the iteration count across the restart
     fresh = true;
@@ -715,7 +903,8 @@ int bddc_set_timing(bddc_ctx* c, int32_t enabled) {
 
 int bddc_kernel_time(bddc_ctx* c, const char* family, int64_t* launches, double* total_ms) {
   if (int rc_ = check_ctx(c)) return rc_;
-  static const char* known[] = {"trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii", "trsv_bwd_ii", "spmv", "apply"};
+  static const char* known[] = {"trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii", "trsv_bwd_ii", "trsv_fwd_g",
+                                "trsv_bwd_g", "mv_t", "mv", "schur", "spmv", "apply"};
   bool ok = false;
   for (const char* k : known) ok |= family && std::strcmp(family, k) == 0;
   if (!ok) return fail(BDDC_EINVAL, "unknown kernel family");

@@ -23,7 +23,9 @@ enum {
   TRSV_FWD_II = 2,  // interior block, rhs = D (r - A v12) on interior rows
   TRSV_BWD_II = 3,  // interior block, z = v12 + D x on interior rows
   TRSV_FWD_C = 4,   // coarse factor, rhs gathered from the subdomain coarse residuals
-  TRSV_BWD_C = 5    // coarse factor, u_c = D x
+  TRSV_BWD_C = 5,   // coarse factor, u_c = D x
+  TRSV_FWD_G = 6,   // trailing interface block L_GG: forward, rhs D W_i R_i r on interface rows
+  TRSV_BWD_G = 7    // trailing interface block: backward with the border coefficients
 };
 
 struct TrsvArgs {
@@ -56,6 +58,21 @@ struct TrsvArgs {
   double* uc;
 };
 
+struct MvArgs {
+  const MatDesc* mats;
+  const void* tiles;
+  const int32_t* tasks;
+  int ntasks;
+  unsigned* ticket;
+  const int* done;
+  const void* xin;      // local input vector (local precision, vec_off layout)
+  void* xout;           // TRANS: local output q
+  const double* ppi;    // corner values of p per subdomain
+  double* part;         // TRANS: partials of W_Pi,G^T q
+  double* sploc;        // non-transposed: (S p)_G per local dof
+  const double* dsc;
+};
+
 struct PcgScalars {
   double tol2;
   double bb;
@@ -83,24 +100,26 @@ void launch_pad_identity(const MatDesc* mats, int nmats, void* tiles, bool fp32,
 void launch_factor(const MatDesc* mats, int nmats, int maxT, int maxTx, void* tiles, void* dinv, bool fp32,
                    int* err, hipStream_t st);
 void launch_local_small(const MatDesc* mats, int nmats, const void* tiles, bool fp32, const double* app,
-                        double* sainv, double* sainve, double* aci, int* err, hipStream_t st);
+                        double* sainv, double* sainve, double* aci, double* cpp, int* err, hipStream_t st);
 void launch_coarse_assembly(const int32_t* src_ptr, const int32_t* src, const int32_t* row, const int32_t* col,
                             const int32_t* diag, int nentries, int nc, const double* aci, double* val, double* dc,
                             double* tiles, int* err, hipStream_t st);
 void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st);
 void launch_coarse_prep(const MatDesc* mats, int nmats, const double* part, const double* sainv,
                         const double* sainve, const int32_t* gmap, const double* wgt, const double* r,
-                        double* gbuf, double* mu, const int* done, hipStream_t st);
+                        double* gbuf, double* mu, const int* done, int iface, hipStream_t st);
 void launch_coarse_coef(const MatDesc* mats, int nmats, const int32_t* rc, const double* uc, const double* mu,
                         const double* sainv, const double* sainve, const double* wgt, double* coef, double* ww,
                         const int* done, hipStream_t st);
 void launch_gather_v12(const int32_t* inv_ptr, const int32_t* inv, const double* ww, const uint8_t* kappa,
                        double* v12, double* z, int64_t n, const int* done, hipStream_t st);
 void launch_zero_interface(const uint8_t* kappa, double* x, int64_t n, hipStream_t st);
+void launch_zero_interior(const uint8_t* kappa, double* x, int64_t n, hipStream_t st);
 void launch_spmv(const int32_t* rowptr, const int32_t* col, const double* val, const double* x, double* y, int64_t n,
                  hipStream_t st);
 void launch_residual(const int32_t* rowptr, const int32_t* col, const double* val, const double* x, const double* b,
-                     double* r, double* part_rr, double* part_bb, int64_t n, hipStream_t st);
+                     double* r, double* part_rr, double* part_bb, int64_t n, hipStream_t st,
+                     const uint8_t* iface_only = nullptr);
 void launch_pcg_init(const double* part_rr, const double* part_bb, PcgScalars* sc, double rtol2, hipStream_t st);
 void launch_pcg_dir(const int32_t* rowptr, const int32_t* col, const double* val, const double* z, double* p,
                     double* q, const double* part_rz, double* part_pq, PcgScalars* sc, int it, int fresh, int64_t n,
@@ -114,5 +133,19 @@ void launch_elem_grad(const MeshDevHost& m, const double* lam, const double* u, 
                       hipStream_t st);
 
 constexpr int VEC_GRID = 1024;   // partial-sum count of the vector kernels
+
+void launch_reset(bool fp32, void* pub, int64_t n_pub, double* pubc, int64_t n_pubc, unsigned* tickets,
+                  const int* done, hipStream_t st);
+void launch_iface_local(const MatDesc* mats, int nmats, int max_len, const int32_t* gmap, const double* dsc,
+                        const double* z, const double* p, const double* part_rz, const PcgScalars* sc, int it,
+                        int fresh, void* vloc, bool fp32, double* ppi, hipStream_t st);
+void launch_tile_mv(bool trans, bool fp32, const MvArgs& a, int grid, hipStream_t st);
+void launch_corner_sp(const MatDesc* mats, int nmats, const double* part, const double* cpp, const double* ppi,
+                      double* sploc, const int* done, hipStream_t st);
+void launch_gather_sp(const int32_t* inv_ptr, const int32_t* inv, const double* sploc, const uint8_t* kappa,
+                      const double* z, double* p, double* q, const double* part_rz, double* part_pq, PcgScalars* sc,
+                      int it, int fresh, int64_t n, hipStream_t st);
+void launch_gather_z(const int32_t* inv_ptr, const int32_t* inv, const double* ww, const uint8_t* kappa,
+                     const double* r, double* z, double* part_rz, int64_t n, const int* done, hipStream_t st);
 
 }  // namespace bddc

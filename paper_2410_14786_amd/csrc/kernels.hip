@@ -545,7 +545,7 @@ void launch_factor(const MatDesc* mats, int nmats, int maxT, int maxTx, void* ti
 template <typename T>
 __global__ __launch_bounds__(256) void local_small_kernel(const MatDesc* mats, const T* tiles,
                                                           const double* app, double* sainv, double* sainve,
-                                                          double* aci, int* err) {
+                                                          double* aci, double* cpp, int* err) {
   const int s = blockIdx.x;
   const MatDesc D = mats[s];
   const int nA = D.n_A, nP = D.n_P, nc = D.n_ci;
@@ -602,8 +602,10 @@ __global__ __launch_bounds__(256) void local_small_kernel(const MatDesc* mats, c
   double* se = sainve + int64_t(s) * MAX_NCI * MAX_NCI;
   double* ao = aci + int64_t(s) * MAX_NCI * MAX_NCI;
   const double* ap = app + int64_t(s) * MAX_NCI * MAX_NCI;
+  double* co = cpp + int64_t(s) * MAX_NCI * MAX_NCI;
   for (int i = tid; i < MAX_NCI * MAX_NCI; i += 256) {
     int r = i / MAX_NCI, c = i % MAX_NCI;
+    co[i] = (r < nP && c < nP) ? ap[i] - G[(nA + r) * MAX_NCI + nA + c] : 0.0;
     so[i] = (r < nA && c < nA) ? X[r * MAX_NCI + c] : 0.0;
     se[i] = (r < nA && c < nP) ? X[r * MAX_NCI + nA + c] : 0.0;
     double v = 0.0;
@@ -624,13 +626,13 @@ __global__ __launch_bounds__(256) void local_small_kernel(const MatDesc* mats, c
 }
 
 void launch_local_small(const MatDesc* mats, int nmats, const void* tiles, bool fp32, const double* app,
-                        double* sainv, double* sainve, double* aci, int* err, hipStream_t st) {
+                        double* sainv, double* sainve, double* aci, double* cpp, int* err, hipStream_t st) {
   if (fp32)
     hipLaunchKernelGGL(local_small_kernel<float>, dim3(nmats), dim3(256), 0, st, mats, (const float*)tiles, app,
-                       sainv, sainve, aci, err);
+                       sainv, sainve, aci, cpp, err);
   else
     hipLaunchKernelGGL(local_small_kernel<double>, dim3(nmats), dim3(256), 0, st, mats, (const double*)tiles,
-                       app, sainv, sainve, aci, err);
+                       app, sainv, sainve, aci, cpp, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -688,7 +690,8 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
   constexpr int LPR = NB / VEC;      // lanes per tile row
   constexpr int RPI = 64 / LPR;      // tile rows per wave instruction
   constexpr int NI = 16 / RPI;       // instructions per 16-row slab
-  constexpr bool FWD = (MODE == TRSV_FWD_RR || MODE == TRSV_FWD_II || MODE == TRSV_FWD_C);
+  constexpr bool FWD = (MODE == TRSV_FWD_RR || MODE == TRSV_FWD_II || MODE == TRSV_FWD_C || MODE == TRSV_FWD_G);
+  constexpr bool IFACE = (MODE == TRSV_FWD_G || MODE == TRSV_BWD_G);
 
   __shared__ T s_rhs[NB];
   __shared__ T s_v[NB];
@@ -714,6 +717,10 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     const MatDesc D = A.mats[s];
     const int T_rows = (MODE == TRSV_FWD_II || MODE == TRSV_BWD_II) ? D.TI : D.T;
     const int nlim = (MODE == TRSV_FWD_II || MODE == TRSV_BWD_II) ? D.n_I : D.n_R;
+    // interface modes work on the trailing block of rows n_I..n_R-1 (L_GG); the
+    // interior rows of the straddling tile are held at zero
+    const int nlo = IFACE ? D.n_I : 0;
+    const int j0 = IFACE ? D.n_I / NB : 0;
     const int64_t tbase = D.tile_off;
     T* my_sol = sol + D.vec_off;
 
@@ -721,8 +728,8 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     if (tid < NB) {
       const int a = k * NB + tid;
       double rhs = 0.0;
-      if (a < nlim) {
-        if (MODE == TRSV_FWD_RR) {
+      if (a >= nlo && a < nlim) {
+        if (MODE == TRSV_FWD_RR || MODE == TRSV_FWD_G) {
           const int64_t l = D.loc_off + a;
           rhs = A.wd[l] * A.rin[A.gmap[l]];
         } else if (MODE == TRSV_FWD_II) {
@@ -743,7 +750,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
       }
       s_rhs[tid] = T(rhs);
     }
-    if (MODE == TRSV_BWD_RR && D.n_ci > 0) {
+    if ((MODE == TRSV_BWD_RR || MODE == TRSV_BWD_G) && D.n_ci > 0) {
       // rhs_k += W_k coef, W_k^T stored in the bordering tile row (rows = constraints)
       __syncthreads();
       const T* bt = tiles + (tbase + tri_tile(D.T, k)) * int64_t(NB * NB);
@@ -751,21 +758,21 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
       if (tid < NB) {
         double v = 0.0;
         for (int c = 0; c < D.n_ci; ++c) v += double(bt[c * NB + tid]) * cf[c];
-        if (k * NB + tid < nlim) s_rhs[tid] += T(v);
+        if (k * NB + tid >= nlo && k * NB + tid < nlim) s_rhs[tid] += T(v);
       }
     }
 
     // ---------------- main loop over off-diagonal tiles ----------------
     T acc[FWD ? NI : VEC];
     for (int i = 0; i < (FWD ? NI : VEC); ++i) acc[i] = T(0);
-    const int nt = FWD ? k : (T_rows - 1 - k);
+    const int nt = FWD ? k - j0 : (T_rows - 1 - k);
     if (nt > 0) {
       auto tile_ptr = [&](int jj) -> const T* {
-        // forward: tile (k, jj) for jj = 0..k-1; backward: tile (j, k) for j = T_rows-1 .. k+1
-        int64_t t = FWD ? tri_tile(k, jj) : tri_tile(T_rows - 1 - jj, k);
+        // forward: tile (k, j0 + jj), jj = 0..k-j0-1; backward: tile (j, k), j = T_rows-1 .. k+1
+        int64_t t = FWD ? tri_tile(k, j0 + jj) : tri_tile(T_rows - 1 - jj, k);
         return tiles + (tbase + t) * int64_t(NB * NB) + (16 * w + lr) * NB + VEC * lc;
       };
-      auto sol_row = [&](int jj) -> int { return FWD ? jj : (T_rows - 1 - jj); };
+      auto sol_row = [&](int jj) -> int { return FWD ? j0 + jj : (T_rows - 1 - jj); };
       V cur[NI], nxt[NI];
       {
         const T* p = tile_ptr(0);
@@ -810,7 +817,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     __syncthreads();
     if (tid < NB) {
       T red = FWD ? s_red[0][tid] : (s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid]);
-      s_v[tid] = (k * NB + tid < nlim) ? (s_rhs[tid] - red) : T(0);
+      s_v[tid] = (k * NB + tid >= nlo && k * NB + tid < nlim) ? (s_rhs[tid] - red) : T(0);
     }
     __syncthreads();
 
@@ -840,7 +847,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
       __syncthreads();
       if (tid < NB) {
         T o = FWD ? s_red[0][tid] : (s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid]);
-        if (k * NB + tid >= nlim) o = T(0);
+        if (k * NB + tid >= nlim || k * NB + tid < nlo) o = T(0);
         s_out[tid] = o;
         store_published(my_sol + k * NB + tid, o);
       }
@@ -848,7 +855,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     __syncthreads();
 
     // ---------------- epilogue ----------------
-    if (MODE == TRSV_FWD_RR && D.n_ci > 0) {
+    if ((MODE == TRSV_FWD_RR || MODE == TRSV_FWD_G) && D.n_ci > 0) {
       // partial border products h_c = sum_r W^T[c][r] y_k[r] for this tile row
       const T* bt = tiles + (tbase + tri_tile(D.T, k)) * int64_t(NB * NB);
       if (tid < D.n_ci) {
@@ -856,10 +863,10 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
         for (int r = 0; r < NB; ++r) v += double(bt[tid * NB + r]) * double(s_out[r]);
         A.part[(D.vec_off / NB + k) * MAX_NCI + tid] = v;
       }
-    } else if (MODE == TRSV_BWD_RR) {
+    } else if (MODE == TRSV_BWD_RR || MODE == TRSV_BWD_G) {
       if (tid < NB) {
         const int a = k * NB + tid;
-        if (a < D.n_R) {
+        if (a >= nlo && a < D.n_R) {
           const int64_t l = D.loc_off + a;
           A.ww[l] = A.wd[l] * double(s_out[tid]);
         }
@@ -892,6 +899,8 @@ static void launch_trsv_t(int mode, const TrsvArgs& a, int grid, hipStream_t st)
     case TRSV_BWD_II: hipLaunchKernelGGL((trsv_kernel<T, TRSV_BWD_II>), dim3(grid), dim3(256), 0, st, a); break;
     case TRSV_FWD_C: hipLaunchKernelGGL((trsv_kernel<T, TRSV_FWD_C>), dim3(grid), dim3(256), 0, st, a); break;
     case TRSV_BWD_C: hipLaunchKernelGGL((trsv_kernel<T, TRSV_BWD_C>), dim3(grid), dim3(256), 0, st, a); break;
+    case TRSV_FWD_G: hipLaunchKernelGGL((trsv_kernel<T, TRSV_FWD_G>), dim3(grid), dim3(256), 0, st, a); break;
+    case TRSV_BWD_G: hipLaunchKernelGGL((trsv_kernel<T, TRSV_BWD_G>), dim3(grid), dim3(256), 0, st, a); break;
   }
 }
 
@@ -913,7 +922,7 @@ void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t s
 __global__ __launch_bounds__(64) void coarse_prep_kernel(const MatDesc* mats, const double* part,
                                                          const double* sainv, const double* sainve,
                                                          const int32_t* gmap, const double* wgt, const double* r,
-                                                         double* gbuf, double* mu, const int* done) {
+                                                         double* gbuf, double* mu, const int* done, int iface) {
   if (done && *done) return;
   const int s = blockIdx.x;
   const MatDesc D = mats[s];
@@ -923,7 +932,7 @@ __global__ __launch_bounds__(64) void coarse_prep_kernel(const MatDesc* mats, co
   if (tid < D.n_ci) {
     double v = 0.0;
     const int64_t base = (D.vec_off / NB) * MAX_NCI;
-    for (int k = 0; k < D.T; ++k) v += part[base + int64_t(k) * MAX_NCI + tid];
+    for (int k = iface ? D.n_I / NB : 0; k < D.T; ++k) v += part[base + int64_t(k) * MAX_NCI + tid];
     h[tid] = v;
   }
   __syncthreads();
@@ -981,9 +990,9 @@ __global__ __launch_bounds__(64) void coarse_coef_kernel(const MatDesc* mats, co
 
 void launch_coarse_prep(const MatDesc* mats, int nmats, const double* part, const double* sainv,
                         const double* sainve, const int32_t* gmap, const double* wgt, const double* r,
-                        double* gbuf, double* mu, const int* done, hipStream_t st) {
+                        double* gbuf, double* mu, const int* done, int iface, hipStream_t st) {
   hipLaunchKernelGGL(coarse_prep_kernel, dim3(nmats), dim3(64), 0, st, mats, part, sainv, sainve, gmap, wgt, r,
-                     gbuf, mu, done);
+                     gbuf, mu, done, iface);
 }
 
 void launch_coarse_coef(const MatDesc* mats, int nmats, const int32_t* rc, const double* uc, const double* mu,
@@ -1016,6 +1025,15 @@ void launch_gather_v12(const int32_t* inv_ptr, const int32_t* inv, const double*
 __global__ void zero_interface_kernel(const uint8_t* kappa, double* x, int64_t n) {
   for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x)
     if (kappa[g] > 1) x[g] = 0.0;
+}
+
+__global__ void zero_interior_kernel(const uint8_t* kappa, double* x, int64_t n) {
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x)
+    if (kappa[g] < 2) x[g] = 0.0;
+}
+
+void launch_zero_interior(const uint8_t* kappa, double* x, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_interior_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, kappa, x, n);
 }
 
 void launch_zero_interface(const uint8_t* kappa, double* x, int64_t n, hipStream_t st) {
@@ -1079,7 +1097,8 @@ void launch_spmv(const int32_t* rowptr, const int32_t* col, const double* val, c
 // r = b - A x, partial sums of r.r and b.b
 __global__ __launch_bounds__(VBLK) void residual_kernel(const int32_t* rowptr, const int32_t* col,
                                                         const double* val, const double* x, const double* b,
-                                                        double* r, double* part_rr, double* part_bb, int64_t n) {
+                                                        double* r, double* part_rr, double* part_bb, int64_t n,
+                                                        const uint8_t* iface_only) {
   __shared__ double sh[VBLK / 64];
   const int sl = threadIdx.x & 31;
   const int64_t hw = (blockIdx.x * int64_t(VBLK) + threadIdx.x) >> 5;
@@ -1088,7 +1107,7 @@ __global__ __launch_bounds__(VBLK) void residual_kernel(const int32_t* rowptr, c
   for (int64_t row = hw; row < n; row += nhw) {
     double v = row_dot(rowptr, col, val, x, row, sl);
     if (sl == 0) {
-      double rv = b[row] - v;
+      double rv = (iface_only && iface_only[row] < 2) ? 0.0 : b[row] - v;
       r[row] = rv;
       rr += rv * rv;
       bb += b[row] * b[row];
@@ -1103,9 +1122,10 @@ __global__ __launch_bounds__(VBLK) void residual_kernel(const int32_t* rowptr, c
 }
 
 void launch_residual(const int32_t* rowptr, const int32_t* col, const double* val, const double* x, const double* b,
-                     double* r, double* part_rr, double* part_bb, int64_t n, hipStream_t st) {
+                     double* r, double* part_rr, double* part_bb, int64_t n, hipStream_t st,
+                     const uint8_t* iface_only) {
   hipLaunchKernelGGL(residual_kernel, dim3(VGRID), dim3(VBLK), 0, st, rowptr, col, val, x, b, r, part_rr, part_bb,
-                     n);
+                     n, iface_only);
 }
 
 // scalars: per-iteration slots (rz[it], pq[it], rr[it], alpha[it], beta[it])
@@ -1241,6 +1261,277 @@ void launch_dot(const double* a, const double* b, double* part, int64_t n, const
 }
 void launch_finish_dot(const double* part, double* out, hipStream_t st) {
   hipLaunchKernelGGL(finish_dot_kernel, dim3(1), dim3(VBLK), 0, st, part, out);
+}
+
+// ---------------------------------------------------------------------------
+// Interface (Schur-complement) operator S_i = A_BB - A_BI A_II^{-1} A_IB
+// ---------------------------------------------------------------------------
+// With B = interface (G = non-corner, Pi = corners) and the bordered factor of
+// the equilibrated A_RR (interior first), the trailing block L_GG is
+// chol(D_G S_GG D_G) and the border rows give W_Pi = L^{-1} D A_RPi, so
+//   (S p)_G  = D^{-1} L_GG q,  q = L_GG^T D^{-1} p_G + W_Pi,G p_Pi
+//   (S p)_Pi = W_Pi,G^T q + (A_PiPi - W_Pi^T W_Pi) p_Pi
+// (the last matrix is stored per subdomain at setup).  q and L_GG q are plain
+// triangular mat-vecs: every tile row is independent.
+
+// direction p = z + beta p (beta from the r.z partials) gathered into the local
+// vectors: v = D^{-1} p on non-corner interface rows (zero elsewhere), p on corners
+__global__ __launch_bounds__(VBLK) void iface_local_kernel(const MatDesc* mats, const int32_t* gmap, const double* dsc, const double* z,
+                                   const double* p, const double* part_rz, const PcgScalars* sc, int it, int fresh,
+                                   void* vloc, bool fp32, double* ppi) {
+  __shared__ double sh[VBLK / 64];
+  if (sc->done) return;
+  double beta = 0.0;
+  if (!fresh) beta = reduce_partials(part_rz, VGRID, sh) / sc->rz[it - 1];   // same bits as gather_sp
+  const MatDesc D = mats[blockIdx.y];
+  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < D.T * NB + D.n_P; a += gridDim.x * blockDim.x) {
+    if (a < D.T * NB) {
+      double v = 0.0;
+      if (a >= D.n_I && a < D.n_R) {
+        const int64_t l = D.loc_off + a;
+        const int g = gmap[l];
+        v = (fresh ? z[g] : z[g] + beta * p[g]) / dsc[l];
+      }
+      if (fp32) static_cast<float*>(vloc)[D.vec_off + a] = float(v);
+      else static_cast<double*>(vloc)[D.vec_off + a] = v;
+    } else {
+      const int c = a - D.T * NB;
+      const int g = gmap[D.loc_off + D.n_R + c];
+      ppi[int64_t(blockIdx.y) * MAX_NCI + c] = fresh ? z[g] : z[g] + beta * p[g];
+    }
+  }
+}
+
+// TRANS: q_k = sum_{j >= k} L_jk^T v_j + W_Pi,k p_Pi, plus partials of W_Pi,G^T q.
+// Otherwise: y_k = sum_{j0 <= j <= k} L_kj q_j, written as (S p)_G = D^{-1} y.
+template <typename T, bool TRANS>
+__global__ __launch_bounds__(256) void tile_mv_kernel(MvArgs A) {
+  using V = typename Traits<T>::V;
+  constexpr int VEC = Traits<T>::VEC;
+  constexpr int LPR = NB / VEC;
+  constexpr int RPI = 64 / LPR;
+  constexpr int NI = 16 / RPI;
+  __shared__ T s_red[4][NB];
+  __shared__ T s_out[NB];
+  __shared__ int s_task;
+  if (A.done && *A.done) return;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int lr = lane / LPR, lc = lane % LPR;
+  const T* tiles = reinterpret_cast<const T*>(A.tiles);
+  const T* xin = reinterpret_cast<const T*>(A.xin);
+  for (;;) {
+    if (tid == 0) s_task = atomicAdd(A.ticket, 1u);
+    __syncthreads();
+    const int task = s_task;
+    __syncthreads();
+    if (task >= A.ntasks) return;
+    const int s = A.tasks[2 * task], k = A.tasks[2 * task + 1];
+    const MatDesc D = A.mats[s];
+    const int j0 = D.n_I / NB;
+    const int64_t tbase = D.tile_off;
+    const T* x = xin + D.vec_off;
+    T acc[TRANS ? VEC : NI];
+    for (int i = 0; i < (TRANS ? VEC : NI); ++i) acc[i] = T(0);
+    // TRANS: tiles (j, k), j = k .. T-1;  otherwise tiles (k, j), j = j0 .. k
+    const int nt = TRANS ? D.T - k : k - j0 + 1;
+    auto tile_ptr = [&](int jj) -> const T* {
+      int64_t t = TRANS ? tri_tile(k + jj, k) : tri_tile(k, j0 + jj);
+      return tiles + (tbase + t) * int64_t(NB * NB) + (16 * w + lr) * NB + VEC * lc;
+    };
+    V cur[NI], nxt[NI];
+    {
+      const T* pp = tile_ptr(0);
+      for (int i = 0; i < NI; ++i) cur[i] = *reinterpret_cast<const V*>(pp + i * RPI * NB);
+    }
+    for (int jj = 0; jj < nt; ++jj) {
+      const T* xs = x + (TRANS ? k + jj : j0 + jj) * NB;
+      T xv[TRANS ? NI : VEC];
+      if (TRANS) {
+        for (int i = 0; i < NI; ++i) xv[i] = xs[16 * w + RPI * i + lr];
+      } else {
+        for (int e = 0; e < VEC; ++e) xv[e] = xs[VEC * lc + e];
+      }
+      if (jj + 1 < nt) {
+        const T* pp = tile_ptr(jj + 1);
+        for (int i = 0; i < NI; ++i) nxt[i] = *reinterpret_cast<const V*>(pp + i * RPI * NB);
+      }
+      if (TRANS) {
+        for (int i = 0; i < NI; ++i)
+          for (int e = 0; e < VEC; ++e) acc[e] += cur[i][e] * xv[i];
+      } else {
+        for (int i = 0; i < NI; ++i)
+          for (int e = 0; e < VEC; ++e) acc[i] += cur[i][e] * xv[e];
+      }
+      for (int i = 0; i < NI; ++i) cur[i] = nxt[i];
+    }
+    if (TRANS) {
+      for (int e = 0; e < VEC; ++e) {
+        T v = acc[e];
+        for (int off = LPR; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+        if (lr == 0) s_red[w][VEC * lc + e] = v;
+      }
+    } else {
+      for (int i = 0; i < NI; ++i) {
+        T v = acc[i];
+        for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lc == 0) s_red[0][16 * w + RPI * i + lr] = v;
+      }
+    }
+    __syncthreads();
+    const int a = k * NB + tid;
+    const bool live = tid < NB && a >= D.n_I && a < D.n_R;
+    if (TRANS) {
+      const T* bt = tiles + (tbase + tri_tile(D.T, k)) * int64_t(NB * NB);
+      if (tid < NB) {
+        double v = double(s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid]);
+        if (live && D.n_P > 0) {
+          const double* pp = A.ppi + int64_t(s) * MAX_NCI;
+          for (int c = 0; c < D.n_P; ++c) v += double(bt[(D.n_A + c) * NB + tid]) * pp[c];
+        }
+        const T o = live ? T(v) : T(0);
+        s_out[tid] = o;
+        reinterpret_cast<T*>(A.xout)[D.vec_off + a] = o;
+      }
+      __syncthreads();
+      if (tid < D.n_P) {
+        double v = 0.0;
+        for (int r = 0; r < NB; ++r) v += double(bt[(D.n_A + tid) * NB + r]) * double(s_out[r]);
+        A.part[(D.vec_off / NB + k) * MAX_NCI + tid] = v;
+      }
+    } else if (live) {
+      const int64_t l = D.loc_off + a;
+      A.sploc[l] = double(s_red[0][tid]) / A.dsc[l];
+    }
+    __syncthreads();
+  }
+}
+
+// corners: (S p)_Pi = sum_k partials + (A_PiPi - W_Pi^T W_Pi) p_Pi
+__global__ __launch_bounds__(64) void corner_sp_kernel(const MatDesc* mats, const double* part, const double* cpp,
+                                                       const double* ppi, double* sploc, const int* done) {
+  if (done && *done) return;
+  const int s = blockIdx.x;
+  const MatDesc D = mats[s];
+  const int c = threadIdx.x;
+  if (c >= D.n_P) return;
+  double v = 0.0;
+  const int64_t base = (D.vec_off / NB) * MAX_NCI;
+  for (int k = D.n_I / NB; k < D.T; ++k) v += part[base + int64_t(k) * MAX_NCI + c];
+  const double* m = cpp + int64_t(s) * MAX_NCI * MAX_NCI;
+  const double* pp = ppi + int64_t(s) * MAX_NCI;
+  for (int q = 0; q < D.n_P; ++q) v += m[c * MAX_NCI + q] * pp[q];
+  sploc[D.loc_off + D.n_R + c] = v;
+}
+
+// q = sum_i R_i^T S_i p_i on interface dofs; p = z + beta p; partial sums of p.q;
+// block 0 records rz[it] (and beta[it-1])
+__global__ __launch_bounds__(VBLK) void gather_sp_kernel(const int32_t* inv_ptr, const int32_t* inv,
+                                                         const double* sploc, const uint8_t* kappa, const double* z,
+                                                         double* p, double* q, const double* part_rz,
+                                                         double* part_pq, PcgScalars* sc, int it, int fresh,
+                                                         int64_t n) {
+  __shared__ double sh[VBLK / 64];
+  if (sc->done) return;
+  const double rz = reduce_partials(part_rz, VEC_GRID, sh);
+  const double beta = fresh ? 0.0 : rz / sc->rz[it - 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rz[it] = rz;
+    if (!fresh) sc->beta[it - 1] = beta;
+  }
+  double pq = 0.0;
+  for (int64_t g = blockIdx.x * int64_t(VBLK) + threadIdx.x; g < n; g += int64_t(gridDim.x) * VBLK) {
+    if (kappa[g] < 2) continue;
+    double v = 0.0;
+    for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) v += sploc[inv[j]];
+    const double pv = fresh ? z[g] : z[g] + beta * p[g];
+    p[g] = pv;
+    q[g] = v;
+    pq += pv * v;
+  }
+  const double t = block_sum(pq, sh);
+  if (threadIdx.x == 0) part_pq[blockIdx.x] = t;
+}
+
+// interface preconditioner output: z = sum_i R_i^T W_i w_i on interface dofs,
+// partial sums of r.z
+__global__ __launch_bounds__(VBLK) void gather_z_kernel(const int32_t* inv_ptr, const int32_t* inv, const double* ww,
+                                                        const uint8_t* kappa, const double* r, double* z,
+                                                        double* part_rz, int64_t n, const int* done) {
+  __shared__ double sh[VBLK / 64];
+  if (done && *done) return;
+  double rz = 0.0;
+  for (int64_t g = blockIdx.x * int64_t(VBLK) + threadIdx.x; g < n; g += int64_t(gridDim.x) * VBLK) {
+    if (kappa[g] < 2) continue;
+    double v = 0.0;
+    for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) v += ww[inv[j]];
+    z[g] = v;
+    rz += r[g] * v;
+  }
+  const double t = block_sum(rz, sh);
+  if (threadIdx.x == 0) part_rz[blockIdx.x] = t;
+}
+
+// sentinel fill of the published buffers and zero tickets, one launch
+template <typename T>
+__global__ void reset_kernel(T* pub, int64_t n_pub, double* pubc, int64_t n_pubc, unsigned* tickets,
+                             const int* done) {
+  if (done && *done) return;
+  using U = typename Traits<T>::U;
+  U* q = reinterpret_cast<U*>(pub);
+  unsigned long long* qc = reinterpret_cast<unsigned long long*>(pubc);
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t i0 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  for (int64_t i = i0; i < n_pub; i += stride) q[i] = Traits<T>::SENT;
+  for (int64_t i = i0; i < n_pubc; i += stride) qc[i] = Traits<double>::SENT;
+  if (i0 < 8) tickets[i0] = 0u;
+}
+
+void launch_reset(bool fp32, void* pub, int64_t n_pub, double* pubc, int64_t n_pubc, unsigned* tickets,
+                  const int* done, hipStream_t st) {
+  const int g = grid_for(n_pub > n_pubc ? n_pub : n_pubc, 256, 2048);
+  if (fp32)
+    hipLaunchKernelGGL(reset_kernel<float>, dim3(g), dim3(256), 0, st, (float*)pub, n_pub, pubc, n_pubc, tickets,
+                       done);
+  else
+    hipLaunchKernelGGL(reset_kernel<double>, dim3(g), dim3(256), 0, st, (double*)pub, n_pub, pubc, n_pubc, tickets,
+                       done);
+}
+
+void launch_iface_local(const MatDesc* mats, int nmats, int max_len, const int32_t* gmap, const double* dsc,
+                        const double* z, const double* p, const double* part_rz, const PcgScalars* sc, int it,
+                        int fresh, void* vloc, bool fp32, double* ppi, hipStream_t st) {
+  dim3 grid((max_len + VBLK - 1) / VBLK, nmats);
+  hipLaunchKernelGGL(iface_local_kernel, grid, dim3(VBLK), 0, st, mats, gmap, dsc, z, p, part_rz, sc, it, fresh, vloc,
+                     fp32, ppi);
+}
+
+void launch_tile_mv(bool trans, bool fp32, const MvArgs& a, int grid, hipStream_t st) {
+  if (a.ntasks <= 0) return;
+  if (fp32) {
+    if (trans) hipLaunchKernelGGL((tile_mv_kernel<float, true>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((tile_mv_kernel<float, false>), dim3(grid), dim3(256), 0, st, a);
+  } else {
+    if (trans) hipLaunchKernelGGL((tile_mv_kernel<double, true>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((tile_mv_kernel<double, false>), dim3(grid), dim3(256), 0, st, a);
+  }
+}
+
+void launch_corner_sp(const MatDesc* mats, int nmats, const double* part, const double* cpp, const double* ppi,
+                      double* sploc, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(corner_sp_kernel, dim3(nmats), dim3(64), 0, st, mats, part, cpp, ppi, sploc, done);
+}
+
+void launch_gather_sp(const int32_t* inv_ptr, const int32_t* inv, const double* sploc, const uint8_t* kappa,
+                      const double* z, double* p, double* q, const double* part_rz, double* part_pq, PcgScalars* sc,
+                      int it, int fresh, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(gather_sp_kernel, dim3(VEC_GRID), dim3(VBLK), 0, st, inv_ptr, inv, sploc, kappa, z, p, q,
+                     part_rz, part_pq, sc, it, fresh, n);
+}
+
+void launch_gather_z(const int32_t* inv_ptr, const int32_t* inv, const double* ww, const uint8_t* kappa,
+                     const double* r, double* z, double* part_rz, int64_t n, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(gather_z_kernel, dim3(VEC_GRID), dim3(VBLK), 0, st, inv_ptr, inv, ww, kappa, r, z, part_rz, n,
+                     done);
 }
 
 // ---------------------------------------------------------------------------

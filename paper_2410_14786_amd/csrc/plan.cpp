@@ -360,6 +360,22 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
   make_tasks(P.bwd_rr, false, true);
   make_tasks(P.fwd_ii, true, false);
   make_tasks(P.bwd_ii, true, true);
+  // interface (trailing) block: tile rows n_I/NB .. T-1
+  {
+    int maxG = 0;
+    for (auto& D : P.subs) maxG = std::max(maxG, int(D.T - D.n_I / NB));
+    for (int d = 0; d < maxG; ++d)
+      for (int s = 0; s < P.nsubs; ++s) {
+        const MatDesc& D = P.subs[s];
+        const int k0 = D.n_I / NB;
+        if (d < D.T - k0) {
+          P.fwd_g.push_back(s);
+          P.fwd_g.push_back(k0 + d);
+          P.bwd_g.push_back(s);
+          P.bwd_g.push_back(D.T - 1 - d);
+        }
+      }
+  }
   return BDDC_OK;
 }
 

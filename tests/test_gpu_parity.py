@@ -102,12 +102,15 @@ def test_spmv_parity(name):
     S.close()
 
 
-@pytest.mark.parametrize("name", ["2d_64_4x4_theta1", "3d_12x10x14_uneven", "3d_24_3x3x3_inclusions"])
-def test_pcg_iterates_match_oracle(name):
-    """Same number K of iterations from the same x0 = P_I b: iterates agree."""
+@pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
+@pytest.mark.parametrize("name", ["2d_64_4x4_theta1", "3d_12x10x14_uneven", "3d_24_3x3x3_inclusions",
+                                  "2d_20x24_uneven", "3d_8_corners_only"])
+def test_pcg_iterates_match_oracle(name, full_space):
+    """Same number K of iterations from the same x0 = P_I b: iterates agree, for
+    the CG run on the whole space and the one restricted to interface dofs."""
     w, P = oracle_for(name)
     ref = O.bddc_pcg(P, w.b, w.rtol)
-    S = bd().solver_for(w)
+    S = bd().solver_for(w, full_space=full_space)
     K = max(ref.iters - 2, 1)
     refK = O.bddc_pcg(P, w.b, 1e-300, maxit=K)
     xK, info = S.solve(dev(w.b), 1e-15, maxit=K, raise_on_noconv=False)
@@ -124,20 +127,22 @@ def test_pcg_iterates_match_oracle(name):
     S.close()
 
 
+@pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
 @pytest.mark.parametrize("name", ["2d_20x24_uneven", "3d_16_2x2x2"])
-def test_solution_matches_sparse_direct(name):
+def test_solution_matches_sparse_direct(name, full_space):
     import scipy.sparse.linalg as spla
     w, P = oracle_for(name)
-    S = bd().solver_for(w)
+    S = bd().solver_for(w, full_space=full_space)
     x, info = S.solve(dev(w.b), 1e-13)
     xs = spla.spsolve(P.A.tocsc(), w.b)
     assert rel(host(x), xs) <= 1e-10
     S.close()
 
 
-def test_single_subdomain_is_direct():
+@pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
+def test_single_subdomain_is_direct(full_space):
     w = W.make_workload("t", 3, (9, 10, 11), (1, 1, 1), theta="lognormal", seed=9)
-    S = bd().solver_for(w)
+    S = bd().solver_for(w, full_space=full_space)
     assert S.n_coarse == 0
     x, info = S.solve(dev(w.b), 1e-12)
     P = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints)
@@ -147,9 +152,10 @@ def test_single_subdomain_is_direct():
     S.close()
 
 
-def test_all_primal_converges_in_one_iteration():
+@pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
+def test_all_primal_converges_in_one_iteration(full_space):
     w = W.make_workload("t", 2, (8, 8), (2, 2), theta="lognormal", constraints=W.ALL_PRIMAL, seed=10)
-    S = bd().solver_for(w)
+    S = bd().solver_for(w, full_space=full_space)
     x, info = S.solve(dev(w.b), 1e-12)
     assert info["iters"] == 1
     S.close()
@@ -167,20 +173,22 @@ def test_apply_and_solve_are_deterministic():
     S.close()
 
 
-def test_warm_start_flag():
+@pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
+def test_warm_start_flag(full_space):
     w, P = oracle_for("3d_12x10x14_uneven")
-    S = bd().solver_for(w)
+    S = bd().solver_for(w, full_space=full_space)
     x, info = S.solve(dev(w.b), 1e-10)
     x2, info2 = S.solve(dev(w.b), 1e-10, x0=x)
     assert info2["iters"] <= 1 and info2["relres_true"] <= 1e-10
     S.close()
 
 
+@pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
 @pytest.mark.parametrize("name", ["3d_16_2x2x2", "3d_24_3x3x3_inclusions", "2d_20x24_uneven"])
-def test_fp32_local_reaches_true_residual(name):
+def test_fp32_local_reaches_true_residual(name, full_space):
     w, P = oracle_for(name)
     ref = O.bddc_pcg(P, w.b, 1e-12)
-    S = bd().solver_for(w, local_bits=32)
+    S = bd().solver_for(w, local_bits=32, full_space=full_space)
     x, info = S.solve(dev(w.b), 1e-8)
     e = rel(host(x), ref.x)
     say(name, "fp32-local iters", info["iters"], "relres_true", info["relres_true"], "err vs oracle", e)
