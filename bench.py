@@ -115,7 +115,7 @@ def load_traffic(kernel, workload, local_bits):
 def run_gpu(w, steps, warmup, local_bits, use_graph=False, full_space=False):
     import torch
     from paper_2410_14786_amd import bddc
-    families = FULL_FAMILIES if full_space else IFACE_FAMILIES
+    families = FULL_FAMILIES if (full_space or local_bits == 32) else IFACE_FAMILIES
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S = bddc.solver_for(w, local_bits=local_bits, use_graph=use_graph, full_space=full_space)

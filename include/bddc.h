@@ -74,7 +74,10 @@ enum { BDDC_SETUP_KEEP_ON_ERROR = 1 };
  * preconditioned residual restricted to the interface is v1 + v2 (v3 only
  * changes interior values).  Both give the same iterates in exact arithmetic;
  * the interior values of x are recovered once at the end by the interior
- * solves of eq. (5).  bddc_apply always applies the full three-part operator. */
+ * solves of eq. (5).  bddc_apply always applies the full three-part operator.
+ * The interface operator is applied through the local factors, so it is only
+ * used with FP64 local factors: with local_bits = 32 CG always runs on the
+ * whole space, whose operator is the FP64 global matrix. */
 enum { BDDC_SETUP_FULL_SPACE = 2 };
 
 /* Solve flags. */

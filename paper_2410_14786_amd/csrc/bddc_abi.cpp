@@ -132,11 +132,34 @@ struct bddc_ctx {
   int* err = nullptr;
   double t_setup_ms = 0.0;
 
+  // HIP graphs of chunks of PCG iterations (use_graph): graph k holds iterations
+  // [k*GRAPH_CHUNK, (k+1)*GRAPH_CHUNK) of a solve, replayed on gst, which is
+  // joined to the ctx stream with events.  The iterate lives in xw so that the
+  // captured kernel arguments stay valid from one solve to the next.
+  static constexpr int GRAPH_CHUNK = 4;
+  hipStream_t gst = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<hipGraphExec_t> graphs;
+  std::vector<hipGraph_t> graph_defs;
+  double* xw = nullptr;
+  int* hsnap = nullptr;               // pinned host copies of (done, iters), two slots
+  hipEvent_t snap_ev[2] = {nullptr, nullptr};
+
   bool timing = false;
   std::map<std::string, TimedFamily> fam;
   std::vector<hipEvent_t> event_pool;
 
   ~bddc_ctx() {
+    for (hipGraphExec_t g : graphs)
+      if (g) hipGraphExecDestroy(g);
+    for (hipGraph_t g : graph_defs)
+      if (g) hipGraphDestroy(g);
+    if (ev_in) hipEventDestroy(ev_in);
+    for (hipEvent_t e : snap_ev)
+      if (e) hipEventDestroy(e);
+    if (hsnap) hipHostFree(hsnap);
+    if (ev_out) hipEventDestroy(ev_out);
+    if (gst) hipStreamDestroy(gst);
     for (auto& kv : fam)
       for (auto& pr : kv.second.pending) {
         hipEventDestroy(pr.first);
@@ -447,11 +470,75 @@ void enqueue_interior_guess(bddc_ctx* c, const double* b, double* x) {
   launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
 }
 
+// one PCG iteration it (fresh: first of a segment, p = z)
+void enqueue_iteration(bddc_ctx* c, double* x, int it, bool fresh) {
+  hipStream_t st = c->st;
+  const int64_t n = c->plan.n_free;
+  const int* done = &c->sc->done;
+  if (c->iface) {
+    enqueue_schur(c, it, fresh, c->part_c, c->part_a);
+  } else {
+    hipEvent_t e = c->begin("spmv");
+    launch_pcg_dir(c->rowptr, c->col, c->val, c->z, c->p, c->q, c->part_c, c->part_a, c->sc, it, fresh ? 1 : 0, n,
+                   st);
+    c->end("spmv", e);
+  }
+  launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st);
+  launch_pcg_check(c->part_b, c->sc, it, st);
+  if (c->iface) {
+    enqueue_apply_iface(c, c->r, c->z, c->part_c, done);
+  } else {
+    enqueue_apply(c, c->r, c->z, done);
+    launch_dot(c->r, c->z, c->part_c, n, done, st);
+  }
+}
+
+// Replays (capturing on first use) the graph of iterations
+// [k*GRAPH_CHUNK, (k+1)*GRAPH_CHUNK); x must be c->xw.
+int launch_chunk_graph(bddc_ctx* c, double* x, int k) {
+  if (!c->gst) {
+    HIP_TRY(hipStreamCreateWithFlags(&c->gst, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+  }
+  if (int(c->graphs.size()) <= k) {
+    c->graphs.resize(k + 1, nullptr);
+    c->graph_defs.resize(k + 1, nullptr);
+  }
+  if (!c->graphs[k]) {
+    hipStream_t user = c->st;
+    const bool timing = c->timing;
+    c->st = c->gst;
+    c->timing = false;
+    HIP_TRY(hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < bddc_ctx::GRAPH_CHUNK; ++i) {
+      const int it = k * bddc_ctx::GRAPH_CHUNK + i;
+      enqueue_iteration(c, x, it, it == 0);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->gst, &g);
+    c->st = user;
+    c->timing = timing;
+    if (e != hipSuccess) return fail(BDDC_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    HIP_TRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    c->graph_defs[k] = g;
+    c->graphs[k] = ex;
+  }
+  HIP_TRY(hipEventRecord(c->ev_in, c->st));
+  HIP_TRY(hipStreamWaitEvent(c->gst, c->ev_in, 0));
+  HIP_TRY(hipGraphLaunch(c->graphs[k], c->gst));
+  HIP_TRY(hipEventRecord(c->ev_out, c->gst));
+  HIP_TRY(hipStreamWaitEvent(c->st, c->ev_out, 0));
+  return BDDC_OK;
+}
+
 // out = xt + P_I (b - A xt) on interior dofs, xt on the interface (xt is zero on
 // interior dofs); out may be xt itself
 void enqueue_interior_complete(bddc_ctx* c, const double* b, const double* xt, double* out) {
   const Plan& P = c->plan;
   hipStream_t st = c->st;
+  if (out != xt) hipMemcpyAsync(out, xt, P.n_free * sizeof(double), hipMemcpyDeviceToDevice, st);
   launch_reset(c->fp32, pub_slot(c, 2), 2 * P.n_vec, nullptr, 0, c->tickets, nullptr, st);
   TrsvArgs a = base_args(c);
   a.tasks = c->t_fwd_ii;
@@ -615,6 +702,9 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->alloc(c->part_c, VEC_GRID))) return rc_;
   if ((rc_ = c->alloc(c->sc, 1))) return rc_;
   if ((rc_ = c->alloc(c->ppi, int64_t(P.nsubs) * MAX_NCI))) return rc_;
+  if ((rc_ = c->alloc(c->xw, P.n_free))) return rc_;
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hsnap), 4 * sizeof(int), hipHostMallocDefault));
+  for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreateWithFlags(&c->snap_ev[i], hipEventDisableTiming));
   if ((rc_ = c->alloc(c->sploc, P.n_loc))) return rc_;
   if (c->fp32) {
     float *v, *q;
@@ -706,7 +796,10 @@ int bddc_setup(const bddc_mesh* mesh, const bddc_partition* part, const bddc_coe
   c->st = static_cast<hipStream_t>(opts->stream);
   c->fp32 = opts->local_bits == 32;
   c->use_graph = opts->use_graph != 0;
-  c->iface = !(opts->flags & BDDC_SETUP_FULL_SPACE);
+  // the interface operator is applied through the local factors, so it is exact
+  // only with FP64 factors; FP32 local factors iterate on the whole space, where
+  // the operator is the FP64 global matrix
+  c->iface = !(opts->flags & BDDC_SETUP_FULL_SPACE) && !c->fp32;
   c->mesh.dim = c->plan.dim;
   for (int a = 0; a < 3; ++a) {
     c->mesh.nel[a] = int(c->plan.nel[a]);
@@ -766,6 +859,12 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
   const int64_t n = P.n_free;
   int* done = &c->sc->done;
   const bool iface = c->iface;
+  double* const x_user = x;
+  if (c->use_graph) {
+    // iterate in the ctx-owned buffer so that captured graphs stay valid
+    if (flags & BDDC_X0_GIVEN) HIP_TRY(hipMemcpyAsync(c->xw, x_user, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    x = c->xw;
+  }
   if (iface) {
     // interface unknowns: x holds the interface part (interior zero) during the
     // iteration; the residual lives on interface dofs
@@ -803,31 +902,37 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
       enqueue_apply(c, c->r, c->z, done);
       launch_dot(c->r, c->z, c->part_c, n, done, st);
     }
-    while (it < maxit) {
-      const int end = std::min(maxit, it + chunk);
-      for (; it < end; ++it) {
-        if (iface) {
-          enqueue_schur(c, it, fresh, c->part_c, c->part_a);
+    // Chunks of iterations are queued one ahead of the convergence check: after
+    // each chunk the (done, iters) words are copied to pinned host memory and an
+    // event is recorded; the host waits for chunk k's event only once chunk k+1
+    // is queued.  Kernels of a converged solve return at once.
+    int pending = 0, slot_w = 0, slot_r = 0;
+    for (;;) {
+      while (pending < 2 && it < maxit) {
+        const int end = std::min(maxit, it + chunk);
+        if (c->use_graph && fresh == (it == 0) && it % bddc_ctx::GRAPH_CHUNK == 0 &&
+            it + bddc_ctx::GRAPH_CHUNK <= maxit && seg_start == 0) {
+          if (int rc_ = launch_chunk_graph(c, x, it / bddc_ctx::GRAPH_CHUNK)) return rc_;
+          it += bddc_ctx::GRAPH_CHUNK;
+          fresh = false;
         } else {
-          hipEvent_t e = c->begin("spmv");
-          launch_pcg_dir(c->rowptr, c->col, c->val, c->z, c->p, c->q, c->part_c, c->part_a, c->sc, it,
-                         fresh ? 1 : 0, n, st);
-          c->end("spmv", e);
+          for (; it < end; ++it) {
+            enqueue_iteration(c, x, it, fresh);
+            fresh = false;
+          }
         }
-        fresh = false;
-        launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st);
-        launch_pcg_check(c->part_b, c->sc, it, st);
-        if (iface) {
-          enqueue_apply_iface(c, c->r, c->z, c->part_c, done);
-        } else {
-          enqueue_apply(c, c->r, c->z, done);
-          launch_dot(c->r, c->z, c->part_c, n, done, st);
-        }
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(c->hsnap + 2 * slot_w, &c->sc->done, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipEventRecord(c->snap_ev[slot_w], st));
+        slot_w ^= 1;
+        ++pending;
       }
-      HIP_TRY(hipGetLastError());
-      HIP_TRY(hipMemcpyAsync(&hs, c->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      if (hs.done) break;
+      if (pending == 0) break;
+      HIP_TRY(hipEventSynchronize(c->snap_ev[slot_r]));
+      const int flag = c->hsnap[2 * slot_r];
+      slot_r ^= 1;
+      --pending;
+      if (flag) break;
     }
     HIP_TRY(hipMemcpyAsync(&hs, c->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -872,6 +977,8 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
     seg_start = it;
     launch_fill<int>(&c->sc->iters, it, 1, st);
   }
+  if (x != x_user) HIP_TRY(hipMemcpyAsync(x_user, x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
   if (info) {
     info->iters = hs.iters;
     info->relres_true = relres_true;
