@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FULL_FAMILIES = ["trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii", "trsv_bwd_ii"]
-IFACE_FAMILIES = ["trsv_fwd_g", "trsv_bwd_g", "mv_t", "mv"]
+IFACE_FAMILIES = ["op_t", "op_n", "pc_n", "pc_t"]
 NB = 64
 
 
@@ -77,14 +77,16 @@ def algorithmic_bytes(w, local_bytes):
                              for nR, nI, nci in s)
     fam["trsv_fwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 4 + local_bytes) for nR, nI, nci in s)
     fam["trsv_bwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 8 + 4 + local_bytes) for nR, nI, nci in s)
-    # interface form: the trailing block L_GG (n_G = n_R - n_I rows) and its border rows
-    fam["trsv_fwd_g"] = sum(tri(nR - nI) * local_bytes + nci * (nR - nI) * local_bytes
-                            + (nR - nI) * (8 + 8 + 4 + local_bytes) for nR, nI, nci in s)
-    fam["trsv_bwd_g"] = sum(tri(nR - nI) * local_bytes + nci * (nR - nI) * local_bytes
-                            + (nR - nI) * (8 + 2 * local_bytes) for nR, nI, nci in s)
-    fam["mv_t"] = sum(tri(nR - nI) * local_bytes + 8 * (nR - nI) * local_bytes + 2 * (nR - nI) * local_bytes
+    # interface form (FP64): each of the four triangular mat-vecs streams one
+    # triangle of n_G = n_R - n_I rows (L_GG or its inverse), plus border rows and
+    # the gathered/written vectors
+    g = lambda nR, nI: nR - nI
+    fam["op_t"] = sum(tri(g(nR, nI)) * local_bytes + 8 * g(nR, nI) * local_bytes
+                      + g(nR, nI) * (8 + 8 + 4 + 8 + 8) for nR, nI, nci in s)
+    fam["op_n"] = sum(tri(g(nR, nI)) * local_bytes + g(nR, nI) * (8 + 8 + 8) for nR, nI, nci in s)
+    fam["pc_n"] = sum(tri(g(nR, nI)) * local_bytes + nci * g(nR, nI) * local_bytes + g(nR, nI) * (8 + 8 + 4 + 8)
                       for nR, nI, nci in s)
-    fam["mv"] = sum(tri(nR - nI) * local_bytes + (nR - nI) * (local_bytes + 16) for nR, nI, nci in s)
+    fam["pc_t"] = sum(tri(g(nR, nI)) * local_bytes + g(nR, nI) * (8 + 8 + 8) for nR, nI, nci in s)
     return fam
 
 
@@ -185,6 +187,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-full-space", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay PCG iterations from captured HIP graphs")
     ap.add_argument("--local-bits", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 512 MiB device copy first (reference for HBM byte counters)")
@@ -208,7 +211,7 @@ def main():
           flush=True)
     main_bits = args.local_bits
     runs = {}
-    runs["main"] = run_gpu(w, args.steps, args.warmup, main_bits)
+    runs["main"] = run_gpu(w, args.steps, args.warmup, main_bits, use_graph=args.graph)
     if not args.no_full_space:
         runs["full_space"] = run_gpu(w, args.steps, args.warmup, main_bits, full_space=True)
     if not args.no_fp32 and main_bits == 64:

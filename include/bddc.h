@@ -174,10 +174,10 @@ int bddc_plan_stats(const bddc_mesh* mesh, const bddc_partition* part,
  * bracketed by HIP events on the ctx stream; bddc_kernel_time returns the
  * number of timed launches and their summed duration in ms (synchronising
  * the stream).  Families: "trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii",
- * "trsv_bwd_ii" (full-space solves), "trsv_fwd_g", "trsv_bwd_g" (interface
- * block solves), "mv_t", "mv" (the two triangular mat-vecs of the Schur
- * operator), "schur" (the whole operator), "spmv", "apply".  Unknown names
- * give EINVAL. */
+ * "trsv_bwd_ii" (full-space solves), "op_t", "op_n" (the two triangular
+ * mat-vecs of the interface Schur operator), "pc_n", "pc_t" (the two
+ * triangular mat-vecs of the interface preconditioner), "schur" (the whole
+ * operator), "spmv", "apply".  Unknown names give EINVAL. */
 int bddc_set_timing(bddc_ctx* ctx, int32_t enabled);
 int bddc_kernel_time(bddc_ctx* ctx, const char* family, int64_t* launches,
                      double* total_ms);

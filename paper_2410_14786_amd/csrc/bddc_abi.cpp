@@ -118,7 +118,9 @@ struct bddc_ctx {
   int Tc = 0;
   int32_t *t_fwd_rr = nullptr, *t_bwd_rr = nullptr, *t_fwd_ii = nullptr, *t_bwd_ii = nullptr;
   int32_t *t_fwd_g = nullptr, *t_bwd_g = nullptr;
-  void *vloc = nullptr, *qloc = nullptr;      // interface operator: local v and q (local precision)
+  void *vloc = nullptr, *qloc = nullptr;      // interface form: local work vectors
+  double* xg = nullptr;                        // inverses of the trailing factor blocks
+  double *zloc = nullptr, *floc = nullptr;     // D^{-1} z and W D r in local-dof order
   double *ppi = nullptr, *sploc = nullptr, *cpp = nullptr;
   int max_loclen = 1;
   void* pub_local = nullptr;   // 4 * n_vec entries of the local precision
@@ -345,26 +347,51 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   c->end("apply", ea);
 }
 
+IfaceArgs iface_args(bddc_ctx* c) {
+  IfaceArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.mats = c->mats;
+  a.tiles = static_cast<const double*>(c->tiles);
+  a.xg = c->xg;
+  a.tasks = c->t_fwd_g;
+  a.ntasks = int(c->plan.fwd_g.size() / 2);
+  a.sc = c->sc;
+  a.gmap = c->gmap;
+  a.dsc = c->dsc;
+  a.wd = c->wd;
+  a.wgt = c->wgt;
+  a.z = c->z;
+  a.p = c->p;
+  a.ppi = c->ppi;
+  a.part = c->part;
+  a.cpp = c->cpp;
+  a.sploc = c->sploc;
+  a.ww = c->ww;
+  a.uc = c->uc;
+  a.rc = c->rc;
+  a.mu = c->mu;
+  a.sainv = c->sainv;
+  a.sainve = c->sainve;
+  return a;
+}
+
 // Interface preconditioner (v1 + v2 restricted to interface dofs) on an
-// interface residual r: forward solve with the trailing block L_GG, coarse
-// problem, backward solve, weighted gather into z (interface entries), and the
-// partial sums of r.z for the next direction.
+// interface residual r: t = X D W r on the trailing rows (with the border
+// partials), coarse problem, t' = t + W coef, x = X^T t', weighted gather into z
+// (interface entries) with the partial sums of r.z.  Expects zero tickets and
+// sentinel coarse buffers, and leaves them so for the next application.
 void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_rz, const int* done) {
   const Plan& P = c->plan;
   hipStream_t st = c->st;
   hipEvent_t ea = c->begin("apply");
-  launch_reset(c->fp32, c->pub_local, 2 * P.n_vec, c->pub_coarse, 2 * int64_t(c->Tc) * NB, c->tickets, done, st);
-  TrsvArgs a = base_args(c);
-  a.done = done;
-  a.tasks = c->t_fwd_g;
-  a.ntasks = int(P.fwd_g.size() / 2);
+  IfaceArgs a = iface_args(c);
+  a.r = r;
+  a.loc_in = c->floc;
   a.ticket = c->tickets + 0;
-  a.sol = pub_slot(c, 0);
-  a.rin = r;
-  a.part = c->part;
-  hipEvent_t e = c->begin("trsv_fwd_g");
-  launch_trsv(TRSV_FWD_G, c->fp32, a, trsv_grid(c, a.ntasks), st);
-  c->end("trsv_fwd_g", e);
+  a.xout = static_cast<double*>(c->vloc);
+  hipEvent_t e = c->begin("pc_n");
+  launch_iface_mv(IMV_PC_N, a, trsv_grid(c, a.ntasks), st);
+  c->end("pc_n", e);
   if (P.n_coarse > 0) {
     launch_coarse_prep(c->mats, P.nsubs, c->part, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done, 1,
                        st);
@@ -389,22 +416,18 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
     cf.sol = c->pub_coarse + int64_t(c->Tc) * NB;
     cf.uc = c->uc;
     launch_trsv(TRSV_BWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
-    launch_coarse_coef(c->mats, P.nsubs, c->rc, c->uc, c->mu, c->sainv, c->sainve, c->wgt, c->coef, c->ww, done,
-                       st);
   }
-  a = base_args(c);
-  a.done = done;
-  a.tasks = c->t_bwd_g;
-  a.ntasks = int(P.bwd_g.size() / 2);
+  a.xin = static_cast<const double*>(c->vloc);
+  a.xout = static_cast<double*>(c->qloc);
+  launch_border_correct(a, st);
+  a.xin = static_cast<const double*>(c->qloc);
+  a.xout = nullptr;
   a.ticket = c->tickets + 1;
-  a.sol = pub_slot(c, 1);
-  a.src = pub_slot(c, 0);
-  a.coef = c->coef;
-  a.ww = c->ww;
-  e = c->begin("trsv_bwd_g");
-  launch_trsv(TRSV_BWD_G, c->fp32, a, trsv_grid(c, a.ntasks), st);
-  c->end("trsv_bwd_g", e);
-  launch_gather_z(c->inv_ptr, c->inv, c->ww, c->kappa, r, z, part_rz, P.n_free, done, st);
+  e = c->begin("pc_t");
+  launch_iface_mv(IMV_PC_T, a, trsv_grid(c, a.ntasks), st);
+  c->end("pc_t", e);
+  launch_gather_z(c->inv_ptr, c->inv, c->ww, c->kappa, r, z, part_rz, P.n_free, done, c->pub_coarse,
+                  2 * int64_t(c->Tc) * NB, c->tickets, c->dsc, c->zloc, st);
   c->end("apply", ea);
 }
 
@@ -412,34 +435,23 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
 void enqueue_schur(bddc_ctx* c, int it, bool fresh, const double* part_rz, double* part_pq) {
   const Plan& P = c->plan;
   hipStream_t st = c->st;
-  const int* done = &c->sc->done;
   hipEvent_t e = c->begin("schur");
-  launch_iface_local(c->mats, P.nsubs, c->max_loclen, c->gmap, c->dsc, c->z, c->p, part_rz, c->sc, it, fresh ? 1 : 0,
-                     c->vloc, c->fp32, c->ppi, st);
-  MvArgs m;
-  std::memset(&m, 0, sizeof(m));
-  m.mats = c->mats;
-  m.tiles = c->tiles;
-  m.tasks = c->t_fwd_g;
-  m.ntasks = int(P.fwd_g.size() / 2);
-  m.done = done;
-  m.ppi = c->ppi;
-  m.part = c->part;
-  m.dsc = c->dsc;
-  m.sploc = c->sploc;
-  m.ticket = c->tickets + 2;
-  m.xin = c->vloc;
-  m.xout = c->qloc;
-  hipEvent_t e1 = c->begin("mv_t");
-  launch_tile_mv(true, c->fp32, m, trsv_grid(c, m.ntasks), st);
-  c->end("mv_t", e1);
-  m.ticket = c->tickets + 3;
-  m.xin = c->qloc;
-  m.xout = nullptr;
-  e1 = c->begin("mv");
-  launch_tile_mv(false, c->fp32, m, trsv_grid(c, m.ntasks), st);
-  c->end("mv", e1);
-  launch_corner_sp(c->mats, P.nsubs, c->part, c->cpp, c->ppi, c->sploc, done, st);
+  IfaceArgs a = iface_args(c);
+  a.it = it;
+  a.fresh = fresh ? 1 : 0;
+  a.part_rz = part_rz;
+  a.loc_in = c->zloc;
+  a.ticket = c->tickets + 2;
+  a.xout = static_cast<double*>(c->qloc);
+  hipEvent_t e1 = c->begin("op_t");
+  launch_iface_mv(IMV_OP_T, a, trsv_grid(c, a.ntasks), st);
+  c->end("op_t", e1);
+  a.ticket = c->tickets + 3;
+  a.xin = static_cast<const double*>(c->qloc);
+  a.xout = nullptr;
+  e1 = c->begin("op_n");
+  launch_iface_mv(IMV_OP_N, a, trsv_grid(c, a.ntasks), st);
+  c->end("op_n", e1);
   launch_gather_sp(c->inv_ptr, c->inv, c->sploc, c->kappa, c->z, c->p, c->q, part_rz, part_pq, c->sc, it,
                    fresh ? 1 : 0, P.n_free, st);
   c->end("schur", e);
@@ -483,7 +495,11 @@ void enqueue_iteration(bddc_ctx* c, double* x, int it, bool fresh) {
                    st);
     c->end("spmv", e);
   }
-  launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st);
+  if (c->iface)
+    launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st, c->inv_ptr, c->inv, c->wd,
+                      c->floc);
+  else
+    launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st);
   launch_pcg_check(c->part_b, c->sc, it, st);
   if (c->iface) {
     enqueue_apply_iface(c, c->r, c->z, c->part_c, done);
@@ -650,6 +666,11 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->alloc(c->cpp, small))) return rc_;
   launch_local_small(c->mats, P.nsubs, c->tiles, c->fp32, c->app, c->sainv, c->sainve, c->aci, c->cpp, c->err + 1,
                      st);
+  if (c->iface) {
+    if ((rc_ = c->alloc(c->xg, P.n_xg * NB * NB))) return rc_;
+    launch_trailing_inverse(c->mats, P.nsubs, P.maxTG, static_cast<const double*>(c->tiles),
+                            static_cast<const double*>(c->dinv), c->xg, st);
+  }
 
   // coarse problem
   const int nc = P.n_coarse;
@@ -703,6 +724,10 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->alloc(c->sc, 1))) return rc_;
   if ((rc_ = c->alloc(c->ppi, int64_t(P.nsubs) * MAX_NCI))) return rc_;
   if ((rc_ = c->alloc(c->xw, P.n_free))) return rc_;
+  if ((rc_ = c->alloc(c->zloc, P.n_loc))) return rc_;
+  if ((rc_ = c->alloc(c->floc, P.n_loc))) return rc_;
+  launch_fill<double>(c->zloc, 0.0, P.n_loc, st);
+  launch_fill<double>(c->floc, 0.0, P.n_loc, st);
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hsnap), 4 * sizeof(int), hipHostMallocDefault));
   for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreateWithFlags(&c->snap_ev[i], hipEventDisableTiming));
   if ((rc_ = c->alloc(c->sploc, P.n_loc))) return rc_;
@@ -897,6 +922,8 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
   for (;;) {
     // (re)start: z = M^{-1} r, rz
     if (iface) {
+      launch_reset(false, nullptr, 0, c->pub_coarse, 2 * int64_t(c->Tc) * NB, c->tickets, done, st);
+      launch_scatter_local(c->inv_ptr, c->inv, c->wd, c->r, c->floc, n, st);
       enqueue_apply_iface(c, c->r, c->z, c->part_c, done);
     } else {
       enqueue_apply(c, c->r, c->z, done);
@@ -1010,8 +1037,8 @@ int bddc_set_timing(bddc_ctx* c, int32_t enabled) {
 
 int bddc_kernel_time(bddc_ctx* c, const char* family, int64_t* launches, double* total_ms) {
   if (int rc_ = check_ctx(c)) return rc_;
-  static const char* known[] = {"trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii", "trsv_bwd_ii", "trsv_fwd_g",
-                                "trsv_bwd_g", "mv_t", "mv", "schur", "spmv", "apply"};
+  static const char* known[] = {"trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii", "trsv_bwd_ii", "op_t", "op_n",
+                                "pc_n", "pc_t", "schur", "spmv", "apply"};
   bool ok = false;
   for (const char* k : known) ok |= family && std::strcmp(family, k) == 0;
   if (!ok) return fail(BDDC_EINVAL, "unknown kernel family");

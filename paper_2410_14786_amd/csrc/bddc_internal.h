@@ -34,6 +34,7 @@ struct MatDesc {
   int32_t box_len[3]; // box length in elements
   int32_t lmap_off;   // offset of the box-node -> local index table
   int32_t pad;
+  int64_t xg_off;     // first tile of the inverse of the trailing block (tile rows n_I/NB .. T-1)
 };
 
 // Host-side plan: everything bddc_setup derives from the mesh and partition
@@ -80,7 +81,8 @@ struct Plan {
   std::vector<int32_t> fwd_rr, bwd_rr, fwd_ii, bwd_ii, fwd_g, bwd_g;
 
   int maxT = 0, maxTx = 0, maxTI = 0;
-  int64_t n_tiles = 0, n_dinv = 0, n_vec = 0, n_loc = 0, n_lmap = 0;
+  int64_t n_tiles = 0, n_dinv = 0, n_vec = 0, n_loc = 0, n_lmap = 0, n_xg = 0;
+  int maxTG = 0;
   int max_nci = 0;
 };
 

@@ -58,20 +58,6 @@ struct TrsvArgs {
   double* uc;
 };
 
-struct MvArgs {
-  const MatDesc* mats;
-  const void* tiles;
-  const int32_t* tasks;
-  int ntasks;
-  unsigned* ticket;
-  const int* done;
-  const void* xin;      // local input vector (local precision, vec_off layout)
-  void* xout;           // TRANS: local output q
-  const double* ppi;    // corner values of p per subdomain
-  double* part;         // TRANS: partials of W_Pi,G^T q
-  double* sploc;        // non-transposed: (S p)_G per local dof
-  const double* dsc;
-};
 
 struct PcgScalars {
   double tol2;
@@ -84,6 +70,39 @@ struct PcgScalars {
   double rr[MAX_PCG_IT + 1];
   double alpha[MAX_PCG_IT + 1];
   double beta[MAX_PCG_IT + 1];
+};
+
+struct IfaceArgs {
+  const MatDesc* mats;
+  const double* tiles;      // local factors (L and the border rows)
+  const double* xg;         // inverse of the tile-aligned trailing block
+  const int32_t* tasks;
+  int ntasks;
+  unsigned* ticket;
+  const PcgScalars* sc;
+  int it;
+  int fresh;
+  const double* part_rz;
+  const int32_t* gmap;
+  const double* dsc;
+  const double* wd;
+  const double* wgt;
+  const double* z;
+  const double* p;
+  const double* r;
+  const double* xin;        // local vector input (vec_off layout)
+  const double* loc_in;     // OP_T: D^{-1} z, PC_N: W D r, both in local-dof order
+  double* xout;             // local vector output
+  double* ppi;              // corner values of the direction
+  double* part;             // per (matrix, tile row) partial border products
+  const double* cpp;        // A_PiPi - W_Pi^T W_Pi
+  double* sploc;            // (S p) per local dof
+  double* ww;               // weighted local preconditioner output
+  const double* uc;
+  const int32_t* rc;
+  const double* mu;
+  const double* sainv;
+  const double* sainve;
 };
 
 template <typename T> void launch_fill(T* p, T v, int64_t n, hipStream_t st);
@@ -125,7 +144,9 @@ void launch_pcg_dir(const int32_t* rowptr, const int32_t* col, const double* val
                     double* q, const double* part_rz, double* part_pq, PcgScalars* sc, int it, int fresh, int64_t n,
                     hipStream_t st);
 void launch_pcg_update(double* x, double* r, const double* p, const double* q, const double* part_pq,
-                       double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st);
+                       double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st,
+                       const int32_t* inv_ptr = nullptr, const int32_t* inv = nullptr, const double* wd = nullptr,
+                       double* floc = nullptr);
 void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, hipStream_t st);
 void launch_dot(const double* a, const double* b, double* part, int64_t n, const int* done, hipStream_t st);
 void launch_finish_dot(const double* part, double* out, hipStream_t st);
@@ -136,16 +157,21 @@ constexpr int VEC_GRID = 1024;   // partial-sum count of the vector kernels
 
 void launch_reset(bool fp32, void* pub, int64_t n_pub, double* pubc, int64_t n_pubc, unsigned* tickets,
                   const int* done, hipStream_t st);
-void launch_iface_local(const MatDesc* mats, int nmats, int max_len, const int32_t* gmap, const double* dsc,
-                        const double* z, const double* p, const double* part_rz, const PcgScalars* sc, int it,
-                        int fresh, void* vloc, bool fp32, double* ppi, hipStream_t st);
-void launch_tile_mv(bool trans, bool fp32, const MvArgs& a, int grid, hipStream_t st);
-void launch_corner_sp(const MatDesc* mats, int nmats, const double* part, const double* cpp, const double* ppi,
-                      double* sploc, const int* done, hipStream_t st);
+
+
+
 void launch_gather_sp(const int32_t* inv_ptr, const int32_t* inv, const double* sploc, const uint8_t* kappa,
                       const double* z, double* p, double* q, const double* part_rz, double* part_pq, PcgScalars* sc,
                       int it, int fresh, int64_t n, hipStream_t st);
 void launch_gather_z(const int32_t* inv_ptr, const int32_t* inv, const double* ww, const uint8_t* kappa,
-                     const double* r, double* z, double* part_rz, int64_t n, const int* done, hipStream_t st);
+                     const double* r, double* z, double* part_rz, int64_t n, const int* done, double* pubc,
+                     int64_t n_pubc, unsigned* tickets, const double* dsc, double* zloc, hipStream_t st);
+void launch_scatter_local(const int32_t* inv_ptr, const int32_t* inv, const double* scale, const double* v,
+                          double* loc, int64_t n, hipStream_t st);
+enum { IMV_OP_T = 0, IMV_OP_N = 1, IMV_PC_N = 2, IMV_PC_T = 3 };
+void launch_iface_mv(int mode, const IfaceArgs& a, int grid, hipStream_t st);
+void launch_border_correct(const IfaceArgs& a, hipStream_t st);
+void launch_trailing_inverse(const MatDesc* mats, int nmats, int maxTG, const double* tiles, const double* dinv,
+                             double* xg, hipStream_t st);
 
 }  // namespace bddc

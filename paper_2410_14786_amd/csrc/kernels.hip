@@ -1036,6 +1036,18 @@ void launch_zero_interior(const uint8_t* kappa, double* x, int64_t n, hipStream_
   hipLaunchKernelGGL(zero_interior_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, kappa, x, n);
 }
 
+__global__ void scatter_local_kernel(const int32_t* inv_ptr, const int32_t* inv, const double* scale, const double* v,
+                                     double* loc, int64_t n) {
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x)
+    for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) loc[inv[j]] = scale[inv[j]] * v[g];
+}
+
+void launch_scatter_local(const int32_t* inv_ptr, const int32_t* inv, const double* scale, const double* v,
+                          double* loc, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(scatter_local_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, inv_ptr, inv, scale, v,
+                     loc, n);
+}
+
 void launch_zero_interface(const uint8_t* kappa, double* x, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(zero_interface_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, kappa, x, n);
 }
@@ -1165,7 +1177,8 @@ __global__ __launch_bounds__(VBLK) void pcg_dir_kernel(const int32_t* rowptr, co
 // alpha = rz/pq; x += alpha p; r -= alpha q; partial sums of r.r
 __global__ __launch_bounds__(VBLK) void pcg_update_kernel(double* x, double* r, const double* p, const double* q,
                                                           const double* part_pq, double* part_rr, PcgScalars* sc,
-                                                          int it, int64_t n) {
+                                                          int it, int64_t n, const int32_t* inv_ptr,
+                                                          const int32_t* inv, const double* wd, double* floc) {
   __shared__ double sh[VBLK / 64];
   if (sc->done) return;
   const double pq = reduce_partials(part_pq, VGRID, sh);
@@ -1182,6 +1195,8 @@ __global__ __launch_bounds__(VBLK) void pcg_update_kernel(double* x, double* r, 
       double rv = r[i] - alpha * q[i];
       r[i] = rv;
       rr += rv * rv;
+      if (floc)   // interface form: the preconditioner reads W D r in local order
+        for (int j = inv_ptr[i]; j < inv_ptr[i + 1]; ++j) floc[inv[j]] = wd[inv[j]] * rv;
     }
   }
   double t = block_sum(rr, sh);
@@ -1250,8 +1265,10 @@ void launch_pcg_init(const double* part_rr, const double* part_bb, PcgScalars* s
   hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(VBLK), 0, st, part_rr, part_bb, sc, rtol2);
 }
 void launch_pcg_update(double* x, double* r, const double* p, const double* q, const double* part_pq,
-                       double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(pcg_update_kernel, dim3(VGRID), dim3(VBLK), 0, st, x, r, p, q, part_pq, part_rr, sc, it, n);
+                       double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st, const int32_t* inv_ptr,
+                       const int32_t* inv, const double* wd, double* floc) {
+  hipLaunchKernelGGL(pcg_update_kernel, dim3(VGRID), dim3(VBLK), 0, st, x, r, p, q, part_pq, part_rr, sc, it, n,
+                     inv_ptr, inv, wd, floc);
 }
 void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, hipStream_t st) {
   hipLaunchKernelGGL(pcg_check_kernel, dim3(1), dim3(VBLK), 0, st, part_rr, sc, it);
@@ -1264,61 +1281,101 @@ void launch_finish_dot(const double* part, double* out, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Interface (Schur-complement) operator S_i = A_BB - A_BI A_II^{-1} A_IB
+// Interface (Schur-complement) form, FP64 local factors
 // ---------------------------------------------------------------------------
 // With B = interface (G = non-corner, Pi = corners) and the bordered factor of
 // the equilibrated A_RR (interior first), the trailing block L_GG is
-// chol(D_G S_GG D_G) and the border rows give W_Pi = L^{-1} D A_RPi, so
+// chol(D_G S_GG D_G) and the border rows give W = L^{-1} D [C_AR^T | A_RPi], so
 //   (S p)_G  = D^{-1} L_GG q,  q = L_GG^T D^{-1} p_G + W_Pi,G p_Pi
 //   (S p)_Pi = W_Pi,G^T q + (A_PiPi - W_Pi^T W_Pi) p_Pi
-// (the last matrix is stored per subdomain at setup).  q and L_GG q are plain
-// triangular mat-vecs: every tile row is independent.
+// and the preconditioner needs t = L_GG^{-1} D f_G and x = L_GG^{-T} t'.  The
+// last two use X = inverse of the tile-aligned trailing block of L (tile rows
+// n_I/64 .. T-1), formed at setup: on vectors that vanish on the interior rows
+// of the first tile, X and X^T act as L_GG^{-1} and L_GG^{-T}.  All four are
+// triangular mat-vecs: tile rows are independent, nothing waits.
 
-// direction p = z + beta p (beta from the r.z partials) gathered into the local
-// vectors: v = D^{-1} p on non-corner interface rows (zero elsewhere), p on corners
-__global__ __launch_bounds__(VBLK) void iface_local_kernel(const MatDesc* mats, const int32_t* gmap, const double* dsc, const double* z,
-                                   const double* p, const double* part_rz, const PcgScalars* sc, int it, int fresh,
-                                   void* vloc, bool fp32, double* ppi) {
-  __shared__ double sh[VBLK / 64];
-  if (sc->done) return;
-  double beta = 0.0;
-  if (!fresh) beta = reduce_partials(part_rz, VGRID, sh) / sc->rz[it - 1];   // same bits as gather_sp
+// X(ii, jj) = -Dinv_i sum_{kk=jj}^{ii-1} L(i, k) X(kk, jj), X(ii, ii) = Dinv_i
+// (i = j0 + ii, k = j0 + kk); one launch per block row ii, one task per (matrix, jj)
+__global__ __launch_bounds__(256) void trailing_inverse_kernel(const MatDesc* mats, const double* tiles,
+                                                               const double* dinv, double* xg, int ii) {
   const MatDesc D = mats[blockIdx.y];
-  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < D.T * NB + D.n_P; a += gridDim.x * blockDim.x) {
-    if (a < D.T * NB) {
-      double v = 0.0;
-      if (a >= D.n_I && a < D.n_R) {
-        const int64_t l = D.loc_off + a;
-        const int g = gmap[l];
-        v = (fresh ? z[g] : z[g] + beta * p[g]) / dsc[l];
-      }
-      if (fp32) static_cast<float*>(vloc)[D.vec_off + a] = float(v);
-      else static_cast<double*>(vloc)[D.vec_off + a] = v;
-    } else {
-      const int c = a - D.T * NB;
-      const int g = gmap[D.loc_off + D.n_R + c];
-      ppi[int64_t(blockIdx.y) * MAX_NCI + c] = fresh ? z[g] : z[g] + beta * p[g];
-    }
+  const int j0 = D.n_I / NB;
+  const int TG = D.T - j0;
+  const int jj = blockIdx.x;
+  if (ii >= TG || jj > ii) return;
+  double* out = xg + (D.xg_off + tri_tile(ii, jj)) * int64_t(NB * NB);
+  const double* di = dinv + (D.dinv_off + j0 + ii) * int64_t(NB * NB);
+  if (jj == ii) {
+    for (int e = threadIdx.x; e < NB * NB; e += 256) out[e] = di[e];
+    return;
   }
+  __shared__ double sa[NB * LDT];
+  __shared__ double sb[NB * LDT];
+  d4v acc[2][2];
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q) acc[p][q] = d4v(0);
+  for (int kk = jj; kk < ii; ++kk) {
+    __syncthreads();
+    const double* a = tiles + (D.tile_off + tri_tile(j0 + ii, j0 + kk)) * int64_t(NB * NB);
+    const double* b = xg + (D.xg_off + tri_tile(kk, jj)) * int64_t(NB * NB);
+    for (int e = threadIdx.x; e < NB * NB; e += 256) {
+      sa[(e / NB) * LDT + (e % NB)] = a[e];
+      sb[(e % NB) * LDT + (e / NB)] = b[e];      // transposed: gemm_nt then gives A B
+    }
+    __syncthreads();
+    gemm_nt_tile<double>(sa, sb, acc);
+  }
+  __syncthreads();
+  // C (in acc) -> transposed into sb; Dinv_i into sa; out = -Dinv_i C
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q)
+      for (int it = 0; it < 4; ++it) {
+        const int r = r0 + 16 * p + Acc4<double>::row(lane, it), c = c0 + 16 * q + (lane & 15);
+        sb[c * LDT + r] = acc[p][q][it];
+      }
+  for (int e = threadIdx.x; e < NB * NB; e += 256) sa[(e / NB) * LDT + (e % NB)] = di[e];
+  __syncthreads();
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q) acc[p][q] = d4v(0);
+  gemm_nt_tile<double>(sa, sb, acc);
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q)
+      for (int it = 0; it < 4; ++it) {
+        const int r = r0 + 16 * p + Acc4<double>::row(lane, it), c = c0 + 16 * q + (lane & 15);
+        out[r * NB + c] = -acc[p][q][it];
+      }
 }
 
-// TRANS: q_k = sum_{j >= k} L_jk^T v_j + W_Pi,k p_Pi, plus partials of W_Pi,G^T q.
-// Otherwise: y_k = sum_{j0 <= j <= k} L_kj q_j, written as (S p)_G = D^{-1} y.
-template <typename T, bool TRANS>
-__global__ __launch_bounds__(256) void tile_mv_kernel(MvArgs A) {
-  using V = typename Traits<T>::V;
-  constexpr int VEC = Traits<T>::VEC;
-  constexpr int LPR = NB / VEC;
-  constexpr int RPI = 64 / LPR;
-  constexpr int NI = 16 / RPI;
-  __shared__ T s_red[4][NB];
-  __shared__ T s_out[NB];
+void launch_trailing_inverse(const MatDesc* mats, int nmats, int maxTG, const double* tiles, const double* dinv,
+                             double* xg, hipStream_t st) {
+  for (int ii = 0; ii < maxTG; ++ii)
+    hipLaunchKernelGGL(trailing_inverse_kernel, dim3(ii + 1, nmats), dim3(256), 0, st, mats, tiles, dinv, xg, ii);
+}
+
+// One kernel for the four interface mat-vecs (see above); task = (matrix, tile row k)
+// for k = n_I/64 .. T-1.
+//   OP_T: q_k = sum_{j>=k} L(j,k)^T v_j + W_Pi(k) z_Pi, v = D^{-1} z (the operator is
+//         applied to z; CG forms S p = S z + beta S p_old); stores q and the
+//         partials W_Pi(k)^T q_k
+//   OP_N: y_k = sum_{j0<=j<=k} L(k,j) q_j, (S z)_G = D^{-1} y; the task k = j0 also
+//         writes (S z)_Pi from the partials
+//   PC_N: t_k = sum_{j0<=j<=k} X(k,j) f_j, f = W D r; stores t and the partials
+//         W(k)^T t_k of all constraints
+//   PC_T: x_k = sum_{j>=k} X(j,k)^T t'_j; weighted local output W D x
+template <int MODE>
+__global__ __launch_bounds__(256) void iface_mv_kernel(IfaceArgs A) {
+  using V = d2v;
+  constexpr int VEC = 2, LPR = 32, RPI = 2, NI = 8;
+  constexpr bool TRANS = (MODE == IMV_OP_T || MODE == IMV_PC_T);
+  constexpr bool ONFLY = (MODE == IMV_OP_T || MODE == IMV_PC_N);
+  __shared__ double s_red[4][NB];
+  __shared__ double s_out[NB];
   __shared__ int s_task;
-  if (A.done && *A.done) return;
+  if (A.sc->done) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int lr = lane / LPR, lc = lane % LPR;
-  const T* tiles = reinterpret_cast<const T*>(A.tiles);
-  const T* xin = reinterpret_cast<const T*>(A.xin);
   for (;;) {
     if (tid == 0) s_task = atomicAdd(A.ticket, 1u);
     __syncthreads();
@@ -1328,31 +1385,42 @@ __global__ __launch_bounds__(256) void tile_mv_kernel(MvArgs A) {
     const int s = A.tasks[2 * task], k = A.tasks[2 * task + 1];
     const MatDesc D = A.mats[s];
     const int j0 = D.n_I / NB;
-    const int64_t tbase = D.tile_off;
-    const T* x = xin + D.vec_off;
-    T acc[TRANS ? VEC : NI];
-    for (int i = 0; i < (TRANS ? VEC : NI); ++i) acc[i] = T(0);
-    // TRANS: tiles (j, k), j = k .. T-1;  otherwise tiles (k, j), j = j0 .. k
-    const int nt = TRANS ? D.T - k : k - j0 + 1;
-    auto tile_ptr = [&](int jj) -> const T* {
-      int64_t t = TRANS ? tri_tile(k + jj, k) : tri_tile(k, j0 + jj);
-      return tiles + (tbase + t) * int64_t(NB * NB) + (16 * w + lr) * NB + VEC * lc;
+    // input value of local row a (zero outside the interface rows n_I..n_R-1):
+    // OP_T reads D^{-1} z and PC_N reads W D r from local-order vectors that the
+    // previous kernels scattered; the other two read this kernel family's output
+    auto input = [&](int a) -> double {
+      if (a < D.n_I || a >= D.n_R) return 0.0;
+      if (ONFLY) return A.loc_in[D.loc_off + a];
+      return A.xin[D.vec_off + a];
     };
+    auto tile_ptr = [&](int jj) -> const double* {
+      int64_t t;
+      if (MODE == IMV_OP_T) t = D.tile_off + tri_tile(k + jj, k);
+      else if (MODE == IMV_OP_N) t = D.tile_off + tri_tile(k, j0 + jj);
+      else if (MODE == IMV_PC_N) t = D.xg_off + tri_tile(k - j0, jj);
+      else t = D.xg_off + tri_tile(k - j0 + jj, k - j0);
+      const double* base = (MODE == IMV_OP_T || MODE == IMV_OP_N) ? A.tiles : A.xg;
+      return base + t * int64_t(NB * NB) + (16 * w + lr) * NB + VEC * lc;
+    };
+    const int nt = TRANS ? D.T - k : k - j0 + 1;
+    const int jfirst = TRANS ? k : j0;
+    double acc[TRANS ? VEC : NI];
+    for (int i = 0; i < (TRANS ? VEC : NI); ++i) acc[i] = 0.0;
     V cur[NI], nxt[NI];
     {
-      const T* pp = tile_ptr(0);
+      const double* pp = tile_ptr(0);
       for (int i = 0; i < NI; ++i) cur[i] = *reinterpret_cast<const V*>(pp + i * RPI * NB);
     }
     for (int jj = 0; jj < nt; ++jj) {
-      const T* xs = x + (TRANS ? k + jj : j0 + jj) * NB;
-      T xv[TRANS ? NI : VEC];
+      const int rb = (jfirst + jj) * NB;
+      double xv[TRANS ? NI : VEC];
       if (TRANS) {
-        for (int i = 0; i < NI; ++i) xv[i] = xs[16 * w + RPI * i + lr];
+        for (int i = 0; i < NI; ++i) xv[i] = input(rb + 16 * w + RPI * i + lr);
       } else {
-        for (int e = 0; e < VEC; ++e) xv[e] = xs[VEC * lc + e];
+        for (int e = 0; e < VEC; ++e) xv[e] = input(rb + VEC * lc + e);
       }
       if (jj + 1 < nt) {
-        const T* pp = tile_ptr(jj + 1);
+        const double* pp = tile_ptr(jj + 1);
         for (int i = 0; i < NI; ++i) nxt[i] = *reinterpret_cast<const V*>(pp + i * RPI * NB);
       }
       if (TRANS) {
@@ -1366,13 +1434,13 @@ __global__ __launch_bounds__(256) void tile_mv_kernel(MvArgs A) {
     }
     if (TRANS) {
       for (int e = 0; e < VEC; ++e) {
-        T v = acc[e];
+        double v = acc[e];
         for (int off = LPR; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
         if (lr == 0) s_red[w][VEC * lc + e] = v;
       }
     } else {
       for (int i = 0; i < NI; ++i) {
-        T v = acc[i];
+        double v = acc[i];
         for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         if (lc == 0) s_red[0][16 * w + RPI * i + lr] = v;
       }
@@ -1380,50 +1448,103 @@ __global__ __launch_bounds__(256) void tile_mv_kernel(MvArgs A) {
     __syncthreads();
     const int a = k * NB + tid;
     const bool live = tid < NB && a >= D.n_I && a < D.n_R;
-    if (TRANS) {
-      const T* bt = tiles + (tbase + tri_tile(D.T, k)) * int64_t(NB * NB);
-      if (tid < NB) {
-        double v = double(s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid]);
-        if (live && D.n_P > 0) {
-          const double* pp = A.ppi + int64_t(s) * MAX_NCI;
-          for (int c = 0; c < D.n_P; ++c) v += double(bt[(D.n_A + c) * NB + tid]) * pp[c];
-        }
-        const T o = live ? T(v) : T(0);
-        s_out[tid] = o;
-        reinterpret_cast<T*>(A.xout)[D.vec_off + a] = o;
+    const double* bt = A.tiles + (D.tile_off + tri_tile(D.T, k)) * int64_t(NB * NB);   // border tile row
+    if (tid < NB) {
+      double v = TRANS ? (s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid]) : s_red[0][tid];
+      if (MODE == IMV_OP_T && live && D.n_P > 0) {
+        const double* zc = A.loc_in + D.loc_off + D.n_R;
+        for (int c = 0; c < D.n_P; ++c) v += bt[(D.n_A + c) * NB + tid] * zc[c];
       }
-      __syncthreads();
-      if (tid < D.n_P) {
-        double v = 0.0;
-        for (int r = 0; r < NB; ++r) v += double(bt[(D.n_A + tid) * NB + r]) * double(s_out[r]);
-        A.part[(D.vec_off / NB + k) * MAX_NCI + tid] = v;
-      }
-    } else if (live) {
-      const int64_t l = D.loc_off + a;
-      A.sploc[l] = double(s_red[0][tid]) / A.dsc[l];
+      if (!live) v = 0.0;
+      s_out[tid] = v;
+      if (MODE == IMV_OP_T || MODE == IMV_PC_N) A.xout[D.vec_off + a] = v;
+      if (MODE == IMV_OP_N && live) A.sploc[D.loc_off + a] = v / A.dsc[D.loc_off + a];
+      if (MODE == IMV_PC_T && live) A.ww[D.loc_off + a] = A.wd[D.loc_off + a] * v;
+    }
+    __syncthreads();
+    if (MODE == IMV_OP_T && tid < D.n_P) {
+      double v = 0.0;
+      for (int r = 0; r < NB; ++r) v += bt[(D.n_A + tid) * NB + r] * s_out[r];
+      A.part[(D.vec_off / NB + k) * MAX_NCI + tid] = v;
+    }
+    if (MODE == IMV_PC_N && tid < D.n_ci) {
+      double v = 0.0;
+      for (int r = 0; r < NB; ++r) v += bt[tid * NB + r] * s_out[r];
+      A.part[(D.vec_off / NB + k) * MAX_NCI + tid] = v;
+    }
+    if (MODE == IMV_OP_N && k == j0 && tid < D.n_P) {
+      // corners: (S p)_Pi = W_Pi,G^T q + (A_PiPi - W_Pi^T W_Pi) p_Pi
+      double v = 0.0;
+      const int64_t base = (D.vec_off / NB) * MAX_NCI;
+      for (int kk = j0; kk < D.T; ++kk) v += A.part[base + int64_t(kk) * MAX_NCI + tid];
+      const double* m = A.cpp + int64_t(s) * MAX_NCI * MAX_NCI;
+      const double* zc = A.loc_in + D.loc_off + D.n_R;
+      for (int q = 0; q < D.n_P; ++q) v += m[tid * MAX_NCI + q] * zc[q];
+      A.sploc[D.loc_off + D.n_R + tid] = v;
     }
     __syncthreads();
   }
 }
 
-// corners: (S p)_Pi = sum_k partials + (A_PiPi - W_Pi^T W_Pi) p_Pi
-__global__ __launch_bounds__(64) void corner_sp_kernel(const MatDesc* mats, const double* part, const double* cpp,
-                                                       const double* ppi, double* sploc, const int* done) {
-  if (done && *done) return;
-  const int s = blockIdx.x;
-  const MatDesc D = mats[s];
-  const int c = threadIdx.x;
-  if (c >= D.n_P) return;
+// t' = t + W coef on the interface rows of tile row k, with the coefficients of the
+// coarse correction computed in place:
+//   u = R_ci u_c, coef_A = -mu + S_A^{-1} u_A + S_A^{-1} E u_Pi, coef_Pi = -u_Pi;
+// the task k = j0 also writes the corner outputs W_Pi u_Pi.
+__global__ __launch_bounds__(64) void border_correct_kernel(IfaceArgs A) {
+  __shared__ double u[MAX_NCI];
+  __shared__ double cf[MAX_NCI];
+  if (A.sc->done) return;
+  const int task = blockIdx.x;
+  const int s = A.tasks[2 * task], k = A.tasks[2 * task + 1];
+  const MatDesc D = A.mats[s];
+  const int tid = threadIdx.x;
+  const int nA = D.n_A, nP = D.n_P;
+  if (tid < D.n_ci) u[tid] = A.uc[A.rc[D.coarse_off + tid]];
+  __syncthreads();
+  if (tid < D.n_ci) {
+    const double* so = A.sainv + int64_t(s) * MAX_NCI * MAX_NCI;
+    const double* se = A.sainve + int64_t(s) * MAX_NCI * MAX_NCI;
+    double v;
+    if (tid < nA) {
+      v = -A.mu[int64_t(s) * MAX_NCI + tid];
+      for (int t = 0; t < nA; ++t) v += so[tid * MAX_NCI + t] * u[t];
+      for (int q = 0; q < nP; ++q) v += se[tid * MAX_NCI + q] * u[nA + q];
+    } else {
+      v = -u[tid];
+      if (k == D.n_I / NB) {
+        const int64_t l = D.loc_off + D.n_R + (tid - nA);
+        A.ww[l] = A.wgt[l] * u[tid];
+      }
+    }
+    cf[tid] = v;
+  }
+  __syncthreads();
+  const int a = k * NB + tid;
   double v = 0.0;
-  const int64_t base = (D.vec_off / NB) * MAX_NCI;
-  for (int k = D.n_I / NB; k < D.T; ++k) v += part[base + int64_t(k) * MAX_NCI + c];
-  const double* m = cpp + int64_t(s) * MAX_NCI * MAX_NCI;
-  const double* pp = ppi + int64_t(s) * MAX_NCI;
-  for (int q = 0; q < D.n_P; ++q) v += m[c * MAX_NCI + q] * pp[q];
-  sploc[D.loc_off + D.n_R + c] = v;
+  if (a >= D.n_I && a < D.n_R) {
+    v = A.xin[D.vec_off + a];
+    const double* bt = A.tiles + (D.tile_off + tri_tile(D.T, k)) * int64_t(NB * NB);
+    for (int c = 0; c < D.n_ci; ++c) v += bt[c * NB + tid] * cf[c];
+  }
+  A.xout[D.vec_off + a] = v;
 }
 
-// q = sum_i R_i^T S_i p_i on interface dofs; p = z + beta p; partial sums of p.q;
+void launch_iface_mv(int mode, const IfaceArgs& a, int grid, hipStream_t st) {
+  if (a.ntasks <= 0) return;
+  switch (mode) {
+    case IMV_OP_T: hipLaunchKernelGGL(iface_mv_kernel<IMV_OP_T>, dim3(grid), dim3(256), 0, st, a); break;
+    case IMV_OP_N: hipLaunchKernelGGL(iface_mv_kernel<IMV_OP_N>, dim3(grid), dim3(256), 0, st, a); break;
+    case IMV_PC_N: hipLaunchKernelGGL(iface_mv_kernel<IMV_PC_N>, dim3(grid), dim3(256), 0, st, a); break;
+    case IMV_PC_T: hipLaunchKernelGGL(iface_mv_kernel<IMV_PC_T>, dim3(grid), dim3(256), 0, st, a); break;
+  }
+}
+
+void launch_border_correct(const IfaceArgs& a, hipStream_t st) {
+  if (a.ntasks <= 0) return;
+  hipLaunchKernelGGL(border_correct_kernel, dim3(a.ntasks), dim3(64), 0, st, a);
+}
+
+// q = S p = sum_i R_i^T S_i z_i + beta q on interface dofs; p = z + beta p; partial sums of p.q;
 // block 0 records rz[it] (and beta[it-1])
 __global__ __launch_bounds__(VBLK) void gather_sp_kernel(const int32_t* inv_ptr, const int32_t* inv,
                                                          const double* sploc, const uint8_t* kappa, const double* z,
@@ -1444,9 +1565,10 @@ __global__ __launch_bounds__(VBLK) void gather_sp_kernel(const int32_t* inv_ptr,
     double v = 0.0;
     for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) v += sploc[inv[j]];
     const double pv = fresh ? z[g] : z[g] + beta * p[g];
+    const double qv = fresh ? v : v + beta * q[g];   // S p = S z + beta S p_old
     p[g] = pv;
-    q[g] = v;
-    pq += pv * v;
+    q[g] = qv;
+    pq += pv * qv;
   }
   const double t = block_sum(pq, sh);
   if (threadIdx.x == 0) part_pq[blockIdx.x] = t;
@@ -1456,9 +1578,18 @@ __global__ __launch_bounds__(VBLK) void gather_sp_kernel(const int32_t* inv_ptr,
 // partial sums of r.z
 __global__ __launch_bounds__(VBLK) void gather_z_kernel(const int32_t* inv_ptr, const int32_t* inv, const double* ww,
                                                         const uint8_t* kappa, const double* r, double* z,
-                                                        double* part_rz, int64_t n, const int* done) {
+                                                        double* part_rz, int64_t n, const int* done,
+                                                        double* pubc, int64_t n_pubc, unsigned* tickets,
+                                                        const double* dsc, double* zloc) {
   __shared__ double sh[VBLK / 64];
   if (done && *done) return;
+  {
+    // the next application's coarse solve starts from sentinels and zero tickets
+    unsigned long long* qc = reinterpret_cast<unsigned long long*>(pubc);
+    const int64_t i0 = blockIdx.x * int64_t(VBLK) + threadIdx.x;
+    for (int64_t i = i0; i < n_pubc; i += int64_t(gridDim.x) * VBLK) qc[i] = Traits<double>::SENT;
+    if (i0 < 8) tickets[i0] = 0u;
+  }
   double rz = 0.0;
   for (int64_t g = blockIdx.x * int64_t(VBLK) + threadIdx.x; g < n; g += int64_t(gridDim.x) * VBLK) {
     if (kappa[g] < 2) continue;
@@ -1466,6 +1597,7 @@ __global__ __launch_bounds__(VBLK) void gather_z_kernel(const int32_t* inv_ptr, 
     for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) v += ww[inv[j]];
     z[g] = v;
     rz += r[g] * v;
+    for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) zloc[inv[j]] = v / dsc[inv[j]];
   }
   const double t = block_sum(rz, sh);
   if (threadIdx.x == 0) part_rz[blockIdx.x] = t;
@@ -1497,29 +1629,8 @@ void launch_reset(bool fp32, void* pub, int64_t n_pub, double* pubc, int64_t n_p
                        done);
 }
 
-void launch_iface_local(const MatDesc* mats, int nmats, int max_len, const int32_t* gmap, const double* dsc,
-                        const double* z, const double* p, const double* part_rz, const PcgScalars* sc, int it,
-                        int fresh, void* vloc, bool fp32, double* ppi, hipStream_t st) {
-  dim3 grid((max_len + VBLK - 1) / VBLK, nmats);
-  hipLaunchKernelGGL(iface_local_kernel, grid, dim3(VBLK), 0, st, mats, gmap, dsc, z, p, part_rz, sc, it, fresh, vloc,
-                     fp32, ppi);
-}
 
-void launch_tile_mv(bool trans, bool fp32, const MvArgs& a, int grid, hipStream_t st) {
-  if (a.ntasks <= 0) return;
-  if (fp32) {
-    if (trans) hipLaunchKernelGGL((tile_mv_kernel<float, true>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((tile_mv_kernel<float, false>), dim3(grid), dim3(256), 0, st, a);
-  } else {
-    if (trans) hipLaunchKernelGGL((tile_mv_kernel<double, true>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((tile_mv_kernel<double, false>), dim3(grid), dim3(256), 0, st, a);
-  }
-}
 
-void launch_corner_sp(const MatDesc* mats, int nmats, const double* part, const double* cpp, const double* ppi,
-                      double* sploc, const int* done, hipStream_t st) {
-  hipLaunchKernelGGL(corner_sp_kernel, dim3(nmats), dim3(64), 0, st, mats, part, cpp, ppi, sploc, done);
-}
 
 void launch_gather_sp(const int32_t* inv_ptr, const int32_t* inv, const double* sploc, const uint8_t* kappa,
                       const double* z, double* p, double* q, const double* part_rz, double* part_pq, PcgScalars* sc,
@@ -1529,9 +1640,10 @@ void launch_gather_sp(const int32_t* inv_ptr, const int32_t* inv, const double* 
 }
 
 void launch_gather_z(const int32_t* inv_ptr, const int32_t* inv, const double* ww, const uint8_t* kappa,
-                     const double* r, double* z, double* part_rz, int64_t n, const int* done, hipStream_t st) {
+                     const double* r, double* z, double* part_rz, int64_t n, const int* done, double* pubc,
+                     int64_t n_pubc, unsigned* tickets, const double* dsc, double* zloc, hipStream_t st) {
   hipLaunchKernelGGL(gather_z_kernel, dim3(VEC_GRID), dim3(VBLK), 0, st, inv_ptr, inv, ww, kappa, r, z, part_rz, n,
-                     done);
+                     done, pubc, n_pubc, tickets, dsc, zloc);
 }
 
 // ---------------------------------------------------------------------------

@@ -285,6 +285,16 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
     P.maxTx = std::max(P.maxTx, int(D.Tx));
     P.maxTI = std::max(P.maxTI, int(D.TI));
   }
+  {
+    int64_t xg = 0;
+    for (auto& D : P.subs) {
+      const int TG = D.T - D.n_I / NB;
+      D.xg_off = xg;
+      xg += tri_tile(TG, 0);
+      P.maxTG = std::max(P.maxTG, TG);
+    }
+    P.n_xg = xg;
+  }
   P.n_tiles = tile_off;
   P.n_dinv = dinv_off;
   P.n_vec = vec_off;
