@@ -177,7 +177,11 @@ int bddc_plan_stats(const bddc_mesh* mesh, const bddc_partition* part,
  * "trsv_bwd_ii" (full-space solves), "op_t", "op_n" (the two triangular
  * mat-vecs of the interface Schur operator), "pc_n", "pc_t" (the two
  * triangular mat-vecs of the interface preconditioner), "schur" (the whole
- * operator), "spmv", "apply".  Unknown names give EINVAL. */
+ * operator), "spmv", "apply".  While timing is enabled, PCG iterations are
+ * launched eagerly even when use_graph is set.  Launches that returned at once
+ * because the solve had already converged (shorter than a fifth of the
+ * family's longest) are not counted.  Each query resets the family.
+ * Unknown names give EINVAL. */
 int bddc_set_timing(bddc_ctx* ctx, int32_t enabled);
 int bddc_kernel_time(bddc_ctx* ctx, const char* family, int64_t* launches,
                      double* total_ms);
@@ -194,6 +198,18 @@ int bddc_kernel_time(bddc_ctx* ctx, const char* family, int64_t* launches,
  *       "dscale" -> equilibration factor of each local dof (n_i values).
  * Returns the number of values written (<= cap) or a negative status. */
 int64_t bddc_debug_read(bddc_ctx* ctx, const char* what, int32_t sub, double* host_out, int64_t cap);
+
+/* Launch shape of the persistent kernels (triangular solves and tile
+ * mat-vecs): wg_per_cu resident workgroups per compute unit, 1..16 (default
+ * 4).  Captured graphs are dropped and recaptured with the new shape. */
+int bddc_set_tuning(bddc_ctx* ctx, int32_t wg_per_cu);
+
+/* Autotuner: for each of the ncand candidate wg_per_cu values, runs `iters`
+ * PCG iterations on a fixed right-hand side (after one untimed warm-up run)
+ * and times them with HIP events; keeps the fastest setting.  *best receives
+ * it and ms_out[i] (may be NULL) the time of candidate i.  Synchronous. */
+int bddc_autotune(bddc_ctx* ctx, const int32_t* candidates, int32_t ncand, int32_t iters, int32_t* best,
+                  double* ms_out);
 
 /* Frees every device and host resource of ctx (NULL is allowed). */
 void bddc_destroy(bddc_ctx* ctx);

@@ -46,7 +46,7 @@ class PcgInfo(ctypes.Structure):
 
 EXPORTS = ["bddc_setup", "bddc_apply", "bddc_pcg_solve", "bddc_spmv", "bddc_elem_grad", "bddc_query",
            "bddc_plan_stats", "bddc_set_timing", "bddc_kernel_time", "bddc_destroy", "bddc_strerror",
-           "bddc_last_error", "bddc_debug_read"]
+           "bddc_last_error", "bddc_debug_read", "bddc_set_tuning", "bddc_autotune"]
 
 _lib = None
 
@@ -73,6 +73,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bddc_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
     lib.bddc_debug_read.argtypes = [vp, ctypes.c_char_p, i32, ctypes.POINTER(dbl), i64]
     lib.bddc_debug_read.restype = ctypes.c_int64
+    lib.bddc_set_tuning.argtypes = [vp, i32]
+    lib.bddc_set_tuning.restype = ctypes.c_int
+    lib.bddc_autotune.argtypes = [vp, ctypes.POINTER(i32), i32, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    lib.bddc_autotune.restype = ctypes.c_int
     lib.bddc_destroy.argtypes = [vp]
     lib.bddc_destroy.restype = None
     lib.bddc_strerror.argtypes = [ctypes.c_int]
@@ -172,6 +176,11 @@ class Solver:
                "bddc_query")
         self.n_free, self.n_sub, self.n_coarse, self.dev_bytes = n.value, ns.value, nc.value, nb.value
         self.n_el = int(np.prod(self.nel))
+        self.wg_per_cu = 4
+        box = sorted({tuple(int(c[i + 1] - c[i]) for i in range(len(c) - 1)) for c in
+                      (np.asarray(cc) for cc in cuts[:dim])})
+        self.tune_key = (f"dim{dim}|nel{'x'.join(map(str, self.nel))}|boxes{box}|bits{local_bits}|"
+                         f"{'full' if (full_space or local_bits == 32) else 'iface'}|graph{int(use_graph)}")
 
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
@@ -236,6 +245,45 @@ class Solver:
         if n < 0:
             _check(int(n), "bddc_debug_read")
         return buf[:n]
+
+    def set_tuning(self, wg_per_cu: int):
+        _check(self.lib.bddc_set_tuning(self.ctx, int(wg_per_cu)), "bddc_set_tuning")
+        self.wg_per_cu = int(wg_per_cu)
+
+    def autotune(self, candidates=(1, 2, 3, 4, 6, 8), iters: int = 8, cache: Optional[str] = None):
+        """Pick the persistent-kernel launch shape by timing short PCG runs; the
+        choice is cached in a JSON file keyed by GPU architecture and problem
+        shape (cache=None: ~/.cache/bddc/autotune.json, "" disables caching)."""
+        import json
+        import torch
+        if cache is None:
+            cache = os.path.join(os.path.expanduser("~"), ".cache", "bddc", "autotune.json")
+        arch = torch.cuda.get_device_properties(0).gcnArchName if torch.cuda.is_available() else "cpu"
+        key = f"{arch}|{self.tune_key}"
+        table = {}
+        if cache:
+            try:
+                with open(cache) as f:
+                    table = json.load(f)
+            except (OSError, ValueError):
+                table = {}
+            if key in table:
+                self.set_tuning(table[key]["wg_per_cu"])
+                return table[key]
+        cand = (ctypes.c_int32 * len(candidates))(*candidates)
+        ms = (ctypes.c_double * len(candidates))()
+        best = ctypes.c_int32()
+        _check(self.lib.bddc_autotune(self.ctx, cand, len(candidates), int(iters), ctypes.byref(best), ms),
+               "bddc_autotune")
+        self.wg_per_cu = best.value
+        rec = {"wg_per_cu": best.value, "candidates": list(candidates), "ms": [round(v, 4) for v in ms],
+               "iters": iters}
+        if cache:
+            table[key] = rec
+            os.makedirs(os.path.dirname(cache), exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1)
+        return rec
 
     def set_timing(self, on: bool):
         _check(self.lib.bddc_set_timing(self.ctx, int(on)), "bddc_set_timing")

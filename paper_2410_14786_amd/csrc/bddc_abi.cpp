@@ -79,9 +79,14 @@ double lanczos_cond(const std::vector<double>& alpha, const std::vector<double>&
 }
 
 struct TimedFamily {
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-  int64_t launches = 0;
-  double total_ms = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;   // eager launches (pooled events)
+  std::vector<float> durations;                             // collected, not yet reported
+};
+
+// event pair recorded inside a captured graph (owned by the graph)
+struct GraphTimed {
+  std::string family;
+  hipEvent_t b, e;
 };
 
 }  // namespace
@@ -97,6 +102,8 @@ struct bddc_ctx {
   int64_t dev_bytes = 0;
   int cus = 256;
   int grid_trsv = 1024;
+  int wg_per_cu = 4;
+  double *tune_b = nullptr, *tune_x = nullptr;
 
   double* theta = nullptr;
   int32_t *rowptr = nullptr, *col = nullptr;
@@ -117,10 +124,12 @@ struct bddc_ctx {
   int32_t *ctask_fwd = nullptr, *ctask_bwd = nullptr;
   int Tc = 0;
   int32_t *t_fwd_rr = nullptr, *t_bwd_rr = nullptr, *t_fwd_ii = nullptr, *t_bwd_ii = nullptr;
-  int32_t *t_fwd_g = nullptr, *t_bwd_g = nullptr;
+  int32_t *t_fwd_g = nullptr, *t_bwd_g = nullptr, *t_mv_n = nullptr, *t_mv_t = nullptr;
   void *vloc = nullptr, *qloc = nullptr;      // interface form: local work vectors
   double* xg = nullptr;                        // inverses of the trailing factor blocks
   double *zloc = nullptr, *floc = nullptr;     // D^{-1} z and W D r in local-dof order
+  double *cxg = nullptr, *cainv = nullptr, *upart = nullptr;   // explicit coarse inverse (interface form)
+  int csplit = 1;
   double *ppi = nullptr, *sploc = nullptr, *cpp = nullptr;
   int max_loclen = 1;
   void* pub_local = nullptr;   // 4 * n_vec entries of the local precision
@@ -141,8 +150,9 @@ struct bddc_ctx {
   static constexpr int GRAPH_CHUNK = 4;
   hipStream_t gst = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  std::vector<hipGraphExec_t> graphs;
+  std::vector<hipGraphExec_t> graphs;      // index 2k: untimed, 2k+1: with timing events
   std::vector<hipGraph_t> graph_defs;
+  std::vector<std::vector<GraphTimed>> graph_timed;
   double* xw = nullptr;
   int* hsnap = nullptr;               // pinned host copies of (done, iters), two slots
   hipEvent_t snap_ev[2] = {nullptr, nullptr};
@@ -156,6 +166,11 @@ struct bddc_ctx {
       if (g) hipGraphExecDestroy(g);
     for (hipGraph_t g : graph_defs)
       if (g) hipGraphDestroy(g);
+    for (auto& v : graph_timed)
+      for (auto& gt : v) {
+        hipEventDestroy(gt.b);
+        hipEventDestroy(gt.e);
+      }
     if (ev_in) hipEventDestroy(ev_in);
     for (hipEvent_t e : snap_ev)
       if (e) hipEventDestroy(e);
@@ -202,15 +217,28 @@ struct bddc_ctx {
     return e;
   }
   // event pair around a launch of a named family when timing is on
+  // Event pairs around launches of a named family when timing is on.  Inside a
+  // graph capture the events become nodes of the graph (fresh events owned by it).
+  std::vector<GraphTimed>* capture_timed = nullptr;
+  std::vector<GraphTimed> graph_pending;
   hipEvent_t begin(const char* name) {
     if (!timing) return nullptr;
-    hipEvent_t e = get_event();
+    hipEvent_t e = nullptr;
+    if (capture_timed) hipEventCreate(&e);
+    else e = get_event();
     hipEventRecord(e, st);
     return e;
   }
   void end(const char* name, hipEvent_t b) {
     if (!timing || !b) return;
-    hipEvent_t e = get_event();
+    hipEvent_t e = nullptr;
+    if (capture_timed) {
+      hipEventCreate(&e);
+      hipEventRecord(e, st);
+      capture_timed->push_back({name, b, e});
+      return;
+    }
+    e = get_event();
     hipEventRecord(e, st);
     fam[name].pending.push_back({b, e});
   }
@@ -220,13 +248,17 @@ struct bddc_ctx {
       for (auto& pr : kv.second.pending) {
         float ms = 0.f;
         hipEventElapsedTime(&ms, pr.first, pr.second);
-        kv.second.total_ms += ms;
-        kv.second.launches += 1;
+        kv.second.durations.push_back(ms);
         event_pool.push_back(pr.first);
         event_pool.push_back(pr.second);
       }
       kv.second.pending.clear();
     }
+    for (auto& gt : graph_pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, gt.b, gt.e) == hipSuccess) fam[gt.family].durations.push_back(ms);
+    }
+    graph_pending.clear();
   }
 };
 
@@ -387,6 +419,7 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
   IfaceArgs a = iface_args(c);
   a.r = r;
   a.loc_in = c->floc;
+  a.tasks = c->t_mv_n;
   a.ticket = c->tickets + 0;
   a.xout = static_cast<double*>(c->vloc);
   hipEvent_t e = c->begin("pc_n");
@@ -395,33 +428,18 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
   if (P.n_coarse > 0) {
     launch_coarse_prep(c->mats, P.nsubs, c->part, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done, 1,
                        st);
-    TrsvArgs cf;
-    std::memset(&cf, 0, sizeof(cf));
-    cf.mats = c->cmat;
-    cf.tiles = c->ctiles;
-    cf.dinv = c->cdinv;
-    cf.done = done;
-    cf.tasks = c->ctask_fwd;
-    cf.ntasks = c->Tc;
-    cf.ticket = c->tickets + 4;
-    cf.sol = c->pub_coarse;
-    cf.cinv_ptr = c->cinv_ptr;
-    cf.cinv = c->cinv;
-    cf.gbuf = c->gbuf;
-    cf.dc = c->dc;
-    launch_trsv(TRSV_FWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
-    cf.tasks = c->ctask_bwd;
-    cf.ticket = c->tickets + 5;
-    cf.src = c->pub_coarse;
-    cf.sol = c->pub_coarse + int64_t(c->Tc) * NB;
-    cf.uc = c->uc;
-    launch_trsv(TRSV_BWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
+    launch_coarse_gemv(c->cainv, P.n_coarse, c->csplit, c->cinv_ptr, c->cinv, c->gbuf, c->upart, done, st);
   }
+  a.uc = c->upart;
+  a.nc = P.n_coarse;
+  a.nsplit = c->csplit;
   a.xin = static_cast<const double*>(c->vloc);
   a.xout = static_cast<double*>(c->qloc);
+  a.tasks = c->t_fwd_g;
   launch_border_correct(a, st);
   a.xin = static_cast<const double*>(c->qloc);
   a.xout = nullptr;
+  a.tasks = c->t_mv_t;
   a.ticket = c->tickets + 1;
   e = c->begin("pc_t");
   launch_iface_mv(IMV_PC_T, a, trsv_grid(c, a.ntasks), st);
@@ -441,12 +459,14 @@ void enqueue_schur(bddc_ctx* c, int it, bool fresh, const double* part_rz, doubl
   a.fresh = fresh ? 1 : 0;
   a.part_rz = part_rz;
   a.loc_in = c->zloc;
+  a.tasks = c->t_mv_t;
   a.ticket = c->tickets + 2;
   a.xout = static_cast<double*>(c->qloc);
   hipEvent_t e1 = c->begin("op_t");
   launch_iface_mv(IMV_OP_T, a, trsv_grid(c, a.ntasks), st);
   c->end("op_t", e1);
   a.ticket = c->tickets + 3;
+  a.tasks = c->t_mv_n;
   a.xin = static_cast<const double*>(c->qloc);
   a.xout = nullptr;
   e1 = c->begin("op_n");
@@ -517,33 +537,34 @@ int launch_chunk_graph(bddc_ctx* c, double* x, int k) {
     HIP_TRY(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
   }
-  if (int(c->graphs.size()) <= k) {
-    c->graphs.resize(k + 1, nullptr);
-    c->graph_defs.resize(k + 1, nullptr);
+  const int slot = k;
+  if (int(c->graphs.size()) <= slot) {
+    c->graphs.resize(slot + 1, nullptr);
+    c->graph_defs.resize(slot + 1, nullptr);
+    c->graph_timed.resize(slot + 1);
   }
-  if (!c->graphs[k]) {
+  if (!c->graphs[slot]) {
     hipStream_t user = c->st;
-    const bool timing = c->timing;
     c->st = c->gst;
-    c->timing = false;
-    HIP_TRY(hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < bddc_ctx::GRAPH_CHUNK; ++i) {
-      const int it = k * bddc_ctx::GRAPH_CHUNK + i;
-      enqueue_iteration(c, x, it, it == 0);
+    hipError_t e = hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int i = 0; i < bddc_ctx::GRAPH_CHUNK; ++i) {
+        const int it = k * bddc_ctx::GRAPH_CHUNK + i;
+        enqueue_iteration(c, x, it, it == 0);
+      }
     }
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(c->gst, &g);
+    if (e == hipSuccess) e = hipStreamEndCapture(c->gst, &g);
     c->st = user;
-    c->timing = timing;
     if (e != hipSuccess) return fail(BDDC_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
     hipGraphExec_t ex = nullptr;
     HIP_TRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
-    c->graph_defs[k] = g;
-    c->graphs[k] = ex;
+    c->graph_defs[slot] = g;
+    c->graphs[slot] = ex;
   }
   HIP_TRY(hipEventRecord(c->ev_in, c->st));
   HIP_TRY(hipStreamWaitEvent(c->gst, c->ev_in, 0));
-  HIP_TRY(hipGraphLaunch(c->graphs[k], c->gst));
+  HIP_TRY(hipGraphLaunch(c->graphs[slot], c->gst));
   HIP_TRY(hipEventRecord(c->ev_out, c->gst));
   HIP_TRY(hipStreamWaitEvent(c->st, c->ev_out, 0));
   return BDDC_OK;
@@ -584,7 +605,7 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, dev));
   c->cus = prop.multiProcessorCount;
-  c->grid_trsv = std::max(64, c->cus * 4);
+  c->grid_trsv = std::max(64, c->cus * c->wg_per_cu);
 
   // coefficients
   if ((rc_ = c->alloc(c->theta, P.n_el))) return rc_;
@@ -623,6 +644,8 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->upload(c->t_bwd_ii, P.bwd_ii))) return rc_;
   if ((rc_ = c->upload(c->t_fwd_g, P.fwd_g))) return rc_;
   if ((rc_ = c->upload(c->t_bwd_g, P.bwd_g))) return rc_;
+  if ((rc_ = c->upload(c->t_mv_n, P.mv_n))) return rc_;
+  if ((rc_ = c->upload(c->t_mv_t, P.mv_t))) return rc_;
 
   // global matrix
   launch_assemble_csr(c->mesh, c->theta, c->rowptr, c->col, c->val, P.n_free, c->err, st);
@@ -701,6 +724,15 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
     launch_coarse_assembly(c->ac_src_ptr, c->ac_src, c->ac_row, c->ac_col, c->ac_diag, int(P.ac_row.size()), nc,
                            c->aci, c->ac_val, c->dc, c->ctiles, c->err + 2, st);
     launch_factor(c->cmat, 1, c->Tc, c->Tc, c->ctiles, c->cdinv, false, c->err + 2, st);
+    if (c->iface) {
+      // A_c^{-1} = D X^T X D, X = inverse of the coarse Cholesky factor
+      if ((rc_ = c->alloc(c->cxg, tri_tile(c->Tc, 0) * NB * NB))) return rc_;
+      if ((rc_ = c->alloc(c->cainv, int64_t(nc) * nc))) return rc_;
+      c->csplit = (nc + COARSE_SPLIT_COLS - 1) / COARSE_SPLIT_COLS;
+      if ((rc_ = c->alloc(c->upart, int64_t(c->csplit) * nc))) return rc_;
+      launch_trailing_inverse(c->cmat, 1, c->Tc, c->ctiles, c->cdinv, c->cxg, st);
+      launch_coarse_inverse(c->cxg, c->dc, nc, c->cainv, st);
+    }
   }
 
   // apply and PCG work space
@@ -937,7 +969,8 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
     for (;;) {
       while (pending < 2 && it < maxit) {
         const int end = std::min(maxit, it + chunk);
-        if (c->use_graph && fresh == (it == 0) && it % bddc_ctx::GRAPH_CHUNK == 0 &&
+        // per-kernel timing needs eager launches (events are not captured into graphs)
+        if (c->use_graph && !c->timing && fresh == (it == 0) && it % bddc_ctx::GRAPH_CHUNK == 0 &&
             it + bddc_ctx::GRAPH_CHUNK <= maxit && seg_start == 0) {
           if (int rc_ = launch_chunk_graph(c, x, it / bddc_ctx::GRAPH_CHUNK)) return rc_;
           it += bddc_ctx::GRAPH_CHUNK;
@@ -1006,6 +1039,7 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
   }
   if (x != x_user) HIP_TRY(hipMemcpyAsync(x_user, x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
+  if (c->timing) c->collect();
   if (info) {
     info->iters = hs.iters;
     info->relres_true = relres_true;
@@ -1044,12 +1078,22 @@ int bddc_kernel_time(bddc_ctx* c, const char* family, int64_t* launches, double*
   if (!ok) return fail(BDDC_EINVAL, "unknown kernel family");
   c->collect();
   auto it = c->fam.find(family);
-  if (launches) *launches = it == c->fam.end() ? 0 : it->second.launches;
-  if (total_ms) *total_ms = it == c->fam.end() ? 0.0 : it->second.total_ms;
+  int64_t n = 0;
+  double tot = 0.0;
   if (it != c->fam.end()) {
-    it->second.launches = 0;
-    it->second.total_ms = 0.0;
+    // launches that returned at once because the solve had already converged
+    // (queued ahead of the host's convergence check) are not counted
+    float mx = 0.f;
+    for (float d : it->second.durations) mx = std::max(mx, d);
+    for (float d : it->second.durations)
+      if (d >= 0.2f * mx) {
+        ++n;
+        tot += d;
+      }
+    it->second.durations.clear();
   }
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = tot;
   return BDDC_OK;
 }
 
@@ -1116,6 +1160,80 @@ int64_t bddc_debug_read(bddc_ctx* c, const char* what, int32_t sub, double* out,
   const int64_t m = std::min<int64_t>(cap, int64_t(res.size()));
   std::memcpy(out, res.data(), size_t(m) * sizeof(double));
   return m;
+}
+
+namespace {
+void drop_graphs(bddc_ctx* c) {
+  hipStreamSynchronize(c->st);
+  if (c->gst) hipStreamSynchronize(c->gst);
+  for (auto& g : c->graphs)
+    if (g) hipGraphExecDestroy(g);
+  for (auto& g : c->graph_defs)
+    if (g) hipGraphDestroy(g);
+  for (auto& v : c->graph_timed)
+    for (auto& gt : v) {
+      hipEventDestroy(gt.b);
+      hipEventDestroy(gt.e);
+    }
+  c->graphs.clear();
+  c->graph_defs.clear();
+  c->graph_timed.clear();
+  c->graph_pending.clear();
+}
+}  // namespace
+
+int bddc_set_tuning(bddc_ctx* c, int32_t wg_per_cu) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  if (wg_per_cu < 1 || wg_per_cu > 16) return fail(BDDC_EINVAL, "wg_per_cu must be in [1, 16]");
+  drop_graphs(c);
+  c->wg_per_cu = wg_per_cu;
+  c->grid_trsv = std::max(64, c->cus * wg_per_cu);
+  return BDDC_OK;
+}
+
+int bddc_autotune(bddc_ctx* c, const int32_t* cand, int32_t ncand, int32_t iters, int32_t* best, double* ms_out) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  if (!cand || ncand < 1 || iters < 1 || iters > 256) return fail(BDDC_EINVAL, "bad autotune arguments");
+  for (int i = 0; i < ncand; ++i)
+    if (cand[i] < 1 || cand[i] > 16) return fail(BDDC_EINVAL, "candidates must be in [1, 16]");
+  const int64_t n = c->plan.n_free;
+  if (!c->tune_b) {
+    if (int rc_ = c->alloc(c->tune_b, n)) return rc_;
+    if (int rc_ = c->alloc(c->tune_x, n)) return rc_;
+    launch_fill<double>(c->tune_b, 1.0, n, c->st);
+  }
+  const bool timing = c->timing;
+  c->timing = false;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double best_ms = 1e300;
+  int best_v = c->wg_per_cu;
+  for (int i = 0; i < ncand; ++i) {
+    if (int rc_ = bddc_set_tuning(c, cand[i])) return rc_;
+    bddc_pcg_info info;
+    double ms_i = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {   // the first run captures graphs and warms caches
+      HIP_TRY(hipEventRecord(e0, c->st));
+      int rc_ = bddc_pcg_solve(c, c->tune_b, c->tune_x, 1e-30, iters, 0, &info);
+      if (rc_ != BDDC_OK && rc_ != BDDC_ENOCONV) return rc_;
+      HIP_TRY(hipEventRecord(e1, c->st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (rep == 1) ms_i = ms;
+    }
+    if (ms_out) ms_out[i] = ms_i;
+    if (ms_i < best_ms) {
+      best_ms = ms_i;
+      best_v = cand[i];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->timing = timing;
+  if (best) *best = best_v;
+  return bddc_set_tuning(c, best_v);
 }
 
 void bddc_destroy(bddc_ctx* c) {

@@ -78,7 +78,7 @@ struct Plan {
   std::vector<int32_t> ac_diag;          // entry index of (p, p)
 
   // ticket-ordered task lists of the triangular solves, (matrix, tile row)
-  std::vector<int32_t> fwd_rr, bwd_rr, fwd_ii, bwd_ii, fwd_g, bwd_g;
+  std::vector<int32_t> fwd_rr, bwd_rr, fwd_ii, bwd_ii, fwd_g, bwd_g, mv_n, mv_t;
 
   int maxT = 0, maxTx = 0, maxTI = 0;
   int64_t n_tiles = 0, n_dinv = 0, n_vec = 0, n_loc = 0, n_lmap = 0, n_xg = 0;

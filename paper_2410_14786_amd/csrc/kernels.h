@@ -98,7 +98,9 @@ struct IfaceArgs {
   const double* cpp;        // A_PiPi - W_Pi^T W_Pi
   double* sploc;            // (S p) per local dof
   double* ww;               // weighted local preconditioner output
-  const double* uc;
+  const double* uc;        // coarse solution as nsplit column-split partials of nc values
+  int nc;
+  int nsplit;
   const int32_t* rc;
   const double* mu;
   const double* sainv;
@@ -171,6 +173,10 @@ void launch_scatter_local(const int32_t* inv_ptr, const int32_t* inv, const doub
 enum { IMV_OP_T = 0, IMV_OP_N = 1, IMV_PC_N = 2, IMV_PC_T = 3 };
 void launch_iface_mv(int mode, const IfaceArgs& a, int grid, hipStream_t st);
 void launch_border_correct(const IfaceArgs& a, hipStream_t st);
+constexpr int COARSE_SPLIT_COLS = 512;   // columns of A_c^{-1} per coarse GEMV block
+void launch_coarse_inverse(const double* xg, const double* dc, int nc, double* ainv, hipStream_t st);
+void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* cinv_ptr, const int32_t* cinv,
+                        const double* gbuf, double* upart, const int* done, hipStream_t st);
 void launch_trailing_inverse(const MatDesc* mats, int nmats, int maxTG, const double* tiles, const double* dinv,
                              double* xg, hipStream_t st);
 

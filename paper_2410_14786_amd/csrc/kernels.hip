@@ -858,10 +858,10 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     if ((MODE == TRSV_FWD_RR || MODE == TRSV_FWD_G) && D.n_ci > 0) {
       // partial border products h_c = sum_r W^T[c][r] y_k[r] for this tile row
       const T* bt = tiles + (tbase + tri_tile(D.T, k)) * int64_t(NB * NB);
-      if (tid < D.n_ci) {
-        double v = 0.0;
-        for (int r = 0; r < NB; ++r) v += double(bt[tid * NB + r]) * double(s_out[r]);
-        A.part[(D.vec_off / NB + k) * MAX_NCI + tid] = v;
+      for (int c = w; c < D.n_ci; c += 4) {   // one wave per constraint row, coalesced
+        double v = double(bt[c * NB + lane]) * double(s_out[lane]);
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) A.part[(D.vec_off / NB + k) * MAX_NCI + c] = v;
       }
     } else if (MODE == TRSV_BWD_RR || MODE == TRSV_BWD_G) {
       if (tid < NB) {
@@ -1354,6 +1354,61 @@ void launch_trailing_inverse(const MatDesc* mats, int nmats, int maxTG, const do
     hipLaunchKernelGGL(trailing_inverse_kernel, dim3(ii + 1, nmats), dim3(256), 0, st, mats, tiles, dinv, xg, ii);
 }
 
+// Explicit coarse inverse for the interface iteration: A_c^{-1} = D X^T X D with
+// X = L_c^{-1} (L_c the Cholesky factor of the equilibrated D A_c D), row-major dense.
+__global__ void coarse_inverse_kernel(const double* xg, const double* dc, int nc, double* ainv) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= nc) return;
+  double v = 0.0;
+  for (int k = max(i, j); k < nc; ++k) {
+    const double* ti = xg + (tri_tile(k / NB, i / NB)) * int64_t(NB * NB) + (k % NB) * NB;
+    const double* tj = xg + (tri_tile(k / NB, j / NB)) * int64_t(NB * NB) + (k % NB) * NB;
+    v += ti[i % NB] * tj[j % NB];
+  }
+  ainv[int64_t(i) * nc + j] = dc[i] * v * dc[j];
+}
+
+void launch_coarse_inverse(const double* xg, const double* dc, int nc, double* ainv, hipStream_t st) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(coarse_inverse_kernel, dim3((nc + 255) / 256, nc), dim3(256), 0, st, xg, dc, nc, ainv);
+}
+
+// u_c = A_c^{-1} r_c with r_c = sum_i R_ci^T g_i gathered per column block; block
+// (row block of 64 rows, column split s) writes its partial u into upart[s*nc + i]
+__global__ __launch_bounds__(256) void coarse_gemv_kernel(const double* ainv, int nc, int cs,
+                                                          const int32_t* cinv_ptr, const int32_t* cinv,
+                                                          const double* gbuf, double* upart, const int* done) {
+  __shared__ double rcs[COARSE_SPLIT_COLS];
+  if (done && *done) return;
+  const int s = blockIdx.y;
+  const int j0 = s * cs, j1 = min(nc, j0 + cs);
+  for (int j = j0 + threadIdx.x; j < j1; j += 256) {
+    double v = 0.0;
+    for (int q = cinv_ptr[j]; q < cinv_ptr[j + 1]; ++q) v += gbuf[cinv[q]];
+    rcs[j - j0] = v;
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int rr = 0; rr < 16; ++rr) {
+    const int i = blockIdx.x * 64 + w * 16 + rr;
+    if (i >= nc) break;
+    const double* row = ainv + int64_t(i) * nc;
+    double v = 0.0;
+    for (int j = j0 + lane; j < j1; j += 64) v += row[j] * rcs[j - j0];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) upart[int64_t(s) * nc + i] = v;
+  }
+}
+
+void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* cinv_ptr, const int32_t* cinv,
+                        const double* gbuf, double* upart, const int* done, hipStream_t st) {
+  if (nc <= 0) return;
+  const int cs = (nc + nsplit - 1) / nsplit;
+  hipLaunchKernelGGL(coarse_gemv_kernel, dim3((nc + 63) / 64, nsplit), dim3(256), 0, st, ainv, nc, cs, cinv_ptr,
+                     cinv, gbuf, upart, done);
+}
+
 // One kernel for the four interface mat-vecs (see above); task = (matrix, tile row k)
 // for k = n_I/64 .. T-1.
 //   OP_T: q_k = sum_{j>=k} L(j,k)^T v_j + W_Pi(k) z_Pi, v = D^{-1} z (the operator is
@@ -1406,10 +1461,15 @@ __global__ __launch_bounds__(256) void iface_mv_kernel(IfaceArgs A) {
     const int jfirst = TRANS ? k : j0;
     double acc[TRANS ? VEC : NI];
     for (int i = 0; i < (TRANS ? VEC : NI); ++i) acc[i] = 0.0;
-    V cur[NI], nxt[NI];
+    // two tiles in flight ahead of the one being multiplied
+    V cur[NI], nx1[NI], nx2[NI];
     {
       const double* pp = tile_ptr(0);
       for (int i = 0; i < NI; ++i) cur[i] = *reinterpret_cast<const V*>(pp + i * RPI * NB);
+      if (nt > 1) {
+        pp = tile_ptr(1);
+        for (int i = 0; i < NI; ++i) nx1[i] = *reinterpret_cast<const V*>(pp + i * RPI * NB);
+      }
     }
     for (int jj = 0; jj < nt; ++jj) {
       const int rb = (jfirst + jj) * NB;
@@ -1419,9 +1479,9 @@ __global__ __launch_bounds__(256) void iface_mv_kernel(IfaceArgs A) {
       } else {
         for (int e = 0; e < VEC; ++e) xv[e] = input(rb + VEC * lc + e);
       }
-      if (jj + 1 < nt) {
-        const double* pp = tile_ptr(jj + 1);
-        for (int i = 0; i < NI; ++i) nxt[i] = *reinterpret_cast<const V*>(pp + i * RPI * NB);
+      if (jj + 2 < nt) {
+        const double* pp = tile_ptr(jj + 2);
+        for (int i = 0; i < NI; ++i) nx2[i] = *reinterpret_cast<const V*>(pp + i * RPI * NB);
       }
       if (TRANS) {
         for (int i = 0; i < NI; ++i)
@@ -1430,7 +1490,10 @@ __global__ __launch_bounds__(256) void iface_mv_kernel(IfaceArgs A) {
         for (int i = 0; i < NI; ++i)
           for (int e = 0; e < VEC; ++e) acc[i] += cur[i][e] * xv[e];
       }
-      for (int i = 0; i < NI; ++i) cur[i] = nxt[i];
+      for (int i = 0; i < NI; ++i) {
+        cur[i] = nx1[i];
+        nx1[i] = nx2[i];
+      }
     }
     if (TRANS) {
       for (int e = 0; e < VEC; ++e) {
@@ -1462,15 +1525,16 @@ __global__ __launch_bounds__(256) void iface_mv_kernel(IfaceArgs A) {
       if (MODE == IMV_PC_T && live) A.ww[D.loc_off + a] = A.wd[D.loc_off + a] * v;
     }
     __syncthreads();
-    if (MODE == IMV_OP_T && tid < D.n_P) {
-      double v = 0.0;
-      for (int r = 0; r < NB; ++r) v += bt[(D.n_A + tid) * NB + r] * s_out[r];
-      A.part[(D.vec_off / NB + k) * MAX_NCI + tid] = v;
-    }
-    if (MODE == IMV_PC_N && tid < D.n_ci) {
-      double v = 0.0;
-      for (int r = 0; r < NB; ++r) v += bt[tid * NB + r] * s_out[r];
-      A.part[(D.vec_off / NB + k) * MAX_NCI + tid] = v;
+    if (MODE == IMV_OP_T || MODE == IMV_PC_N) {
+      // partial border products: one wave per constraint row, lanes over the
+      // 64 columns (coalesced row reads), wave reduction
+      const int c0 = (MODE == IMV_OP_T) ? D.n_A : 0;
+      const int nrows = (MODE == IMV_OP_T) ? D.n_P : D.n_ci;
+      for (int c = w; c < nrows; c += 4) {
+        double v = bt[(c0 + c) * NB + lane] * s_out[lane];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) A.part[(D.vec_off / NB + k) * MAX_NCI + c] = v;
+      }
     }
     if (MODE == IMV_OP_N && k == j0 && tid < D.n_P) {
       // corners: (S p)_Pi = W_Pi,G^T q + (A_PiPi - W_Pi^T W_Pi) p_Pi
@@ -1499,7 +1563,12 @@ __global__ __launch_bounds__(64) void border_correct_kernel(IfaceArgs A) {
   const MatDesc D = A.mats[s];
   const int tid = threadIdx.x;
   const int nA = D.n_A, nP = D.n_P;
-  if (tid < D.n_ci) u[tid] = A.uc[A.rc[D.coarse_off + tid]];
+  if (tid < D.n_ci) {
+    const int pc = A.rc[D.coarse_off + tid];
+    double v = 0.0;
+    for (int q = 0; q < A.nsplit; ++q) v += A.uc[int64_t(q) * A.nc + pc];
+    u[tid] = v;
+  }
   __syncthreads();
   if (tid < D.n_ci) {
     const double* so = A.sainv + int64_t(s) * MAX_NCI * MAX_NCI;

@@ -385,6 +385,24 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
           P.bwd_g.push_back(D.T - 1 - d);
         }
       }
+    // the interface mat-vecs have independent tasks: take the longest first
+    // (tile row k streams k - k0 + 1 tiles, its transpose T - k)
+    struct Job { int len, s, k; };
+    std::vector<Job> jn, jt;
+    for (int s = 0; s < P.nsubs; ++s) {
+      const MatDesc& D = P.subs[s];
+      for (int k = D.n_I / NB; k < D.T; ++k) {
+        jn.push_back({k - D.n_I / NB + 1, s, k});
+        jt.push_back({D.T - k, s, k});
+      }
+    }
+    auto by_len = [](const Job& a, const Job& b) {
+      return a.len != b.len ? a.len > b.len : (a.s != b.s ? a.s < b.s : a.k < b.k);
+    };
+    std::sort(jn.begin(), jn.end(), by_len);
+    std::sort(jt.begin(), jt.end(), by_len);
+    for (auto& j : jn) { P.mv_n.push_back(j.s); P.mv_n.push_back(j.k); }
+    for (auto& j : jt) { P.mv_t.push_back(j.s); P.mv_t.push_back(j.k); }
   }
   return BDDC_OK;
 }

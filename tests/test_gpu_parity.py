@@ -270,3 +270,40 @@ def test_graph_replays_match_eager(full_space):
             assert np.array_equal(host(x), xr), (rep, key)
     Se.close()
     Sg.close()
+
+
+def test_kernel_timing_with_graph_solver():
+    """Timing switches a graph-replaying solver to eager launches."""
+    w, P = oracle_for("3d_16_2x2x2")
+    S = bd().solver_for(w, use_graph=True)
+    S.set_timing(True)
+    for _ in range(2):
+        x, info = S.solve(dev(w.b), 1e-10)
+    for fam in ("op_t", "op_n", "pc_n", "pc_t"):
+        n, ms = S.kernel_time(fam)
+        assert n >= 2 * info["iters"] - 2 and ms > 0, (fam, n, ms)
+    S.set_timing(False)
+    S.close()
+
+
+@pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
+def test_autotune_keeps_results_bitwise(full_space, tmp_path):
+    """The launch shape changes only how tasks are spread over workgroups: every
+    task computes the same sums, so the solution is bitwise the same."""
+    w, P = oracle_for("3d_12x10x14_uneven")
+    S = bd().solver_for(w, full_space=full_space, use_graph=True)
+    x0, i0 = S.solve(dev(w.b), 1e-10)
+    x0 = host(x0)
+    rec = S.autotune(candidates=(1, 3, 8), iters=4, cache=str(tmp_path / "tune.json"))
+    assert rec["wg_per_cu"] in (1, 3, 8) and len(rec["ms"]) == 3
+    x1, i1 = S.solve(dev(w.b), 1e-10)
+    assert np.array_equal(host(x1), x0) and i1["iters"] == i0["iters"]
+    S2 = bd().solver_for(w, full_space=full_space, use_graph=True)
+    rec2 = S2.autotune(candidates=(1, 3, 8), iters=4, cache=str(tmp_path / "tune.json"))
+    assert rec2["wg_per_cu"] == rec["wg_per_cu"]        # served from the cache
+    for wg in (1, 2, 16):
+        S2.set_tuning(wg)
+        x2, i2 = S2.solve(dev(w.b), 1e-10)
+        assert np.array_equal(host(x2), x0)
+    S.close()
+    S2.close()
