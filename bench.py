@@ -29,13 +29,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FULL_FAMILIES = ["trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii", "trsv_bwd_ii"]
-IFACE_FAMILIES = ["op_t", "op_n", "pc_n", "pc_t"]
+IFACE_FAMILIES = ["op", "pc"]
 NB = 64
 
 
 def sub_sizes(w):
     """Per-subdomain sizes of a tensor box partition: n_R (interior + non-corner
-    interface rows of the local factor), n_I (interior rows), n_ci (constraints)."""
+    interface rows of the local factor), n_I (interior rows), n_ci (constraints),
+    n_P (corners)."""
     from paper_2410_14786_amd.workloads import CORNERS, EDGES, FACES
     dim = w.dim
     out = []
@@ -61,7 +62,7 @@ def sub_sizes(w):
         else:
             edges, faces = sum(ends), 0
         n_A = (edges if w.constraints & EDGES else 0) + (faces if w.constraints & FACES else 0)
-        out.append((n_i - corners, n_I, n_A + corners))
+        out.append((n_i - corners, n_I, n_A + corners, corners))
     return out
 
 
@@ -73,21 +74,18 @@ def algorithmic_bytes(w, local_bytes):
     s = sub_sizes(w)
     tri = lambda n: n * (n + 1) // 2
     fam["trsv_fwd_rr"] = sum(tri(nR) * local_bytes + nci * nR * local_bytes + nR * (8 + 8 + 4 + local_bytes)
-                             for nR, nI, nci in s)
+                             for nR, nI, nci, nP in s)
     fam["trsv_bwd_rr"] = sum(tri(nR) * local_bytes + nci * nR * local_bytes + nR * (8 + 2 * local_bytes)
-                             for nR, nI, nci in s)
-    fam["trsv_fwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 4 + local_bytes) for nR, nI, nci in s)
-    fam["trsv_bwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 8 + 4 + local_bytes) for nR, nI, nci in s)
-    # interface form (FP64): each of the four triangular mat-vecs streams one
-    # triangle of n_G = n_R - n_I rows (L_GG or its inverse), plus border rows and
-    # the gathered/written vectors
-    g = lambda nR, nI: nR - nI
-    fam["op_t"] = sum(tri(g(nR, nI)) * local_bytes + 8 * g(nR, nI) * local_bytes
-                      + g(nR, nI) * (8 + 8 + 4 + 8 + 8) for nR, nI, nci in s)
-    fam["op_n"] = sum(tri(g(nR, nI)) * local_bytes + g(nR, nI) * (8 + 8 + 8) for nR, nI, nci in s)
-    fam["pc_n"] = sum(tri(g(nR, nI)) * local_bytes + nci * g(nR, nI) * local_bytes + g(nR, nI) * (8 + 8 + 4 + 8)
-                      for nR, nI, nci in s)
-    fam["pc_t"] = sum(tri(g(nR, nI)) * local_bytes + g(nR, nI) * (8 + 8 + 8) for nR, nI, nci in s)
+                             for nR, nI, nci, nP in s)
+    fam["trsv_fwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 4 + local_bytes) for nR, nI, nci, nP in s)
+    fam["trsv_bwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 8 + 4 + local_bytes) for nR, nI, nci, nP in s)
+    # interface form (FP64): the operator streams the lower triangle of the local
+    # Schur complement on n_G + n_P rows (n_G = n_R - n_I interface rows, n_P
+    # corners), the preconditioner that of X^T X on n_G rows plus the n_ci x n_G
+    # border block; each reads its input and writes its output once
+    fam["op"] = sum(tri(nR - nI + nP) * 8 + (nR - nI + nP) * (8 + 8) for nR, nI, nci, nP in s)
+    fam["pc"] = sum(tri(nR - nI) * 8 + nci * (nR - nI) * 8 + (nR - nI) * (8 + 8) + nci * 8
+                    for nR, nI, nci, nP in s)
     return fam
 
 

@@ -174,10 +174,10 @@ int bddc_plan_stats(const bddc_mesh* mesh, const bddc_partition* part,
  * bracketed by HIP events on the ctx stream; bddc_kernel_time returns the
  * number of timed launches and their summed duration in ms (synchronising
  * the stream).  Families: "trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii",
- * "trsv_bwd_ii" (full-space solves), "op_t", "op_n" (the two triangular
- * mat-vecs of the interface Schur operator), "pc_n", "pc_t" (the two
- * triangular mat-vecs of the interface preconditioner), "schur" (the whole
- * operator), "spmv", "apply".  While timing is enabled, PCG iterations are
+ * "trsv_bwd_ii" (full-space solves), "op" (the symmetric mat-vec with the
+ * local Schur complements of the interface operator), "pc" (the symmetric
+ * mat-vec of the interface preconditioner), "schur" (the whole operator),
+ * "spmv", "apply".  While timing is enabled, PCG iterations are
  * launched eagerly even when use_graph is set.  Launches that returned at once
  * because the solve had already converged (shorter than a fifth of the
  * family's longest) are not counted.  Each query resets the family.

@@ -124,13 +124,14 @@ struct bddc_ctx {
   int32_t *ctask_fwd = nullptr, *ctask_bwd = nullptr;
   int Tc = 0;
   int32_t *t_fwd_rr = nullptr, *t_bwd_rr = nullptr, *t_fwd_ii = nullptr, *t_bwd_ii = nullptr;
-  int32_t *t_fwd_g = nullptr, *t_bwd_g = nullptr, *t_mv_n = nullptr, *t_mv_t = nullptr;
-  void *vloc = nullptr, *qloc = nullptr;      // interface form: local work vectors
+  int32_t *t_fwd_g = nullptr, *t_bwd_g = nullptr, *t_sym = nullptr, *t_symfin = nullptr;
   double* xg = nullptr;                        // inverses of the trailing factor blocks
+  double *sg = nullptr, *hg = nullptr;         // interface form: Schur complements, X^T X (+ border rows)
+  double* symp = nullptr;                      // their partial products, 64 per stored tile
   double *zloc = nullptr, *floc = nullptr;     // D^{-1} z and W D r in local-dof order
   double *cxg = nullptr, *cainv = nullptr, *upart = nullptr;   // explicit coarse inverse (interface form)
   int csplit = 1;
-  double *ppi = nullptr, *sploc = nullptr, *cpp = nullptr;
+  double *sploc = nullptr, *cpp = nullptr;
   int max_loclen = 1;
   void* pub_local = nullptr;   // 4 * n_vec entries of the local precision
   double* pub_coarse = nullptr;
@@ -311,7 +312,7 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   c->end("trsv_fwd_rr", e);
 
   if (P.n_coarse > 0) {
-    launch_coarse_prep(c->mats, P.nsubs, c->part, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done, 0,
+    launch_coarse_prep(c->mats, P.nsubs, c->part, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done, nullptr,
                        st);
     TrsvArgs cf;
     std::memset(&cf, 0, sizeof(cf));
@@ -383,23 +384,14 @@ IfaceArgs iface_args(bddc_ctx* c) {
   IfaceArgs a;
   std::memset(&a, 0, sizeof(a));
   a.mats = c->mats;
-  a.tiles = static_cast<const double*>(c->tiles);
-  a.xg = c->xg;
-  a.tasks = c->t_fwd_g;
-  a.ntasks = int(c->plan.fwd_g.size() / 2);
+  a.maxtg = c->plan.maxTG;
   a.sc = c->sc;
-  a.gmap = c->gmap;
+  a.part = c->symp;
   a.dsc = c->dsc;
   a.wd = c->wd;
   a.wgt = c->wgt;
-  a.z = c->z;
-  a.p = c->p;
-  a.ppi = c->ppi;
-  a.part = c->part;
-  a.cpp = c->cpp;
   a.sploc = c->sploc;
   a.ww = c->ww;
-  a.uc = c->uc;
   a.rc = c->rc;
   a.mu = c->mu;
   a.sainv = c->sainv;
@@ -408,70 +400,58 @@ IfaceArgs iface_args(bddc_ctx* c) {
 }
 
 // Interface preconditioner (v1 + v2 restricted to interface dofs) on an
-// interface residual r: t = X D W r on the trailing rows (with the border
-// partials), coarse problem, t' = t + W coef, x = X^T t', weighted gather into z
-// (interface entries) with the partial sums of r.z.  Expects zero tickets and
-// sentinel coarse buffers, and leaves them so for the next application.
+// interface residual r (scattered as f = W D r into floc): the products of
+// X^T X and of the border row W_G^T X with f, the coarse problem, then
+// x = X^T X f + X^T W_G coef weighted into ww, gathered into z (interface
+// entries) with the partial sums of r.z.  Expects zero tickets and sentinel
+// coarse buffers, and leaves them so for the next application.
 void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_rz, const int* done) {
   const Plan& P = c->plan;
   hipStream_t st = c->st;
   hipEvent_t ea = c->begin("apply");
   IfaceArgs a = iface_args(c);
-  a.r = r;
+  a.m = c->hg;
   a.loc_in = c->floc;
-  a.tasks = c->t_mv_n;
+  a.tasks = c->t_sym;
+  a.ntasks = int(P.sym.size() / 2);
   a.ticket = c->tickets + 0;
-  a.xout = static_cast<double*>(c->vloc);
-  hipEvent_t e = c->begin("pc_n");
-  launch_iface_mv(IMV_PC_N, a, trsv_grid(c, a.ntasks), st);
-  c->end("pc_n", e);
+  hipEvent_t e = c->begin("pc");
+  launch_sym_mv(SYM_PC, a, trsv_grid(c, a.ntasks), st);
+  c->end("pc", e);
   if (P.n_coarse > 0) {
-    launch_coarse_prep(c->mats, P.nsubs, c->part, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done, 1,
-                       st);
+    launch_coarse_prep(c->mats, P.nsubs, nullptr, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done,
+                       c->symp, st);
     launch_coarse_gemv(c->cainv, P.n_coarse, c->csplit, c->cinv_ptr, c->cinv, c->gbuf, c->upart, done, st);
   }
   a.uc = c->upart;
   a.nc = P.n_coarse;
   a.nsplit = c->csplit;
-  a.xin = static_cast<const double*>(c->vloc);
-  a.xout = static_cast<double*>(c->qloc);
-  a.tasks = c->t_fwd_g;
-  launch_border_correct(a, st);
-  a.xin = static_cast<const double*>(c->qloc);
-  a.xout = nullptr;
-  a.tasks = c->t_mv_t;
-  a.ticket = c->tickets + 1;
-  e = c->begin("pc_t");
-  launch_iface_mv(IMV_PC_T, a, trsv_grid(c, a.ntasks), st);
-  c->end("pc_t", e);
+  a.tasks = c->t_symfin;
+  a.ntasks = int(P.symfin.size() / 2);
+  launch_pc_finish(a, st);
   launch_gather_z(c->inv_ptr, c->inv, c->ww, c->kappa, r, z, part_rz, P.n_free, done, c->pub_coarse,
                   2 * int64_t(c->Tc) * NB, c->tickets, c->dsc, c->zloc, st);
   c->end("apply", ea);
 }
 
-// q = S p with p = z + beta p (iteration it), partial sums of p.q into part_pq
+// q = S p with p = z + beta p (iteration it), partial sums of p.q into part_pq:
+// S z from the explicit local Schur complements, then q = S z + beta q
 void enqueue_schur(bddc_ctx* c, int it, bool fresh, const double* part_rz, double* part_pq) {
   const Plan& P = c->plan;
   hipStream_t st = c->st;
   hipEvent_t e = c->begin("schur");
   IfaceArgs a = iface_args(c);
-  a.it = it;
-  a.fresh = fresh ? 1 : 0;
-  a.part_rz = part_rz;
+  a.m = c->sg;
   a.loc_in = c->zloc;
-  a.tasks = c->t_mv_t;
+  a.tasks = c->t_sym;
+  a.ntasks = int(P.sym.size() / 2);
   a.ticket = c->tickets + 2;
-  a.xout = static_cast<double*>(c->qloc);
-  hipEvent_t e1 = c->begin("op_t");
-  launch_iface_mv(IMV_OP_T, a, trsv_grid(c, a.ntasks), st);
-  c->end("op_t", e1);
-  a.ticket = c->tickets + 3;
-  a.tasks = c->t_mv_n;
-  a.xin = static_cast<const double*>(c->qloc);
-  a.xout = nullptr;
-  e1 = c->begin("op_n");
-  launch_iface_mv(IMV_OP_N, a, trsv_grid(c, a.ntasks), st);
-  c->end("op_n", e1);
+  hipEvent_t e1 = c->begin("op");
+  launch_sym_mv(SYM_OP, a, trsv_grid(c, a.ntasks), st);
+  c->end("op", e1);
+  a.tasks = c->t_symfin;
+  a.ntasks = int(P.symfin.size() / 2);
+  launch_op_finish(a, st);
   launch_gather_sp(c->inv_ptr, c->inv, c->sploc, c->kappa, c->z, c->p, c->q, part_rz, part_pq, c->sc, it,
                    fresh ? 1 : 0, P.n_free, st);
   c->end("schur", e);
@@ -644,8 +624,8 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->upload(c->t_bwd_ii, P.bwd_ii))) return rc_;
   if ((rc_ = c->upload(c->t_fwd_g, P.fwd_g))) return rc_;
   if ((rc_ = c->upload(c->t_bwd_g, P.bwd_g))) return rc_;
-  if ((rc_ = c->upload(c->t_mv_n, P.mv_n))) return rc_;
-  if ((rc_ = c->upload(c->t_mv_t, P.mv_t))) return rc_;
+  if ((rc_ = c->upload(c->t_sym, P.sym))) return rc_;
+  if ((rc_ = c->upload(c->t_symfin, P.symfin))) return rc_;
 
   // global matrix
   launch_assemble_csr(c->mesh, c->theta, c->rowptr, c->col, c->val, P.n_free, c->err, st);
@@ -693,6 +673,13 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
     if ((rc_ = c->alloc(c->xg, P.n_xg * NB * NB))) return rc_;
     launch_trailing_inverse(c->mats, P.nsubs, P.maxTG, static_cast<const double*>(c->tiles),
                             static_cast<const double*>(c->dinv), c->xg, st);
+    if ((rc_ = c->alloc(c->sg, P.n_sg * NB * NB))) return rc_;
+    if ((rc_ = c->alloc(c->hg, P.n_sg * NB * NB))) return rc_;
+    if ((rc_ = c->alloc(c->symp, P.n_sg * NB))) return rc_;
+    launch_sym_build(SYM_OP, c->mats, P.nsubs, P.maxTG, static_cast<const double*>(c->tiles), c->xg, c->cpp, c->sg,
+                     st);
+    launch_sym_build(SYM_PC, c->mats, P.nsubs, P.maxTG, static_cast<const double*>(c->tiles), c->xg, c->cpp, c->hg,
+                     st);
   }
 
   // coarse problem
@@ -754,7 +741,6 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->alloc(c->part_b, VEC_GRID))) return rc_;
   if ((rc_ = c->alloc(c->part_c, VEC_GRID))) return rc_;
   if ((rc_ = c->alloc(c->sc, 1))) return rc_;
-  if ((rc_ = c->alloc(c->ppi, int64_t(P.nsubs) * MAX_NCI))) return rc_;
   if ((rc_ = c->alloc(c->xw, P.n_free))) return rc_;
   if ((rc_ = c->alloc(c->zloc, P.n_loc))) return rc_;
   if ((rc_ = c->alloc(c->floc, P.n_loc))) return rc_;
@@ -763,19 +749,6 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hsnap), 4 * sizeof(int), hipHostMallocDefault));
   for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreateWithFlags(&c->snap_ev[i], hipEventDisableTiming));
   if ((rc_ = c->alloc(c->sploc, P.n_loc))) return rc_;
-  if (c->fp32) {
-    float *v, *q;
-    if ((rc_ = c->alloc(v, P.n_vec))) return rc_;
-    if ((rc_ = c->alloc(q, P.n_vec))) return rc_;
-    c->vloc = v;
-    c->qloc = q;
-  } else {
-    double *v, *q;
-    if ((rc_ = c->alloc(v, P.n_vec))) return rc_;
-    if ((rc_ = c->alloc(q, P.n_vec))) return rc_;
-    c->vloc = v;
-    c->qloc = q;
-  }
   for (auto& D : P.subs) c->max_loclen = std::max(c->max_loclen, int(D.T * NB + D.n_P));
   if ((rc_ = c->alloc(c->scal, 8))) return rc_;
 
@@ -857,6 +830,10 @@ int bddc_setup(const bddc_mesh* mesh, const bddc_partition* part, const bddc_coe
   // only with FP64 factors; FP32 local factors iterate on the whole space, where
   // the operator is the FP64 global matrix
   c->iface = !(opts->flags & BDDC_SETUP_FULL_SPACE) && !c->fp32;
+  // the interface mat-vecs stage a subdomain's trailing rows in LDS: at most
+  // IFACE_MAX_TG tile rows (4096 interface rows); larger boxes iterate on the whole space
+  for (auto& D : c->plan.subs)
+    if (D.T - D.n_I / NB > IFACE_MAX_TG) c->iface = false;
   c->mesh.dim = c->plan.dim;
   for (int a = 0; a < 3; ++a) {
     c->mesh.nel[a] = int(c->plan.nel[a]);
@@ -1071,8 +1048,8 @@ int bddc_set_timing(bddc_ctx* c, int32_t enabled) {
 
 int bddc_kernel_time(bddc_ctx* c, const char* family, int64_t* launches, double* total_ms) {
   if (int rc_ = check_ctx(c)) return rc_;
-  static const char* known[] = {"trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii", "trsv_bwd_ii", "op_t", "op_n",
-                                "pc_n", "pc_t", "schur", "spmv", "apply"};
+  static const char* known[] = {"trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii", "trsv_bwd_ii", "op", "pc",
+                                "schur", "spmv", "apply"};
   bool ok = false;
   for (const char* k : known) ok |= family && std::strcmp(family, k) == 0;
   if (!ok) return fail(BDDC_EINVAL, "unknown kernel family");

@@ -35,6 +35,8 @@ struct MatDesc {
   int32_t lmap_off;   // offset of the box-node -> local index table
   int32_t pad;
   int64_t xg_off;     // first tile of the inverse of the trailing block (tile rows n_I/NB .. T-1)
+  int64_t sg_off;     // first tile of the symmetric interface matrices (TG + 1 tile rows,
+                      // TG = T - n_I/NB; the last one is the border row)
 };
 
 // Host-side plan: everything bddc_setup derives from the mesh and partition
@@ -78,10 +80,13 @@ struct Plan {
   std::vector<int32_t> ac_diag;          // entry index of (p, p)
 
   // ticket-ordered task lists of the triangular solves, (matrix, tile row)
-  std::vector<int32_t> fwd_rr, bwd_rr, fwd_ii, bwd_ii, fwd_g, bwd_g, mv_n, mv_t;
+  std::vector<int32_t> fwd_rr, bwd_rr, fwd_ii, bwd_ii, fwd_g, bwd_g;
+  // interface form, (matrix, ii) with ii = 0..TG a row of the symmetric interface
+  // matrices: sym longest first (row ii streams ii + 1 tiles), symfin in order
+  std::vector<int32_t> sym, symfin;
 
   int maxT = 0, maxTx = 0, maxTI = 0;
-  int64_t n_tiles = 0, n_dinv = 0, n_vec = 0, n_loc = 0, n_lmap = 0, n_xg = 0;
+  int64_t n_tiles = 0, n_dinv = 0, n_vec = 0, n_loc = 0, n_lmap = 0, n_xg = 0, n_sg = 0;
   int maxTG = 0;
   int max_nci = 0;
 };

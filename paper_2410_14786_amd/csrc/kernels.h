@@ -74,37 +74,26 @@ struct PcgScalars {
 
 struct IfaceArgs {
   const MatDesc* mats;
-  const double* tiles;      // local factors (L and the border rows)
-  const double* xg;         // inverse of the tile-aligned trailing block
-  const int32_t* tasks;
+  const double* m;          // symmetric interface matrix (operator or preconditioner)
+  const int32_t* tasks;     // (matrix, row ii of the symmetric matrices)
   int ntasks;
   unsigned* ticket;
   const PcgScalars* sc;
-  int it;
-  int fresh;
-  const double* part_rz;
-  const int32_t* gmap;
+  const double* loc_in;     // SYM_OP: D^{-1} z, SYM_PC: W D r, both in local-dof order
+  double* part;             // 64 partial products per stored tile of the symmetric matrices
   const double* dsc;
   const double* wd;
   const double* wgt;
-  const double* z;
-  const double* p;
-  const double* r;
-  const double* xin;        // local vector input (vec_off layout)
-  const double* loc_in;     // OP_T: D^{-1} z, PC_N: W D r, both in local-dof order
-  double* xout;             // local vector output
-  double* ppi;              // corner values of the direction
-  double* part;             // per (matrix, tile row) partial border products
-  const double* cpp;        // A_PiPi - W_Pi^T W_Pi
-  double* sploc;            // (S p) per local dof
+  double* sploc;            // (S z) per local dof
   double* ww;               // weighted local preconditioner output
-  const double* uc;        // coarse solution as nsplit column-split partials of nc values
+  const double* uc;         // coarse solution as nsplit column-split partials of nc values
   int nc;
   int nsplit;
   const int32_t* rc;
   const double* mu;
   const double* sainv;
   const double* sainve;
+  int maxtg;                // largest trailing block, in tile rows (at most IFACE_MAX_TG)
 };
 
 template <typename T> void launch_fill(T* p, T v, int64_t n, hipStream_t st);
@@ -128,7 +117,7 @@ void launch_coarse_assembly(const int32_t* src_ptr, const int32_t* src, const in
 void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st);
 void launch_coarse_prep(const MatDesc* mats, int nmats, const double* part, const double* sainv,
                         const double* sainve, const int32_t* gmap, const double* wgt, const double* r,
-                        double* gbuf, double* mu, const int* done, int iface, hipStream_t st);
+                        double* gbuf, double* mu, const int* done, const double* symp, hipStream_t st);
 void launch_coarse_coef(const MatDesc* mats, int nmats, const int32_t* rc, const double* uc, const double* mu,
                         const double* sainv, const double* sainve, const double* wgt, double* coef, double* ww,
                         const int* done, hipStream_t st);
@@ -170,10 +159,14 @@ void launch_gather_z(const int32_t* inv_ptr, const int32_t* inv, const double* w
                      int64_t n_pubc, unsigned* tickets, const double* dsc, double* zloc, hipStream_t st);
 void launch_scatter_local(const int32_t* inv_ptr, const int32_t* inv, const double* scale, const double* v,
                           double* loc, int64_t n, hipStream_t st);
-enum { IMV_OP_T = 0, IMV_OP_N = 1, IMV_PC_N = 2, IMV_PC_T = 3 };
-void launch_iface_mv(int mode, const IfaceArgs& a, int grid, hipStream_t st);
-void launch_border_correct(const IfaceArgs& a, hipStream_t st);
+enum { SYM_OP = 0, SYM_PC = 1 };
+void launch_sym_build(int mode, const MatDesc* mats, int nmats, int maxTG, const double* tiles, const double* xg,
+                      const double* cpp, double* out, hipStream_t st);
+void launch_sym_mv(int mode, const IfaceArgs& a, int grid, hipStream_t st);
+void launch_op_finish(const IfaceArgs& a, hipStream_t st);
+void launch_pc_finish(const IfaceArgs& a, hipStream_t st);
 constexpr int COARSE_SPLIT_COLS = 512;   // columns of A_c^{-1} per coarse GEMV block
+constexpr int IFACE_MAX_TG = 64;         // interface form: at most 64 trailing tile rows per subdomain
 void launch_coarse_inverse(const double* xg, const double* dc, int nc, double* ainv, hipStream_t st);
 void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* cinv_ptr, const int32_t* cinv,
                         const double* gbuf, double* upart, const int* done, hipStream_t st);

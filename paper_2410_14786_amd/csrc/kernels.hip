@@ -922,7 +922,8 @@ void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t s
 __global__ __launch_bounds__(64) void coarse_prep_kernel(const MatDesc* mats, const double* part,
                                                          const double* sainv, const double* sainve,
                                                          const int32_t* gmap, const double* wgt, const double* r,
-                                                         double* gbuf, double* mu, const int* done, int iface) {
+                                                         double* gbuf, double* mu, const int* done,
+                                                         const double* symp) {
   if (done && *done) return;
   const int s = blockIdx.x;
   const MatDesc D = mats[s];
@@ -931,8 +932,14 @@ __global__ __launch_bounds__(64) void coarse_prep_kernel(const MatDesc* mats, co
   if (D.n_ci == 0) return;
   if (tid < D.n_ci) {
     double v = 0.0;
-    const int64_t base = (D.vec_off / NB) * MAX_NCI;
-    for (int k = iface ? D.n_I / NB : 0; k < D.T; ++k) v += part[base + int64_t(k) * MAX_NCI + tid];
+    if (symp) {
+      // interface form: W^T t is the row product of the border row (W_G^T X) f
+      const int TG = D.T - D.n_I / NB;
+      v = symp[(D.sg_off + tri_tile(TG, TG)) * NB + tid];
+    } else {
+      const int64_t base = (D.vec_off / NB) * MAX_NCI;
+      for (int k = 0; k < D.T; ++k) v += part[base + int64_t(k) * MAX_NCI + tid];
+    }
     h[tid] = v;
   }
   __syncthreads();
@@ -990,9 +997,9 @@ __global__ __launch_bounds__(64) void coarse_coef_kernel(const MatDesc* mats, co
 
 void launch_coarse_prep(const MatDesc* mats, int nmats, const double* part, const double* sainv,
                         const double* sainve, const int32_t* gmap, const double* wgt, const double* r,
-                        double* gbuf, double* mu, const int* done, int iface, hipStream_t st) {
+                        double* gbuf, double* mu, const int* done, const double* symp, hipStream_t st) {
   hipLaunchKernelGGL(coarse_prep_kernel, dim3(nmats), dim3(64), 0, st, mats, part, sainv, sainve, gmap, wgt, r,
-                     gbuf, mu, done, iface);
+                     gbuf, mu, done, symp);
 }
 
 void launch_coarse_coef(const MatDesc* mats, int nmats, const int32_t* rc, const double* uc, const double* mu,
@@ -1288,11 +1295,10 @@ void launch_finish_dot(const double* part, double* out, hipStream_t st) {
 // chol(D_G S_GG D_G) and the border rows give W = L^{-1} D [C_AR^T | A_RPi], so
 //   (S p)_G  = D^{-1} L_GG q,  q = L_GG^T D^{-1} p_G + W_Pi,G p_Pi
 //   (S p)_Pi = W_Pi,G^T q + (A_PiPi - W_Pi^T W_Pi) p_Pi
-// and the preconditioner needs t = L_GG^{-1} D f_G and x = L_GG^{-T} t'.  The
-// last two use X = inverse of the tile-aligned trailing block of L (tile rows
-// n_I/64 .. T-1), formed at setup: on vectors that vanish on the interior rows
-// of the first tile, X and X^T act as L_GG^{-1} and L_GG^{-T}.  All four are
-// triangular mat-vecs: tile rows are independent, nothing waits.
+// and the preconditioner needs L_GG^{-T} (L_GG^{-1} D f_G + W_G coef).  Setup forms
+// X = inverse of the tile-aligned trailing block of L, then both operators as
+// explicit symmetric matrices (the Schur complement itself and X^T X with the
+// border row W_G^T X), so each application streams one triangle of tiles.
 
 // X(ii, jj) = -Dinv_i sum_{kk=jj}^{ii-1} L(i, k) X(kk, jj), X(ii, ii) = Dinv_i
 // (i = j0 + ii, k = j0 + kk); one launch per block row ii, one task per (matrix, jj)
@@ -1409,159 +1415,225 @@ void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* c
                      cinv, gbuf, upart, done);
 }
 
-// One kernel for the four interface mat-vecs (see above); task = (matrix, tile row k)
-// for k = n_I/64 .. T-1.
-//   OP_T: q_k = sum_{j>=k} L(j,k)^T v_j + W_Pi(k) z_Pi, v = D^{-1} z (the operator is
-//         applied to z; CG forms S p = S z + beta S p_old); stores q and the
-//         partials W_Pi(k)^T q_k
-//   OP_N: y_k = sum_{j0<=j<=k} L(k,j) q_j, (S z)_G = D^{-1} y; the task k = j0 also
-//         writes (S z)_Pi from the partials
-//   PC_N: t_k = sum_{j0<=j<=k} X(k,j) f_j, f = W D r; stores t and the partials
-//         W(k)^T t_k of all constraints
-//   PC_T: x_k = sum_{j>=k} X(j,k)^T t'_j; weighted local output W D x
+// Symmetric interface matrices, lower tile triangle over TG + 1 tile rows
+// (ii < TG: trailing tile row j0 + ii, j0 = n_I/64; ii = TG: the border row, whose
+// rows are constraint indices), M = K K^T with
+//   SYM_OP: K(ii, kk) = L(j0+ii, j0+kk) for kk <= ii, K(TG, kk) = the corner rows of
+//           the border tile (T, j0+kk), plus A_PiPi - W_Pi^T W_Pi on the corner block
+//           of M(TG, TG).  M is the equilibrated local Schur complement on [G | Pi]:
+//           M_GG = L_GG L_GG^T, M_PiG = W_Pi,G^T L_GG^T, M_PiPi = cpp + W_Pi,G^T W_Pi,G.
+//   SYM_PC: K(ii, kk) = X(kk, ii)^T for kk >= ii, K(TG, kk) = the border tile
+//           (T, j0+kk) (all constraint rows), so M_GG = X^T X = (L_GG L_GG^T)^{-1}
+//           and the border row holds W_G^T X = (L_GG^{-T} W_G)^T; M(TG, TG) = 0.
+// Rows and columns of the trailing block outside the interface rows [n_I, n_R)
+// are zero in K, hence in M.  One workgroup per output tile, MFMA products.
 template <int MODE>
-__global__ __launch_bounds__(256) void iface_mv_kernel(IfaceArgs A) {
+__device__ void load_k_tile(double* dst, const MatDesc& D, const double* tiles, const double* xg, int ii, int kk) {
+  const int j0 = D.n_I / NB, TG = D.T - j0;
+  const bool border = ii == TG;
+  if (border && D.n_ci == 0) {   // no border row is stored
+    for (int e = threadIdx.x; e < NB * NB; e += 256) dst[(e / NB) * LDT + (e % NB)] = 0.0;
+    return;
+  }
+  const bool trans = !border && MODE == SYM_PC;
+  const double* src;
+  if (border) src = tiles + (D.tile_off + tri_tile(D.T, j0 + kk)) * int64_t(NB * NB);
+  else if (MODE == SYM_OP) src = tiles + (D.tile_off + tri_tile(j0 + ii, j0 + kk)) * int64_t(NB * NB);
+  else src = xg + (D.xg_off + tri_tile(kk, ii)) * int64_t(NB * NB);
+  const int rb = (j0 + ii) * NB, cb = (j0 + kk) * NB;
+  const int blo = MODE == SYM_OP ? D.n_A : 0;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int i1 = e / NB, i2 = e % NB;
+    const int r = trans ? i2 : i1, c = trans ? i1 : i2;   // row, column of K
+    bool keep = cb + c >= D.n_I && cb + c < D.n_R;
+    if (border) keep = keep && r >= blo && r < D.n_ci;
+    else keep = keep && rb + r >= D.n_I && rb + r < D.n_R;
+    dst[r * LDT + c] = keep ? src[e] : 0.0;
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void sym_build_kernel(const MatDesc* mats, const double* tiles, const double* xg,
+                                                         const double* cpp, double* out) {
+  const int s = blockIdx.y;
+  const MatDesc D = mats[s];
+  const int TG = D.T - D.n_I / NB;
+  const int64_t pidx = blockIdx.x;
+  if (pidx >= tri_tile(TG + 1, 0)) return;
+  int ii = int((sqrt(8.0 * double(pidx) + 1.0) - 1.0) * 0.5);
+  while (tri_tile(ii, 0) > pidx) --ii;
+  while (tri_tile(ii + 1, 0) <= pidx) ++ii;
+  const int jj = int(pidx - tri_tile(ii, 0));
+  // K(ii, kk) and K(jj, kk) (jj <= ii) are both nonzero only for kk in [k0, k1)
+  int k0, k1;
+  if (MODE == SYM_OP) {
+    k0 = 0;
+    k1 = min(jj + 1, TG);
+  } else {
+    k0 = ii < TG ? ii : jj;
+    k1 = (ii == TG && jj == TG) ? k0 : TG;
+  }
+  __shared__ double sa[NB * LDT];
+  __shared__ double sb[NB * LDT];
+  d4v acc[2][2];
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q) acc[p][q] = d4v(0);
+  for (int kk = k0; kk < k1; ++kk) {
+    __syncthreads();
+    load_k_tile<MODE>(sa, D, tiles, xg, ii, kk);
+    if (jj != ii) load_k_tile<MODE>(sb, D, tiles, xg, jj, kk);
+    __syncthreads();
+    gemm_nt_tile<double>(sa, jj != ii ? sb : sa, acc);
+  }
+  double* o = out + (D.sg_off + pidx) * int64_t(NB * NB);
+  const bool corner_blk = MODE == SYM_OP && ii == TG && jj == TG;
+  const double* m = cpp + int64_t(s) * MAX_NCI * MAX_NCI;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q)
+      for (int it = 0; it < 4; ++it) {
+        const int r = r0 + 16 * p + Acc4<double>::row(lane, it), c = c0 + 16 * q + (lane & 15);
+        double v = acc[p][q][it];
+        if (corner_blk && r >= D.n_A && r < D.n_ci && c >= D.n_A && c < D.n_ci)
+          v += m[(r - D.n_A) * MAX_NCI + (c - D.n_A)];
+        o[r * NB + c] = v;
+      }
+}
+
+void launch_sym_build(int mode, const MatDesc* mats, int nmats, int maxTG, const double* tiles, const double* xg,
+                      const double* cpp, double* out, hipStream_t st) {
+  const dim3 grid(unsigned(tri_tile(maxTG + 1, 0)), nmats);
+  if (mode == SYM_OP)
+    hipLaunchKernelGGL(sym_build_kernel<SYM_OP>, grid, dim3(256), 0, st, mats, tiles, xg, cpp, out);
+  else
+    hipLaunchKernelGGL(sym_build_kernel<SYM_PC>, grid, dim3(256), 0, st, mats, tiles, xg, cpp, out);
+}
+
+// y = M v for a symmetric interface matrix; task = (matrix, row ii).  The task
+// streams the contiguous tiles (ii, 0..ii) once and uses each twice: the row
+// product sum_jj M(ii, jj) v_jj, stored in the slot of the diagonal tile, and
+// for jj < ii the column product M(ii, jj)^T v_ii, stored in the slot of tile
+// (ii, jj); then y_k = slot(k, k) + sum_{i > k} slot(i, k).  Inputs (staged in
+// LDS): the local-order vector on the interface rows and, for SYM_OP, the corner
+// values on the border rows n_A..n_ci-1 (zero elsewhere).
+// Wave w owns columns 16w..16w+15 of every tile; lane = 8 * rg + cp holds rows
+// rg + 8t (t < 8) of columns 16w + 2cp, +1, so a column product reduces over the
+// eight rg lanes of one wave and a row product over the eight cp lanes.
+template <int MODE>
+__global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   using V = d2v;
-  constexpr int VEC = 2, LPR = 32, RPI = 2, NI = 8;
-  constexpr bool TRANS = (MODE == IMV_OP_T || MODE == IMV_PC_T);
-  constexpr bool ONFLY = (MODE == IMV_OP_T || MODE == IMV_PC_N);
+  extern __shared__ double s_x[];   // inputs of tile rows 0..ii
   __shared__ double s_red[4][NB];
-  __shared__ double s_out[NB];
   __shared__ int s_task;
   if (A.sc->done) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int lr = lane / LPR, lc = lane % LPR;
+  const int rg = lane >> 3, cp = lane & 7;
+  const int col = 16 * w + 2 * cp;
   for (;;) {
     if (tid == 0) s_task = atomicAdd(A.ticket, 1u);
     __syncthreads();
     const int task = s_task;
-    __syncthreads();
     if (task >= A.ntasks) return;
-    const int s = A.tasks[2 * task], k = A.tasks[2 * task + 1];
+    const int s = A.tasks[2 * task], ii = A.tasks[2 * task + 1];
     const MatDesc D = A.mats[s];
-    const int j0 = D.n_I / NB;
-    // input value of local row a (zero outside the interface rows n_I..n_R-1):
-    // OP_T reads D^{-1} z and PC_N reads W D r from local-order vectors that the
-    // previous kernels scattered; the other two read this kernel family's output
-    auto input = [&](int a) -> double {
-      if (a < D.n_I || a >= D.n_R) return 0.0;
-      if (ONFLY) return A.loc_in[D.loc_off + a];
-      return A.xin[D.vec_off + a];
-    };
-    auto tile_ptr = [&](int jj) -> const double* {
-      int64_t t;
-      if (MODE == IMV_OP_T) t = D.tile_off + tri_tile(k + jj, k);
-      else if (MODE == IMV_OP_N) t = D.tile_off + tri_tile(k, j0 + jj);
-      else if (MODE == IMV_PC_N) t = D.xg_off + tri_tile(k - j0, jj);
-      else t = D.xg_off + tri_tile(k - j0 + jj, k - j0);
-      const double* base = (MODE == IMV_OP_T || MODE == IMV_OP_N) ? A.tiles : A.xg;
-      return base + t * int64_t(NB * NB) + (16 * w + lr) * NB + VEC * lc;
-    };
-    const int nt = TRANS ? D.T - k : k - j0 + 1;
-    const int jfirst = TRANS ? k : j0;
-    double acc[TRANS ? VEC : NI];
-    for (int i = 0; i < (TRANS ? VEC : NI); ++i) acc[i] = 0.0;
-    // two tiles in flight ahead of the one being multiplied
-    V cur[NI], nx1[NI], nx2[NI];
-    {
-      const double* pp = tile_ptr(0);
-      for (int i = 0; i < NI; ++i) cur[i] = *reinterpret_cast<const V*>(pp + i * RPI * NB);
-      if (nt > 1) {
-        pp = tile_ptr(1);
-        for (int i = 0; i < NI; ++i) nx1[i] = *reinterpret_cast<const V*>(pp + i * RPI * NB);
-      }
-    }
-    for (int jj = 0; jj < nt; ++jj) {
-      const int rb = (jfirst + jj) * NB;
-      double xv[TRANS ? NI : VEC];
-      if (TRANS) {
-        for (int i = 0; i < NI; ++i) xv[i] = input(rb + 16 * w + RPI * i + lr);
-      } else {
-        for (int e = 0; e < VEC; ++e) xv[e] = input(rb + VEC * lc + e);
-      }
-      if (jj + 2 < nt) {
-        const double* pp = tile_ptr(jj + 2);
-        for (int i = 0; i < NI; ++i) nx2[i] = *reinterpret_cast<const V*>(pp + i * RPI * NB);
-      }
-      if (TRANS) {
-        for (int i = 0; i < NI; ++i)
-          for (int e = 0; e < VEC; ++e) acc[e] += cur[i][e] * xv[i];
-      } else {
-        for (int i = 0; i < NI; ++i)
-          for (int e = 0; e < VEC; ++e) acc[i] += cur[i][e] * xv[e];
-      }
-      for (int i = 0; i < NI; ++i) {
-        cur[i] = nx1[i];
-        nx1[i] = nx2[i];
-      }
-    }
-    if (TRANS) {
-      for (int e = 0; e < VEC; ++e) {
-        double v = acc[e];
-        for (int off = LPR; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-        if (lr == 0) s_red[w][VEC * lc + e] = v;
-      }
-    } else {
-      for (int i = 0; i < NI; ++i) {
-        double v = acc[i];
-        for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lc == 0) s_red[0][16 * w + RPI * i + lr] = v;
-      }
-    }
-    __syncthreads();
-    const int a = k * NB + tid;
-    const bool live = tid < NB && a >= D.n_I && a < D.n_R;
-    const double* bt = A.tiles + (D.tile_off + tri_tile(D.T, k)) * int64_t(NB * NB);   // border tile row
-    if (tid < NB) {
-      double v = TRANS ? (s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid]) : s_red[0][tid];
-      if (MODE == IMV_OP_T && live && D.n_P > 0) {
-        const double* zc = A.loc_in + D.loc_off + D.n_R;
-        for (int c = 0; c < D.n_P; ++c) v += bt[(D.n_A + c) * NB + tid] * zc[c];
-      }
-      if (!live) v = 0.0;
-      s_out[tid] = v;
-      if (MODE == IMV_OP_T || MODE == IMV_PC_N) A.xout[D.vec_off + a] = v;
-      if (MODE == IMV_OP_N && live) A.sploc[D.loc_off + a] = v / A.dsc[D.loc_off + a];
-      if (MODE == IMV_PC_T && live) A.ww[D.loc_off + a] = A.wd[D.loc_off + a] * v;
-    }
-    __syncthreads();
-    if (MODE == IMV_OP_T || MODE == IMV_PC_N) {
-      // partial border products: one wave per constraint row, lanes over the
-      // 64 columns (coalesced row reads), wave reduction
-      const int c0 = (MODE == IMV_OP_T) ? D.n_A : 0;
-      const int nrows = (MODE == IMV_OP_T) ? D.n_P : D.n_ci;
-      for (int c = w; c < nrows; c += 4) {
-        double v = bt[(c0 + c) * NB + lane] * s_out[lane];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) A.part[(D.vec_off / NB + k) * MAX_NCI + c] = v;
-      }
-    }
-    if (MODE == IMV_OP_N && k == j0 && tid < D.n_P) {
-      // corners: (S p)_Pi = W_Pi,G^T q + (A_PiPi - W_Pi^T W_Pi) p_Pi
+    const int j0 = D.n_I / NB, TG = D.T - j0;
+    for (int e = tid; e < (ii + 1) * NB; e += 256) {
+      const int jj = e / NB, r = e % NB;
       double v = 0.0;
-      const int64_t base = (D.vec_off / NB) * MAX_NCI;
-      for (int kk = j0; kk < D.T; ++kk) v += A.part[base + int64_t(kk) * MAX_NCI + tid];
-      const double* m = A.cpp + int64_t(s) * MAX_NCI * MAX_NCI;
-      const double* zc = A.loc_in + D.loc_off + D.n_R;
-      for (int q = 0; q < D.n_P; ++q) v += m[tid * MAX_NCI + q] * zc[q];
-      A.sploc[D.loc_off + D.n_R + tid] = v;
+      if (jj < TG) {
+        const int a = (j0 + jj) * NB + r;
+        if (a >= D.n_I && a < D.n_R) v = A.loc_in[D.loc_off + a];
+      } else if (MODE == SYM_OP && r >= D.n_A && r < D.n_ci) {
+        v = A.loc_in[D.loc_off + D.n_R + (r - D.n_A)];
+      }
+      s_x[e] = v;
     }
+    __syncthreads();
+    const int nt = ii + 1;
+    const double* base = A.m + (D.sg_off + tri_tile(ii, 0)) * int64_t(NB * NB) + rg * NB + col;
+    double* pcol = A.part + (D.sg_off + tri_tile(ii, 0)) * NB + col;
+    double xi[8], racc[8];
+    for (int t = 0; t < 8; ++t) {
+      xi[t] = s_x[ii * NB + rg + 8 * t];
+      racc[t] = 0.0;
+    }
+    // two tiles in flight ahead of the one being multiplied
+    V cur[8], nx1[8], nx2[8];
+    for (int t = 0; t < 8; ++t) cur[t] = *reinterpret_cast<const V*>(base + t * 8 * NB);
+    if (nt > 1)
+      for (int t = 0; t < 8; ++t) nx1[t] = *reinterpret_cast<const V*>(base + NB * NB + t * 8 * NB);
+    for (int jj = 0; jj < nt; ++jj) {
+      if (jj + 2 < nt)
+        for (int t = 0; t < 8; ++t)
+          nx2[t] = *reinterpret_cast<const V*>(base + int64_t(jj + 2) * NB * NB + t * 8 * NB);
+      const double x0 = s_x[jj * NB + col], x1 = s_x[jj * NB + col + 1];
+      double c0 = 0.0, c1 = 0.0;
+      for (int t = 0; t < 8; ++t) {
+        racc[t] += cur[t][0] * x0 + cur[t][1] * x1;
+        c0 += cur[t][0] * xi[t];
+        c1 += cur[t][1] * xi[t];
+      }
+      if (jj < ii) {
+        for (int off = 8; off < 64; off <<= 1) {
+          c0 += __shfl_xor(c0, off, 64);
+          c1 += __shfl_xor(c1, off, 64);
+        }
+        if (rg == 0) {
+          V o;
+          o[0] = c0;
+          o[1] = c1;
+          *reinterpret_cast<V*>(pcol + jj * NB) = o;
+        }
+      }
+      for (int t = 0; t < 8; ++t) {
+        cur[t] = nx1[t];
+        nx1[t] = nx2[t];
+      }
+    }
+    for (int t = 0; t < 8; ++t) {
+      double v = racc[t];
+      for (int off = 1; off < 8; off <<= 1) v += __shfl_xor(v, off, 64);
+      if (cp == 0) s_red[w][rg + 8 * t] = v;
+    }
+    __syncthreads();
+    if (tid < NB)
+      A.part[(D.sg_off + tri_tile(ii, ii)) * NB + tid] = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
     __syncthreads();
   }
 }
 
-// t' = t + W coef on the interface rows of tile row k, with the coefficients of the
-// coarse correction computed in place:
+// (S z) per local dof from the partial products of the operator matrix:
+// sploc = D^{-1} y on the interface rows, y itself on the corners (border row).
+__global__ __launch_bounds__(64) void op_finish_kernel(IfaceArgs A) {
+  if (A.sc->done) return;
+  const int s = A.tasks[2 * blockIdx.x], ii = A.tasks[2 * blockIdx.x + 1];
+  const MatDesc D = A.mats[s];
+  const int j0 = D.n_I / NB, TG = D.T - j0, tid = threadIdx.x;
+  const double* pp = A.part + D.sg_off * NB + tid;
+  double y = pp[tri_tile(ii, ii) * NB];
+  for (int i2 = ii + 1; i2 <= TG; ++i2) y += pp[tri_tile(i2, ii) * NB];
+  if (ii < TG) {
+    const int a = (j0 + ii) * NB + tid;
+    if (a >= D.n_I && a < D.n_R) A.sploc[D.loc_off + a] = y / A.dsc[D.loc_off + a];
+  } else if (tid >= D.n_A && tid < D.n_ci) {
+    A.sploc[D.loc_off + D.n_R + (tid - D.n_A)] = y;
+  }
+}
+
+// Preconditioner output on the interface rows of row ii < TG:
+//   x = (X^T X f)_ii + (X^T W)_ii coef,  ww = W D x,
+// with the coefficients of the coarse correction computed in place:
 //   u = R_ci u_c, coef_A = -mu + S_A^{-1} u_A + S_A^{-1} E u_Pi, coef_Pi = -u_Pi;
-// the task k = j0 also writes the corner outputs W_Pi u_Pi.
-__global__ __launch_bounds__(64) void border_correct_kernel(IfaceArgs A) {
+// the task ii = 0 also writes the corner outputs W_Pi u_Pi.
+__global__ __launch_bounds__(64) void pc_finish_kernel(IfaceArgs A) {
   __shared__ double u[MAX_NCI];
   __shared__ double cf[MAX_NCI];
   if (A.sc->done) return;
-  const int task = blockIdx.x;
-  const int s = A.tasks[2 * task], k = A.tasks[2 * task + 1];
+  const int s = A.tasks[2 * blockIdx.x], ii = A.tasks[2 * blockIdx.x + 1];
   const MatDesc D = A.mats[s];
-  const int tid = threadIdx.x;
+  const int j0 = D.n_I / NB, TG = D.T - j0, tid = threadIdx.x;
+  if (ii >= TG) return;
   const int nA = D.n_A, nP = D.n_P;
   if (tid < D.n_ci) {
     const int pc = A.rc[D.coarse_off + tid];
@@ -1580,7 +1652,7 @@ __global__ __launch_bounds__(64) void border_correct_kernel(IfaceArgs A) {
       for (int q = 0; q < nP; ++q) v += se[tid * MAX_NCI + q] * u[nA + q];
     } else {
       v = -u[tid];
-      if (k == D.n_I / NB) {
+      if (ii == 0) {
         const int64_t l = D.loc_off + D.n_R + (tid - nA);
         A.ww[l] = A.wgt[l] * u[tid];
       }
@@ -1588,29 +1660,34 @@ __global__ __launch_bounds__(64) void border_correct_kernel(IfaceArgs A) {
     cf[tid] = v;
   }
   __syncthreads();
-  const int a = k * NB + tid;
-  double v = 0.0;
+  const int a = (j0 + ii) * NB + tid;
   if (a >= D.n_I && a < D.n_R) {
-    v = A.xin[D.vec_off + a];
-    const double* bt = A.tiles + (D.tile_off + tri_tile(D.T, k)) * int64_t(NB * NB);
-    for (int c = 0; c < D.n_ci; ++c) v += bt[c * NB + tid] * cf[c];
-  }
-  A.xout[D.vec_off + a] = v;
-}
-
-void launch_iface_mv(int mode, const IfaceArgs& a, int grid, hipStream_t st) {
-  if (a.ntasks <= 0) return;
-  switch (mode) {
-    case IMV_OP_T: hipLaunchKernelGGL(iface_mv_kernel<IMV_OP_T>, dim3(grid), dim3(256), 0, st, a); break;
-    case IMV_OP_N: hipLaunchKernelGGL(iface_mv_kernel<IMV_OP_N>, dim3(grid), dim3(256), 0, st, a); break;
-    case IMV_PC_N: hipLaunchKernelGGL(iface_mv_kernel<IMV_PC_N>, dim3(grid), dim3(256), 0, st, a); break;
-    case IMV_PC_T: hipLaunchKernelGGL(iface_mv_kernel<IMV_PC_T>, dim3(grid), dim3(256), 0, st, a); break;
+    const double* pp = A.part + D.sg_off * NB + tid;
+    double v = pp[tri_tile(ii, ii) * NB];
+    for (int i2 = ii + 1; i2 < TG; ++i2) v += pp[tri_tile(i2, ii) * NB];
+    const double* yt = A.m + (D.sg_off + tri_tile(TG, ii)) * int64_t(NB * NB);
+    for (int c = 0; c < D.n_ci; ++c) v += yt[c * NB + tid] * cf[c];
+    A.ww[D.loc_off + a] = A.wd[D.loc_off + a] * v;
   }
 }
 
-void launch_border_correct(const IfaceArgs& a, hipStream_t st) {
+void launch_sym_mv(int mode, const IfaceArgs& a, int grid, hipStream_t st) {
   if (a.ntasks <= 0) return;
-  hipLaunchKernelGGL(border_correct_kernel, dim3(a.ntasks), dim3(64), 0, st, a);
+  const size_t lds = size_t(a.maxtg + 1) * NB * sizeof(double);
+  if (mode == SYM_OP)
+    hipLaunchKernelGGL(sym_mv_kernel<SYM_OP>, dim3(grid), dim3(256), lds, st, a);
+  else
+    hipLaunchKernelGGL(sym_mv_kernel<SYM_PC>, dim3(grid), dim3(256), lds, st, a);
+}
+
+void launch_op_finish(const IfaceArgs& a, hipStream_t st) {
+  if (a.ntasks <= 0) return;
+  hipLaunchKernelGGL(op_finish_kernel, dim3(a.ntasks), dim3(64), 0, st, a);
+}
+
+void launch_pc_finish(const IfaceArgs& a, hipStream_t st) {
+  if (a.ntasks <= 0) return;
+  hipLaunchKernelGGL(pc_finish_kernel, dim3(a.ntasks), dim3(64), 0, st, a);
 }
 
 // q = S p = sum_i R_i^T S_i z_i + beta q on interface dofs; p = z + beta p; partial sums of p.q;

@@ -286,14 +286,17 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
     P.maxTI = std::max(P.maxTI, int(D.TI));
   }
   {
-    int64_t xg = 0;
+    int64_t xg = 0, sg = 0;
     for (auto& D : P.subs) {
       const int TG = D.T - D.n_I / NB;
       D.xg_off = xg;
+      D.sg_off = sg;
       xg += tri_tile(TG, 0);
+      sg += tri_tile(TG + 1, 0);
       P.maxTG = std::max(P.maxTG, TG);
     }
     P.n_xg = xg;
+    P.n_sg = sg;
   }
   P.n_tiles = tile_off;
   P.n_dinv = dinv_off;
@@ -385,24 +388,23 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
           P.bwd_g.push_back(D.T - 1 - d);
         }
       }
-    // the interface mat-vecs have independent tasks: take the longest first
-    // (tile row k streams k - k0 + 1 tiles, its transpose T - k)
-    struct Job { int len, s, k; };
-    std::vector<Job> jn, jt;
+    // rows of the symmetric interface matrices are independent tasks: take the
+    // longest first (row ii streams ii + 1 tiles)
+    struct Job { int len, s, ii; };
+    std::vector<Job> jobs;
     for (int s = 0; s < P.nsubs; ++s) {
       const MatDesc& D = P.subs[s];
-      for (int k = D.n_I / NB; k < D.T; ++k) {
-        jn.push_back({k - D.n_I / NB + 1, s, k});
-        jt.push_back({D.T - k, s, k});
+      const int TG = D.T - D.n_I / NB;
+      for (int ii = 0; ii <= TG; ++ii) {
+        jobs.push_back({ii + 1, s, ii});
+        P.symfin.push_back(s);
+        P.symfin.push_back(ii);
       }
     }
-    auto by_len = [](const Job& a, const Job& b) {
-      return a.len != b.len ? a.len > b.len : (a.s != b.s ? a.s < b.s : a.k < b.k);
-    };
-    std::sort(jn.begin(), jn.end(), by_len);
-    std::sort(jt.begin(), jt.end(), by_len);
-    for (auto& j : jn) { P.mv_n.push_back(j.s); P.mv_n.push_back(j.k); }
-    for (auto& j : jt) { P.mv_t.push_back(j.s); P.mv_t.push_back(j.k); }
+    std::sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& b) {
+      return a.len != b.len ? a.len > b.len : (a.s != b.s ? a.s < b.s : a.ii < b.ii);
+    });
+    for (auto& j : jobs) { P.sym.push_back(j.s); P.sym.push_back(j.ii); }
   }
   return BDDC_OK;
 }

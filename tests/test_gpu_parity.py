@@ -279,7 +279,7 @@ def test_kernel_timing_with_graph_solver():
     S.set_timing(True)
     for _ in range(2):
         x, info = S.solve(dev(w.b), 1e-10)
-    for fam in ("op_t", "op_n", "pc_n", "pc_t"):
+    for fam in ("op", "pc"):
         n, ms = S.kernel_time(fam)
         assert n >= 2 * info["iters"] - 2 and ms > 0, (fam, n, ms)
     S.set_timing(False)
