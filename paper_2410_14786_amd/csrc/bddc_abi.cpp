@@ -124,7 +124,8 @@ struct bddc_ctx {
   int32_t *ctask_fwd = nullptr, *ctask_bwd = nullptr;
   int Tc = 0;
   int32_t *t_fwd_rr = nullptr, *t_bwd_rr = nullptr, *t_fwd_ii = nullptr, *t_bwd_ii = nullptr;
-  int32_t *t_fwd_g = nullptr, *t_bwd_g = nullptr, *t_sym = nullptr, *t_symfin = nullptr;
+  int32_t *t_sym = nullptr, *t_symfin = nullptr;
+  int32_t *fcol = nullptr, *fcol_ii = nullptr, *lrow_rr = nullptr, *lrow_ii = nullptr;   // factor envelopes
   double* xg = nullptr;                        // inverses of the trailing factor blocks
   double *sg = nullptr, *hg = nullptr;         // interface form: Schur complements, X^T X (+ border rows)
   double* symp = nullptr;                      // their partial products, 64 per stored tile
@@ -302,6 +303,7 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   TrsvArgs a = base_args(c);
   a.done = done;
   a.tasks = c->t_fwd_rr;
+  a.fcol = c->fcol;
   a.ntasks = int(P.fwd_rr.size() / 2);
   a.ticket = c->tickets + 0;
   a.sol = pub_slot(c, 0);
@@ -342,6 +344,7 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   a = base_args(c);
   a.done = done;
   a.tasks = c->t_bwd_rr;
+  a.lrow = c->lrow_rr;
   a.ntasks = int(P.bwd_rr.size() / 2);
   a.ticket = c->tickets + 1;
   a.sol = pub_slot(c, 1);
@@ -357,6 +360,7 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   a = base_args(c);
   a.done = done;
   a.tasks = c->t_fwd_ii;
+  a.fcol = c->fcol_ii;
   a.ntasks = int(P.fwd_ii.size() / 2);
   a.ticket = c->tickets + 2;
   a.sol = pub_slot(c, 2);
@@ -368,6 +372,7 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   a = base_args(c);
   a.done = done;
   a.tasks = c->t_bwd_ii;
+  a.lrow = c->lrow_ii;
   a.ntasks = int(P.bwd_ii.size() / 2);
   a.ticket = c->tickets + 3;
   a.sol = pub_slot(c, 3);
@@ -467,6 +472,7 @@ void enqueue_interior_guess(bddc_ctx* c, const double* b, double* x) {
   launch_zero_interface(c->kappa, x, P.n_free, st);
   TrsvArgs a = base_args(c);
   a.tasks = c->t_fwd_ii;
+  a.fcol = c->fcol_ii;
   a.ntasks = int(P.fwd_ii.size() / 2);
   a.ticket = c->tickets + 2;
   a.sol = pub_slot(c, 2);
@@ -474,6 +480,7 @@ void enqueue_interior_guess(bddc_ctx* c, const double* b, double* x) {
   launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
   a = base_args(c);
   a.tasks = c->t_bwd_ii;
+  a.lrow = c->lrow_ii;
   a.ntasks = int(P.bwd_ii.size() / 2);
   a.ticket = c->tickets + 3;
   a.sol = pub_slot(c, 3);
@@ -559,6 +566,7 @@ void enqueue_interior_complete(bddc_ctx* c, const double* b, const double* xt, d
   launch_reset(c->fp32, pub_slot(c, 2), 2 * P.n_vec, nullptr, 0, c->tickets, nullptr, st);
   TrsvArgs a = base_args(c);
   a.tasks = c->t_fwd_ii;
+  a.fcol = c->fcol_ii;
   a.ntasks = int(P.fwd_ii.size() / 2);
   a.ticket = c->tickets + 2;
   a.sol = pub_slot(c, 2);
@@ -567,6 +575,7 @@ void enqueue_interior_complete(bddc_ctx* c, const double* b, const double* xt, d
   launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
   a = base_args(c);
   a.tasks = c->t_bwd_ii;
+  a.lrow = c->lrow_ii;
   a.ntasks = int(P.bwd_ii.size() / 2);
   a.ticket = c->tickets + 3;
   a.sol = pub_slot(c, 3);
@@ -622,9 +631,11 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->upload(c->t_bwd_rr, P.bwd_rr))) return rc_;
   if ((rc_ = c->upload(c->t_fwd_ii, P.fwd_ii))) return rc_;
   if ((rc_ = c->upload(c->t_bwd_ii, P.bwd_ii))) return rc_;
-  if ((rc_ = c->upload(c->t_fwd_g, P.fwd_g))) return rc_;
-  if ((rc_ = c->upload(c->t_bwd_g, P.bwd_g))) return rc_;
   if ((rc_ = c->upload(c->t_sym, P.sym))) return rc_;
+  if ((rc_ = c->upload(c->fcol, P.fcol))) return rc_;
+  if ((rc_ = c->upload(c->fcol_ii, P.fcol_ii))) return rc_;
+  if ((rc_ = c->upload(c->lrow_rr, P.lrow_rr))) return rc_;
+  if ((rc_ = c->upload(c->lrow_ii, P.lrow_ii))) return rc_;
   if ((rc_ = c->upload(c->t_symfin, P.symfin))) return rc_;
 
   // global matrix
@@ -665,7 +676,7 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   for (auto& D : P.subs) max_ni = std::max(max_ni, int(D.n_i));
   launch_local_assembly(c->mesh, c->theta, c->mats, P.nsubs, max_ni, c->gmap, c->lmap, c->wgt, c->dsc, c->wd,
                         c->avg_of, c->avg_coef, c->tiles, c->fp32, c->app, c->err + 1, st);
-  launch_factor(c->mats, P.nsubs, P.maxT, P.maxTx, c->tiles, c->dinv, c->fp32, c->err + 1, st);
+  launch_factor(c->mats, P.nsubs, P.maxT, P.maxTx, c->tiles, c->dinv, c->fp32, c->fcol, c->err + 1, st);
   if ((rc_ = c->alloc(c->cpp, small))) return rc_;
   launch_local_small(c->mats, P.nsubs, c->tiles, c->fp32, c->app, c->sainv, c->sainve, c->aci, c->cpp, c->err + 1,
                      st);
@@ -710,7 +721,7 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
     launch_pad_identity(c->cmat, 1, c->ctiles, false, st);
     launch_coarse_assembly(c->ac_src_ptr, c->ac_src, c->ac_row, c->ac_col, c->ac_diag, int(P.ac_row.size()), nc,
                            c->aci, c->ac_val, c->dc, c->ctiles, c->err + 2, st);
-    launch_factor(c->cmat, 1, c->Tc, c->Tc, c->ctiles, c->cdinv, false, c->err + 2, st);
+    launch_factor(c->cmat, 1, c->Tc, c->Tc, c->ctiles, c->cdinv, false, nullptr, c->err + 2, st);
     if (c->iface) {
       // A_c^{-1} = D X^T X D, X = inverse of the coarse Cholesky factor
       if ((rc_ = c->alloc(c->cxg, tri_tile(c->Tc, 0) * NB * NB))) return rc_;

@@ -79,8 +79,16 @@ struct Plan {
   std::vector<int32_t> ac_src;           // source = s * MAX_NCI*MAX_NCI + a*MAX_NCI + b
   std::vector<int32_t> ac_diag;          // entry index of (p, p)
 
+  // envelope of each local factor (indexed vec_off/NB + tile row): fcol = first
+  // tile column holding a nonzero of that tile row of L (tiles left of it are
+  // zero: Cholesky fills no entry left of a row's first nonzero of A_RR), fcol_ii
+  // the same over the interior rows only; lrow_rr / lrow_ii = last tile row j
+  // (j < T with fcol[j] <= k, resp. j < TI with fcol_ii[j] <= k), the rows a
+  // backward pass over column k reads
+  std::vector<int32_t> fcol, fcol_ii, lrow_rr, lrow_ii;
+
   // ticket-ordered task lists of the triangular solves, (matrix, tile row)
-  std::vector<int32_t> fwd_rr, bwd_rr, fwd_ii, bwd_ii, fwd_g, bwd_g;
+  std::vector<int32_t> fwd_rr, bwd_rr, fwd_ii, bwd_ii;
   // interface form, (matrix, ii) with ii = 0..TG a row of the symmetric interface
   // matrices: sym longest first (row ii streams ii + 1 tiles), symfin in order
   std::vector<int32_t> sym, symfin;

@@ -23,9 +23,7 @@ enum {
   TRSV_FWD_II = 2,  // interior block, rhs = D (r - A v12) on interior rows
   TRSV_BWD_II = 3,  // interior block, z = v12 + D x on interior rows
   TRSV_FWD_C = 4,   // coarse factor, rhs gathered from the subdomain coarse residuals
-  TRSV_BWD_C = 5,   // coarse factor, u_c = D x
-  TRSV_FWD_G = 6,   // trailing interface block L_GG: forward, rhs D W_i R_i r on interface rows
-  TRSV_BWD_G = 7    // trailing interface block: backward with the border coefficients
+  TRSV_BWD_C = 5    // coarse factor, u_c = D x
 };
 
 struct TrsvArgs {
@@ -56,6 +54,8 @@ struct TrsvArgs {
   const double* gbuf;
   const double* dc;
   double* uc;
+  const int32_t* fcol;   // per tile row: first nonzero tile column (null: dense)
+  const int32_t* lrow;   // backward passes, per tile column k: last tile row to read (null: dense)
 };
 
 
@@ -108,7 +108,7 @@ void launch_local_assembly(const MeshDevHost& m, const double* theta, const MatD
                            int* err, hipStream_t st);
 void launch_pad_identity(const MatDesc* mats, int nmats, void* tiles, bool fp32, hipStream_t st);
 void launch_factor(const MatDesc* mats, int nmats, int maxT, int maxTx, void* tiles, void* dinv, bool fp32,
-                   int* err, hipStream_t st);
+                   const int32_t* fcol, int* err, hipStream_t st);
 void launch_local_small(const MatDesc* mats, int nmats, const void* tiles, bool fp32, const double* app,
                         double* sainv, double* sainve, double* aci, double* cpp, int* err, hipStream_t st);
 void launch_coarse_assembly(const int32_t* src_ptr, const int32_t* src, const int32_t* row, const int32_t* col,

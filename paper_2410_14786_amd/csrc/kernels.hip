@@ -449,11 +449,18 @@ __device__ __forceinline__ void load_tile_lds(T* dst, const T* src) {
 }
 
 // L_ik = A_ik * Dinv_k^T for tile rows i in (k, Tx) (the border row included).
+// Tiles outside the envelope (fcol, per tile row; the border row is dense) are
+// zero in A and stay zero in L, so the panel and update steps skip them.
+__device__ __forceinline__ bool tile_zero(const int32_t* fcol, const MatDesc& D, int i, int k) {
+  return fcol && i < D.T && fcol[D.vec_off / NB + i] > k;
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void trsm_panel_kernel(const MatDesc* mats, T* tiles, const T* dinv, int k) {
+__global__ __launch_bounds__(256) void trsm_panel_kernel(const MatDesc* mats, T* tiles, const T* dinv, int k,
+                                                          const int32_t* fcol) {
   const MatDesc D = mats[blockIdx.y];
   const int i = k + 1 + blockIdx.x;
-  if (k >= D.T || i >= D.Tx) return;
+  if (k >= D.T || i >= D.Tx || tile_zero(fcol, D, i, k)) return;
   __shared__ T sa[NB * LDT];
   __shared__ T sb[NB * LDT];
   T* tik = tiles + (D.tile_off + tri_tile(i, k)) * int64_t(NB * NB);
@@ -476,7 +483,7 @@ __global__ __launch_bounds__(256) void trsm_panel_kernel(const MatDesc* mats, T*
 
 // A_ij -= L_ik L_jk^T for k < j <= i < Tx (pairs enumerated row by row).
 template <typename T>
-__global__ __launch_bounds__(256) void syrk_update_kernel(const MatDesc* mats, T* tiles, int k) {
+__global__ __launch_bounds__(256) void syrk_update_kernel(const MatDesc* mats, T* tiles, int k, const int32_t* fcol) {
   const MatDesc D = mats[blockIdx.y];
   if (k >= D.T) return;
   const int m = D.Tx - k - 1;                 // tile rows below k
@@ -487,6 +494,7 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(const MatDesc* mats, T
   while (int64_t(ii + 1) * (ii + 2) / 2 <= pidx) ++ii;
   const int jj = int(pidx - int64_t(ii) * (ii + 1) / 2);
   const int i = k + 1 + ii, j = k + 1 + jj;
+  if (tile_zero(fcol, D, i, k) || tile_zero(fcol, D, j, k)) return;
   __shared__ T sa[NB * LDT];
   __shared__ T sb[NB * LDT];
   const T* lik = tiles + (D.tile_off + tri_tile(i, k)) * int64_t(NB * NB);
@@ -510,7 +518,7 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(const MatDesc* mats, T
 }
 
 void launch_factor(const MatDesc* mats, int nmats, int maxT, int maxTx, void* tiles, void* dinv, bool fp32,
-                   int* err, hipStream_t st) {
+                   const int32_t* fcol, int* err, hipStream_t st) {
   for (int k = 0; k < maxT; ++k) {
     const int below = maxTx - k - 1;
     if (fp32) {
@@ -518,18 +526,18 @@ void launch_factor(const MatDesc* mats, int nmats, int maxT, int maxTx, void* ti
                          (float*)dinv, k, err);
       if (below > 0) {
         hipLaunchKernelGGL(trsm_panel_kernel<float>, dim3(below, nmats), dim3(256), 0, st, mats, (float*)tiles,
-                           (const float*)dinv, k);
+                           (const float*)dinv, k, fcol);
         hipLaunchKernelGGL(syrk_update_kernel<float>, dim3(int64_t(below) * (below + 1) / 2, nmats), dim3(256),
-                           0, st, mats, (float*)tiles, k);
+                           0, st, mats, (float*)tiles, k, fcol);
       }
     } else {
       hipLaunchKernelGGL(potrf_diag_kernel<double>, dim3(nmats), dim3(256), 0, st, mats, (double*)tiles,
                          (double*)dinv, k, err);
       if (below > 0) {
         hipLaunchKernelGGL(trsm_panel_kernel<double>, dim3(below, nmats), dim3(256), 0, st, mats,
-                           (double*)tiles, (const double*)dinv, k);
+                           (double*)tiles, (const double*)dinv, k, fcol);
         hipLaunchKernelGGL(syrk_update_kernel<double>, dim3(int64_t(below) * (below + 1) / 2, nmats),
-                           dim3(256), 0, st, mats, (double*)tiles, k);
+                           dim3(256), 0, st, mats, (double*)tiles, k, fcol);
       }
     }
   }
@@ -690,8 +698,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
   constexpr int LPR = NB / VEC;      // lanes per tile row
   constexpr int RPI = 64 / LPR;      // tile rows per wave instruction
   constexpr int NI = 16 / RPI;       // instructions per 16-row slab
-  constexpr bool FWD = (MODE == TRSV_FWD_RR || MODE == TRSV_FWD_II || MODE == TRSV_FWD_C || MODE == TRSV_FWD_G);
-  constexpr bool IFACE = (MODE == TRSV_FWD_G || MODE == TRSV_BWD_G);
+  constexpr bool FWD = (MODE == TRSV_FWD_RR || MODE == TRSV_FWD_II || MODE == TRSV_FWD_C);
 
   __shared__ T s_rhs[NB];
   __shared__ T s_v[NB];
@@ -717,10 +724,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     const MatDesc D = A.mats[s];
     const int T_rows = (MODE == TRSV_FWD_II || MODE == TRSV_BWD_II) ? D.TI : D.T;
     const int nlim = (MODE == TRSV_FWD_II || MODE == TRSV_BWD_II) ? D.n_I : D.n_R;
-    // interface modes work on the trailing block of rows n_I..n_R-1 (L_GG); the
-    // interior rows of the straddling tile are held at zero
-    const int nlo = IFACE ? D.n_I : 0;
-    const int j0 = IFACE ? D.n_I / NB : 0;
+    const int nlo = 0, j0 = 0;
     const int64_t tbase = D.tile_off;
     T* my_sol = sol + D.vec_off;
 
@@ -729,7 +733,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
       const int a = k * NB + tid;
       double rhs = 0.0;
       if (a >= nlo && a < nlim) {
-        if (MODE == TRSV_FWD_RR || MODE == TRSV_FWD_G) {
+        if (MODE == TRSV_FWD_RR) {
           const int64_t l = D.loc_off + a;
           rhs = A.wd[l] * A.rin[A.gmap[l]];
         } else if (MODE == TRSV_FWD_II) {
@@ -750,7 +754,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
       }
       s_rhs[tid] = T(rhs);
     }
-    if ((MODE == TRSV_BWD_RR || MODE == TRSV_BWD_G) && D.n_ci > 0) {
+    if (MODE == TRSV_BWD_RR && D.n_ci > 0) {
       // rhs_k += W_k coef, W_k^T stored in the bordering tile row (rows = constraints)
       __syncthreads();
       const T* bt = tiles + (tbase + tri_tile(D.T, k)) * int64_t(NB * NB);
@@ -765,14 +769,18 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     // ---------------- main loop over off-diagonal tiles ----------------
     T acc[FWD ? NI : VEC];
     for (int i = 0; i < (FWD ? NI : VEC); ++i) acc[i] = T(0);
-    const int nt = FWD ? k - j0 : (T_rows - 1 - k);
+    // only the tiles inside the envelope: forward reads (k, jlo..k-1), backward
+    // reads (jhi..k+1, k); the tiles outside are zero
+    const int jlo = (FWD && A.fcol) ? max(j0, int(A.fcol[D.vec_off / NB + k])) : j0;
+    const int jhi = (!FWD && A.lrow) ? int(A.lrow[D.vec_off / NB + k]) : T_rows - 1;
+    const int nt = FWD ? k - jlo : (jhi - k);
     if (nt > 0) {
       auto tile_ptr = [&](int jj) -> const T* {
-        // forward: tile (k, j0 + jj), jj = 0..k-j0-1; backward: tile (j, k), j = T_rows-1 .. k+1
-        int64_t t = FWD ? tri_tile(k, j0 + jj) : tri_tile(T_rows - 1 - jj, k);
+        // forward: tile (k, jlo + jj), jj = 0..k-jlo-1; backward: tile (j, k), j = jhi .. k+1
+        int64_t t = FWD ? tri_tile(k, jlo + jj) : tri_tile(jhi - jj, k);
         return tiles + (tbase + t) * int64_t(NB * NB) + (16 * w + lr) * NB + VEC * lc;
       };
-      auto sol_row = [&](int jj) -> int { return FWD ? j0 + jj : (T_rows - 1 - jj); };
+      auto sol_row = [&](int jj) -> int { return FWD ? jlo + jj : (jhi - jj); };
       V cur[NI], nxt[NI];
       {
         const T* p = tile_ptr(0);
@@ -855,7 +863,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     __syncthreads();
 
     // ---------------- epilogue ----------------
-    if ((MODE == TRSV_FWD_RR || MODE == TRSV_FWD_G) && D.n_ci > 0) {
+    if (MODE == TRSV_FWD_RR && D.n_ci > 0) {
       // partial border products h_c = sum_r W^T[c][r] y_k[r] for this tile row
       const T* bt = tiles + (tbase + tri_tile(D.T, k)) * int64_t(NB * NB);
       for (int c = w; c < D.n_ci; c += 4) {   // one wave per constraint row, coalesced
@@ -863,7 +871,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         if (lane == 0) A.part[(D.vec_off / NB + k) * MAX_NCI + c] = v;
       }
-    } else if (MODE == TRSV_BWD_RR || MODE == TRSV_BWD_G) {
+    } else if (MODE == TRSV_BWD_RR) {
       if (tid < NB) {
         const int a = k * NB + tid;
         if (a >= nlo && a < D.n_R) {
@@ -899,8 +907,6 @@ static void launch_trsv_t(int mode, const TrsvArgs& a, int grid, hipStream_t st)
     case TRSV_BWD_II: hipLaunchKernelGGL((trsv_kernel<T, TRSV_BWD_II>), dim3(grid), dim3(256), 0, st, a); break;
     case TRSV_FWD_C: hipLaunchKernelGGL((trsv_kernel<T, TRSV_FWD_C>), dim3(grid), dim3(256), 0, st, a); break;
     case TRSV_BWD_C: hipLaunchKernelGGL((trsv_kernel<T, TRSV_BWD_C>), dim3(grid), dim3(256), 0, st, a); break;
-    case TRSV_FWD_G: hipLaunchKernelGGL((trsv_kernel<T, TRSV_FWD_G>), dim3(grid), dim3(256), 0, st, a); break;
-    case TRSV_BWD_G: hipLaunchKernelGGL((trsv_kernel<T, TRSV_BWD_G>), dim3(grid), dim3(256), 0, st, a); break;
   }
 }
 
@@ -1381,7 +1387,7 @@ void launch_coarse_inverse(const double* xg, const double* dc, int nc, double* a
 }
 
 // u_c = A_c^{-1} r_c with r_c = sum_i R_ci^T g_i gathered per column block; block
-// (row block of 64 rows, column split s) writes its partial u into upart[s*nc + i]
+// (four rows, column split s) writes its partial u into upart[s*nc + i]
 __global__ __launch_bounds__(256) void coarse_gemv_kernel(const double* ainv, int nc, int cs,
                                                           const int32_t* cinv_ptr, const int32_t* cinv,
                                                           const double* gbuf, double* upart, const int* done) {
@@ -1395,23 +1401,22 @@ __global__ __launch_bounds__(256) void coarse_gemv_kernel(const double* ainv, in
     rcs[j - j0] = v;
   }
   __syncthreads();
+  // one row per wave: the rows are independent, so many short chains in flight
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int rr = 0; rr < 16; ++rr) {
-    const int i = blockIdx.x * 64 + w * 16 + rr;
-    if (i >= nc) break;
-    const double* row = ainv + int64_t(i) * nc;
-    double v = 0.0;
-    for (int j = j0 + lane; j < j1; j += 64) v += row[j] * rcs[j - j0];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) upart[int64_t(s) * nc + i] = v;
-  }
+  const int i = blockIdx.x * 4 + w;
+  if (i >= nc) return;
+  const double* row = ainv + int64_t(i) * nc;
+  double v = 0.0;
+  for (int j = j0 + lane; j < j1; j += 64) v += row[j] * rcs[j - j0];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) upart[int64_t(s) * nc + i] = v;
 }
 
 void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* cinv_ptr, const int32_t* cinv,
                         const double* gbuf, double* upart, const int* done, hipStream_t st) {
   if (nc <= 0) return;
   const int cs = (nc + nsplit - 1) / nsplit;
-  hipLaunchKernelGGL(coarse_gemv_kernel, dim3((nc + 63) / 64, nsplit), dim3(256), 0, st, ainv, nc, cs, cinv_ptr,
+  hipLaunchKernelGGL(coarse_gemv_kernel, dim3((nc + 3) / 4, nsplit), dim3(256), 0, st, ainv, nc, cs, cinv_ptr,
                      cinv, gbuf, upart, done);
 }
 
@@ -1510,6 +1515,26 @@ void launch_sym_build(int mode, const MatDesc* mats, int nmats, int maxTG, const
     hipLaunchKernelGGL(sym_build_kernel<SYM_PC>, grid, dim3(256), 0, st, mats, tiles, xg, cpp, out);
 }
 
+// Sum over the lanes l, l^8, l^16, ... l^56 (lane bits 3..5) without the LDS
+// crossbar: bit 3 by a DPP rotation by 8 inside each row of 16 lanes, bits 4
+// and 5 by the row and half-wave swaps (each swap returns both halves, whose
+// sum is the same in every lane).
+__device__ __forceinline__ double sum_rg(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  v += __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, 0x128, 0xf, 0xf, false),
+                        __builtin_amdgcn_update_dpp(0, lo, 0x128, 0xf, 0xf, false));
+  lo = __double2loint(v);
+  hi = __double2hiint(v);
+  auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  v = __hiloint2double(ph[0], pl[0]) + __hiloint2double(ph[1], pl[1]);
+  lo = __double2loint(v);
+  hi = __double2hiint(v);
+  pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double(ph[0], pl[0]) + __hiloint2double(ph[1], pl[1]);
+}
+
 // y = M v for a symmetric interface matrix; task = (matrix, row ii).  The task
 // streams the contiguous tiles (ii, 0..ii) once and uses each twice: the row
 // product sum_jj M(ii, jj) v_jj, stored in the slot of the diagonal tile, and
@@ -1520,6 +1545,7 @@ void launch_sym_build(int mode, const MatDesc* mats, int nmats, int maxTG, const
 // Wave w owns columns 16w..16w+15 of every tile; lane = 8 * rg + cp holds rows
 // rg + 8t (t < 8) of columns 16w + 2cp, +1, so a column product reduces over the
 // eight rg lanes of one wave and a row product over the eight cp lanes.
+constexpr int SYM_UNROLL = 2;
 template <int MODE>
 __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   using V = d2v;
@@ -1550,7 +1576,6 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
       s_x[e] = v;
     }
     __syncthreads();
-    const int nt = ii + 1;
     const double* base = A.m + (D.sg_off + tri_tile(ii, 0)) * int64_t(NB * NB) + rg * NB + col;
     double* pcol = A.part + (D.sg_off + tri_tile(ii, 0)) * NB + col;
     double xi[8], racc[8];
@@ -1558,37 +1583,37 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
       xi[t] = s_x[ii * NB + rg + 8 * t];
       racc[t] = 0.0;
     }
-    // two tiles in flight ahead of the one being multiplied
-    V cur[8], nx1[8], nx2[8];
-    for (int t = 0; t < 8; ++t) cur[t] = *reinterpret_cast<const V*>(base + t * 8 * NB);
-    if (nt > 1)
-      for (int t = 0; t < 8; ++t) nx1[t] = *reinterpret_cast<const V*>(base + NB * NB + t * 8 * NB);
-    for (int jj = 0; jj < nt; ++jj) {
-      if (jj + 2 < nt)
-        for (int t = 0; t < 8; ++t)
-          nx2[t] = *reinterpret_cast<const V*>(base + int64_t(jj + 2) * NB * NB + t * 8 * NB);
-      const double x0 = s_x[jj * NB + col], x1 = s_x[jj * NB + col + 1];
-      double c0 = 0.0, c1 = 0.0;
-      for (int t = 0; t < 8; ++t) {
-        racc[t] += cur[t][0] * x0 + cur[t][1] * x1;
-        c0 += cur[t][0] * xi[t];
-        c1 += cur[t][1] * xi[t];
+    // Tiles in the order ii (the diagonal: row product only), 0, 1, .., ii-1,
+    // SYM_UNROLL at a time: all their loads are issued before the first is
+    // used, and no register buffer lives across iterations (many waves per SIMD
+    // keep HBM busy while one multiplies).  Loads past the end of the row
+    // re-read the row's last tile, which is still cached.  Only the eight lanes
+    // of the first row group store a column product (all lanes hold the sums).
+    V b[SYM_UNROLL][8];
+    for (int k = 0; k <= ii; k += SYM_UNROLL) {
+      int jt[SYM_UNROLL];
+      for (int u = 0; u < SYM_UNROLL; ++u) {
+        const int kk = min(k + u, ii);
+        jt[u] = kk == 0 ? ii : kk - 1;
+        const double* p = base + int64_t(jt[u]) * NB * NB;
+        for (int t = 0; t < 8; ++t) b[u][t] = *reinterpret_cast<const V*>(p + t * 8 * NB);
       }
-      if (jj < ii) {
-        for (int off = 8; off < 64; off <<= 1) {
-          c0 += __shfl_xor(c0, off, 64);
-          c1 += __shfl_xor(c1, off, 64);
-        }
-        if (rg == 0) {
+      for (int u = 0; u < SYM_UNROLL; ++u) {
+        if (k + u > ii) break;
+        const int jj = jt[u];
+        const double x0 = s_x[jj * NB + col], x1 = s_x[jj * NB + col + 1];
+        for (int t = 0; t < 8; ++t) racc[t] += b[u][t][0] * x0 + b[u][t][1] * x1;
+        if (k + u > 0) {
+          double c0 = 0.0, c1 = 0.0;
+          for (int t = 0; t < 8; ++t) {
+            c0 += b[u][t][0] * xi[t];
+            c1 += b[u][t][1] * xi[t];
+          }
           V o;
-          o[0] = c0;
-          o[1] = c1;
-          *reinterpret_cast<V*>(pcol + jj * NB) = o;
+          o[0] = sum_rg(c0);
+          o[1] = sum_rg(c1);
+          if (rg == 0) *reinterpret_cast<V*>(pcol + jj * NB) = o;   // one 128 B segment per wave
         }
-      }
-      for (int t = 0; t < 8; ++t) {
-        cur[t] = nx1[t];
-        nx1[t] = nx2[t];
       }
     }
     for (int t = 0; t < 8; ++t) {

@@ -275,6 +275,39 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
     for (int64_t q : interior) push_local(q);
     for (int64_t q : gamma) push_local(q);
     for (auto& cq : corners) push_local(cq.second);
+    // envelope of A_RR by tile rows: a Q1 node couples with the nodes of the
+    // elements around it, |offset| <= 1 per axis inside the box
+    {
+      std::vector<int32_t> fc(D.T), fi(D.T);   // all rows of A_RR, interior rows only
+      for (int k = 0; k < D.T; ++k) fc[k] = fi[k] = k;
+      for (int64_t q = 0; q < nbox; ++q) {
+        const int32_t la = P.lmap[lmap_off + q];
+        if (la < 0 || la >= D.n_R) continue;
+        const int64_t lc[3] = {q % n1[0], (q / n1[0]) % n1[1], q / (n1[0] * n1[1])};
+        int32_t fmin = la;
+        for (int dz = (dim == 3 ? -1 : 0); dz <= (dim == 3 ? 1 : 0); ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              const int64_t x = lc[0] + dx, y = lc[1] + dy, z = lc[2] + dz;
+              if (x < 0 || x >= n1[0] || y < 0 || y >= n1[1] || z < 0 || z >= n1[2]) continue;
+              const int32_t lb = P.lmap[lmap_off + (z * n1[1] + y) * n1[0] + x];
+              if (lb >= 0 && lb < D.n_R) fmin = std::min(fmin, lb);
+            }
+        fc[la / NB] = std::min(fc[la / NB], fmin / NB);
+        if (la < D.n_I) fi[la / NB] = std::min(fi[la / NB], fmin / NB);
+      }
+      for (int k = 0; k < D.T; ++k) {
+        int32_t lr = k, li = k;
+        for (int j = k + 1; j < D.T; ++j) {
+          if (fc[j] <= k) lr = j;
+          if (j < D.TI && fi[j] <= k) li = j;
+        }
+        P.lrow_rr.push_back(lr);
+        P.lrow_ii.push_back(li);
+      }
+      P.fcol.insert(P.fcol.end(), fc.begin(), fc.end());
+      P.fcol_ii.insert(P.fcol_ii.end(), fi.begin(), fi.end());
+    }
     // local coarse order [averages | corners]
     for (auto& a : avgs) P.rc.push_back(a.first);
     for (auto& cq : corners) P.rc.push_back(cq.first);
@@ -373,21 +406,8 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
   make_tasks(P.bwd_rr, false, true);
   make_tasks(P.fwd_ii, true, false);
   make_tasks(P.bwd_ii, true, true);
-  // interface (trailing) block: tile rows n_I/NB .. T-1
+  // interface form
   {
-    int maxG = 0;
-    for (auto& D : P.subs) maxG = std::max(maxG, int(D.T - D.n_I / NB));
-    for (int d = 0; d < maxG; ++d)
-      for (int s = 0; s < P.nsubs; ++s) {
-        const MatDesc& D = P.subs[s];
-        const int k0 = D.n_I / NB;
-        if (d < D.T - k0) {
-          P.fwd_g.push_back(s);
-          P.fwd_g.push_back(k0 + d);
-          P.bwd_g.push_back(s);
-          P.bwd_g.push_back(D.T - 1 - d);
-        }
-      }
     // rows of the symmetric interface matrices are independent tasks: take the
     // longest first (row ii streams ii + 1 tiles)
     struct Job { int len, s, ii; };
