@@ -124,12 +124,12 @@ struct bddc_ctx {
   int32_t *ctask_fwd = nullptr, *ctask_bwd = nullptr;
   int Tc = 0;
   int32_t *t_fwd_rr = nullptr, *t_bwd_rr = nullptr, *t_fwd_ii = nullptr, *t_bwd_ii = nullptr;
-  int32_t *t_sym = nullptr, *t_symfin = nullptr;
+  int32_t *t_symfin = nullptr, *tinfo = nullptr, *padz = nullptr, *padf = nullptr;
   int32_t *fcol = nullptr, *fcol_ii = nullptr, *lrow_rr = nullptr, *lrow_ii = nullptr;   // factor envelopes
   double* xg = nullptr;                        // inverses of the trailing factor blocks
   double *sg = nullptr, *hg = nullptr;         // interface form: Schur complements, X^T X (+ border rows)
-  double* symp = nullptr;                      // their partial products, 64 per stored tile
-  double *zloc = nullptr, *floc = nullptr;     // D^{-1} z and W D r in local-dof order
+  double *symp = nullptr, *rowp = nullptr;     // their column / row partial products
+  double *zpad = nullptr, *fpad = nullptr;     // D^{-1} z (+ corners) and W D r in padded rows
   double *cxg = nullptr, *cainv = nullptr, *upart = nullptr;   // explicit coarse inverse (interface form)
   int csplit = 1;
   double *sploc = nullptr, *cpp = nullptr;
@@ -231,6 +231,15 @@ struct bddc_ctx {
     hipEventRecord(e, st);
     return e;
   }
+  // a start/stop pair that the kernel dispatch itself records (the kernel's own
+  // duration, without the queue gap in front of it)
+  void kernel_events(const char* name, hipEvent_t* b, hipEvent_t* e) {
+    *b = *e = nullptr;
+    if (!timing || capture_timed) return;
+    *b = get_event();
+    *e = get_event();
+    fam[name].pending.push_back({*b, *e});
+  }
   void end(const char* name, hipEvent_t b) {
     if (!timing || !b) return;
     hipEvent_t e = nullptr;
@@ -309,13 +318,15 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   a.sol = pub_slot(c, 0);
   a.rin = r;
   a.part = c->part;
-  hipEvent_t e = c->begin("trsv_fwd_rr");
-  launch_trsv(TRSV_FWD_RR, c->fp32, a, trsv_grid(c, a.ntasks), st);
-  c->end("trsv_fwd_rr", e);
+  {
+    hipEvent_t k0, k1;
+    c->kernel_events("trsv_fwd_rr", &k0, &k1);
+    launch_trsv(TRSV_FWD_RR, c->fp32, a, trsv_grid(c, a.ntasks), st, k0, k1);
+  }
 
   if (P.n_coarse > 0) {
     launch_coarse_prep(c->mats, P.nsubs, c->part, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done, nullptr,
-                       st);
+                       0, 0, st);
     TrsvArgs cf;
     std::memset(&cf, 0, sizeof(cf));
     cf.mats = c->cmat;
@@ -351,9 +362,11 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   a.src = pub_slot(c, 0);
   a.coef = c->coef;
   a.ww = c->ww;
-  e = c->begin("trsv_bwd_rr");
-  launch_trsv(TRSV_BWD_RR, c->fp32, a, trsv_grid(c, a.ntasks), st);
-  c->end("trsv_bwd_rr", e);
+  {
+    hipEvent_t k0, k1;
+    c->kernel_events("trsv_bwd_rr", &k0, &k1);
+    launch_trsv(TRSV_BWD_RR, c->fp32, a, trsv_grid(c, a.ntasks), st, k0, k1);
+  }
   // v1 + v2 = sum_i R_i^T W_i w_i
   launch_gather_v12(c->inv_ptr, c->inv, c->ww, c->kappa, c->v12, z, P.n_free, done, st);
   // v3: interior solves of r1 = r - A (v1 + v2)
@@ -366,9 +379,11 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   a.sol = pub_slot(c, 2);
   a.rin = r;
   a.v12 = c->v12;
-  e = c->begin("trsv_fwd_ii");
-  launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
-  c->end("trsv_fwd_ii", e);
+  {
+    hipEvent_t k0, k1;
+    c->kernel_events("trsv_fwd_ii", &k0, &k1);
+    launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st, k0, k1);
+  }
   a = base_args(c);
   a.done = done;
   a.tasks = c->t_bwd_ii;
@@ -379,9 +394,11 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   a.src = pub_slot(c, 2);
   a.zout = z;
   a.base = c->v12;
-  e = c->begin("trsv_bwd_ii");
-  launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
-  c->end("trsv_bwd_ii", e);
+  {
+    hipEvent_t k0, k1;
+    c->kernel_events("trsv_bwd_ii", &k0, &k1);
+    launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st, k0, k1);
+  }
   c->end("apply", ea);
 }
 
@@ -389,7 +406,10 @@ IfaceArgs iface_args(bddc_ctx* c) {
   IfaceArgs a;
   std::memset(&a, 0, sizeof(a));
   a.mats = c->mats;
-  a.maxtg = c->plan.maxTG;
+  a.tinfo = c->tinfo;
+  a.ntiles = c->plan.n_sg;
+  a.nwg = int(std::min<int64_t>(c->grid_trsv, c->plan.n_sg));
+  a.rowp = c->rowp;
   a.sc = c->sc;
   a.part = c->symp;
   a.dsc = c->dsc;
@@ -416,16 +436,15 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
   hipEvent_t ea = c->begin("apply");
   IfaceArgs a = iface_args(c);
   a.m = c->hg;
-  a.loc_in = c->floc;
-  a.tasks = c->t_sym;
-  a.ntasks = int(P.sym.size() / 2);
-  a.ticket = c->tickets + 0;
-  hipEvent_t e = c->begin("pc");
-  launch_sym_mv(SYM_PC, a, trsv_grid(c, a.ntasks), st);
-  c->end("pc", e);
+  a.xpad = c->fpad;
+  {
+    hipEvent_t k0, k1;
+    c->kernel_events("pc", &k0, &k1);
+    launch_sym_mv(a, st, k0, k1);
+  }
   if (P.n_coarse > 0) {
     launch_coarse_prep(c->mats, P.nsubs, nullptr, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done,
-                       c->symp, st);
+                       c->rowp, a.ntiles, a.nwg, st);
     launch_coarse_gemv(c->cainv, P.n_coarse, c->csplit, c->cinv_ptr, c->cinv, c->gbuf, c->upart, done, st);
   }
   a.uc = c->upart;
@@ -435,7 +454,7 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
   a.ntasks = int(P.symfin.size() / 2);
   launch_pc_finish(a, st);
   launch_gather_z(c->inv_ptr, c->inv, c->ww, c->kappa, r, z, part_rz, P.n_free, done, c->pub_coarse,
-                  2 * int64_t(c->Tc) * NB, c->tickets, c->dsc, c->zloc, st);
+                  2 * int64_t(c->Tc) * NB, c->tickets, c->dsc, c->padz, c->zpad, st);
   c->end("apply", ea);
 }
 
@@ -447,13 +466,12 @@ void enqueue_schur(bddc_ctx* c, int it, bool fresh, const double* part_rz, doubl
   hipEvent_t e = c->begin("schur");
   IfaceArgs a = iface_args(c);
   a.m = c->sg;
-  a.loc_in = c->zloc;
-  a.tasks = c->t_sym;
-  a.ntasks = int(P.sym.size() / 2);
-  a.ticket = c->tickets + 2;
-  hipEvent_t e1 = c->begin("op");
-  launch_sym_mv(SYM_OP, a, trsv_grid(c, a.ntasks), st);
-  c->end("op", e1);
+  a.xpad = c->zpad;
+  {
+    hipEvent_t k0, k1;
+    c->kernel_events("op", &k0, &k1);
+    launch_sym_mv(a, st, k0, k1);
+  }
   a.tasks = c->t_symfin;
   a.ntasks = int(P.symfin.size() / 2);
   launch_op_finish(a, st);
@@ -504,7 +522,7 @@ void enqueue_iteration(bddc_ctx* c, double* x, int it, bool fresh) {
   }
   if (c->iface)
     launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st, c->inv_ptr, c->inv, c->wd,
-                      c->floc);
+                      c->padf, c->fpad);
   else
     launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st);
   launch_pcg_check(c->part_b, c->sc, it, st);
@@ -631,7 +649,9 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->upload(c->t_bwd_rr, P.bwd_rr))) return rc_;
   if ((rc_ = c->upload(c->t_fwd_ii, P.fwd_ii))) return rc_;
   if ((rc_ = c->upload(c->t_bwd_ii, P.bwd_ii))) return rc_;
-  if ((rc_ = c->upload(c->t_sym, P.sym))) return rc_;
+  if ((rc_ = c->upload(c->tinfo, P.tinfo))) return rc_;
+  if ((rc_ = c->upload(c->padz, P.padz))) return rc_;
+  if ((rc_ = c->upload(c->padf, P.padf))) return rc_;
   if ((rc_ = c->upload(c->fcol, P.fcol))) return rc_;
   if ((rc_ = c->upload(c->fcol_ii, P.fcol_ii))) return rc_;
   if ((rc_ = c->upload(c->lrow_rr, P.lrow_rr))) return rc_;
@@ -687,9 +707,10 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
     if ((rc_ = c->alloc(c->sg, P.n_sg * NB * NB))) return rc_;
     if ((rc_ = c->alloc(c->hg, P.n_sg * NB * NB))) return rc_;
     if ((rc_ = c->alloc(c->symp, P.n_sg * NB))) return rc_;
-    launch_sym_build(SYM_OP, c->mats, P.nsubs, P.maxTG, static_cast<const double*>(c->tiles), c->xg, c->cpp, c->sg,
+    if ((rc_ = c->alloc(c->rowp, P.n_sg * 4 * NB))) return rc_;
+    launch_sym_build(SYM_OP, c->mats, P.nsubs, P.maxTS, static_cast<const double*>(c->tiles), c->xg, c->cpp, c->sg,
                      st);
-    launch_sym_build(SYM_PC, c->mats, P.nsubs, P.maxTG, static_cast<const double*>(c->tiles), c->xg, c->cpp, c->hg,
+    launch_sym_build(SYM_PC, c->mats, P.nsubs, P.maxTS, static_cast<const double*>(c->tiles), c->xg, c->cpp, c->hg,
                      st);
   }
 
@@ -753,10 +774,10 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->alloc(c->part_c, VEC_GRID))) return rc_;
   if ((rc_ = c->alloc(c->sc, 1))) return rc_;
   if ((rc_ = c->alloc(c->xw, P.n_free))) return rc_;
-  if ((rc_ = c->alloc(c->zloc, P.n_loc))) return rc_;
-  if ((rc_ = c->alloc(c->floc, P.n_loc))) return rc_;
-  launch_fill<double>(c->zloc, 0.0, P.n_loc, st);
-  launch_fill<double>(c->floc, 0.0, P.n_loc, st);
+  if ((rc_ = c->alloc(c->zpad, P.n_symrows * NB + 1))) return rc_;
+  if ((rc_ = c->alloc(c->fpad, P.n_symrows * NB + 1))) return rc_;
+  launch_fill<double>(c->zpad, 0.0, P.n_symrows * NB + 1, st);
+  launch_fill<double>(c->fpad, 0.0, P.n_symrows * NB + 1, st);
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hsnap), 4 * sizeof(int), hipHostMallocDefault));
   for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreateWithFlags(&c->snap_ev[i], hipEventDisableTiming));
   if ((rc_ = c->alloc(c->sploc, P.n_loc))) return rc_;
@@ -841,10 +862,10 @@ int bddc_setup(const bddc_mesh* mesh, const bddc_partition* part, const bddc_coe
   // only with FP64 factors; FP32 local factors iterate on the whole space, where
   // the operator is the FP64 global matrix
   c->iface = !(opts->flags & BDDC_SETUP_FULL_SPACE) && !c->fp32;
-  // the interface mat-vecs stage a subdomain's trailing rows in LDS: at most
-  // IFACE_MAX_TG tile rows (4096 interface rows); larger boxes iterate on the whole space
+  // the interface mat-vec packs a tile's row distance into 8 bits: at most
+  // IFACE_MAX_TS tile rows per subdomain; larger boxes iterate on the whole space
   for (auto& D : c->plan.subs)
-    if (D.T - D.n_I / NB > IFACE_MAX_TG) c->iface = false;
+    if (sym_tile_rows(D) > IFACE_MAX_TS) c->iface = false;
   c->mesh.dim = c->plan.dim;
   for (int a = 0; a < 3; ++a) {
     c->mesh.nel[a] = int(c->plan.nel[a]);
@@ -943,7 +964,7 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
     // (re)start: z = M^{-1} r, rz
     if (iface) {
       launch_reset(false, nullptr, 0, c->pub_coarse, 2 * int64_t(c->Tc) * NB, c->tickets, done, st);
-      launch_scatter_local(c->inv_ptr, c->inv, c->wd, c->r, c->floc, n, st);
+      launch_scatter_pad(c->inv_ptr, c->inv, c->wd, c->r, c->padf, c->fpad, n, st);
       enqueue_apply_iface(c, c->r, c->z, c->part_c, done);
     } else {
       enqueue_apply(c, c->r, c->z, done);

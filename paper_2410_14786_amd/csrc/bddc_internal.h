@@ -33,10 +33,9 @@ struct MatDesc {
   int32_t box_lo[3];  // first element of the box along each axis
   int32_t box_len[3]; // box length in elements
   int32_t lmap_off;   // offset of the box-node -> local index table
-  int32_t pad;
+  int32_t sym_row;    // global index of this matrix's first row of symmetric interface tiles
   int64_t xg_off;     // first tile of the inverse of the trailing block (tile rows n_I/NB .. T-1)
-  int64_t sg_off;     // first tile of the symmetric interface matrices (TG + 1 tile rows,
-                      // TG = T - n_I/NB; the last one is the border row)
+  int64_t sg_off;     // first tile of the symmetric interface matrices (sym_tile_rows tile rows)
 };
 
 // Host-side plan: everything bddc_setup derives from the mesh and partition
@@ -89,13 +88,18 @@ struct Plan {
 
   // ticket-ordered task lists of the triangular solves, (matrix, tile row)
   std::vector<int32_t> fwd_rr, bwd_rr, fwd_ii, bwd_ii;
-  // interface form, (matrix, ii) with ii = 0..TG a row of the symmetric interface
-  // matrices: sym longest first (row ii streams ii + 1 tiles), symfin in order
-  std::vector<int32_t> sym, symfin;
+  // interface form: the symmetric interface matrices of all subdomains form one
+  // stream of n_sg tiles (sg_off order) and n_symrows tile rows (sym_row order).
+  // symfin = (matrix, ii) per row; tinfo per tile = (global row << 8) | (ii - jj);
+  // padz / padf per local dof: its slot in the padded per-row input vectors
+  // (64 per row) of the operator (interface and corner dofs) and of the
+  // preconditioner (interface dofs), -1 elsewhere
+  std::vector<int32_t> symfin, tinfo, padz, padf;
+  int64_t n_symrows = 0;
 
   int maxT = 0, maxTx = 0, maxTI = 0;
   int64_t n_tiles = 0, n_dinv = 0, n_vec = 0, n_loc = 0, n_lmap = 0, n_xg = 0, n_sg = 0;
-  int maxTG = 0;
+  int maxTG = 0, maxTS = 0;
   int max_nci = 0;
 };
 
@@ -111,5 +115,9 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
 
 // Tile index of tile (i, j), j <= i, inside a matrix's packed lower storage.
 BDDC_HD inline int64_t tri_tile(int64_t i, int64_t j) { return i * (i + 1) / 2 + j; }
+
+// Symmetric interface matrices of a subdomain: rows 0..n_G-1 are its interface
+// rows (local dofs n_I..n_R-1), rows n_G..n_G+n_ci-1 its constraints; tile rows:
+BDDC_HD inline int sym_tile_rows(const MatDesc& D) { return (D.n_R - D.n_I + D.n_ci + NB - 1) / NB; }
 
 }  // namespace bddc

@@ -74,13 +74,16 @@ struct PcgScalars {
 
 struct IfaceArgs {
   const MatDesc* mats;
-  const double* m;          // symmetric interface matrix (operator or preconditioner)
-  const int32_t* tasks;     // (matrix, row ii of the symmetric matrices)
+  const double* m;          // symmetric interface matrices, one stream of ntiles tiles
+  const int32_t* tinfo;     // per tile: (global row << 8) | (ii - jj)
+  int64_t ntiles;
+  int nwg;                  // workgroups of the mat-vec launch (its range split)
+  const int32_t* tasks;     // finishers: (matrix, row ii)
   int ntasks;
-  unsigned* ticket;
   const PcgScalars* sc;
-  const double* loc_in;     // SYM_OP: D^{-1} z, SYM_PC: W D r, both in local-dof order
-  double* part;             // 64 partial products per stored tile of the symmetric matrices
+  const double* xpad;       // padded per-row input (64 per row): D^{-1} z + corners, or W D r
+  double* part;             // column products, 64 per tile
+  double* rowp;             // row products per piece and wave, 4 x 64 per piece start tile
   const double* dsc;
   const double* wd;
   const double* wgt;
@@ -93,7 +96,6 @@ struct IfaceArgs {
   const double* mu;
   const double* sainv;
   const double* sainve;
-  int maxtg;                // largest trailing block, in tile rows (at most IFACE_MAX_TG)
 };
 
 template <typename T> void launch_fill(T* p, T v, int64_t n, hipStream_t st);
@@ -114,10 +116,13 @@ void launch_local_small(const MatDesc* mats, int nmats, const void* tiles, bool 
 void launch_coarse_assembly(const int32_t* src_ptr, const int32_t* src, const int32_t* row, const int32_t* col,
                             const int32_t* diag, int nentries, int nc, const double* aci, double* val, double* dc,
                             double* tiles, int* err, hipStream_t st);
-void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st);
+// t0 / t1: optional events recorded by the dispatch itself at kernel start / end
+void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st, hipEvent_t t0 = nullptr,
+                 hipEvent_t t1 = nullptr);
 void launch_coarse_prep(const MatDesc* mats, int nmats, const double* part, const double* sainv,
                         const double* sainve, const int32_t* gmap, const double* wgt, const double* r,
-                        double* gbuf, double* mu, const int* done, const double* symp, hipStream_t st);
+                        double* gbuf, double* mu, const int* done, const double* rowp, int64_t ntiles, int nwg,
+                        hipStream_t st);
 void launch_coarse_coef(const MatDesc* mats, int nmats, const int32_t* rc, const double* uc, const double* mu,
                         const double* sainv, const double* sainve, const double* wgt, double* coef, double* ww,
                         const int* done, hipStream_t st);
@@ -137,7 +142,7 @@ void launch_pcg_dir(const int32_t* rowptr, const int32_t* col, const double* val
 void launch_pcg_update(double* x, double* r, const double* p, const double* q, const double* part_pq,
                        double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st,
                        const int32_t* inv_ptr = nullptr, const int32_t* inv = nullptr, const double* wd = nullptr,
-                       double* floc = nullptr);
+                       const int32_t* padf = nullptr, double* fpad = nullptr);
 void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, hipStream_t st);
 void launch_dot(const double* a, const double* b, double* part, int64_t n, const int* done, hipStream_t st);
 void launch_finish_dot(const double* part, double* out, hipStream_t st);
@@ -156,17 +161,18 @@ void launch_gather_sp(const int32_t* inv_ptr, const int32_t* inv, const double* 
                       int it, int fresh, int64_t n, hipStream_t st);
 void launch_gather_z(const int32_t* inv_ptr, const int32_t* inv, const double* ww, const uint8_t* kappa,
                      const double* r, double* z, double* part_rz, int64_t n, const int* done, double* pubc,
-                     int64_t n_pubc, unsigned* tickets, const double* dsc, double* zloc, hipStream_t st);
-void launch_scatter_local(const int32_t* inv_ptr, const int32_t* inv, const double* scale, const double* v,
-                          double* loc, int64_t n, hipStream_t st);
+                     int64_t n_pubc, unsigned* tickets, const double* dsc, const int32_t* padz, double* zpad,
+                     hipStream_t st);
+void launch_scatter_pad(const int32_t* inv_ptr, const int32_t* inv, const double* scale, const double* v,
+                        const int32_t* pad, double* out, int64_t n, hipStream_t st);
 enum { SYM_OP = 0, SYM_PC = 1 };
-void launch_sym_build(int mode, const MatDesc* mats, int nmats, int maxTG, const double* tiles, const double* xg,
+void launch_sym_build(int mode, const MatDesc* mats, int nmats, int maxTS, const double* tiles, const double* xg,
                       const double* cpp, double* out, hipStream_t st);
-void launch_sym_mv(int mode, const IfaceArgs& a, int grid, hipStream_t st);
+void launch_sym_mv(const IfaceArgs& a, hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_op_finish(const IfaceArgs& a, hipStream_t st);
 void launch_pc_finish(const IfaceArgs& a, hipStream_t st);
 constexpr int COARSE_SPLIT_COLS = 512;   // columns of A_c^{-1} per coarse GEMV block
-constexpr int IFACE_MAX_TG = 64;         // interface form: at most 64 trailing tile rows per subdomain
+constexpr int IFACE_MAX_TS = 255;        // interface form: tile rows of a symmetric interface matrix
 void launch_coarse_inverse(const double* xg, const double* dc, int nc, double* ainv, hipStream_t st);
 void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* cinv_ptr, const int32_t* cinv,
                         const double* gbuf, double* upart, const int* done, hipStream_t st);

@@ -14,6 +14,7 @@
 //    value doubles as its own ready flag (a signalling-NaN sentinel until it
 //    is written), read and written with device-scope atomics.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 
@@ -766,6 +767,14 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
       }
     }
 
+    // the inverse diagonal tile does not depend on other tasks: load it before
+    // waiting on any published value
+    V dv[NI];
+    {
+      const T* dt = dinv + (D.dinv_off + k) * int64_t(NB * NB) + (16 * w + lr) * NB + VEC * lc;
+      for (int i = 0; i < NI; ++i) dv[i] = *reinterpret_cast<const V*>(dt + i * RPI * NB);
+    }
+
     // ---------------- main loop over off-diagonal tiles ----------------
     T acc[FWD ? NI : VEC];
     for (int i = 0; i < (FWD ? NI : VEC); ++i) acc[i] = T(0);
@@ -831,9 +840,6 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
 
     // ---------------- diagonal block: multiply by the inverse tile ----------------
     {
-      const T* dt = dinv + (D.dinv_off + k) * int64_t(NB * NB) + (16 * w + lr) * NB + VEC * lc;
-      V dv[NI];
-      for (int i = 0; i < NI; ++i) dv[i] = *reinterpret_cast<const V*>(dt + i * RPI * NB);
       if (FWD) {
         for (int i = 0; i < NI; ++i) {
           T v = T(0);
@@ -898,24 +904,53 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
   }
 }
 
+// A launch whose dispatch records t0 / t1 (when given) at kernel start / end.
+template <typename K, typename... Args>
+static void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t st, hipEvent_t t0, hipEvent_t t1,
+                         Args... args) {
+  if (t0)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, t0, t1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
+
 template <typename T>
-static void launch_trsv_t(int mode, const TrsvArgs& a, int grid, hipStream_t st) {
+static void launch_trsv_t(int mode, const TrsvArgs& a, int grid, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
+  const dim3 g(grid), b(256);
   switch (mode) {
-    case TRSV_FWD_RR: hipLaunchKernelGGL((trsv_kernel<T, TRSV_FWD_RR>), dim3(grid), dim3(256), 0, st, a); break;
-    case TRSV_BWD_RR: hipLaunchKernelGGL((trsv_kernel<T, TRSV_BWD_RR>), dim3(grid), dim3(256), 0, st, a); break;
-    case TRSV_FWD_II: hipLaunchKernelGGL((trsv_kernel<T, TRSV_FWD_II>), dim3(grid), dim3(256), 0, st, a); break;
-    case TRSV_BWD_II: hipLaunchKernelGGL((trsv_kernel<T, TRSV_BWD_II>), dim3(grid), dim3(256), 0, st, a); break;
-    case TRSV_FWD_C: hipLaunchKernelGGL((trsv_kernel<T, TRSV_FWD_C>), dim3(grid), dim3(256), 0, st, a); break;
-    case TRSV_BWD_C: hipLaunchKernelGGL((trsv_kernel<T, TRSV_BWD_C>), dim3(grid), dim3(256), 0, st, a); break;
+    case TRSV_FWD_RR: launch_timed(trsv_kernel<T, TRSV_FWD_RR>, g, b, st, t0, t1, a); break;
+    case TRSV_BWD_RR: launch_timed(trsv_kernel<T, TRSV_BWD_RR>, g, b, st, t0, t1, a); break;
+    case TRSV_FWD_II: launch_timed(trsv_kernel<T, TRSV_FWD_II>, g, b, st, t0, t1, a); break;
+    case TRSV_BWD_II: launch_timed(trsv_kernel<T, TRSV_BWD_II>, g, b, st, t0, t1, a); break;
+    case TRSV_FWD_C: launch_timed(trsv_kernel<T, TRSV_FWD_C>, g, b, st, t0, t1, a); break;
+    case TRSV_BWD_C: launch_timed(trsv_kernel<T, TRSV_BWD_C>, g, b, st, t0, t1, a); break;
   }
 }
 
-void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st) {
+void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
   if (a.ntasks <= 0) return;
   if (fp32 && mode != TRSV_FWD_C && mode != TRSV_BWD_C)
-    launch_trsv_t<float>(mode, a, grid, st);
+    launch_trsv_t<float>(mode, a, grid, st, t0, t1);
   else
-    launch_trsv_t<double>(mode, a, grid, st);
+    launch_trsv_t<double>(mode, a, grid, st, t0, t1);
+}
+
+// The symmetric interface matrices of all subdomains form one stream of ntiles
+// tiles; workgroup g of a mat-vec launch with nwg workgroups takes the tiles
+// [g ntiles / nwg, (g+1) ntiles / nwg).  Each of its four waves stores the row
+// product of every row piece it covers (a piece starts at a row's first tile or
+// at a range start) in rowp[(start tile * 4 + wave) * 64 + row].  This sums the
+// pieces of the row whose len tiles start at tr0, in a fixed order.
+__device__ double sym_row_product(const double* rowp, int64_t tr0, int len, int64_t ntiles, int64_t nwg, int lane) {
+  double v = 0.0;
+  for (int w = 0; w < 4; ++w) v += rowp[(tr0 * 4 + w) * NB + lane];
+  for (int64_t g = (tr0 * nwg) / ntiles; g < nwg; ++g) {
+    const int64_t b = (g * ntiles) / nwg;
+    if (b <= tr0) continue;
+    if (b >= tr0 + len) break;
+    for (int w = 0; w < 4; ++w) v += rowp[(b * 4 + w) * NB + lane];
+  }
+  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -929,7 +964,7 @@ __global__ __launch_bounds__(64) void coarse_prep_kernel(const MatDesc* mats, co
                                                          const double* sainv, const double* sainve,
                                                          const int32_t* gmap, const double* wgt, const double* r,
                                                          double* gbuf, double* mu, const int* done,
-                                                         const double* symp) {
+                                                         const double* rowp, int64_t ntiles, int nwg) {
   if (done && *done) return;
   const int s = blockIdx.x;
   const MatDesc D = mats[s];
@@ -938,10 +973,11 @@ __global__ __launch_bounds__(64) void coarse_prep_kernel(const MatDesc* mats, co
   if (D.n_ci == 0) return;
   if (tid < D.n_ci) {
     double v = 0.0;
-    if (symp) {
-      // interface form: W^T t is the row product of the border row (W_G^T X) f
-      const int TG = D.T - D.n_I / NB;
-      v = symp[(D.sg_off + tri_tile(TG, TG)) * NB + tid];
+    if (rowp) {
+      // interface form: W^T t is the row product of constraint row n_G + tid,
+      // (W_G^T X) f
+      const int R = D.n_R - D.n_I + tid;
+      v = sym_row_product(rowp, D.sg_off + tri_tile(R / NB, 0), R / NB + 1, ntiles, nwg, R % NB);
     } else {
       const int64_t base = (D.vec_off / NB) * MAX_NCI;
       for (int k = 0; k < D.T; ++k) v += part[base + int64_t(k) * MAX_NCI + tid];
@@ -1003,9 +1039,10 @@ __global__ __launch_bounds__(64) void coarse_coef_kernel(const MatDesc* mats, co
 
 void launch_coarse_prep(const MatDesc* mats, int nmats, const double* part, const double* sainv,
                         const double* sainve, const int32_t* gmap, const double* wgt, const double* r,
-                        double* gbuf, double* mu, const int* done, const double* symp, hipStream_t st) {
+                        double* gbuf, double* mu, const int* done, const double* rowp, int64_t ntiles, int nwg,
+                        hipStream_t st) {
   hipLaunchKernelGGL(coarse_prep_kernel, dim3(nmats), dim3(64), 0, st, mats, part, sainv, sainve, gmap, wgt, r,
-                     gbuf, mu, done, symp);
+                     gbuf, mu, done, rowp, ntiles, nwg);
 }
 
 void launch_coarse_coef(const MatDesc* mats, int nmats, const int32_t* rc, const double* uc, const double* mu,
@@ -1049,16 +1086,21 @@ void launch_zero_interior(const uint8_t* kappa, double* x, int64_t n, hipStream_
   hipLaunchKernelGGL(zero_interior_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, kappa, x, n);
 }
 
-__global__ void scatter_local_kernel(const int32_t* inv_ptr, const int32_t* inv, const double* scale, const double* v,
-                                     double* loc, int64_t n) {
+// out[pad[l]] = scale[l] v[g] for the local copies l of every global dof g that
+// have a slot (pad[l] >= 0)
+__global__ void scatter_pad_kernel(const int32_t* inv_ptr, const int32_t* inv, const double* scale, const double* v,
+                                   const int32_t* pad, double* out, int64_t n) {
   for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x)
-    for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) loc[inv[j]] = scale[inv[j]] * v[g];
+    for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) {
+      const int32_t slot = pad[inv[j]];
+      if (slot >= 0) out[slot] = scale[inv[j]] * v[g];
+    }
 }
 
-void launch_scatter_local(const int32_t* inv_ptr, const int32_t* inv, const double* scale, const double* v,
-                          double* loc, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(scatter_local_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, inv_ptr, inv, scale, v,
-                     loc, n);
+void launch_scatter_pad(const int32_t* inv_ptr, const int32_t* inv, const double* scale, const double* v,
+                        const int32_t* pad, double* out, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(scatter_pad_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, inv_ptr, inv, scale, v, pad,
+                     out, n);
 }
 
 void launch_zero_interface(const uint8_t* kappa, double* x, int64_t n, hipStream_t st) {
@@ -1092,20 +1134,23 @@ __device__ __forceinline__ double reduce_partials(const double* part, int np, do
   return block_sum(v, sh);
 }
 
+// CSR row times x by a group of ROW_LANES consecutive lanes (a Q1 row has at most
+// 27 entries in 3D): many rows in flight per wave, short reductions
+constexpr int ROW_LANES = 4;
 __device__ __forceinline__ double row_dot(const int32_t* rowptr, const int32_t* col, const double* val,
                                           const double* x, int64_t row, int sl) {
   const int b = rowptr[row], e = rowptr[row + 1];
   double v = 0.0;
-  for (int j = b + sl; j < e; j += 32) v += val[j] * x[col[j]];
-  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 32);
+  for (int j = b + sl; j < e; j += ROW_LANES) v += val[j] * x[col[j]];
+  for (int off = ROW_LANES / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, ROW_LANES);
   return v;
 }
 
 __global__ __launch_bounds__(VBLK) void spmv_kernel(const int32_t* rowptr, const int32_t* col, const double* val,
                                                     const double* x, double* y, int64_t n) {
-  const int sl = threadIdx.x & 31;
-  const int64_t hw = (blockIdx.x * int64_t(VBLK) + threadIdx.x) >> 5;
-  const int64_t nhw = (int64_t(gridDim.x) * VBLK) >> 5;
+  const int sl = threadIdx.x % ROW_LANES;
+  const int64_t hw = (blockIdx.x * int64_t(VBLK) + threadIdx.x) / ROW_LANES;
+  const int64_t nhw = (int64_t(gridDim.x) * VBLK) / ROW_LANES;
   for (int64_t row = hw; row < n; row += nhw) {
     double v = row_dot(rowptr, col, val, x, row, sl);
     if (sl == 0) y[row] = v;
@@ -1125,9 +1170,9 @@ __global__ __launch_bounds__(VBLK) void residual_kernel(const int32_t* rowptr, c
                                                         double* r, double* part_rr, double* part_bb, int64_t n,
                                                         const uint8_t* iface_only) {
   __shared__ double sh[VBLK / 64];
-  const int sl = threadIdx.x & 31;
-  const int64_t hw = (blockIdx.x * int64_t(VBLK) + threadIdx.x) >> 5;
-  const int64_t nhw = (int64_t(gridDim.x) * VBLK) >> 5;
+  const int sl = threadIdx.x % ROW_LANES;
+  const int64_t hw = (blockIdx.x * int64_t(VBLK) + threadIdx.x) / ROW_LANES;
+  const int64_t nhw = (int64_t(gridDim.x) * VBLK) / ROW_LANES;
   double rr = 0.0, bb = 0.0;
   for (int64_t row = hw; row < n; row += nhw) {
     double v = row_dot(rowptr, col, val, x, row, sl);
@@ -1169,9 +1214,9 @@ __global__ __launch_bounds__(VBLK) void pcg_dir_kernel(const int32_t* rowptr, co
     sc->rz[it] = rz;
     if (!fresh) sc->beta[it - 1] = beta;
   }
-  const int sl = threadIdx.x & 31;
-  const int64_t hw = (blockIdx.x * int64_t(VBLK) + threadIdx.x) >> 5;
-  const int64_t nhw = (int64_t(gridDim.x) * VBLK) >> 5;
+  const int sl = threadIdx.x % ROW_LANES;
+  const int64_t hw = (blockIdx.x * int64_t(VBLK) + threadIdx.x) / ROW_LANES;
+  const int64_t nhw = (int64_t(gridDim.x) * VBLK) / ROW_LANES;
   double pq = 0.0;
   for (int64_t row = hw; row < n; row += nhw) {
     double az = row_dot(rowptr, col, val, z, row, sl);
@@ -1191,7 +1236,8 @@ __global__ __launch_bounds__(VBLK) void pcg_dir_kernel(const int32_t* rowptr, co
 __global__ __launch_bounds__(VBLK) void pcg_update_kernel(double* x, double* r, const double* p, const double* q,
                                                           const double* part_pq, double* part_rr, PcgScalars* sc,
                                                           int it, int64_t n, const int32_t* inv_ptr,
-                                                          const int32_t* inv, const double* wd, double* floc) {
+                                                          const int32_t* inv, const double* wd,
+                                                          const int32_t* padf, double* fpad) {
   __shared__ double sh[VBLK / 64];
   if (sc->done) return;
   const double pq = reduce_partials(part_pq, VGRID, sh);
@@ -1208,8 +1254,11 @@ __global__ __launch_bounds__(VBLK) void pcg_update_kernel(double* x, double* r, 
       double rv = r[i] - alpha * q[i];
       r[i] = rv;
       rr += rv * rv;
-      if (floc)   // interface form: the preconditioner reads W D r in local order
-        for (int j = inv_ptr[i]; j < inv_ptr[i + 1]; ++j) floc[inv[j]] = wd[inv[j]] * rv;
+      if (fpad)   // interface form: the preconditioner reads W D r in its padded rows
+        for (int j = inv_ptr[i]; j < inv_ptr[i + 1]; ++j) {
+          const int32_t slot = padf[inv[j]];
+          if (slot >= 0) fpad[slot] = wd[inv[j]] * rv;
+        }
     }
   }
   double t = block_sum(rr, sh);
@@ -1279,9 +1328,9 @@ void launch_pcg_init(const double* part_rr, const double* part_bb, PcgScalars* s
 }
 void launch_pcg_update(double* x, double* r, const double* p, const double* q, const double* part_pq,
                        double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st, const int32_t* inv_ptr,
-                       const int32_t* inv, const double* wd, double* floc) {
+                       const int32_t* inv, const double* wd, const int32_t* padf, double* fpad) {
   hipLaunchKernelGGL(pcg_update_kernel, dim3(VGRID), dim3(VBLK), 0, st, x, r, p, q, part_pq, part_rr, sc, it, n,
-                     inv_ptr, inv, wd, floc);
+                     inv_ptr, inv, wd, padf, fpad);
 }
 void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, hipStream_t st) {
   hipLaunchKernelGGL(pcg_check_kernel, dim3(1), dim3(VBLK), 0, st, part_rr, sc, it);
@@ -1420,40 +1469,42 @@ void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* c
                      cinv, gbuf, upart, done);
 }
 
-// Symmetric interface matrices, lower tile triangle over TG + 1 tile rows
-// (ii < TG: trailing tile row j0 + ii, j0 = n_I/64; ii = TG: the border row, whose
-// rows are constraint indices), M = K K^T with
-//   SYM_OP: K(ii, kk) = L(j0+ii, j0+kk) for kk <= ii, K(TG, kk) = the corner rows of
-//           the border tile (T, j0+kk), plus A_PiPi - W_Pi^T W_Pi on the corner block
-//           of M(TG, TG).  M is the equilibrated local Schur complement on [G | Pi]:
-//           M_GG = L_GG L_GG^T, M_PiG = W_Pi,G^T L_GG^T, M_PiPi = cpp + W_Pi,G^T W_Pi,G.
-//   SYM_PC: K(ii, kk) = X(kk, ii)^T for kk >= ii, K(TG, kk) = the border tile
-//           (T, j0+kk) (all constraint rows), so M_GG = X^T X = (L_GG L_GG^T)^{-1}
-//           and the border row holds W_G^T X = (L_GG^{-T} W_G)^T; M(TG, TG) = 0.
-// Rows and columns of the trailing block outside the interface rows [n_I, n_R)
-// are zero in K, hence in M.  One workgroup per output tile, MFMA products.
+// Symmetric interface matrices of a subdomain, lower tile triangle over
+// sym_tile_rows tile rows.  Rows (and columns) 0..n_G-1 are the interface rows
+// (local dofs n_I + r), rows n_G + c the constraints c < n_ci.  M = K K^T with
+// K of n_G columns (the interface rows again):
+//   SYM_OP: K(r, k) = L(n_I+r, n_I+k) (k <= r), K(n_G+c, k) = W^T(c, n_I+k) for the
+//           corners c >= n_A (zero for the averages); A_PiPi - W_Pi^T W_Pi is added
+//           to the corner block.  M is the equilibrated local Schur complement on
+//           [G | Pi]: L_GG L_GG^T, W_Pi,G^T L_GG^T, cpp + W_Pi,G^T W_Pi,G.
+//   SYM_PC: K(r, k) = X(n_I+k, n_I+r) (k >= r), K(n_G+c, k) = W^T(c, n_I+k) for all
+//           constraints, so M_GG = X_GG^T X_GG = (L_GG L_GG^T)^{-1} and the
+//           constraint rows hold W_G^T X_GG = (L_GG^{-T} W_G)^T.
+// (X, the inverse of the tile-aligned trailing block of L, acts on the interface
+// rows through its block X_GG = L_GG^{-1}.)  One workgroup per output tile, MFMA.
 template <int MODE>
 __device__ void load_k_tile(double* dst, const MatDesc& D, const double* tiles, const double* xg, int ii, int kk) {
-  const int j0 = D.n_I / NB, TG = D.T - j0;
-  const bool border = ii == TG;
-  if (border && D.n_ci == 0) {   // no border row is stored
-    for (int e = threadIdx.x; e < NB * NB; e += 256) dst[(e / NB) * LDT + (e % NB)] = 0.0;
-    return;
-  }
-  const bool trans = !border && MODE == SYM_PC;
-  const double* src;
-  if (border) src = tiles + (D.tile_off + tri_tile(D.T, j0 + kk)) * int64_t(NB * NB);
-  else if (MODE == SYM_OP) src = tiles + (D.tile_off + tri_tile(j0 + ii, j0 + kk)) * int64_t(NB * NB);
-  else src = xg + (D.xg_off + tri_tile(kk, ii)) * int64_t(NB * NB);
-  const int rb = (j0 + ii) * NB, cb = (j0 + kk) * NB;
-  const int blo = MODE == SYM_OP ? D.n_A : 0;
+  const int nG = D.n_R - D.n_I, j0 = D.n_I / NB;
   for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    const int i1 = e / NB, i2 = e % NB;
-    const int r = trans ? i2 : i1, c = trans ? i1 : i2;   // row, column of K
-    bool keep = cb + c >= D.n_I && cb + c < D.n_R;
-    if (border) keep = keep && r >= blo && r < D.n_ci;
-    else keep = keep && rb + r >= D.n_I && rb + r < D.n_R;
-    dst[r * LDT + c] = keep ? src[e] : 0.0;
+    const int rl = e / NB, cl = e % NB;
+    const int r = ii * NB + rl, k = kk * NB + cl;
+    double v = 0.0;
+    if (k < nG) {
+      const int b = D.n_I + k;
+      if (r < nG) {
+        const int a = D.n_I + r;
+        if (MODE == SYM_OP) {
+          if (k <= r) v = tiles[(D.tile_off + tri_tile(a / NB, b / NB)) * (NB * NB) + (a % NB) * NB + b % NB];
+        } else {
+          if (k >= r) v = xg[(D.xg_off + tri_tile(b / NB - j0, a / NB - j0)) * (NB * NB) + (b % NB) * NB + a % NB];
+        }
+      } else {
+        const int c = r - nG;
+        if (c < D.n_ci && (MODE == SYM_PC || c >= D.n_A))
+          v = tiles[(D.tile_off + tri_tile(D.T, b / NB)) * (NB * NB) + c * NB + b % NB];
+      }
+    }
+    dst[rl * LDT + cl] = v;
   }
 }
 
@@ -1462,21 +1513,22 @@ __global__ __launch_bounds__(256) void sym_build_kernel(const MatDesc* mats, con
                                                          const double* cpp, double* out) {
   const int s = blockIdx.y;
   const MatDesc D = mats[s];
-  const int TG = D.T - D.n_I / NB;
+  const int TS = sym_tile_rows(D), nG = D.n_R - D.n_I;
+  const int KG = (nG + NB - 1) / NB;
   const int64_t pidx = blockIdx.x;
-  if (pidx >= tri_tile(TG + 1, 0)) return;
+  if (pidx >= tri_tile(TS, 0)) return;
   int ii = int((sqrt(8.0 * double(pidx) + 1.0) - 1.0) * 0.5);
   while (tri_tile(ii, 0) > pidx) --ii;
   while (tri_tile(ii + 1, 0) <= pidx) ++ii;
   const int jj = int(pidx - tri_tile(ii, 0));
-  // K(ii, kk) and K(jj, kk) (jj <= ii) are both nonzero only for kk in [k0, k1)
-  int k0, k1;
+  // K(ii, kk) and K(jj, kk) (jj <= ii) are both nonzero only for kk in [k0, k1);
+  // a tile row without constraint rows is triangular in K
+  const bool pure_i = (ii + 1) * NB <= nG, pure_j = (jj + 1) * NB <= nG;
+  int k0 = 0, k1 = KG;
   if (MODE == SYM_OP) {
-    k0 = 0;
-    k1 = min(jj + 1, TG);
+    if (pure_j) k1 = min(jj + 1, KG);
   } else {
-    k0 = ii < TG ? ii : jj;
-    k1 = (ii == TG && jj == TG) ? k0 : TG;
+    k0 = max(pure_i ? ii : 0, pure_j ? jj : 0);
   }
   __shared__ double sa[NB * LDT];
   __shared__ double sb[NB * LDT];
@@ -1491,8 +1543,8 @@ __global__ __launch_bounds__(256) void sym_build_kernel(const MatDesc* mats, con
     gemm_nt_tile<double>(sa, jj != ii ? sb : sa, acc);
   }
   double* o = out + (D.sg_off + pidx) * int64_t(NB * NB);
-  const bool corner_blk = MODE == SYM_OP && ii == TG && jj == TG;
   const double* m = cpp + int64_t(s) * MAX_NCI * MAX_NCI;
+  const int p0 = nG + D.n_A, p1 = nG + D.n_ci;   // corner rows
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
   for (int p = 0; p < 2; ++p)
@@ -1500,15 +1552,16 @@ __global__ __launch_bounds__(256) void sym_build_kernel(const MatDesc* mats, con
       for (int it = 0; it < 4; ++it) {
         const int r = r0 + 16 * p + Acc4<double>::row(lane, it), c = c0 + 16 * q + (lane & 15);
         double v = acc[p][q][it];
-        if (corner_blk && r >= D.n_A && r < D.n_ci && c >= D.n_A && c < D.n_ci)
-          v += m[(r - D.n_A) * MAX_NCI + (c - D.n_A)];
+        const int R = ii * NB + r, C = jj * NB + c;
+        if (MODE == SYM_OP && R >= p0 && R < p1 && C >= p0 && C < p1) v += m[(R - p0) * MAX_NCI + (C - p0)];
         o[r * NB + c] = v;
       }
 }
 
-void launch_sym_build(int mode, const MatDesc* mats, int nmats, int maxTG, const double* tiles, const double* xg,
+void launch_sym_build(int mode, const MatDesc* mats, int nmats, int maxTS, const double* tiles, const double* xg,
                       const double* cpp, double* out, hipStream_t st) {
-  const dim3 grid(unsigned(tri_tile(maxTG + 1, 0)), nmats);
+  if (maxTS <= 0 || nmats <= 0) return;   // no interface (a single subdomain)
+  const dim3 grid(unsigned(tri_tile(maxTS, 0)), nmats);
   if (mode == SYM_OP)
     hipLaunchKernelGGL(sym_build_kernel<SYM_OP>, grid, dim3(256), 0, st, mats, tiles, xg, cpp, out);
   else
@@ -1535,184 +1588,211 @@ __device__ __forceinline__ double sum_rg(double v) {
   return __hiloint2double(ph[0], pl[0]) + __hiloint2double(ph[1], pl[1]);
 }
 
-// y = M v for a symmetric interface matrix; task = (matrix, row ii).  The task
-// streams the contiguous tiles (ii, 0..ii) once and uses each twice: the row
-// product sum_jj M(ii, jj) v_jj, stored in the slot of the diagonal tile, and
-// for jj < ii the column product M(ii, jj)^T v_ii, stored in the slot of tile
-// (ii, jj); then y_k = slot(k, k) + sum_{i > k} slot(i, k).  Inputs (staged in
-// LDS): the local-order vector on the interface rows and, for SYM_OP, the corner
-// values on the border rows n_A..n_ci-1 (zero elsewhere).
+// y = M v for the symmetric interface matrices, all subdomains at once.  The
+// launch splits the tile stream into equal contiguous ranges (no tickets, no
+// barriers, nothing staged): every tile (ii, jj) is read once and used twice,
+// for the row product sum_jj M(ii, jj) v_jj (kept in registers along a row
+// piece and stored per piece and wave, see sym_row_product) and, for jj < ii,
+// the column product M(ii, jj)^T v_ii (stored at the tile's slot in part).
+// Output row k of a subdomain is then its row product plus the column products
+// of the tiles (i, k), i > k.  Inputs come from padded per-row vectors (zero
+// where a row has no interface dof).
 // Wave w owns columns 16w..16w+15 of every tile; lane = 8 * rg + cp holds rows
 // rg + 8t (t < 8) of columns 16w + 2cp, +1, so a column product reduces over the
 // eight rg lanes of one wave and a row product over the eight cp lanes.
 constexpr int SYM_UNROLL = 2;
-template <int MODE>
+// tile descriptors are uniform per wave and read-only: scalar loads (constant
+// address space), which complete independently of the vector memory counter
+typedef __attribute__((address_space(4))) const int32_t cint32_t;
 __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   using V = d2v;
-  extern __shared__ double s_x[];   // inputs of tile rows 0..ii
-  __shared__ double s_red[4][NB];
-  __shared__ int s_task;
   if (A.sc->done) return;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rg = lane >> 3, cp = lane & 7;
   const int col = 16 * w + 2 * cp;
-  for (;;) {
-    if (tid == 0) s_task = atomicAdd(A.ticket, 1u);
-    __syncthreads();
-    const int task = s_task;
-    if (task >= A.ntasks) return;
-    const int s = A.tasks[2 * task], ii = A.tasks[2 * task + 1];
-    const MatDesc D = A.mats[s];
-    const int j0 = D.n_I / NB, TG = D.T - j0;
-    for (int e = tid; e < (ii + 1) * NB; e += 256) {
-      const int jj = e / NB, r = e % NB;
-      double v = 0.0;
-      if (jj < TG) {
-        const int a = (j0 + jj) * NB + r;
-        if (a >= D.n_I && a < D.n_R) v = A.loc_in[D.loc_off + a];
-      } else if (MODE == SYM_OP && r >= D.n_A && r < D.n_ci) {
-        v = A.loc_in[D.loc_off + D.n_R + (r - D.n_A)];
-      }
-      s_x[e] = v;
-    }
-    __syncthreads();
-    const double* base = A.m + (D.sg_off + tri_tile(ii, 0)) * int64_t(NB * NB) + rg * NB + col;
-    double* pcol = A.part + (D.sg_off + tri_tile(ii, 0)) * NB + col;
-    double xi[8], racc[8];
-    for (int t = 0; t < 8; ++t) {
-      xi[t] = s_x[ii * NB + rg + 8 * t];
-      racc[t] = 0.0;
-    }
-    // Tiles in the order ii (the diagonal: row product only), 0, 1, .., ii-1,
-    // SYM_UNROLL at a time: all their loads are issued before the first is
-    // used, and no register buffer lives across iterations (many waves per SIMD
-    // keep HBM busy while one multiplies).  Loads past the end of the row
-    // re-read the row's last tile, which is still cached.  Only the eight lanes
-    // of the first row group store a column product (all lanes hold the sums).
-    V b[SYM_UNROLL][8];
-    for (int k = 0; k <= ii; k += SYM_UNROLL) {
-      int jt[SYM_UNROLL];
-      for (int u = 0; u < SYM_UNROLL; ++u) {
-        const int kk = min(k + u, ii);
-        jt[u] = kk == 0 ? ii : kk - 1;
-        const double* p = base + int64_t(jt[u]) * NB * NB;
-        for (int t = 0; t < 8; ++t) b[u][t] = *reinterpret_cast<const V*>(p + t * 8 * NB);
-      }
-      for (int u = 0; u < SYM_UNROLL; ++u) {
-        if (k + u > ii) break;
-        const int jj = jt[u];
-        const double x0 = s_x[jj * NB + col], x1 = s_x[jj * NB + col + 1];
-        for (int t = 0; t < 8; ++t) racc[t] += b[u][t][0] * x0 + b[u][t][1] * x1;
-        if (k + u > 0) {
-          double c0 = 0.0, c1 = 0.0;
-          for (int t = 0; t < 8; ++t) {
-            c0 += b[u][t][0] * xi[t];
-            c1 += b[u][t][1] * xi[t];
-          }
-          V o;
-          o[0] = sum_rg(c0);
-          o[1] = sum_rg(c1);
-          if (rg == 0) *reinterpret_cast<V*>(pcol + jj * NB) = o;   // one 128 B segment per wave
-        }
-      }
-    }
+  const int64_t N = A.ntiles, G = gridDim.x;
+  const int64_t t0 = blockIdx.x * N / G, t1 = (blockIdx.x + 1) * N / G;
+  if (t0 >= t1) return;
+  const double* xv = A.xpad;
+  const cint32_t* tinfo = (const cint32_t*)(A.tinfo);
+  int cur_row = tinfo[t0] >> 8;
+  int64_t pstart = t0;
+  double xi[8], racc[8];
+  for (int t = 0; t < 8; ++t) {
+    xi[t] = xv[int64_t(cur_row) * NB + rg + 8 * t];
+    racc[t] = 0.0;
+  }
+  auto flush = [&]() {
     for (int t = 0; t < 8; ++t) {
       double v = racc[t];
-      for (int off = 1; off < 8; off <<= 1) v += __shfl_xor(v, off, 64);
-      if (cp == 0) s_red[w][rg + 8 * t] = v;
+      v += __shfl_xor(v, 1, 8);
+      v += __shfl_xor(v, 2, 8);
+      v += __shfl_xor(v, 4, 8);
+      if (cp == 0) A.rowp[(pstart * 4 + w) * NB + rg + 8 * t] = v;
+      racc[t] = 0.0;
     }
-    __syncthreads();
-    if (tid < NB)
-      A.part[(D.sg_off + tri_tile(ii, ii)) * NB + tid] = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
-    __syncthreads();
+  };
+  // the tile descriptors run one batch ahead, so that every load of a batch
+  // (tiles, inputs, the inputs of a row that starts in it) issues at once
+  int inf_next[SYM_UNROLL];
+  for (int u = 0; u < SYM_UNROLL; ++u) inf_next[u] = tinfo[min(t0 + u, t1 - 1)];
+  for (int64_t t = t0; t < t1; t += SYM_UNROLL) {
+    V b[SYM_UNROLL][8];
+    V xx[SYM_UNROLL];
+    double xn[SYM_UNROLL][8];
+    int inf[SYM_UNROLL];
+    for (int u = 0; u < SYM_UNROLL; ++u) inf[u] = inf_next[u];
+    for (int u = 0; u < SYM_UNROLL; ++u) {
+      const int64_t tt = min(t + u, t1 - 1);   // past the range end: the last tile again
+      const double* p = A.m + tt * (NB * NB) + rg * NB + col;
+      for (int k = 0; k < 8; ++k) b[u][k] = *reinterpret_cast<const V*>(p + k * 8 * NB);
+    }
+    for (int u = 0; u < SYM_UNROLL; ++u) {
+      const int row = inf[u] >> 8, d = inf[u] & 255;
+      xx[u] = *reinterpret_cast<const V*>(xv + int64_t(row - d) * NB + col);
+      const int prev = u == 0 ? cur_row : (inf[u - 1] >> 8);
+      if (row != prev)
+        for (int k = 0; k < 8; ++k) xn[u][k] = xv[int64_t(row) * NB + rg + 8 * k];
+    }
+    for (int u = 0; u < SYM_UNROLL; ++u) inf_next[u] = tinfo[min(t + SYM_UNROLL + u, t1 - 1)];
+    for (int u = 0; u < SYM_UNROLL; ++u) {
+      if (t + u >= t1) break;
+      const int row = inf[u] >> 8, d = inf[u] & 255;
+      if (row != cur_row) {
+        flush();
+        pstart = t + u;
+        cur_row = row;
+        for (int k = 0; k < 8; ++k) xi[k] = xn[u][k];
+      }
+      for (int k = 0; k < 8; ++k) racc[k] += b[u][k][0] * xx[u][0] + b[u][k][1] * xx[u][1];
+      if (d > 0) {
+        double c0 = 0.0, c1 = 0.0;
+        for (int k = 0; k < 8; ++k) {
+          c0 += b[u][k][0] * xi[k];
+          c1 += b[u][k][1] * xi[k];
+        }
+        V o;
+        o[0] = sum_rg(c0);
+        o[1] = sum_rg(c1);
+        if (rg == 0) *reinterpret_cast<V*>(A.part + (t + u) * NB + col) = o;
+      }
+    }
   }
+  flush();
 }
 
-// (S z) per local dof from the partial products of the operator matrix:
-// sploc = D^{-1} y on the interface rows, y itself on the corners (border row).
-__global__ __launch_bounds__(64) void op_finish_kernel(IfaceArgs A) {
+// Output row ii of a subdomain's symmetric matrix: the row product (over its
+// pieces) plus the column products of tiles (i2, ii), i2 = ii+1 .. TS-1; the
+// four waves take every fourth term, the result is in s_red[0..3] (summed by
+// the caller in that fixed order).
+__device__ __forceinline__ void sum_row(const IfaceArgs& A, const MatDesc& D, int ii, int TS, double (*s_red)[NB]) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double y = 0.0;
+  if (w == 0) y = sym_row_product(A.rowp, D.sg_off + tri_tile(ii, 0), ii + 1, A.ntiles, A.nwg, lane);
+  const double* pp = A.part + D.sg_off * NB + lane;
+  for (int i2 = ii + 1 + w; i2 < TS; i2 += 4) y += pp[tri_tile(i2, ii) * NB];
+  s_red[w][lane] = y;
+}
+
+// (S z) per local dof: sploc = D^{-1} y on the interface rows, y itself on the
+// corners.
+__global__ __launch_bounds__(256) void op_finish_kernel(IfaceArgs A) {
+  __shared__ double s_red[4][NB];
   if (A.sc->done) return;
   const int s = A.tasks[2 * blockIdx.x], ii = A.tasks[2 * blockIdx.x + 1];
   const MatDesc D = A.mats[s];
-  const int j0 = D.n_I / NB, TG = D.T - j0, tid = threadIdx.x;
-  const double* pp = A.part + D.sg_off * NB + tid;
-  double y = pp[tri_tile(ii, ii) * NB];
-  for (int i2 = ii + 1; i2 <= TG; ++i2) y += pp[tri_tile(i2, ii) * NB];
-  if (ii < TG) {
-    const int a = (j0 + ii) * NB + tid;
-    if (a >= D.n_I && a < D.n_R) A.sploc[D.loc_off + a] = y / A.dsc[D.loc_off + a];
-  } else if (tid >= D.n_A && tid < D.n_ci) {
-    A.sploc[D.loc_off + D.n_R + (tid - D.n_A)] = y;
+  const int TS = sym_tile_rows(D), nG = D.n_R - D.n_I, tid = threadIdx.x;
+  sum_row(A, D, ii, TS, s_red);
+  __syncthreads();
+  if (tid >= NB) return;
+  const double y = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
+  const int r = ii * NB + tid;
+  if (r < nG) {
+    A.sploc[D.loc_off + D.n_I + r] = y / A.dsc[D.loc_off + D.n_I + r];
+  } else if (r - nG >= D.n_A && r - nG < D.n_ci) {
+    A.sploc[D.loc_off + D.n_R + (r - nG - D.n_A)] = y;
   }
 }
 
-// Preconditioner output on the interface rows of row ii < TG:
-//   x = (X^T X f)_ii + (X^T W)_ii coef,  ww = W D x,
+// Preconditioner output on the interface rows of tile row ii:
+//   x = (X^T X f)_r + sum_c (W^T X)(c, r) coef_c,  ww = W D x,
 // with the coefficients of the coarse correction computed in place:
 //   u = R_ci u_c, coef_A = -mu + S_A^{-1} u_A + S_A^{-1} E u_Pi, coef_Pi = -u_Pi;
-// the task ii = 0 also writes the corner outputs W_Pi u_Pi.
-__global__ __launch_bounds__(64) void pc_finish_kernel(IfaceArgs A) {
+// the task ii = 0 also writes the corner outputs W_Pi u_Pi.  (Products with the
+// constraint rows vanish: their input is zero.)
+__global__ __launch_bounds__(256) void pc_finish_kernel(IfaceArgs A) {
   __shared__ double u[MAX_NCI];
   __shared__ double cf[MAX_NCI];
+  __shared__ double s_red[4][NB];
   if (A.sc->done) return;
   const int s = A.tasks[2 * blockIdx.x], ii = A.tasks[2 * blockIdx.x + 1];
   const MatDesc D = A.mats[s];
-  const int j0 = D.n_I / NB, TG = D.T - j0, tid = threadIdx.x;
-  if (ii >= TG) return;
-  const int nA = D.n_A, nP = D.n_P;
-  if (tid < D.n_ci) {
+  const int TS = sym_tile_rows(D), nG = D.n_R - D.n_I, tid = threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63;
+  const bool rows = ii * NB < nG;   // uniform: this tile row holds interface rows
+  if (!rows && ii != 0) return;
+  const int nA = D.n_A, nP = D.n_P, nci = D.n_ci;
+  // partial sums of the output row first (independent of the coarse solution)
+  if (rows) sum_row(A, D, ii, TS, s_red);
+  if (tid < nci) {
     const int pc = A.rc[D.coarse_off + tid];
     double v = 0.0;
     for (int q = 0; q < A.nsplit; ++q) v += A.uc[int64_t(q) * A.nc + pc];
     u[tid] = v;
   }
   __syncthreads();
-  if (tid < D.n_ci) {
-    const double* so = A.sainv + int64_t(s) * MAX_NCI * MAX_NCI;
-    const double* se = A.sainve + int64_t(s) * MAX_NCI * MAX_NCI;
-    double v;
-    if (tid < nA) {
-      v = -A.mu[int64_t(s) * MAX_NCI + tid];
-      for (int t = 0; t < nA; ++t) v += so[tid * MAX_NCI + t] * u[t];
-      for (int q = 0; q < nP; ++q) v += se[tid * MAX_NCI + q] * u[nA + q];
-    } else {
-      v = -u[tid];
-      if (ii == 0) {
-        const int64_t l = D.loc_off + D.n_R + (tid - nA);
-        A.ww[l] = A.wgt[l] * u[tid];
-      }
+  {
+    // coefficient c = tid / 4, lanes tid % 4 split its terms
+    const int c = tid >> 2, l4 = tid & 3;
+    double v = 0.0;
+    if (c < nA) {
+      const double* so = A.sainv + int64_t(s) * MAX_NCI * MAX_NCI + c * MAX_NCI;
+      const double* se = A.sainve + int64_t(s) * MAX_NCI * MAX_NCI + c * MAX_NCI;
+      for (int t = l4; t < nA; t += 4) v += so[t] * u[t];
+      for (int q = l4; q < nP; q += 4) v += se[q] * u[nA + q];
     }
-    cf[tid] = v;
+    v += __shfl_xor(v, 1, 4);
+    v += __shfl_xor(v, 2, 4);
+    if (l4 == 0 && c < nci) cf[c] = c < nA ? v - A.mu[int64_t(s) * MAX_NCI + c] : -u[c];
+    if (ii == 0 && tid >= nA && tid < nci) {
+      const int64_t l = D.loc_off + D.n_R + (tid - nA);
+      A.ww[l] = A.wgt[l] * u[tid];
+    }
+  }
+  if (!rows) return;
+  __syncthreads();
+  // constraint rows: wave w takes c = w, w+4, ...; M(nG + c, r) lies in tile
+  // ((nG + c) / 64, ii)
+  {
+    double v = 0.0;
+    for (int c = w; c < nci; c += 4) {
+      const int R = nG + c;
+      v += A.m[(D.sg_off + tri_tile(R / NB, ii)) * int64_t(NB * NB) + (R % NB) * NB + lane] * cf[c];
+    }
+    s_red[w][lane] += v;
   }
   __syncthreads();
-  const int a = (j0 + ii) * NB + tid;
-  if (a >= D.n_I && a < D.n_R) {
-    const double* pp = A.part + D.sg_off * NB + tid;
-    double v = pp[tri_tile(ii, ii) * NB];
-    for (int i2 = ii + 1; i2 < TG; ++i2) v += pp[tri_tile(i2, ii) * NB];
-    const double* yt = A.m + (D.sg_off + tri_tile(TG, ii)) * int64_t(NB * NB);
-    for (int c = 0; c < D.n_ci; ++c) v += yt[c * NB + tid] * cf[c];
-    A.ww[D.loc_off + a] = A.wd[D.loc_off + a] * v;
+  if (tid >= NB) return;
+  const int r = ii * NB + tid;
+  if (r < nG) {
+    const double x = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
+    A.ww[D.loc_off + D.n_I + r] = A.wd[D.loc_off + D.n_I + r] * x;
   }
 }
 
-void launch_sym_mv(int mode, const IfaceArgs& a, int grid, hipStream_t st) {
-  if (a.ntasks <= 0) return;
-  const size_t lds = size_t(a.maxtg + 1) * NB * sizeof(double);
-  if (mode == SYM_OP)
-    hipLaunchKernelGGL(sym_mv_kernel<SYM_OP>, dim3(grid), dim3(256), lds, st, a);
-  else
-    hipLaunchKernelGGL(sym_mv_kernel<SYM_PC>, dim3(grid), dim3(256), lds, st, a);
+void launch_sym_mv(const IfaceArgs& a, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
+  if (a.ntiles <= 0 || a.nwg <= 0) return;
+  launch_timed(sym_mv_kernel, dim3(a.nwg), dim3(256), st, t0, t1, a);
 }
 
 void launch_op_finish(const IfaceArgs& a, hipStream_t st) {
   if (a.ntasks <= 0) return;
-  hipLaunchKernelGGL(op_finish_kernel, dim3(a.ntasks), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(op_finish_kernel, dim3(a.ntasks), dim3(256), 0, st, a);
 }
 
 void launch_pc_finish(const IfaceArgs& a, hipStream_t st) {
   if (a.ntasks <= 0) return;
-  hipLaunchKernelGGL(pc_finish_kernel, dim3(a.ntasks), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(pc_finish_kernel, dim3(a.ntasks), dim3(256), 0, st, a);
 }
 
 // q = S p = sum_i R_i^T S_i z_i + beta q on interface dofs; p = z + beta p; partial sums of p.q;
@@ -1751,7 +1831,7 @@ __global__ __launch_bounds__(VBLK) void gather_z_kernel(const int32_t* inv_ptr, 
                                                         const uint8_t* kappa, const double* r, double* z,
                                                         double* part_rz, int64_t n, const int* done,
                                                         double* pubc, int64_t n_pubc, unsigned* tickets,
-                                                        const double* dsc, double* zloc) {
+                                                        const double* dsc, const int32_t* padz, double* zpad) {
   __shared__ double sh[VBLK / 64];
   if (done && *done) return;
   {
@@ -1768,7 +1848,7 @@ __global__ __launch_bounds__(VBLK) void gather_z_kernel(const int32_t* inv_ptr, 
     for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) v += ww[inv[j]];
     z[g] = v;
     rz += r[g] * v;
-    for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) zloc[inv[j]] = v / dsc[inv[j]];
+    for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) zpad[padz[inv[j]]] = v / dsc[inv[j]];
   }
   const double t = block_sum(rz, sh);
   if (threadIdx.x == 0) part_rz[blockIdx.x] = t;
@@ -1812,9 +1892,10 @@ void launch_gather_sp(const int32_t* inv_ptr, const int32_t* inv, const double* 
 
 void launch_gather_z(const int32_t* inv_ptr, const int32_t* inv, const double* ww, const uint8_t* kappa,
                      const double* r, double* z, double* part_rz, int64_t n, const int* done, double* pubc,
-                     int64_t n_pubc, unsigned* tickets, const double* dsc, double* zloc, hipStream_t st) {
+                     int64_t n_pubc, unsigned* tickets, const double* dsc, const int32_t* padz, double* zpad,
+                     hipStream_t st) {
   hipLaunchKernelGGL(gather_z_kernel, dim3(VEC_GRID), dim3(VBLK), 0, st, inv_ptr, inv, ww, kappa, r, z, part_rz, n,
-                     done, pubc, n_pubc, tickets, dsc, zloc);
+                     done, pubc, n_pubc, tickets, dsc, padz, zpad);
 }
 
 // ---------------------------------------------------------------------------

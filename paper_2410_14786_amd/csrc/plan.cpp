@@ -319,17 +319,38 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
     P.maxTI = std::max(P.maxTI, int(D.TI));
   }
   {
-    int64_t xg = 0, sg = 0;
+    int64_t xg = 0, sg = 0, rows = 0;
     for (auto& D : P.subs) {
       const int TG = D.T - D.n_I / NB;
       D.xg_off = xg;
       D.sg_off = sg;
+      const int TS = sym_tile_rows(D);
+      D.sym_row = int32_t(rows);
+      for (int ii = 0; ii < TS; ++ii)
+        for (int jj = 0; jj <= ii; ++jj) P.tinfo.push_back(int32_t(((rows + ii) << 8) | (ii - jj)));
       xg += tri_tile(TG, 0);
-      sg += tri_tile(TG + 1, 0);
+      sg += tri_tile(TS, 0);
+      rows += TS;
       P.maxTG = std::max(P.maxTG, TG);
+      P.maxTS = std::max(P.maxTS, TS);
     }
     P.n_xg = xg;
     P.n_sg = sg;
+    P.n_symrows = rows;
+    if (rows >= (int64_t(1) << 23)) { err = "too many interface tile rows"; return BDDC_EINVAL; }
+    // padded input slots of the local dofs
+    P.padz.assign(loc_off, -1);
+    P.padf.assign(loc_off, -1);
+    for (auto& D : P.subs) {
+      const int nG = D.n_R - D.n_I;
+      for (int r = 0; r < nG; ++r) {
+        const int32_t slot = int32_t(int64_t(D.sym_row) * NB + r);
+        P.padz[D.loc_off + D.n_I + r] = slot;
+        P.padf[D.loc_off + D.n_I + r] = slot;
+      }
+      for (int c = 0; c < D.n_P; ++c)
+        P.padz[D.loc_off + D.n_R + c] = int32_t(int64_t(D.sym_row) * NB + nG + D.n_A + c);
+    }
   }
   P.n_tiles = tile_off;
   P.n_dinv = dinv_off;
@@ -408,23 +429,13 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
   make_tasks(P.bwd_ii, true, true);
   // interface form
   {
-    // rows of the symmetric interface matrices are independent tasks: take the
-    // longest first (row ii streams ii + 1 tiles)
-    struct Job { int len, s, ii; };
-    std::vector<Job> jobs;
     for (int s = 0; s < P.nsubs; ++s) {
-      const MatDesc& D = P.subs[s];
-      const int TG = D.T - D.n_I / NB;
-      for (int ii = 0; ii <= TG; ++ii) {
-        jobs.push_back({ii + 1, s, ii});
+      const int TS = sym_tile_rows(P.subs[s]);
+      for (int ii = 0; ii < TS; ++ii) {
         P.symfin.push_back(s);
         P.symfin.push_back(ii);
       }
     }
-    std::sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& b) {
-      return a.len != b.len ? a.len > b.len : (a.s != b.s ? a.s < b.s : a.ii < b.ii);
-    });
-    for (auto& j : jobs) { P.sym.push_back(j.s); P.sym.push_back(j.ii); }
   }
   return BDDC_OK;
 }

@@ -288,8 +288,14 @@ def test_kernel_timing_with_graph_solver():
 
 @pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
 def test_autotune_keeps_results_bitwise(full_space, tmp_path):
-    """The launch shape changes only how tasks are spread over workgroups: every
-    task computes the same sums, so the solution is bitwise the same."""
+    """The launch shape changes only how tasks are spread over workgroups.  In the
+    full-space iteration every task computes the same sums, so the solution is
+    bitwise the same; the interface mat-vec splits its tile stream at workgroup
+    boundaries, so its row sums may be grouped differently (rounding only)."""
+    def same(a, b):
+        if full_space:
+            return np.array_equal(a, b)
+        return np.allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(b).max())
     w, P = oracle_for("3d_12x10x14_uneven")
     S = bd().solver_for(w, full_space=full_space, use_graph=True)
     x0, i0 = S.solve(dev(w.b), 1e-10)
@@ -297,13 +303,13 @@ def test_autotune_keeps_results_bitwise(full_space, tmp_path):
     rec = S.autotune(candidates=(1, 3, 8), iters=4, cache=str(tmp_path / "tune.json"))
     assert rec["wg_per_cu"] in (1, 3, 8) and len(rec["ms"]) == 3
     x1, i1 = S.solve(dev(w.b), 1e-10)
-    assert np.array_equal(host(x1), x0) and i1["iters"] == i0["iters"]
+    assert same(host(x1), x0) and i1["iters"] == i0["iters"]
     S2 = bd().solver_for(w, full_space=full_space, use_graph=True)
     rec2 = S2.autotune(candidates=(1, 3, 8), iters=4, cache=str(tmp_path / "tune.json"))
     assert rec2["wg_per_cu"] == rec["wg_per_cu"]        # served from the cache
     for wg in (1, 2, 16):
         S2.set_tuning(wg)
         x2, i2 = S2.solve(dev(w.b), 1e-10)
-        assert np.array_equal(host(x2), x0)
+        assert same(host(x2), x0)
     S.close()
     S2.close()
