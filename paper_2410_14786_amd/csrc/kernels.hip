@@ -710,6 +710,17 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
   if (A.done && *A.done) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int lr = lane / LPR, lc = lane % LPR;
+  // Register layout of a tile.  Forward passes (row products) let wave w own
+  // columns 16w..16w+15: lane = CPL * rg + cp holds rows rg + RG i, columns
+  // 16w + VEC cp + e, so a row sum reduces over CPL lanes, then the four waves.
+  // Backward passes (column products) let wave w own rows 16w..16w+15: lane =
+  // LPR * lr + lc holds rows 16w + RPI i + lr, columns VEC lc + e, so a column sum
+  // reduces over RPI lanes, then the four waves.  Both take NI loads per lane.
+  constexpr int CPL = 16 / VEC, RG = 64 / CPL;
+  static_assert(64 / RG == NI, "layouts differ in loads per lane");
+  const int rg = lane / CPL, cp = lane % CPL;
+  const int64_t lane_off = FWD ? (int64_t(rg) * NB + 16 * w + VEC * cp) : (int64_t(16 * w + lr) * NB + VEC * lc);
+  constexpr int64_t STEP = FWD ? RG * NB : RPI * NB;   // between a lane's consecutive loads
   const T* tiles = reinterpret_cast<const T*>(A.tiles);
   const T* dinv = reinterpret_cast<const T*>(A.dinv);
   T* sol = reinterpret_cast<T*>(A.sol);
@@ -730,7 +741,22 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     T* my_sol = sol + D.vec_off;
 
     // ---------------- prologue: right-hand side of tile row k ----------------
-    if (tid < NB) {
+    if (MODE == TRSV_FWD_II && A.v12) {
+      // interior rows of r - A v12: four lanes per CSR row
+      const int row = tid >> 2, sl = tid & 3;
+      const int a = k * NB + row;
+      double v = 0.0;
+      int64_t l = 0;
+      int g = 0;
+      if (a < nlim) {
+        l = D.loc_off + a;
+        g = A.gmap[l];
+        for (int j = A.rowptr[g] + sl; j < A.rowptr[g + 1]; j += 4) v += A.vals[j] * A.v12[A.colind[j]];
+      }
+      v += __shfl_xor(v, 1, 4);
+      v += __shfl_xor(v, 2, 4);
+      if (sl == 0) s_rhs[row] = a < nlim ? T(A.dsc[l] * (A.rin[g] - v)) : T(0);
+    } else if (tid < NB) {
       const int a = k * NB + tid;
       double rhs = 0.0;
       if (a >= nlo && a < nlim) {
@@ -739,12 +765,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
           rhs = A.wd[l] * A.rin[A.gmap[l]];
         } else if (MODE == TRSV_FWD_II) {
           const int64_t l = D.loc_off + a;
-          const int g = A.gmap[l];
-          double v = A.rin[g];
-          if (A.v12) {
-            for (int j = A.rowptr[g]; j < A.rowptr[g + 1]; ++j) v -= A.vals[j] * A.v12[A.colind[j]];
-          }
-          rhs = A.dsc[l] * v;
+          rhs = A.dsc[l] * A.rin[A.gmap[l]];
         } else if (MODE == TRSV_FWD_C) {
           double v = 0.0;
           for (int j = A.cinv_ptr[a]; j < A.cinv_ptr[a + 1]; ++j) v += A.gbuf[A.cinv[j]];
@@ -771,8 +792,8 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     // waiting on any published value
     V dv[NI];
     {
-      const T* dt = dinv + (D.dinv_off + k) * int64_t(NB * NB) + (16 * w + lr) * NB + VEC * lc;
-      for (int i = 0; i < NI; ++i) dv[i] = *reinterpret_cast<const V*>(dt + i * RPI * NB);
+      const T* dt = dinv + (D.dinv_off + k) * int64_t(NB * NB) + lane_off;
+      for (int i = 0; i < NI; ++i) dv[i] = *reinterpret_cast<const V*>(dt + i * STEP);
     }
 
     // ---------------- main loop over off-diagonal tiles ----------------
@@ -787,25 +808,25 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
       auto tile_ptr = [&](int jj) -> const T* {
         // forward: tile (k, jlo + jj), jj = 0..k-jlo-1; backward: tile (j, k), j = jhi .. k+1
         int64_t t = FWD ? tri_tile(k, jlo + jj) : tri_tile(jhi - jj, k);
-        return tiles + (tbase + t) * int64_t(NB * NB) + (16 * w + lr) * NB + VEC * lc;
+        return tiles + (tbase + t) * int64_t(NB * NB) + lane_off;
       };
       auto sol_row = [&](int jj) -> int { return FWD ? jlo + jj : (jhi - jj); };
       V cur[NI], nxt[NI];
       {
         const T* p = tile_ptr(0);
-        for (int i = 0; i < NI; ++i) cur[i] = *reinterpret_cast<const V*>(p + i * RPI * NB);
+        for (int i = 0; i < NI; ++i) cur[i] = *reinterpret_cast<const V*>(p + i * STEP);
       }
       for (int jj = 0; jj < nt; ++jj) {
         const T* ys = my_sol + sol_row(jj) * NB;
         T xv[FWD ? VEC : NI];
         if (FWD) {
-          for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + VEC * lc + e);
+          for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + 16 * w + VEC * cp + e);
         } else {
           for (int i = 0; i < NI; ++i) xv[i] = poll_published(ys + 16 * w + RPI * i + lr);
         }
         if (jj + 1 < nt) {
           const T* p = tile_ptr(jj + 1);
-          for (int i = 0; i < NI; ++i) nxt[i] = *reinterpret_cast<const V*>(p + i * RPI * NB);
+          for (int i = 0; i < NI; ++i) nxt[i] = *reinterpret_cast<const V*>(p + i * STEP);
         }
         if (FWD) {
           for (int i = 0; i < NI; ++i)
@@ -821,8 +842,8 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     if (FWD) {
       for (int i = 0; i < NI; ++i) {
         T v = acc[i];
-        for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lc == 0) s_red[0][16 * w + RPI * i + lr] = v;
+        for (int off = 1; off < CPL; off <<= 1) v += __shfl_xor(v, off, CPL);
+        if (cp == 0) s_red[w][rg + RG * i] = v;
       }
     } else {
       for (int e = 0; e < VEC; ++e) {
@@ -833,7 +854,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     }
     __syncthreads();
     if (tid < NB) {
-      T red = FWD ? s_red[0][tid] : (s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid]);
+      T red = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
       s_v[tid] = (k * NB + tid >= nlo && k * NB + tid < nlim) ? (s_rhs[tid] - red) : T(0);
     }
     __syncthreads();
@@ -843,9 +864,9 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
       if (FWD) {
         for (int i = 0; i < NI; ++i) {
           T v = T(0);
-          for (int e = 0; e < VEC; ++e) v += dv[i][e] * s_v[VEC * lc + e];
-          for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-          if (lc == 0) s_red[0][16 * w + RPI * i + lr] = v;
+          for (int e = 0; e < VEC; ++e) v += dv[i][e] * s_v[16 * w + VEC * cp + e];
+          for (int off = 1; off < CPL; off <<= 1) v += __shfl_xor(v, off, CPL);
+          if (cp == 0) s_red[w][rg + RG * i] = v;
         }
       } else {
         T a2[VEC];
@@ -860,7 +881,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
       }
       __syncthreads();
       if (tid < NB) {
-        T o = FWD ? s_red[0][tid] : (s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid]);
+        T o = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
         if (k * NB + tid >= nlim || k * NB + tid < nlo) o = T(0);
         s_out[tid] = o;
         store_published(my_sol + k * NB + tid, o);
