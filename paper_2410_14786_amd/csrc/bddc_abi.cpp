@@ -124,7 +124,9 @@ struct bddc_ctx {
   int32_t *ctask_fwd = nullptr, *ctask_bwd = nullptr;
   int Tc = 0;
   int32_t *t_fwd_rr = nullptr, *t_bwd_rr = nullptr, *t_fwd_ii = nullptr, *t_bwd_ii = nullptr;
-  int32_t *t_symfin = nullptr, *tinfo = nullptr, *padz = nullptr, *padf = nullptr;
+  int32_t *t_symfin = nullptr, *tinfo = nullptr;
+  int32_t *ifc_g = nullptr, *ifc_l = nullptr, *ifc_slotz = nullptr, *ifc_slotf = nullptr;   // interface dofs
+  double *ifc_dsc = nullptr, *ifc_wd = nullptr;
   int32_t *fcol = nullptr, *fcol_ii = nullptr, *lrow_rr = nullptr, *lrow_ii = nullptr;   // factor envelopes
   double* xg = nullptr;                        // inverses of the trailing factor blocks
   double *sg = nullptr, *hg = nullptr;         // interface form: Schur complements, X^T X (+ border rows)
@@ -402,6 +404,27 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   c->end("apply", ea);
 }
 
+IfcArgs ifc_args(bddc_ctx* c) {
+  IfcArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.g = c->ifc_g;
+  a.l = c->ifc_l;
+  a.slotz = c->ifc_slotz;
+  a.slotf = c->ifc_slotf;
+  a.dsc = c->ifc_dsc;
+  a.wd = c->ifc_wd;
+  a.n = int64_t(c->plan.ifc_g.size());
+  a.sc = c->sc;
+  a.sploc = c->sploc;
+  a.r = c->r;
+  a.z = c->z;
+  a.p = c->p;
+  a.q = c->q;
+  a.zpad = c->zpad;
+  a.fpad = c->fpad;
+  return a;
+}
+
 IfaceArgs iface_args(bddc_ctx* c) {
   IfaceArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -453,8 +476,14 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
   a.tasks = c->t_symfin;
   a.ntasks = int(P.symfin.size() / 2);
   launch_pc_finish(a, st);
-  launch_gather_z(c->inv_ptr, c->inv, c->ww, c->kappa, r, z, part_rz, P.n_free, done, c->pub_coarse,
-                  2 * int64_t(c->Tc) * NB, c->tickets, c->dsc, c->padz, c->zpad, st);
+  {
+    IfcArgs g = ifc_args(c);
+    g.ww = c->ww;
+    g.r = const_cast<double*>(r);
+    g.z = z;
+    g.part_out = part_rz;
+    launch_gather_z_ifc(g, st);
+  }
   c->end("apply", ea);
 }
 
@@ -475,8 +504,14 @@ void enqueue_schur(bddc_ctx* c, int it, bool fresh, const double* part_rz, doubl
   a.tasks = c->t_symfin;
   a.ntasks = int(P.symfin.size() / 2);
   launch_op_finish(a, st);
-  launch_gather_sp(c->inv_ptr, c->inv, c->sploc, c->kappa, c->z, c->p, c->q, part_rz, part_pq, c->sc, it,
-                   fresh ? 1 : 0, P.n_free, st);
+  {
+    IfcArgs g = ifc_args(c);
+    g.it = it;
+    g.fresh = fresh ? 1 : 0;
+    g.part_in = part_rz;
+    g.part_out = part_pq;
+    launch_gather_sp_ifc(g, st);
+  }
   c->end("schur", e);
 }
 
@@ -521,9 +556,14 @@ void enqueue_iteration(bddc_ctx* c, double* x, int it, bool fresh) {
     c->end("spmv", e);
   }
   if (c->iface)
-    launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st, c->inv_ptr, c->inv, c->wd,
-                      c->padf, c->fpad);
-  else
+  {
+    IfcArgs g = ifc_args(c);
+    g.x = x;
+    g.it = it;
+    g.part_in = c->part_a;
+    g.part_out = c->part_b;
+    launch_pcg_update_ifc(g, st);
+  } else
     launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st);
   launch_pcg_check(c->part_b, c->sc, it, st);
   if (c->iface) {
@@ -650,8 +690,10 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->upload(c->t_fwd_ii, P.fwd_ii))) return rc_;
   if ((rc_ = c->upload(c->t_bwd_ii, P.bwd_ii))) return rc_;
   if ((rc_ = c->upload(c->tinfo, P.tinfo))) return rc_;
-  if ((rc_ = c->upload(c->padz, P.padz))) return rc_;
-  if ((rc_ = c->upload(c->padf, P.padf))) return rc_;
+  if ((rc_ = c->upload(c->ifc_g, P.ifc_g))) return rc_;
+  if ((rc_ = c->upload(c->ifc_l, P.ifc_l))) return rc_;
+  if ((rc_ = c->upload(c->ifc_slotz, P.ifc_slotz))) return rc_;
+  if ((rc_ = c->upload(c->ifc_slotf, P.ifc_slotf))) return rc_;
   if ((rc_ = c->upload(c->fcol, P.fcol))) return rc_;
   if ((rc_ = c->upload(c->fcol_ii, P.fcol_ii))) return rc_;
   if ((rc_ = c->upload(c->lrow_rr, P.lrow_rr))) return rc_;
@@ -696,6 +738,9 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   for (auto& D : P.subs) max_ni = std::max(max_ni, int(D.n_i));
   launch_local_assembly(c->mesh, c->theta, c->mats, P.nsubs, max_ni, c->gmap, c->lmap, c->wgt, c->dsc, c->wd,
                         c->avg_of, c->avg_coef, c->tiles, c->fp32, c->app, c->err + 1, st);
+  if ((rc_ = c->alloc(c->ifc_dsc, int64_t(P.ifc_l.size()) + 1))) return rc_;
+  if ((rc_ = c->alloc(c->ifc_wd, int64_t(P.ifc_l.size()) + 1))) return rc_;
+  launch_ifc_setup(c->ifc_l, c->dsc, c->wd, c->ifc_dsc, c->ifc_wd, int64_t(P.ifc_g.size()), st);
   launch_factor(c->mats, P.nsubs, P.maxT, P.maxTx, c->tiles, c->dinv, c->fp32, c->fcol, c->err + 1, st);
   if ((rc_ = c->alloc(c->cpp, small))) return rc_;
   launch_local_small(c->mats, P.nsubs, c->tiles, c->fp32, c->app, c->sainv, c->sainve, c->aci, c->cpp, c->err + 1,
@@ -964,7 +1009,7 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
     // (re)start: z = M^{-1} r, rz
     if (iface) {
       launch_reset(false, nullptr, 0, c->pub_coarse, 2 * int64_t(c->Tc) * NB, c->tickets, done, st);
-      launch_scatter_pad(c->inv_ptr, c->inv, c->wd, c->r, c->padf, c->fpad, n, st);
+      launch_scatter_f_ifc(ifc_args(c), st);
       enqueue_apply_iface(c, c->r, c->z, c->part_c, done);
     } else {
       enqueue_apply(c, c->r, c->z, done);

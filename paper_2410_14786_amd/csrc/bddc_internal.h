@@ -11,6 +11,7 @@ namespace bddc {
 
 constexpr int NB = 64;        // tile edge (rows and columns) of every dense factor
 constexpr int MAX_NCI = 64;   // constraints per subdomain (one extra tile row)
+constexpr int IFC_MAXC = 8;   // subdomains sharing one dof (2^dim at most for box partitions)
 
 // Per-matrix descriptor used by the factorisation and the triangular solves.
 // A "matrix" is a subdomain's equilibrated A_RR bordered by one extra tile row
@@ -96,6 +97,9 @@ struct Plan {
   // preconditioner (interface dofs), -1 elsewhere
   std::vector<int32_t> symfin, tinfo, padz, padf;
   int64_t n_symrows = 0;
+  // interface dofs (kappa >= 2): global index and IFC_MAXC local copies each
+  // (local dof, operator slot, preconditioner slot; -1 past the last copy)
+  std::vector<int32_t> ifc_g, ifc_l, ifc_slotz, ifc_slotf;
 
   int maxT = 0, maxTx = 0, maxTI = 0;
   int64_t n_tiles = 0, n_dinv = 0, n_vec = 0, n_loc = 0, n_lmap = 0, n_xg = 0, n_sg = 0;

@@ -140,9 +140,7 @@ void launch_pcg_dir(const int32_t* rowptr, const int32_t* col, const double* val
                     double* q, const double* part_rz, double* part_pq, PcgScalars* sc, int it, int fresh, int64_t n,
                     hipStream_t st);
 void launch_pcg_update(double* x, double* r, const double* p, const double* q, const double* part_pq,
-                       double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st,
-                       const int32_t* inv_ptr = nullptr, const int32_t* inv = nullptr, const double* wd = nullptr,
-                       const int32_t* padf = nullptr, double* fpad = nullptr);
+                       double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st);
 void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, hipStream_t st);
 void launch_dot(const double* a, const double* b, double* part, int64_t n, const int* done, hipStream_t st);
 void launch_finish_dot(const double* part, double* out, hipStream_t st);
@@ -156,15 +154,36 @@ void launch_reset(bool fp32, void* pub, int64_t n_pub, double* pubc, int64_t n_p
 
 
 
-void launch_gather_sp(const int32_t* inv_ptr, const int32_t* inv, const double* sploc, const uint8_t* kappa,
-                      const double* z, double* p, double* q, const double* part_rz, double* part_pq, PcgScalars* sc,
-                      int it, int fresh, int64_t n, hipStream_t st);
-void launch_gather_z(const int32_t* inv_ptr, const int32_t* inv, const double* ww, const uint8_t* kappa,
-                     const double* r, double* z, double* part_rz, int64_t n, const int* done, double* pubc,
-                     int64_t n_pubc, unsigned* tickets, const double* dsc, const int32_t* padz, double* zpad,
-                     hipStream_t st);
-void launch_scatter_pad(const int32_t* inv_ptr, const int32_t* inv, const double* scale, const double* v,
-                        const int32_t* pad, double* out, int64_t n, hipStream_t st);
+// interface-form vector kernels over the interface dofs (IFC_MAXC copy slots each)
+struct IfcArgs {
+  const int32_t* g;         // global index of interface dof k
+  const int32_t* l;         // local copies (-1 past the last)
+  const int32_t* slotz;     // their slots in the operator's padded input
+  const int32_t* slotf;     // their slots in the preconditioner's padded input
+  const double* dsc;        // equilibration of each copy
+  const double* wd;         // weight * equilibration of each copy
+  int64_t n;
+  PcgScalars* sc;
+  int it;
+  int fresh;
+  const double* part_in;    // partial sums read (r.z or p.q)
+  double* part_out;         // partial sums written
+  const double* ww;         // weighted local preconditioner output
+  const double* sploc;      // (S z) per local dof
+  double* x;
+  double* r;
+  double* z;
+  double* p;
+  double* q;
+  double* zpad;
+  double* fpad;
+};
+void launch_ifc_setup(const int32_t* ifc_l, const double* dsc, const double* wd, double* ifc_dsc, double* ifc_wd,
+                      int64_t n_ifc, hipStream_t st);
+void launch_gather_z_ifc(const IfcArgs& a, hipStream_t st);
+void launch_gather_sp_ifc(const IfcArgs& a, hipStream_t st);
+void launch_pcg_update_ifc(const IfcArgs& a, hipStream_t st);
+void launch_scatter_f_ifc(const IfcArgs& a, hipStream_t st);
 enum { SYM_OP = 0, SYM_PC = 1 };
 void launch_sym_build(int mode, const MatDesc* mats, int nmats, int maxTS, const double* tiles, const double* xg,
                       const double* cpp, double* out, hipStream_t st);

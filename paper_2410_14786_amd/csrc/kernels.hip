@@ -1107,23 +1107,6 @@ void launch_zero_interior(const uint8_t* kappa, double* x, int64_t n, hipStream_
   hipLaunchKernelGGL(zero_interior_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, kappa, x, n);
 }
 
-// out[pad[l]] = scale[l] v[g] for the local copies l of every global dof g that
-// have a slot (pad[l] >= 0)
-__global__ void scatter_pad_kernel(const int32_t* inv_ptr, const int32_t* inv, const double* scale, const double* v,
-                                   const int32_t* pad, double* out, int64_t n) {
-  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x)
-    for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) {
-      const int32_t slot = pad[inv[j]];
-      if (slot >= 0) out[slot] = scale[inv[j]] * v[g];
-    }
-}
-
-void launch_scatter_pad(const int32_t* inv_ptr, const int32_t* inv, const double* scale, const double* v,
-                        const int32_t* pad, double* out, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(scatter_pad_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, inv_ptr, inv, scale, v, pad,
-                     out, n);
-}
-
 void launch_zero_interface(const uint8_t* kappa, double* x, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(zero_interface_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, kappa, x, n);
 }
@@ -1256,9 +1239,7 @@ __global__ __launch_bounds__(VBLK) void pcg_dir_kernel(const int32_t* rowptr, co
 // alpha = rz/pq; x += alpha p; r -= alpha q; partial sums of r.r
 __global__ __launch_bounds__(VBLK) void pcg_update_kernel(double* x, double* r, const double* p, const double* q,
                                                           const double* part_pq, double* part_rr, PcgScalars* sc,
-                                                          int it, int64_t n, const int32_t* inv_ptr,
-                                                          const int32_t* inv, const double* wd,
-                                                          const int32_t* padf, double* fpad) {
+                                                          int it, int64_t n) {
   __shared__ double sh[VBLK / 64];
   if (sc->done) return;
   const double pq = reduce_partials(part_pq, VGRID, sh);
@@ -1275,11 +1256,6 @@ __global__ __launch_bounds__(VBLK) void pcg_update_kernel(double* x, double* r, 
       double rv = r[i] - alpha * q[i];
       r[i] = rv;
       rr += rv * rv;
-      if (fpad)   // interface form: the preconditioner reads W D r in its padded rows
-        for (int j = inv_ptr[i]; j < inv_ptr[i + 1]; ++j) {
-          const int32_t slot = padf[inv[j]];
-          if (slot >= 0) fpad[slot] = wd[inv[j]] * rv;
-        }
     }
   }
   double t = block_sum(rr, sh);
@@ -1348,10 +1324,8 @@ void launch_pcg_init(const double* part_rr, const double* part_bb, PcgScalars* s
   hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(VBLK), 0, st, part_rr, part_bb, sc, rtol2);
 }
 void launch_pcg_update(double* x, double* r, const double* p, const double* q, const double* part_pq,
-                       double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st, const int32_t* inv_ptr,
-                       const int32_t* inv, const double* wd, const int32_t* padf, double* fpad) {
-  hipLaunchKernelGGL(pcg_update_kernel, dim3(VGRID), dim3(VBLK), 0, st, x, r, p, q, part_pq, part_rr, sc, it, n,
-                     inv_ptr, inv, wd, padf, fpad);
+                       double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_update_kernel, dim3(VGRID), dim3(VBLK), 0, st, x, r, p, q, part_pq, part_rr, sc, it, n);
 }
 void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, hipStream_t st) {
   hipLaunchKernelGGL(pcg_check_kernel, dim3(1), dim3(VBLK), 0, st, part_rr, sc, it);
@@ -1589,6 +1563,22 @@ void launch_sym_build(int mode, const MatDesc* mats, int nmats, int maxTS, const
     hipLaunchKernelGGL(sym_build_kernel<SYM_PC>, grid, dim3(256), 0, st, mats, tiles, xg, cpp, out);
 }
 
+// Sum over the eight lanes l ^ (0..7) (lane bits 0..2) without the LDS crossbar:
+// two quad permutations, then the mirror inside each half-row of eight lanes
+// (after the first two steps every lane of a quad holds the quad's sum).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double sum_cp(double v) {
+  v += dpp_f64<0xB1>(v);    // quad permutation [1,0,3,2]
+  v += dpp_f64<0x4E>(v);    // quad permutation [2,3,0,1]
+  v += dpp_f64<0x141>(v);   // mirror inside each half-row
+  return v;
+}
+
 // Sum over the lanes l, l^8, l^16, ... l^56 (lane bits 3..5) without the LDS
 // crossbar: bit 3 by a DPP rotation by 8 inside each row of 16 lanes, bits 4
 // and 5 by the row and half-wave swaps (each swap returns both halves, whose
@@ -1645,10 +1635,7 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   }
   auto flush = [&]() {
     for (int t = 0; t < 8; ++t) {
-      double v = racc[t];
-      v += __shfl_xor(v, 1, 8);
-      v += __shfl_xor(v, 2, 8);
-      v += __shfl_xor(v, 4, 8);
+      const double v = sum_cp(racc[t]);
       if (cp == 0) A.rowp[(pstart * 4 + w) * NB + rg + 8 * t] = v;
       racc[t] = 0.0;
     }
@@ -1815,64 +1802,143 @@ void launch_pc_finish(const IfaceArgs& a, hipStream_t st) {
   if (a.ntasks <= 0) return;
   hipLaunchKernelGGL(pc_finish_kernel, dim3(a.ntasks), dim3(256), 0, st, a);
 }
+// ---------------------------------------------------------------------------
+// Interface-form vector kernels over the interface dofs only: the interface
+// iterate, residual and directions vanish on subdomain interiors.  Interface dof
+// k has global index ifc_g[k] and IFC_MAXC copy slots (-1 past its last copy):
+// local dof, slot in the operator's padded input, slot in the preconditioner's.
+// ---------------------------------------------------------------------------
+struct IfcCopies {
+  int32_t l[IFC_MAXC];
+};
+__device__ __forceinline__ IfcCopies load_copies(const int32_t* a, int64_t k) {
+  IfcCopies c;
+  const int4* p = reinterpret_cast<const int4*>(a + k * IFC_MAXC);
+  const int4 u = p[0], v = p[1];
+  c.l[0] = u.x; c.l[1] = u.y; c.l[2] = u.z; c.l[3] = u.w;
+  c.l[4] = v.x; c.l[5] = v.y; c.l[6] = v.z; c.l[7] = v.w;
+  return c;
+}
 
-// q = S p = sum_i R_i^T S_i z_i + beta q on interface dofs; p = z + beta p; partial sums of p.q;
-// block 0 records rz[it] (and beta[it-1])
-__global__ __launch_bounds__(VBLK) void gather_sp_kernel(const int32_t* inv_ptr, const int32_t* inv,
-                                                         const double* sploc, const uint8_t* kappa, const double* z,
-                                                         double* p, double* q, const double* part_rz,
-                                                         double* part_pq, PcgScalars* sc, int it, int fresh,
-                                                         int64_t n) {
+// per copy slot: equilibration and weighted equilibration of its local dof
+__global__ void ifc_setup_kernel(const int32_t* ifc_l, const double* dsc, const double* wd, double* ifc_dsc,
+                                 double* ifc_wd, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t l = ifc_l[i];
+    ifc_dsc[i] = l >= 0 ? dsc[l] : 1.0;
+    ifc_wd[i] = l >= 0 ? wd[l] : 0.0;
+  }
+}
+
+// z = sum_i R_i^T W_i w_i on interface dofs, D^{-1} z into the operator's padded
+// input, partial sums of r.z
+__global__ __launch_bounds__(VBLK) void gather_z_ifc_kernel(IfcArgs A) {
   __shared__ double sh[VBLK / 64];
+  if (A.sc->done) return;
+  double rz = 0.0;
+  for (int64_t k = blockIdx.x * int64_t(VBLK) + threadIdx.x; k < A.n; k += int64_t(gridDim.x) * VBLK) {
+    const int g = A.g[k];
+    const IfcCopies l = load_copies(A.l, k), sz = load_copies(A.slotz, k);
+    double v = 0.0;
+    for (int c = 0; c < IFC_MAXC; ++c)
+      if (l.l[c] >= 0) v += A.ww[l.l[c]];
+    A.z[g] = v;
+    rz += A.r[g] * v;
+    for (int c = 0; c < IFC_MAXC; ++c)
+      if (sz.l[c] >= 0) A.zpad[sz.l[c]] = v / A.dsc[k * IFC_MAXC + c];
+  }
+  const double t = block_sum(rz, sh);
+  if (threadIdx.x == 0) A.part_out[blockIdx.x] = t;
+}
+
+// q = S p = sum_i R_i^T (S_i z)_i + beta q, p = z + beta p on interface dofs (beta
+// from the partial sums of r.z), partial sums of p.q
+__global__ __launch_bounds__(VBLK) void gather_sp_ifc_kernel(IfcArgs A) {
+  __shared__ double sh[VBLK / 64];
+  PcgScalars* sc = A.sc;
   if (sc->done) return;
-  const double rz = reduce_partials(part_rz, VEC_GRID, sh);
-  const double beta = fresh ? 0.0 : rz / sc->rz[it - 1];
+  const double rz = reduce_partials(A.part_in, VEC_GRID, sh);
+  const double beta = A.fresh ? 0.0 : rz / sc->rz[A.it - 1];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc->rz[it] = rz;
-    if (!fresh) sc->beta[it - 1] = beta;
+    sc->rz[A.it] = rz;
+    if (!A.fresh) sc->beta[A.it - 1] = beta;
   }
   double pq = 0.0;
-  for (int64_t g = blockIdx.x * int64_t(VBLK) + threadIdx.x; g < n; g += int64_t(gridDim.x) * VBLK) {
-    if (kappa[g] < 2) continue;
+  for (int64_t k = blockIdx.x * int64_t(VBLK) + threadIdx.x; k < A.n; k += int64_t(gridDim.x) * VBLK) {
+    const int g = A.g[k];
+    const IfcCopies l = load_copies(A.l, k);
     double v = 0.0;
-    for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) v += sploc[inv[j]];
-    const double pv = fresh ? z[g] : z[g] + beta * p[g];
-    const double qv = fresh ? v : v + beta * q[g];   // S p = S z + beta S p_old
-    p[g] = pv;
-    q[g] = qv;
+    for (int c = 0; c < IFC_MAXC; ++c)
+      if (l.l[c] >= 0) v += A.sploc[l.l[c]];
+    const double pv = A.fresh ? A.z[g] : A.z[g] + beta * A.p[g];
+    const double qv = A.fresh ? v : v + beta * A.q[g];
+    A.p[g] = pv;
+    A.q[g] = qv;
     pq += pv * qv;
   }
   const double t = block_sum(pq, sh);
-  if (threadIdx.x == 0) part_pq[blockIdx.x] = t;
+  if (threadIdx.x == 0) A.part_out[blockIdx.x] = t;
 }
 
-// interface preconditioner output: z = sum_i R_i^T W_i w_i on interface dofs,
-// partial sums of r.z
-__global__ __launch_bounds__(VBLK) void gather_z_kernel(const int32_t* inv_ptr, const int32_t* inv, const double* ww,
-                                                        const uint8_t* kappa, const double* r, double* z,
-                                                        double* part_rz, int64_t n, const int* done,
-                                                        double* pubc, int64_t n_pubc, unsigned* tickets,
-                                                        const double* dsc, const int32_t* padz, double* zpad) {
+// alpha = rz/pq; x += alpha p; r -= alpha q on interface dofs; W D r into the
+// preconditioner's padded input; partial sums of r.r
+__global__ __launch_bounds__(VBLK) void pcg_update_ifc_kernel(IfcArgs A) {
   __shared__ double sh[VBLK / 64];
-  if (done && *done) return;
-  {
-    // the next application's coarse solve starts from sentinels and zero tickets
-    unsigned long long* qc = reinterpret_cast<unsigned long long*>(pubc);
-    const int64_t i0 = blockIdx.x * int64_t(VBLK) + threadIdx.x;
-    for (int64_t i = i0; i < n_pubc; i += int64_t(gridDim.x) * VBLK) qc[i] = Traits<double>::SENT;
-    if (i0 < 8) tickets[i0] = 0u;
+  PcgScalars* sc = A.sc;
+  if (sc->done) return;
+  const double pq = reduce_partials(A.part_in, VEC_GRID, sh);
+  const double rz = sc->rz[A.it];
+  const double alpha = rz / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->pq[A.it] = pq;
+    sc->alpha[A.it] = alpha;
   }
-  double rz = 0.0;
-  for (int64_t g = blockIdx.x * int64_t(VBLK) + threadIdx.x; g < n; g += int64_t(gridDim.x) * VBLK) {
-    if (kappa[g] < 2) continue;
-    double v = 0.0;
-    for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) v += ww[inv[j]];
-    z[g] = v;
-    rz += r[g] * v;
-    for (int j = inv_ptr[g]; j < inv_ptr[g + 1]; ++j) zpad[padz[inv[j]]] = v / dsc[inv[j]];
+  double rr = 0.0;
+  if (pq > 0.0 && rz > 0.0) {
+    for (int64_t k = blockIdx.x * int64_t(VBLK) + threadIdx.x; k < A.n; k += int64_t(gridDim.x) * VBLK) {
+      const int g = A.g[k];
+      const IfcCopies sf = load_copies(A.slotf, k);
+      A.x[g] += alpha * A.p[g];
+      const double rv = A.r[g] - alpha * A.q[g];
+      A.r[g] = rv;
+      rr += rv * rv;
+      for (int c = 0; c < IFC_MAXC; ++c)
+        if (sf.l[c] >= 0) A.fpad[sf.l[c]] = A.wd[k * IFC_MAXC + c] * rv;
+    }
   }
-  const double t = block_sum(rz, sh);
-  if (threadIdx.x == 0) part_rz[blockIdx.x] = t;
+  const double t = block_sum(rr, sh);
+  if (threadIdx.x == 0) A.part_out[blockIdx.x] = t;
+}
+
+// W D r into the preconditioner's padded input (start of a CG segment)
+__global__ void scatter_f_ifc_kernel(IfcArgs A) {
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < A.n; k += int64_t(gridDim.x) * blockDim.x) {
+    const double rv = A.r[A.g[k]];
+    const IfcCopies sf = load_copies(A.slotf, k);
+    for (int c = 0; c < IFC_MAXC; ++c)
+      if (sf.l[c] >= 0) A.fpad[sf.l[c]] = A.wd[k * IFC_MAXC + c] * rv;
+  }
+}
+
+void launch_ifc_setup(const int32_t* ifc_l, const double* dsc, const double* wd, double* ifc_dsc, double* ifc_wd,
+                      int64_t n_ifc, hipStream_t st) {
+  const int64_t n = n_ifc * IFC_MAXC;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(ifc_setup_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, ifc_l, dsc, wd, ifc_dsc,
+                     ifc_wd, n);
+}
+void launch_gather_z_ifc(const IfcArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(gather_z_ifc_kernel, dim3(VGRID), dim3(VBLK), 0, st, a);
+}
+void launch_gather_sp_ifc(const IfcArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(gather_sp_ifc_kernel, dim3(VGRID), dim3(VBLK), 0, st, a);
+}
+void launch_pcg_update_ifc(const IfcArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_update_ifc_kernel, dim3(VGRID), dim3(VBLK), 0, st, a);
+}
+void launch_scatter_f_ifc(const IfcArgs& a, hipStream_t st) {
+  if (a.n <= 0) return;
+  hipLaunchKernelGGL(scatter_f_ifc_kernel, dim3(grid_for(a.n, 256, 4096)), dim3(256), 0, st, a);
 }
 
 // sentinel fill of the published buffers and zero tickets, one launch
@@ -1904,20 +1970,7 @@ void launch_reset(bool fp32, void* pub, int64_t n_pub, double* pubc, int64_t n_p
 
 
 
-void launch_gather_sp(const int32_t* inv_ptr, const int32_t* inv, const double* sploc, const uint8_t* kappa,
-                      const double* z, double* p, double* q, const double* part_rz, double* part_pq, PcgScalars* sc,
-                      int it, int fresh, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(gather_sp_kernel, dim3(VEC_GRID), dim3(VBLK), 0, st, inv_ptr, inv, sploc, kappa, z, p, q,
-                     part_rz, part_pq, sc, it, fresh, n);
-}
 
-void launch_gather_z(const int32_t* inv_ptr, const int32_t* inv, const double* ww, const uint8_t* kappa,
-                     const double* r, double* z, double* part_rz, int64_t n, const int* done, double* pubc,
-                     int64_t n_pubc, unsigned* tickets, const double* dsc, const int32_t* padz, double* zpad,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(gather_z_kernel, dim3(VEC_GRID), dim3(VBLK), 0, st, inv_ptr, inv, ww, kappa, r, z, part_rz, n,
-                     done, pubc, n_pubc, tickets, dsc, padz, zpad);
-}
 
 // ---------------------------------------------------------------------------
 // Per-element gradient g_e = -lam_e^T K_ref u_e

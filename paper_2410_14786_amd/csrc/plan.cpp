@@ -369,6 +369,18 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
   }
   for (int64_t g = 0; g < nfree; ++g)
     if (P.inv_ptr[g + 1] - P.inv_ptr[g] != P.kappa[g]) { err = "internal: multiplicity mismatch"; return BDDC_EINVAL; }
+  for (int64_t g = 0; g < nfree; ++g) {
+    const int32_t b = P.inv_ptr[g], e = P.inv_ptr[g + 1];
+    if (e - b < 2) continue;
+    if (e - b > IFC_MAXC) { err = "internal: more than 8 subdomains share a dof"; return BDDC_EINVAL; }
+    P.ifc_g.push_back(int32_t(g));
+    for (int c = 0; c < IFC_MAXC; ++c) {
+      const int32_t l = b + c < e ? P.inv[b + c] : -1;
+      P.ifc_l.push_back(l);
+      P.ifc_slotz.push_back(l >= 0 ? P.padz[l] : -1);
+      P.ifc_slotf.push_back(l >= 0 ? P.padf[l] : -1);
+    }
+  }
   P.cinv_ptr.assign(P.n_coarse + 1, 0);
   for (int32_t p : P.rc) P.cinv_ptr[p + 1] += 1;
   for (int p = 0; p < P.n_coarse; ++p) P.cinv_ptr[p + 1] += P.cinv_ptr[p];
