@@ -124,7 +124,7 @@ struct bddc_ctx {
   int32_t *ctask_fwd = nullptr, *ctask_bwd = nullptr;
   int Tc = 0;
   int32_t *t_fwd_rr = nullptr, *t_bwd_rr = nullptr, *t_fwd_ii = nullptr, *t_bwd_ii = nullptr;
-  int32_t *t_symfin = nullptr, *tinfo = nullptr;
+  int32_t *t_symfin = nullptr, *tinfo = nullptr, *trows_op = nullptr, *trows_pc = nullptr;
   int32_t *ifc_g = nullptr, *ifc_l = nullptr, *ifc_slotz = nullptr, *ifc_slotf = nullptr;   // interface dofs
   double *ifc_dsc = nullptr, *ifc_wd = nullptr;
   int32_t *fcol = nullptr, *fcol_ii = nullptr, *lrow_rr = nullptr, *lrow_ii = nullptr;   // factor envelopes
@@ -459,6 +459,7 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
   hipEvent_t ea = c->begin("apply");
   IfaceArgs a = iface_args(c);
   a.m = c->hg;
+  a.trows = c->trows_pc;
   a.xpad = c->fpad;
   {
     hipEvent_t k0, k1;
@@ -495,6 +496,7 @@ void enqueue_schur(bddc_ctx* c, int it, bool fresh, const double* part_rz, doubl
   hipEvent_t e = c->begin("schur");
   IfaceArgs a = iface_args(c);
   a.m = c->sg;
+  a.trows = c->trows_op;
   a.xpad = c->zpad;
   {
     hipEvent_t k0, k1;
@@ -690,6 +692,8 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->upload(c->t_fwd_ii, P.fwd_ii))) return rc_;
   if ((rc_ = c->upload(c->t_bwd_ii, P.bwd_ii))) return rc_;
   if ((rc_ = c->upload(c->tinfo, P.tinfo))) return rc_;
+  if ((rc_ = c->upload(c->trows_op, P.trows_op))) return rc_;
+  if ((rc_ = c->upload(c->trows_pc, P.trows_pc))) return rc_;
   if ((rc_ = c->upload(c->ifc_g, P.ifc_g))) return rc_;
   if ((rc_ = c->upload(c->ifc_l, P.ifc_l))) return rc_;
   if ((rc_ = c->upload(c->ifc_slotz, P.ifc_slotz))) return rc_;

@@ -76,6 +76,7 @@ struct IfaceArgs {
   const MatDesc* mats;
   const double* m;          // symmetric interface matrices, one stream of ntiles tiles
   const int32_t* tinfo;     // per tile: (global row << 8) | (ii - jj)
+  const int32_t* trows;     // per tile: rows to read, h | z0 << 8 | z1 << 16 (rows r < h outside [z0, z1))
   int64_t ntiles;
   int nwg;                  // workgroups of the mat-vec launch (its range split)
   const int32_t* tasks;     // finishers: (matrix, row ii)

@@ -1603,14 +1603,18 @@ __device__ __forceinline__ double sum_rg(double v) {
 // launch splits the tile stream into equal contiguous ranges (no tickets, no
 // barriers, nothing staged): every tile (ii, jj) is read once and used twice,
 // for the row product sum_jj M(ii, jj) v_jj (kept in registers along a row
-// piece and stored per piece and wave, see sym_row_product) and, for jj < ii,
-// the column product M(ii, jj)^T v_ii (stored at the tile's slot in part).
-// Output row k of a subdomain is then its row product plus the column products
-// of the tiles (i, k), i > k.  Inputs come from padded per-row vectors (zero
-// where a row has no interface dof).
+// piece and stored per piece and wave, see sym_row_product) and the column
+// product M(ii, jj)^T v_ii (stored at the tile's slot in part).  A diagonal tile
+// counts its lower triangle in the row product and its strict lower triangle in
+// the column product.  Output row k of a subdomain is then its row product plus
+// the column products of the tiles (i, k), i >= k.  Inputs come from padded
+// per-row vectors (zero where a row has no interface dof).
 // Wave w owns columns 16w..16w+15 of every tile; lane = 8 * rg + cp holds rows
 // rg + 8t (t < 8) of columns 16w + 2cp, +1, so a column product reduces over the
-// eight rg lanes of one wave and a row product over the eight cp lanes.
+// eight rg lanes of one wave and a row product over the eight cp lanes.  Rows
+// that hold nothing are not read: past the matrix's last row, in a zero row
+// range (the average-constraint rows of the operator), and in a diagonal tile
+// the row blocks above wave w's columns.
 constexpr int SYM_UNROLL = 2;
 // tile descriptors are uniform per wave and read-only: scalar loads (constant
 // address space), which complete independently of the vector memory counter
@@ -1626,6 +1630,7 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   if (t0 >= t1) return;
   const double* xv = A.xpad;
   const cint32_t* tinfo = (const cint32_t*)(A.tinfo);
+  const cint32_t* trows = (const cint32_t*)(A.trows);
   int cur_row = tinfo[t0] >> 8;
   int64_t pstart = t0;
   double xi[8], racc[8];
@@ -1642,8 +1647,11 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   };
   // the tile descriptors run one batch ahead, so that every load of a batch
   // (tiles, inputs, the inputs of a row that starts in it) issues at once
-  int inf_next[SYM_UNROLL];
-  for (int u = 0; u < SYM_UNROLL; ++u) inf_next[u] = tinfo[min(t0 + u, t1 - 1)];
+  int inf_next[SYM_UNROLL], rws_next[SYM_UNROLL];
+  for (int u = 0; u < SYM_UNROLL; ++u) {
+    inf_next[u] = tinfo[min(t0 + u, t1 - 1)];
+    rws_next[u] = trows[min(t0 + u, t1 - 1)];
+  }
   for (int64_t t = t0; t < t1; t += SYM_UNROLL) {
     V b[SYM_UNROLL][8];
     V xx[SYM_UNROLL];
@@ -1653,7 +1661,17 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
     for (int u = 0; u < SYM_UNROLL; ++u) {
       const int64_t tt = min(t + u, t1 - 1);   // past the range end: the last tile again
       const double* p = A.m + tt * (NB * NB) + rg * NB + col;
-      for (int k = 0; k < 8; ++k) b[u][k] = *reinterpret_cast<const V*>(p + k * 8 * NB);
+      // rows kept: r < h, outside [z0, z1), and (diagonal tile) r >= 16 w
+      const int rws = rws_next[u], h = rws & 255, z0 = (rws >> 8) & 255, z1 = rws >> 16;
+      const int rmin = (inf[u] & 255) == 0 ? 16 * w : 0;
+      for (int k = 0; k < 8; ++k) {
+        const int r = rg + 8 * k;
+        V v;
+        v[0] = 0.0;
+        v[1] = 0.0;
+        if (r < h && r >= rmin && (r < z0 || r >= z1)) v = *reinterpret_cast<const V*>(p + k * 8 * NB);
+        b[u][k] = v;
+      }
     }
     for (int u = 0; u < SYM_UNROLL; ++u) {
       const int row = inf[u] >> 8, d = inf[u] & 255;
@@ -1662,7 +1680,11 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
       if (row != prev)
         for (int k = 0; k < 8; ++k) xn[u][k] = xv[int64_t(row) * NB + rg + 8 * k];
     }
-    for (int u = 0; u < SYM_UNROLL; ++u) inf_next[u] = tinfo[min(t + SYM_UNROLL + u, t1 - 1)];
+    for (int u = 0; u < SYM_UNROLL; ++u) {
+      const int64_t tn = min(t + SYM_UNROLL + u, t1 - 1);
+      inf_next[u] = tinfo[tn];
+      rws_next[u] = trows[tn];
+    }
     for (int u = 0; u < SYM_UNROLL; ++u) {
       if (t + u >= t1) break;
       const int row = inf[u] >> 8, d = inf[u] & 255;
@@ -1672,25 +1694,35 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
         cur_row = row;
         for (int k = 0; k < 8; ++k) xi[k] = xn[u][k];
       }
-      for (int k = 0; k < 8; ++k) racc[k] += b[u][k][0] * xx[u][0] + b[u][k][1] * xx[u][1];
+      double c0 = 0.0, c1 = 0.0;
       if (d > 0) {
-        double c0 = 0.0, c1 = 0.0;
         for (int k = 0; k < 8; ++k) {
+          racc[k] += b[u][k][0] * xx[u][0] + b[u][k][1] * xx[u][1];
           c0 += b[u][k][0] * xi[k];
           c1 += b[u][k][1] * xi[k];
         }
-        V o;
-        o[0] = sum_rg(c0);
-        o[1] = sum_rg(c1);
-        if (rg == 0) *reinterpret_cast<V*>(A.part + (t + u) * NB + col) = o;
+      } else {
+        // diagonal tile: lower triangle (c <= r) in the row product, strict lower
+        // triangle (c < r) in the column product
+        for (int k = 0; k < 8; ++k) {
+          const int r = rg + 8 * k;
+          const double m0 = col <= r ? b[u][k][0] : 0.0, m1 = col + 1 <= r ? b[u][k][1] : 0.0;
+          racc[k] += m0 * xx[u][0] + m1 * xx[u][1];
+          c0 += (col < r ? m0 : 0.0) * xi[k];
+          c1 += (col + 1 < r ? m1 : 0.0) * xi[k];
+        }
       }
+      V o;
+      o[0] = sum_rg(c0);
+      o[1] = sum_rg(c1);
+      if (rg == 0) *reinterpret_cast<V*>(A.part + (t + u) * NB + col) = o;
     }
   }
   flush();
 }
 
 // Output row ii of a subdomain's symmetric matrix: the row product (over its
-// pieces) plus the column products of tiles (i2, ii), i2 = ii+1 .. TS-1; the
+// pieces) plus the column products of tiles (i2, ii), i2 = ii .. TS-1; the
 // four waves take every fourth term, the result is in s_red[0..3] (summed by
 // the caller in that fixed order).
 __device__ __forceinline__ void sum_row(const IfaceArgs& A, const MatDesc& D, int ii, int TS, double (*s_red)[NB]) {
@@ -1698,7 +1730,7 @@ __device__ __forceinline__ void sum_row(const IfaceArgs& A, const MatDesc& D, in
   double y = 0.0;
   if (w == 0) y = sym_row_product(A.rowp, D.sg_off + tri_tile(ii, 0), ii + 1, A.ntiles, A.nwg, lane);
   const double* pp = A.part + D.sg_off * NB + lane;
-  for (int i2 = ii + 1 + w; i2 < TS; i2 += 4) y += pp[tri_tile(i2, ii) * NB];
+  for (int i2 = ii + w; i2 < TS; i2 += 4) y += pp[tri_tile(i2, ii) * NB];
   s_red[w][lane] = y;
 }
 

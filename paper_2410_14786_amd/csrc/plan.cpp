@@ -326,8 +326,17 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
       D.sg_off = sg;
       const int TS = sym_tile_rows(D);
       D.sym_row = int32_t(rows);
-      for (int ii = 0; ii < TS; ++ii)
-        for (int jj = 0; jj <= ii; ++jj) P.tinfo.push_back(int32_t(((rows + ii) << 8) | (ii - jj)));
+      const int nG = D.n_R - D.n_I, m = nG + D.n_ci;
+      auto clamp64 = [](int v) { return std::max(0, std::min(NB, v)); };
+      for (int ii = 0; ii < TS; ++ii) {
+        const int h = clamp64(m - ii * NB);
+        const int z0 = clamp64(nG - ii * NB), z1 = clamp64(nG + D.n_A - ii * NB);
+        for (int jj = 0; jj <= ii; ++jj) {
+          P.tinfo.push_back(int32_t(((rows + ii) << 8) | (ii - jj)));
+          P.trows_op.push_back(h | (z0 << 8) | (z1 << 16));
+          P.trows_pc.push_back(h);
+        }
+      }
       xg += tri_tile(TG, 0);
       sg += tri_tile(TS, 0);
       rows += TS;
