@@ -433,6 +433,7 @@ IfaceArgs iface_args(bddc_ctx* c) {
   a.ntiles = c->plan.n_sg;
   a.nwg = int(std::min<int64_t>(c->grid_trsv, c->plan.n_sg));
   a.rowp = c->rowp;
+  a.check_it = -1;
   a.sc = c->sc;
   a.part = c->symp;
   a.dsc = c->dsc;
@@ -448,12 +449,13 @@ IfaceArgs iface_args(bddc_ctx* c) {
 }
 
 // Interface preconditioner (v1 + v2 restricted to interface dofs) on an
-// interface residual r (scattered as f = W D r into floc): the products of
-// X^T X and of the border row W_G^T X with f, the coarse problem, then
-// x = X^T X f + X^T W_G coef weighted into ww, gathered into z (interface
-// entries) with the partial sums of r.z.  Expects zero tickets and sentinel
-// coarse buffers, and leaves them so for the next application.
-void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_rz, const int* done) {
+// interface residual r (its f = W D r already in the padded input fpad): the
+// products of X^T X and of the constraint rows W_G^T X with f, the coarse
+// problem, then x = X^T X f + X^T W_G coef weighted into ww, gathered into z
+// (interface entries) with the partial sums of r.z.  check_it >= 0: the
+// mat-vec first takes the convergence decision of that CG iteration.
+void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_rz, const int* done,
+                         int check_it = -1) {
   const Plan& P = c->plan;
   hipStream_t st = c->st;
   hipEvent_t ea = c->begin("apply");
@@ -461,6 +463,8 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
   a.m = c->hg;
   a.trows = c->trows_pc;
   a.xpad = c->fpad;
+  a.check_it = check_it;
+  a.part_rr = c->part_b;
   {
     hipEvent_t k0, k1;
     c->kernel_events("pc", &k0, &k1);
@@ -557,20 +561,18 @@ void enqueue_iteration(bddc_ctx* c, double* x, int it, bool fresh) {
                    st);
     c->end("spmv", e);
   }
-  if (c->iface)
-  {
+  if (c->iface) {
     IfcArgs g = ifc_args(c);
     g.x = x;
     g.it = it;
     g.part_in = c->part_a;
     g.part_out = c->part_b;
     launch_pcg_update_ifc(g, st);
-  } else
-    launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st);
-  launch_pcg_check(c->part_b, c->sc, it, st);
-  if (c->iface) {
-    enqueue_apply_iface(c, c->r, c->z, c->part_c, done);
+    // the preconditioner's mat-vec takes this iteration's convergence decision
+    enqueue_apply_iface(c, c->r, c->z, c->part_c, done, it);
   } else {
+    launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st);
+    launch_pcg_check(c->part_b, c->sc, it, st);
     enqueue_apply(c, c->r, c->z, done);
     launch_dot(c->r, c->z, c->part_c, n, done, st);
   }

@@ -83,6 +83,8 @@ struct IfaceArgs {
   int ntasks;
   const PcgScalars* sc;
   const double* xpad;       // padded per-row input (64 per row): D^{-1} z + corners, or W D r
+  int check_it;             // >= 0: first take the convergence decision of this CG iteration
+  const double* part_rr;    // its partial sums of r.r
   double* part;             // column products, 64 per tile
   double* rowp;             // row products per piece and wave, 4 x 64 per piece start tile
   const double* dsc;

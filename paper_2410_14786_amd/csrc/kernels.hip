@@ -1622,6 +1622,24 @@ typedef __attribute__((address_space(4))) const int32_t cint32_t;
 __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   using V = d2v;
   if (A.sc->done) return;
+  if (A.check_it >= 0) {
+    // the convergence decision of CG iteration check_it, taken by every
+    // workgroup from the same partial sums of r.r (workgroup 0 records it)
+    __shared__ double sh[VBLK / 64];
+    const double rr = reduce_partials(A.part_rr, VEC_GRID, sh);
+    const int it = A.check_it;
+    PcgScalars* sc = const_cast<PcgScalars*>(A.sc);
+    const double pq = sc->pq[it], rz = sc->rz[it];
+    const bool bad = !(pq > 0.0) || !(rz > 0.0) || !(rr == rr);
+    const bool conv = rr <= sc->tol2;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->rr[it] = rr;
+      sc->iters = bad ? it : it + 1;   // a breakdown leaves this iteration's update unapplied
+      if (bad) sc->done = 2;
+      else if (conv) sc->done = 1;
+    }
+    if (bad || conv) return;
+  }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rg = lane >> 3, cp = lane & 7;
   const int col = 16 * w + 2 * cp;
