@@ -465,6 +465,7 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
   a.xpad = c->fpad;
   a.check_it = check_it;
   a.part_rr = c->part_b;
+  a.nparts_rr = ifc_blocks(int64_t(P.ifc_g.size()));
   {
     hipEvent_t k0, k1;
     c->kernel_events("pc", &k0, &k1);

@@ -85,6 +85,7 @@ struct IfaceArgs {
   const double* xpad;       // padded per-row input (64 per row): D^{-1} z + corners, or W D r
   int check_it;             // >= 0: first take the convergence decision of this CG iteration
   const double* part_rr;    // its partial sums of r.r
+  int nparts_rr;            // their count
   double* part;             // column products, 64 per tile
   double* rowp;             // row products per piece and wave, 4 x 64 per piece start tile
   const double* dsc;
@@ -183,6 +184,7 @@ struct IfcArgs {
 };
 void launch_ifc_setup(const int32_t* ifc_l, const double* dsc, const double* wd, double* ifc_dsc, double* ifc_wd,
                       int64_t n_ifc, hipStream_t st);
+int ifc_blocks(int64_t n);
 void launch_gather_z_ifc(const IfcArgs& a, hipStream_t st);
 void launch_gather_sp_ifc(const IfcArgs& a, hipStream_t st);
 void launch_pcg_update_ifc(const IfcArgs& a, hipStream_t st);

@@ -1626,7 +1626,7 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
     // the convergence decision of CG iteration check_it, taken by every
     // workgroup from the same partial sums of r.r (workgroup 0 records it)
     __shared__ double sh[VBLK / 64];
-    const double rr = reduce_partials(A.part_rr, VEC_GRID, sh);
+    const double rr = reduce_partials(A.part_rr, A.nparts_rr, sh);
     const int it = A.check_it;
     PcgScalars* sc = const_cast<PcgScalars*>(A.sc);
     const double pq = sc->pq[it], rz = sc->rz[it];
@@ -1907,7 +1907,7 @@ __global__ __launch_bounds__(VBLK) void gather_sp_ifc_kernel(IfcArgs A) {
   __shared__ double sh[VBLK / 64];
   PcgScalars* sc = A.sc;
   if (sc->done) return;
-  const double rz = reduce_partials(A.part_in, VEC_GRID, sh);
+  const double rz = reduce_partials(A.part_in, gridDim.x, sh);
   const double beta = A.fresh ? 0.0 : rz / sc->rz[A.it - 1];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc->rz[A.it] = rz;
@@ -1936,7 +1936,7 @@ __global__ __launch_bounds__(VBLK) void pcg_update_ifc_kernel(IfcArgs A) {
   __shared__ double sh[VBLK / 64];
   PcgScalars* sc = A.sc;
   if (sc->done) return;
-  const double pq = reduce_partials(A.part_in, VEC_GRID, sh);
+  const double pq = reduce_partials(A.part_in, gridDim.x, sh);
   const double rz = sc->rz[A.it];
   const double alpha = rz / pq;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1977,14 +1977,17 @@ void launch_ifc_setup(const int32_t* ifc_l, const double* dsc, const double* wd,
   hipLaunchKernelGGL(ifc_setup_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, ifc_l, dsc, wd, ifc_dsc,
                      ifc_wd, n);
 }
+// The three kernels use the same grid, ifc_blocks(n): each reduces the partial
+// sums of the previous one, one per block.
+int ifc_blocks(int64_t n) { return int(std::max<int64_t>(1, std::min<int64_t>(VGRID, (n + VBLK - 1) / VBLK))); }
 void launch_gather_z_ifc(const IfcArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(gather_z_ifc_kernel, dim3(VGRID), dim3(VBLK), 0, st, a);
+  hipLaunchKernelGGL(gather_z_ifc_kernel, dim3(ifc_blocks(a.n)), dim3(VBLK), 0, st, a);
 }
 void launch_gather_sp_ifc(const IfcArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(gather_sp_ifc_kernel, dim3(VGRID), dim3(VBLK), 0, st, a);
+  hipLaunchKernelGGL(gather_sp_ifc_kernel, dim3(ifc_blocks(a.n)), dim3(VBLK), 0, st, a);
 }
 void launch_pcg_update_ifc(const IfcArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(pcg_update_ifc_kernel, dim3(VGRID), dim3(VBLK), 0, st, a);
+  hipLaunchKernelGGL(pcg_update_ifc_kernel, dim3(ifc_blocks(a.n)), dim3(VBLK), 0, st, a);
 }
 void launch_scatter_f_ifc(const IfcArgs& a, hipStream_t st) {
   if (a.n <= 0) return;
