@@ -1615,7 +1615,7 @@ __device__ __forceinline__ double sum_rg(double v) {
 // that hold nothing are not read: past the matrix's last row, in a zero row
 // range (the average-constraint rows of the operator), and in a diagonal tile
 // the row blocks above wave w's columns.
-constexpr int SYM_UNROLL = 2;
+constexpr int SYM_UNROLL = 1;
 // tile descriptors are uniform per wave and read-only: scalar loads (constant
 // address space), which complete independently of the vector memory counter
 typedef __attribute__((address_space(4))) const int32_t cint32_t;
