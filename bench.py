@@ -10,10 +10,11 @@ resident in HBM when the timed region starts.
 Prints one JSON line with the FP64 solve rate as `value` (CG restricted to the
 interface dofs, the default of bddc_pcg_solve, iterations replayed from
 captured HIP graphs), the same solve launched eagerly, the same solve with CG on the
-whole space (the three-part preconditioner applied as written) and the
-FP32-local rate beside it, the roofline of the dominant kernel (algorithmic
-bytes per launch over its HIP-event-timed average duration) and a CPU-oracle
-baseline on a bounded sample of the same workload.
+whole space (the three-part preconditioner applied as written), the FP32-local
+rates beside it (interface form with the preconditioner's local solves in
+FP32, and whole-space form with FP32 local factors), the roofline of the
+dominant kernel (algorithmic bytes per launch over its HIP-event-timed average
+duration) and a CPU-oracle baseline on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -79,12 +80,13 @@ def algorithmic_bytes(w, local_bytes):
                              for nR, nI, nci, nP in s)
     fam["trsv_fwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 4 + local_bytes) for nR, nI, nci, nP in s)
     fam["trsv_bwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 8 + 4 + local_bytes) for nR, nI, nci, nP in s)
-    # interface form (FP64): the operator streams the lower triangle of the local
-    # Schur complement on n_G + n_P rows (n_G = n_R - n_I interface rows, n_P
-    # corners), the preconditioner that of X^T X on n_G rows plus the n_ci x n_G
-    # border block; each reads its input and writes its output once
+    # interface form: the operator (always FP64) streams the lower triangle of
+    # the local Schur complement on n_G + n_P rows (n_G = n_R - n_I interface
+    # rows, n_P corners), the preconditioner (local precision) that of X^T X on
+    # n_G rows plus the n_ci x n_G border block; each reads its FP64 input and
+    # writes its FP64 output once
     fam["op"] = sum(tri(nR - nI + nP) * 8 + (nR - nI + nP) * (8 + 8) for nR, nI, nci, nP in s)
-    fam["pc"] = sum(tri(nR - nI) * 8 + nci * (nR - nI) * 8 + (nR - nI) * (8 + 8) + nci * 8
+    fam["pc"] = sum(tri(nR - nI) * local_bytes + nci * (nR - nI) * local_bytes + (nR - nI) * (8 + 8) + nci * 8
                     for nR, nI, nci, nP in s)
     return fam
 
@@ -116,7 +118,7 @@ def load_traffic(kernel, workload, local_bits):
 def run_gpu(w, steps, warmup, local_bits, use_graph=False, full_space=False, autotune=True, timing=True):
     import torch
     from paper_2410_14786_amd import bddc
-    families = FULL_FAMILIES if (full_space or local_bits == 32) else IFACE_FAMILIES
+    families = FULL_FAMILIES if full_space else IFACE_FAMILIES
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S = bddc.solver_for(w, local_bits=local_bits, use_graph=use_graph, full_space=full_space)
@@ -221,7 +223,12 @@ def main():
     if not args.no_full_space:
         runs["full_space"] = run_gpu(w, args.steps, args.warmup, main_bits, full_space=True)
     if not args.no_fp32 and main_bits == 64:
-        runs["fp32_local"] = run_gpu(w, args.steps, args.warmup, 32)
+        runs["fp32_local"] = run_gpu(w, args.steps, args.warmup, 32, use_graph=not args.no_graph,
+                                     timing=args.no_graph)
+        if not args.no_graph:
+            runs["fp32_local_eager"] = run_gpu(w, args.steps, args.warmup, 32)
+        if not args.no_full_space:
+            runs["fp32_local_full_space"] = run_gpu(w, args.steps, args.warmup, 32, full_space=True)
     for name, r in runs.items():
         print(f"[bench] {name}: {1000 * r['elapsed_s'] / args.steps:.2f} ms/solve, iters {r['iters'][-1]}, "
               f"setup {r['setup_s']:.2f} s", file=sys.stderr, flush=True)
@@ -286,7 +293,17 @@ def main():
     if "full_space" in runs:
         out["full_space"] = summarize(runs["full_space"], main_bits)
     if "fp32_local" in runs:
-        out["fp32_local"] = summarize(runs["fp32_local"], 32)
+        f = summarize(runs["fp32_local"], 32)
+        f["cg_space"] = "interface"
+        f["local_precision"] = "FP32 preconditioner matrices (FP64 factors, operator and interior solves)"
+        if "fp32_local_eager" in runs:
+            f["eager"] = summarize(runs["fp32_local_eager"], 32)
+            for k in ["applies_per_s", "kernel_ms", "streamed_hbm_frac", "roofline"]:
+                f[k] = f["eager"][k]
+        if "fp32_local_full_space" in runs:
+            f["full_space"] = summarize(runs["fp32_local_full_space"], 32)
+            f["full_space"]["local_precision"] = "FP32 local factors and triangular solves"
+        out["fp32_local"] = f
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m["iters"])
     print(json.dumps(out), flush=True)

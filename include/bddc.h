@@ -75,9 +75,10 @@ enum { BDDC_SETUP_KEEP_ON_ERROR = 1 };
  * changes interior values).  Both give the same iterates in exact arithmetic;
  * the interior values of x are recovered once at the end by the interior
  * solves of eq. (5).  bddc_apply always applies the full three-part operator.
- * The interface operator is applied through the local factors, so it is only
- * used with FP64 local factors: with local_bits = 32 CG always runs on the
- * whole space, whose operator is the FP64 global matrix. */
+ * The interface operator and the interior solves come from the local factors
+ * and must be exact, so the interface form keeps FP64 factors also with
+ * local_bits = 32 and runs the preconditioner's local solves (there explicit
+ * interface matrices) in FP32; see bddc_options.local_bits. */
 enum { BDDC_SETUP_FULL_SPACE = 2 };
 
 /* Solve flags. */
@@ -108,8 +109,16 @@ typedef struct {
 } bddc_coefficients;
 
 typedef struct {
-  int32_t local_bits;   /* 64: local factors and solves in FP64; 32: in FP32
-                           (outer CG, r1, the coarse factor and solve stay FP64) */
+  int32_t local_bits;   /* 64: local factors and solves in FP64.  32: the
+                           preconditioner's local solves in FP32, with FP32
+                           accumulation; the outer CG, r1, the coarse factor and
+                           solve stay FP64.  With BDDC_SETUP_FULL_SPACE the local
+                           Cholesky factors and every triangular solve are FP32.
+                           In the interface form the factors are FP64 and the
+                           local solves of the preconditioner (the matrices X^T X
+                           and W_G^T X of eqs. (2)-(4) on the interface) are
+                           stored and applied in FP32; bddc_apply then applies
+                           the FP64 three-part operator. */
   int32_t use_graph;    /* 1: replay PCG iterations from a captured HIP graph   */
   int32_t nb_override;  /* 0 = default tile size (64); other values: ENOTIMPL   */
   void* stream;         /* hipStream_t for all work of this ctx                 */

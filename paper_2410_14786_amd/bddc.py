@@ -180,7 +180,7 @@ class Solver:
         box = sorted({tuple(int(c[i + 1] - c[i]) for i in range(len(c) - 1)) for c in
                       (np.asarray(cc) for cc in cuts[:dim])})
         self.tune_key = (f"dim{dim}|nel{'x'.join(map(str, self.nel))}|boxes{box}|bits{local_bits}|"
-                         f"{'full' if (full_space or local_bits == 32) else 'iface'}|graph{int(use_graph)}")
+                         f"{'full' if full_space else 'iface'}|graph{int(use_graph)}")
 
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:

@@ -94,7 +94,8 @@ struct GraphTimed {
 struct bddc_ctx {
   Plan plan;
   hipStream_t st = nullptr;
-  bool fp32 = false;
+  bool fp32 = false;                // local factors and triangular solves in FP32
+  bool pc32 = false;                // interface form: preconditioner matrices in FP32
   bool use_graph = false;
   bool iface = true;                // interface-restricted CG (see bddc.h)
   MeshDevHost mesh{};
@@ -130,6 +131,7 @@ struct bddc_ctx {
   int32_t *fcol = nullptr, *fcol_ii = nullptr, *lrow_rr = nullptr, *lrow_ii = nullptr;   // factor envelopes
   double* xg = nullptr;                        // inverses of the trailing factor blocks
   double *sg = nullptr, *hg = nullptr;         // interface form: Schur complements, X^T X (+ border rows)
+  float* hg32 = nullptr;                       // X^T X (+ border rows) in FP32 (pc32, instead of hg)
   double *symp = nullptr, *rowp = nullptr;     // their column / row partial products
   double *zpad = nullptr, *fpad = nullptr;     // D^{-1} z (+ corners) and W D r in padded rows
   double *cxg = nullptr, *cainv = nullptr, *upart = nullptr;   // explicit coarse inverse (interface form)
@@ -460,7 +462,8 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
   hipStream_t st = c->st;
   hipEvent_t ea = c->begin("apply");
   IfaceArgs a = iface_args(c);
-  a.m = c->hg;
+  a.m = c->pc32 ? static_cast<const void*>(c->hg32) : c->hg;
+  a.m32 = c->pc32 ? 1 : 0;
   a.trows = c->trows_pc;
   a.xpad = c->fpad;
   a.check_it = check_it;
@@ -757,13 +760,17 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
     launch_trailing_inverse(c->mats, P.nsubs, P.maxTG, static_cast<const double*>(c->tiles),
                             static_cast<const double*>(c->dinv), c->xg, st);
     if ((rc_ = c->alloc(c->sg, P.n_sg * NB * NB))) return rc_;
-    if ((rc_ = c->alloc(c->hg, P.n_sg * NB * NB))) return rc_;
+    if (c->pc32) {
+      if ((rc_ = c->alloc(c->hg32, P.n_sg * NB * NB))) return rc_;
+    } else if ((rc_ = c->alloc(c->hg, P.n_sg * NB * NB))) {
+      return rc_;
+    }
     if ((rc_ = c->alloc(c->symp, P.n_sg * NB))) return rc_;
     if ((rc_ = c->alloc(c->rowp, P.n_sg * 4 * NB))) return rc_;
     launch_sym_build(SYM_OP, c->mats, P.nsubs, P.maxTS, static_cast<const double*>(c->tiles), c->xg, c->cpp, c->sg,
-                     st);
-    launch_sym_build(SYM_PC, c->mats, P.nsubs, P.maxTS, static_cast<const double*>(c->tiles), c->xg, c->cpp, c->hg,
-                     st);
+                     false, st);
+    launch_sym_build(SYM_PC, c->mats, P.nsubs, P.maxTS, static_cast<const double*>(c->tiles), c->xg, c->cpp,
+                     c->pc32 ? static_cast<void*>(c->hg32) : c->hg, c->pc32, st);
   }
 
   // coarse problem
@@ -908,16 +915,20 @@ int bddc_setup(const bddc_mesh* mesh, const bddc_partition* part, const bddc_coe
       }
   }
   c->st = static_cast<hipStream_t>(opts->stream);
-  c->fp32 = opts->local_bits == 32;
   c->use_graph = opts->use_graph != 0;
-  // the interface operator is applied through the local factors, so it is exact
-  // only with FP64 factors; FP32 local factors iterate on the whole space, where
-  // the operator is the FP64 global matrix
-  c->iface = !(opts->flags & BDDC_SETUP_FULL_SPACE) && !c->fp32;
+  c->iface = !(opts->flags & BDDC_SETUP_FULL_SPACE);
   // the interface mat-vec packs a tile's row distance into 8 bits: at most
   // IFACE_MAX_TS tile rows per subdomain; larger boxes iterate on the whole space
   for (auto& D : c->plan.subs)
     if (sym_tile_rows(D) > IFACE_MAX_TS) c->iface = false;
+  // FP32 local solves: on the whole space the local factors and triangular
+  // solves are FP32 (the operator there is the FP64 global matrix).  The
+  // interface operator and the interior solves come from the local factors and
+  // must be exact, so the interface form keeps FP64 factors and applies the
+  // preconditioner's local solves, its explicit matrices, in FP32.
+  const bool local32 = opts->local_bits == 32;
+  c->fp32 = local32 && !c->iface;
+  c->pc32 = local32 && c->iface;
   c->mesh.dim = c->plan.dim;
   for (int a = 0; a < 3; ++a) {
     c->mesh.nel[a] = int(c->plan.nel[a]);

@@ -74,7 +74,8 @@ struct PcgScalars {
 
 struct IfaceArgs {
   const MatDesc* mats;
-  const double* m;          // symmetric interface matrices, one stream of ntiles tiles
+  const void* m;            // symmetric interface matrices, one stream of ntiles tiles
+  int m32;                  // their elements: 0 double, 1 float (applied with FP32 accumulation)
   const int32_t* tinfo;     // per tile: (global row << 8) | (ii - jj)
   const int32_t* trows;     // per tile: rows to read, h | z0 << 8 | z1 << 16 (rows r < h outside [z0, z1))
   int64_t ntiles;
@@ -190,8 +191,9 @@ void launch_gather_sp_ifc(const IfcArgs& a, hipStream_t st);
 void launch_pcg_update_ifc(const IfcArgs& a, hipStream_t st);
 void launch_scatter_f_ifc(const IfcArgs& a, hipStream_t st);
 enum { SYM_OP = 0, SYM_PC = 1 };
+// out32: write the matrices as float (the preconditioner's only)
 void launch_sym_build(int mode, const MatDesc* mats, int nmats, int maxTS, const double* tiles, const double* xg,
-                      const double* cpp, double* out, hipStream_t st);
+                      const double* cpp, void* out, bool out32, hipStream_t st);
 void launch_sym_mv(const IfaceArgs& a, hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_op_finish(const IfaceArgs& a, hipStream_t st);
 void launch_pc_finish(const IfaceArgs& a, hipStream_t st);

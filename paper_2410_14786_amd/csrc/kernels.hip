@@ -1503,9 +1503,9 @@ __device__ void load_k_tile(double* dst, const MatDesc& D, const double* tiles, 
   }
 }
 
-template <int MODE>
+template <int MODE, typename TO>
 __global__ __launch_bounds__(256) void sym_build_kernel(const MatDesc* mats, const double* tiles, const double* xg,
-                                                         const double* cpp, double* out) {
+                                                         const double* cpp, TO* out) {
   const int s = blockIdx.y;
   const MatDesc D = mats[s];
   const int TS = sym_tile_rows(D), nG = D.n_R - D.n_I;
@@ -1537,7 +1537,7 @@ __global__ __launch_bounds__(256) void sym_build_kernel(const MatDesc* mats, con
     __syncthreads();
     gemm_nt_tile<double>(sa, jj != ii ? sb : sa, acc);
   }
-  double* o = out + (D.sg_off + pidx) * int64_t(NB * NB);
+  TO* o = out + (D.sg_off + pidx) * int64_t(NB * NB);
   const double* m = cpp + int64_t(s) * MAX_NCI * MAX_NCI;
   const int p0 = nG + D.n_A, p1 = nG + D.n_ci;   // corner rows
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1549,46 +1549,41 @@ __global__ __launch_bounds__(256) void sym_build_kernel(const MatDesc* mats, con
         double v = acc[p][q][it];
         const int R = ii * NB + r, C = jj * NB + c;
         if (MODE == SYM_OP && R >= p0 && R < p1 && C >= p0 && C < p1) v += m[(R - p0) * MAX_NCI + (C - p0)];
-        o[r * NB + c] = v;
+        o[r * NB + c] = TO(v);
       }
 }
 
 void launch_sym_build(int mode, const MatDesc* mats, int nmats, int maxTS, const double* tiles, const double* xg,
-                      const double* cpp, double* out, hipStream_t st) {
+                      const double* cpp, void* out, bool out32, hipStream_t st) {
   if (maxTS <= 0 || nmats <= 0) return;   // no interface (a single subdomain)
   const dim3 grid(unsigned(tri_tile(maxTS, 0)), nmats);
   if (mode == SYM_OP)
-    hipLaunchKernelGGL(sym_build_kernel<SYM_OP>, grid, dim3(256), 0, st, mats, tiles, xg, cpp, out);
+    hipLaunchKernelGGL((sym_build_kernel<SYM_OP, double>), grid, dim3(256), 0, st, mats, tiles, xg, cpp,
+                       static_cast<double*>(out));
+  else if (out32)
+    hipLaunchKernelGGL((sym_build_kernel<SYM_PC, float>), grid, dim3(256), 0, st, mats, tiles, xg, cpp,
+                       static_cast<float*>(out));
   else
-    hipLaunchKernelGGL(sym_build_kernel<SYM_PC>, grid, dim3(256), 0, st, mats, tiles, xg, cpp, out);
+    hipLaunchKernelGGL((sym_build_kernel<SYM_PC, double>), grid, dim3(256), 0, st, mats, tiles, xg, cpp,
+                       static_cast<double*>(out));
 }
 
-// Sum over the eight lanes l ^ (0..7) (lane bits 0..2) without the LDS crossbar:
-// two quad permutations, then the mirror inside each half-row of eight lanes
-// (after the first two steps every lane of a quad holds the quad's sum).
+// Lane reductions of the interface mat-vec (no LDS crossbar).  A double moves
+// as two 32-bit halves.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
   const int lo = __double2loint(v), hi = __double2hiint(v);
   return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false),
                           __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false));
 }
-__device__ __forceinline__ double sum_cp(double v) {
-  v += dpp_f64<0xB1>(v);    // quad permutation [1,0,3,2]
-  v += dpp_f64<0x4E>(v);    // quad permutation [2,3,0,1]
-  v += dpp_f64<0x141>(v);   // mirror inside each half-row
-  return v;
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
-
-// Sum over the lanes l, l^8, l^16, ... l^56 (lane bits 3..5) without the LDS
-// crossbar: bit 3 by a DPP rotation by 8 inside each row of 16 lanes, bits 4
-// and 5 by the row and half-wave swaps (each swap returns both halves, whose
-// sum is the same in every lane).
-__device__ __forceinline__ double sum_rg(double v) {
+// the sum over lane bits 4 and 5 by the row and half-wave swaps (each swap
+// returns both halves, whose sum is the same in every lane)
+__device__ __forceinline__ double sum_hi_bits(double v) {
   int lo = __double2loint(v), hi = __double2hiint(v);
-  v += __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, 0x128, 0xf, 0xf, false),
-                        __builtin_amdgcn_update_dpp(0, lo, 0x128, 0xf, 0xf, false));
-  lo = __double2loint(v);
-  hi = __double2hiint(v);
   auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
   auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
   v = __hiloint2double(ph[0], pl[0]) + __hiloint2double(ph[1], pl[1]);
@@ -1598,6 +1593,53 @@ __device__ __forceinline__ double sum_rg(double v) {
   ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
   return __hiloint2double(ph[0], pl[0]) + __hiloint2double(ph[1], pl[1]);
 }
+__device__ __forceinline__ float sum_hi_bits(float v) {
+  auto p = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+  v = __int_as_float(p[0]) + __int_as_float(p[1]);
+  p = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+  return __int_as_float(p[0]) + __int_as_float(p[1]);
+}
+// FP64 layout: the sum over lane bits 0..2 (two quad permutations, then the
+// mirror inside each half-row of eight lanes: after the first two steps every
+// lane of a quad holds the quad's sum) and over lane bits 3..5 (a rotation by
+// 8 inside each row of 16 lanes, then the swaps).
+__device__ __forceinline__ double sum_cp(double v) {
+  v += dpp_f64<0xB1>(v);    // quad permutation [1,0,3,2]
+  v += dpp_f64<0x4E>(v);    // quad permutation [2,3,0,1]
+  v += dpp_f64<0x141>(v);   // mirror inside each half-row
+  return v;
+}
+__device__ __forceinline__ double sum_rg(double v) {
+  v += dpp_f64<0x128>(v);   // row rotation by 8
+  return sum_hi_bits(v);
+}
+// FP32 layout: the sum over lane bits 0..1 (the quad permutations) and over
+// lane bits 2..5 (rotations by 4 and 8 inside each row, then the swaps).
+__device__ __forceinline__ float sum_cp(float v) {
+  v += dpp_f32<0xB1>(v);
+  v += dpp_f32<0x4E>(v);
+  return v;
+}
+__device__ __forceinline__ float sum_rg(float v) {
+  v += dpp_f32<0x124>(v);   // row rotation by 4
+  v += dpp_f32<0x128>(v);   // row rotation by 8
+  return sum_hi_bits(v);
+}
+
+// Lane layout of the interface mat-vec for matrix elements of type T: a lane
+// loads VEC consecutive columns (16 bytes), CPL lanes cover the 16 columns of
+// a wave, and lane = CPL * rg + cp holds rows rg + RG t (t < KR).  Products
+// accumulate in T (an FP32 matrix is applied with FP32 accumulation); the
+// partial results are stored in FP64.
+template <typename T> struct SymLayout;
+template <> struct SymLayout<double> {
+  using V = d2v;
+  static constexpr int VEC = 2, CPL = 8, RG = 8, KR = 8;
+};
+template <> struct SymLayout<float> {
+  using V = f4v;
+  static constexpr int VEC = 4, CPL = 4, RG = 16, KR = 4;
+};
 
 // y = M v for the symmetric interface matrices, all subdomains at once.  The
 // launch splits the tile stream into equal contiguous ranges (no tickets, no
@@ -1609,18 +1651,19 @@ __device__ __forceinline__ double sum_rg(double v) {
 // the column product.  Output row k of a subdomain is then its row product plus
 // the column products of the tiles (i, k), i >= k.  Inputs come from padded
 // per-row vectors (zero where a row has no interface dof).
-// Wave w owns columns 16w..16w+15 of every tile; lane = 8 * rg + cp holds rows
-// rg + 8t (t < 8) of columns 16w + 2cp, +1, so a column product reduces over the
-// eight rg lanes of one wave and a row product over the eight cp lanes.  Rows
-// that hold nothing are not read: past the matrix's last row, in a zero row
-// range (the average-constraint rows of the operator), and in a diagonal tile
-// the row blocks above wave w's columns.
-constexpr int SYM_UNROLL = 1;
-// tile descriptors are uniform per wave and read-only: scalar loads (constant
-// address space), which complete independently of the vector memory counter
+// Wave w owns columns 16w..16w+15 of every tile (lane layout: SymLayout), so a
+// column product reduces over the RG row-group lanes of one wave and a row
+// product over the CPL column lanes.  Rows that hold nothing are not read: past
+// the matrix's last row, in a zero row range (the average-constraint rows of the
+// operator), and in a diagonal tile the row blocks above wave w's columns.
+// Tile descriptors are uniform per wave and read-only: scalar loads (constant
+// address space), which complete independently of the vector memory counter.
 typedef __attribute__((address_space(4))) const int32_t cint32_t;
+template <typename T>
 __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
-  using V = d2v;
+  using L = SymLayout<T>;
+  using V = typename L::V;
+  constexpr int VEC = L::VEC, CPL = L::CPL, RG = L::RG, KR = L::KR;
   if (A.sc->done) return;
   if (A.check_it >= 0) {
     // the convergence decision of CG iteration check_it, taken by every
@@ -1641,100 +1684,99 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
     if (bad || conv) return;
   }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rg = lane >> 3, cp = lane & 7;
-  const int col = 16 * w + 2 * cp;
+  const int rg = lane / CPL, cp = lane % CPL;
+  const int col = 16 * w + VEC * cp;
   const int64_t N = A.ntiles, G = gridDim.x;
   const int64_t t0 = blockIdx.x * N / G, t1 = (blockIdx.x + 1) * N / G;
   if (t0 >= t1) return;
+  const T* mat = static_cast<const T*>(A.m);
   const double* xv = A.xpad;
   const cint32_t* tinfo = (const cint32_t*)(A.tinfo);
   const cint32_t* trows = (const cint32_t*)(A.trows);
   int cur_row = tinfo[t0] >> 8;
   int64_t pstart = t0;
-  double xi[8], racc[8];
-  for (int t = 0; t < 8; ++t) {
-    xi[t] = xv[int64_t(cur_row) * NB + rg + 8 * t];
-    racc[t] = 0.0;
+  T xi[KR], racc[KR];
+  for (int t = 0; t < KR; ++t) {
+    xi[t] = T(xv[int64_t(cur_row) * NB + rg + RG * t]);
+    racc[t] = T(0);
   }
   auto flush = [&]() {
-    for (int t = 0; t < 8; ++t) {
-      const double v = sum_cp(racc[t]);
-      if (cp == 0) A.rowp[(pstart * 4 + w) * NB + rg + 8 * t] = v;
-      racc[t] = 0.0;
+    for (int t = 0; t < KR; ++t) {
+      const T v = sum_cp(racc[t]);
+      if (cp == 0) A.rowp[(pstart * 4 + w) * NB + rg + RG * t] = double(v);
+      racc[t] = T(0);
     }
   };
-  // the tile descriptors run one batch ahead, so that every load of a batch
-  // (tiles, inputs, the inputs of a row that starts in it) issues at once
-  int inf_next[SYM_UNROLL], rws_next[SYM_UNROLL];
-  for (int u = 0; u < SYM_UNROLL; ++u) {
-    inf_next[u] = tinfo[min(t0 + u, t1 - 1)];
-    rws_next[u] = trows[min(t0 + u, t1 - 1)];
-  }
-  for (int64_t t = t0; t < t1; t += SYM_UNROLL) {
-    V b[SYM_UNROLL][8];
-    V xx[SYM_UNROLL];
-    double xn[SYM_UNROLL][8];
-    int inf[SYM_UNROLL];
-    for (int u = 0; u < SYM_UNROLL; ++u) inf[u] = inf_next[u];
-    for (int u = 0; u < SYM_UNROLL; ++u) {
-      const int64_t tt = min(t + u, t1 - 1);   // past the range end: the last tile again
-      const double* p = A.m + tt * (NB * NB) + rg * NB + col;
+  // the tile descriptors run one tile ahead, so that every load of a tile (its
+  // elements, its inputs, the inputs of a row that starts at it) issues at once
+  int inf_next = tinfo[t0], rws_next = trows[t0];
+  for (int64_t t = t0; t < t1; ++t) {
+    const int inf = inf_next, rws = rws_next;
+    const int row = inf >> 8, d = inf & 255;
+    V b[KR];
+    {
+      const T* p = mat + t * (NB * NB) + rg * NB + col;
       // rows kept: r < h, outside [z0, z1), and (diagonal tile) r >= 16 w
-      const int rws = rws_next[u], h = rws & 255, z0 = (rws >> 8) & 255, z1 = rws >> 16;
-      const int rmin = (inf[u] & 255) == 0 ? 16 * w : 0;
-      for (int k = 0; k < 8; ++k) {
-        const int r = rg + 8 * k;
-        V v;
-        v[0] = 0.0;
-        v[1] = 0.0;
-        if (r < h && r >= rmin && (r < z0 || r >= z1)) v = *reinterpret_cast<const V*>(p + k * 8 * NB);
-        b[u][k] = v;
+      const int h = rws & 255, z0 = (rws >> 8) & 255, z1 = rws >> 16;
+      const int rmin = d == 0 ? 16 * w : 0;
+      for (int k = 0; k < KR; ++k) {
+        const int r = rg + RG * k;
+        V v = V(T(0));
+        if (r < h && r >= rmin && (r < z0 || r >= z1)) v = *reinterpret_cast<const V*>(p + k * RG * NB);
+        b[k] = v;
       }
     }
-    for (int u = 0; u < SYM_UNROLL; ++u) {
-      const int row = inf[u] >> 8, d = inf[u] & 255;
-      xx[u] = *reinterpret_cast<const V*>(xv + int64_t(row - d) * NB + col);
-      const int prev = u == 0 ? cur_row : (inf[u - 1] >> 8);
-      if (row != prev)
-        for (int k = 0; k < 8; ++k) xn[u][k] = xv[int64_t(row) * NB + rg + 8 * k];
+    T xx[VEC];
+    for (int j = 0; j < VEC; j += 2) {
+      const d2v x2 = *reinterpret_cast<const d2v*>(xv + int64_t(row - d) * NB + col + j);
+      xx[j] = T(x2[0]);
+      xx[j + 1] = T(x2[1]);
     }
-    for (int u = 0; u < SYM_UNROLL; ++u) {
-      const int64_t tn = min(t + SYM_UNROLL + u, t1 - 1);
-      inf_next[u] = tinfo[tn];
-      rws_next[u] = trows[tn];
+    double xn[KR];
+    if (row != cur_row)
+      for (int k = 0; k < KR; ++k) xn[k] = xv[int64_t(row) * NB + rg + RG * k];
+    {
+      const int64_t tn = min(t + 1, t1 - 1);
+      inf_next = tinfo[tn];
+      rws_next = trows[tn];
     }
-    for (int u = 0; u < SYM_UNROLL; ++u) {
-      if (t + u >= t1) break;
-      const int row = inf[u] >> 8, d = inf[u] & 255;
-      if (row != cur_row) {
-        flush();
-        pstart = t + u;
-        cur_row = row;
-        for (int k = 0; k < 8; ++k) xi[k] = xn[u][k];
+    if (row != cur_row) {
+      flush();
+      pstart = t;
+      cur_row = row;
+      for (int k = 0; k < KR; ++k) xi[k] = T(xn[k]);
+    }
+    T c[VEC];
+    for (int j = 0; j < VEC; ++j) c[j] = T(0);
+    if (d > 0) {
+      for (int k = 0; k < KR; ++k) {
+        T s = b[k][0] * xx[0];
+        for (int j = 1; j < VEC; ++j) s += b[k][j] * xx[j];
+        racc[k] += s;
+        for (int j = 0; j < VEC; ++j) c[j] += b[k][j] * xi[k];
       }
-      double c0 = 0.0, c1 = 0.0;
-      if (d > 0) {
-        for (int k = 0; k < 8; ++k) {
-          racc[k] += b[u][k][0] * xx[u][0] + b[u][k][1] * xx[u][1];
-          c0 += b[u][k][0] * xi[k];
-          c1 += b[u][k][1] * xi[k];
-        }
-      } else {
-        // diagonal tile: lower triangle (c <= r) in the row product, strict lower
-        // triangle (c < r) in the column product
-        for (int k = 0; k < 8; ++k) {
-          const int r = rg + 8 * k;
-          const double m0 = col <= r ? b[u][k][0] : 0.0, m1 = col + 1 <= r ? b[u][k][1] : 0.0;
-          racc[k] += m0 * xx[u][0] + m1 * xx[u][1];
-          c0 += (col < r ? m0 : 0.0) * xi[k];
-          c1 += (col + 1 < r ? m1 : 0.0) * xi[k];
-        }
+    } else {
+      // diagonal tile: lower triangle (c <= r) in the row product, strict lower
+      // triangle (c < r) in the column product
+      for (int k = 0; k < KR; ++k) {
+        const int r = rg + RG * k;
+        T m[VEC];
+        for (int j = 0; j < VEC; ++j) m[j] = col + j <= r ? b[k][j] : T(0);
+        T s = m[0] * xx[0];
+        for (int j = 1; j < VEC; ++j) s += m[j] * xx[j];
+        racc[k] += s;
+        for (int j = 0; j < VEC; ++j) c[j] += (col + j < r ? m[j] : T(0)) * xi[k];
       }
-      V o;
-      o[0] = sum_rg(c0);
-      o[1] = sum_rg(c1);
-      if (rg == 0) *reinterpret_cast<V*>(A.part + (t + u) * NB + col) = o;
     }
+    double o[VEC];
+    for (int j = 0; j < VEC; ++j) o[j] = double(sum_rg(c[j]));
+    if (rg == 0)
+      for (int j = 0; j < VEC; j += 2) {
+        d2v o2;
+        o2[0] = o[j];
+        o2[1] = o[j + 1];
+        *reinterpret_cast<d2v*>(A.part + t * NB + col + j) = o2;
+      }
   }
   flush();
 }
@@ -1825,7 +1867,8 @@ __global__ __launch_bounds__(256) void pc_finish_kernel(IfaceArgs A) {
     double v = 0.0;
     for (int c = w; c < nci; c += 4) {
       const int R = nG + c;
-      v += A.m[(D.sg_off + tri_tile(R / NB, ii)) * int64_t(NB * NB) + (R % NB) * NB + lane] * cf[c];
+      const int64_t e = (D.sg_off + tri_tile(R / NB, ii)) * int64_t(NB * NB) + (R % NB) * NB + lane;
+      v += (A.m32 ? double(static_cast<const float*>(A.m)[e]) : static_cast<const double*>(A.m)[e]) * cf[c];
     }
     s_red[w][lane] += v;
   }
@@ -1840,7 +1883,8 @@ __global__ __launch_bounds__(256) void pc_finish_kernel(IfaceArgs A) {
 
 void launch_sym_mv(const IfaceArgs& a, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
   if (a.ntiles <= 0 || a.nwg <= 0) return;
-  launch_timed(sym_mv_kernel, dim3(a.nwg), dim3(256), st, t0, t1, a);
+  if (a.m32) launch_timed(sym_mv_kernel<float>, dim3(a.nwg), dim3(256), st, t0, t1, a);
+  else launch_timed(sym_mv_kernel<double>, dim3(a.nwg), dim3(256), st, t0, t1, a);
 }
 
 void launch_op_finish(const IfaceArgs& a, hipStream_t st) {

@@ -197,9 +197,36 @@ def test_fp32_local_reaches_true_residual(name, full_space):
     S.close()
 
 
+@pytest.mark.parametrize("name", ["3d_12x10x14_uneven", "3d_24_3x3x3_inclusions", "2d_20x24_uneven"])
+def test_fp32_local_interface_iterates_close_to_oracle(name):
+    """Interface form with the preconditioner's local solves in FP32: the same
+    operator as the oracle's up to the FP32 rounding of its matrices and sums
+    (relative error of a local product <= n u32, n <= 2000, u32 = 6e-8, so about
+    1e-4 at worst), so K iterates, the iteration count and the Lanczos estimate
+    stay that close to the oracle's FP64 run."""
+    w, P = oracle_for(name)
+    ref = O.bddc_pcg(P, w.b, w.rtol)
+    S = bd().solver_for(w, local_bits=32)
+    K = max(ref.iters - 2, 1)
+    refK = O.bddc_pcg(P, w.b, 1e-300, maxit=K)
+    xK, info = S.solve(dev(w.b), 1e-15, maxit=K, raise_on_noconv=False)
+    e = rel(host(xK), refK.x)
+    say(name, "fp32-local interface K", K, "iterate rel err", e)
+    assert info["iters"] == K
+    assert e <= 1e-4
+    x, info = S.solve(dev(w.b), w.rtol)
+    say(name, "iters gpu", info["iters"], "oracle", ref.iters, "relres", info["relres_true"],
+        "cond", info["cond_est"], ref.cond_est)
+    assert abs(info["iters"] - ref.iters) <= 1
+    assert info["relres_true"] <= w.rtol
+    assert abs(info["cond_est"] - ref.cond_est) <= 1e-4 * ref.cond_est
+    S.close()
+
+
 def test_fp32_local_apply_close_to_oracle():
     w, P = oracle_for("3d_16_2x2x2")
-    S = bd().solver_for(w, local_bits=32)
+    # the three-part apply with FP32 local factors (whole-space form)
+    S = bd().solver_for(w, local_bits=32, full_space=True)
     r = np.random.default_rng(3).standard_normal(P.n)
     e = rel(host(S.apply(dev(r))), P.apply(r))
     say("fp32-local apply rel err", e)

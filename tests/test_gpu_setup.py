@@ -45,7 +45,9 @@ def test_local_setup_against_numpy(case, bits):
     name, make = case
     w = make()
     P = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints)
-    S = bddc.Solver(w.dim, w.nel, w.cuts, w.theta, w.constraints, local_bits=bits)
+    # FP32 local factors exist in the whole-space form (the interface form keeps
+    # FP64 factors and runs only the preconditioner's local solves in FP32)
+    S = bddc.Solver(w.dim, w.nel, w.cuts, w.theta, w.constraints, local_bits=bits, full_space=bits == 32)
     eps = np.finfo(np.float64 if bits == 64 else np.float32).eps
     for sub in range(min(S.n_sub, 4)):
         s = P.subs[sub]
