@@ -27,6 +27,14 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
+// Factor and interface-matrix tiles are read once per pass and not again
+// before the whole stream has gone by: non-temporal loads, so that they do not
+// displace the vectors and partial results that are reused from the caches.
+template <typename V>
+__device__ __forceinline__ V stream_load(const V* p) {
+  return __builtin_nontemporal_load(p);
+}
+
 template <typename T> struct Traits;
 template <> struct Traits<double> {
   using U = unsigned long long;
@@ -793,7 +801,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     V dv[NI];
     {
       const T* dt = dinv + (D.dinv_off + k) * int64_t(NB * NB) + lane_off;
-      for (int i = 0; i < NI; ++i) dv[i] = *reinterpret_cast<const V*>(dt + i * STEP);
+      for (int i = 0; i < NI; ++i) dv[i] = stream_load(reinterpret_cast<const V*>(dt + i * STEP));
     }
 
     // ---------------- main loop over off-diagonal tiles ----------------
@@ -814,7 +822,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
       V cur[NI], nxt[NI];
       {
         const T* p = tile_ptr(0);
-        for (int i = 0; i < NI; ++i) cur[i] = *reinterpret_cast<const V*>(p + i * STEP);
+        for (int i = 0; i < NI; ++i) cur[i] = stream_load(reinterpret_cast<const V*>(p + i * STEP));
       }
       for (int jj = 0; jj < nt; ++jj) {
         const T* ys = my_sol + sol_row(jj) * NB;
@@ -826,7 +834,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
         }
         if (jj + 1 < nt) {
           const T* p = tile_ptr(jj + 1);
-          for (int i = 0; i < NI; ++i) nxt[i] = *reinterpret_cast<const V*>(p + i * STEP);
+          for (int i = 0; i < NI; ++i) nxt[i] = stream_load(reinterpret_cast<const V*>(p + i * STEP));
         }
         if (FWD) {
           for (int i = 0; i < NI; ++i)
@@ -1722,7 +1730,7 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
       for (int k = 0; k < KR; ++k) {
         const int r = rg + RG * k;
         V v = V(T(0));
-        if (r < h && r >= rmin && (r < z0 || r >= z1)) v = *reinterpret_cast<const V*>(p + k * RG * NB);
+        if (r < h && r >= rmin && (r < z0 || r >= z1)) v = stream_load(reinterpret_cast<const V*>(p + k * RG * NB));
         b[k] = v;
       }
     }
