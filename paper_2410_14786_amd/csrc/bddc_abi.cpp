@@ -160,7 +160,12 @@ struct bddc_ctx {
   std::vector<hipGraph_t> graph_defs;
   std::vector<std::vector<GraphTimed>> graph_timed;
   double* xw = nullptr;
-  int* hsnap = nullptr;               // pinned host copies of (done, iters), two slots
+  // mapped pinned host memory: the word the iteration sets when the solve ends,
+  // and the scalars read back at the end of a CG segment (5 + 3 MAX_PCG_IT)
+  int* hdone = nullptr;
+  int* hdone_dev = nullptr;
+  double* hback = nullptr;
+  double* hback_dev = nullptr;
   hipEvent_t snap_ev[2] = {nullptr, nullptr};
 
   bool timing = false;
@@ -180,7 +185,8 @@ struct bddc_ctx {
     if (ev_in) hipEventDestroy(ev_in);
     for (hipEvent_t e : snap_ev)
       if (e) hipEventDestroy(e);
-    if (hsnap) hipHostFree(hsnap);
+    if (hdone) hipHostFree(hdone);
+    if (hback) hipHostFree(hback);
     if (ev_out) hipEventDestroy(ev_out);
     if (gst) hipStreamDestroy(gst);
     for (auto& kv : fam)
@@ -467,6 +473,7 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
   a.trows = c->trows_pc;
   a.xpad = c->fpad;
   a.check_it = check_it;
+  a.hdone = check_it >= 0 ? c->hdone_dev : nullptr;
   a.part_rr = c->part_b;
   a.nparts_rr = ifc_blocks(int64_t(P.ifc_g.size()));
   {
@@ -576,7 +583,7 @@ void enqueue_iteration(bddc_ctx* c, double* x, int it, bool fresh) {
     enqueue_apply_iface(c, c->r, c->z, c->part_c, done, it);
   } else {
     launch_pcg_update(x, c->r, c->p, c->q, c->part_a, c->part_b, c->sc, it, n, st);
-    launch_pcg_check(c->part_b, c->sc, it, st);
+    launch_pcg_check(c->part_b, c->sc, it, c->hdone_dev, st);
     enqueue_apply(c, c->r, c->z, done);
     launch_dot(c->r, c->z, c->part_c, n, done, st);
   }
@@ -837,7 +844,12 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->alloc(c->fpad, P.n_symrows * NB + 1))) return rc_;
   launch_fill<double>(c->zpad, 0.0, P.n_symrows * NB + 1, st);
   launch_fill<double>(c->fpad, 0.0, P.n_symrows * NB + 1, st);
-  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hsnap), 4 * sizeof(int), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hdone), sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+  HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hdone_dev), c->hdone, 0));
+  *c->hdone = 0;
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hback), (5 + 3 * size_t(MAX_PCG_IT)) * sizeof(double),
+                        hipHostMallocMapped | hipHostMallocCoherent));
+  HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hback_dev), c->hback, 0));
   for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreateWithFlags(&c->snap_ev[i], hipEventDisableTiming));
   if ((rc_ = c->alloc(c->sploc, P.n_loc))) return rc_;
   for (auto& D : P.subs) c->max_loclen = std::max(c->max_loclen, int(D.T * NB + D.n_P));
@@ -996,10 +1008,9 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
   }
   if (iface) {
     // interface unknowns: x holds the interface part (interior zero) during the
-    // iteration; the residual lives on interface dofs
-    launch_fill<double>(c->z, 0.0, n, st);
-    launch_fill<double>(c->p, 0.0, n, st);
-    launch_fill<double>(c->q, 0.0, n, st);
+    // iteration; the residual lives on interface dofs (z, p and q are only
+    // touched on interface dofs, and the first iteration of a segment does not
+    // read p or q)
     if (flags & BDDC_X0_GIVEN) {
       launch_zero_interior(c->kappa, x, n, st);
       enqueue_interior_complete(c, b, x, c->tmp);
@@ -1020,10 +1031,11 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
   int restarts = 0;
   int status = BDDC_OK;
   double relres_true = 0.0, relres_rec = 0.0;
-  const int chunk = 4;
   bool fresh = true;
   int seg_start = 0;
+  volatile int* const hdone = c->hdone;
   for (;;) {
+    *hdone = 0;   // nothing of this ctx is in flight here
     // (re)start: z = M^{-1} r, rz
     if (iface) {
       launch_reset(false, nullptr, 0, c->pub_coarse, 2 * int64_t(c->Tc) * NB, c->tickets, done, st);
@@ -1033,64 +1045,51 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
       enqueue_apply(c, c->r, c->z, done);
       launch_dot(c->r, c->z, c->part_c, n, done, st);
     }
-    // Chunks of iterations are queued one ahead of the convergence check: after
-    // each chunk the (done, iters) words are copied to pinned host memory and an
-    // event is recorded; the host waits for chunk k's event only once chunk k+1
-    // is queued.  Kernels of a converged solve return at once.
+    // Iterations are queued at most two steps (one iteration eagerly, one graph
+    // chunk with graphs) ahead of the last step the host has seen complete, and
+    // no further once the iteration has set the host's end-of-solve word; the
+    // kernels of a converged solve return at once.
     int pending = 0, slot_w = 0, slot_r = 0;
     for (;;) {
-      while (pending < 2 && it < maxit) {
-        const int end = std::min(maxit, it + chunk);
+      while (pending < 2 && it < maxit && !*hdone) {
         // per-kernel timing needs eager launches (events are not captured into graphs)
         if (c->use_graph && !c->timing && fresh == (it == 0) && it % bddc_ctx::GRAPH_CHUNK == 0 &&
             it + bddc_ctx::GRAPH_CHUNK <= maxit && seg_start == 0) {
           if (int rc_ = launch_chunk_graph(c, x, it / bddc_ctx::GRAPH_CHUNK)) return rc_;
           it += bddc_ctx::GRAPH_CHUNK;
-          fresh = false;
         } else {
-          for (; it < end; ++it) {
-            enqueue_iteration(c, x, it, fresh);
-            fresh = false;
-          }
+          enqueue_iteration(c, x, it, fresh);
+          ++it;
         }
+        fresh = false;
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(c->hsnap + 2 * slot_w, &c->sc->done, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipEventRecord(c->snap_ev[slot_w], st));
         slot_w ^= 1;
         ++pending;
       }
-      if (pending == 0) break;
+      if (pending == 0 || *hdone) break;
       HIP_TRY(hipEventSynchronize(c->snap_ev[slot_r]));
-      const int flag = c->hsnap[2 * slot_r];
       slot_r ^= 1;
       --pending;
-      if (flag) break;
     }
-    HIP_TRY(hipMemcpyAsync(&hs, c->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    const int iters = hs.iters;
-    // CG coefficients of this segment
-    if (iters > seg_start) {
-      std::vector<double> al(iters - seg_start), be(iters - seg_start);
-      HIP_TRY(hipMemcpy(al.data(), c->sc->alpha + seg_start, al.size() * sizeof(double), hipMemcpyDeviceToHost));
-      HIP_TRY(hipMemcpy(be.data(), c->sc->beta + seg_start, be.size() * sizeof(double), hipMemcpyDeviceToHost));
-      if (restarts == 0) {
-        alphas = al;
-        betas.assign(be.begin(), be.end() - 1);
-      }
-    }
-    double rr = 0.0;
-    if (iters > 0) HIP_TRY(hipMemcpy(&rr, c->sc->rr + iters - 1, sizeof(double), hipMemcpyDeviceToHost));
-    else rr = hs.rr0;
-    relres_rec = hs.bb > 0 ? std::sqrt(rr / hs.bb) : 0.0;
-    // interior values of x (interface form), then the true residual
+    // interior values of x (interface form) and the true residual, then every
+    // scalar the host needs, in one readback
     if (iface) enqueue_interior_complete(c, b, x, x);
     launch_residual(c->rowptr, c->col, c->val, x, b, c->tmp, c->part_a, c->part_b, n, st);
     launch_finish_dot(c->part_a, c->scal, st);
-    double rr_true = 0.0;
-    HIP_TRY(hipMemcpyAsync(&rr_true, c->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    launch_pack_readback(c->sc, c->scal, 0, it, c->hback_dev, st);
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
-    relres_true = hs.bb > 0 ? std::sqrt(rr_true / hs.bb) : 0.0;
+    const double* hb = c->hback;
+    std::memcpy(&hs, hb, sizeof(hs));
+    const int iters = hs.iters;
+    if (iters > seg_start && restarts == 0) {
+      alphas.assign(hb + 5, hb + 5 + iters);
+      betas.assign(hb + 5 + it, hb + 5 + it + iters - 1);
+    }
+    const double rr = iters > 0 ? hb[5 + 2 * it + iters - 1] : hs.rr0;
+    relres_rec = hs.bb > 0 ? std::sqrt(rr / hs.bb) : 0.0;
+    relres_true = hs.bb > 0 ? std::sqrt(hb[4] / hs.bb) : 0.0;
     if (hs.done == 2) { status = BDDC_EBREAKDOWN; break; }
     if (hs.done == 1 && relres_true <= rtol) { status = BDDC_OK; break; }
     if (it >= maxit) { status = BDDC_ENOCONV; break; }
@@ -1099,10 +1098,7 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
     ++restarts;
     launch_residual(c->rowptr, c->col, c->val, x, b, c->r, c->part_a, c->part_b, n, st,
                     iface ? c->kappa : nullptr);
-    if (iface) {
-      launch_zero_interior(c->kappa, x, n, st);
-      launch_fill<double>(c->p, 0.0, n, st);
-    }
+    if (iface) launch_zero_interior(c->kappa, x, n, st);
     launch_pcg_init(c->part_a, c->part_b, c->sc, rtol * rtol, st);
     // keep the iteration count across the restart
     fresh = true;

@@ -85,6 +85,7 @@ struct IfaceArgs {
   const PcgScalars* sc;
   const double* xpad;       // padded per-row input (64 per row): D^{-1} z + corners, or W D r
   int check_it;             // >= 0: first take the convergence decision of this CG iteration
+  int* hdone;               // mapped pinned host word set to 1 when that decision ends the solve
   const double* part_rr;    // its partial sums of r.r
   int nparts_rr;            // their count
   double* part;             // column products, 64 per tile
@@ -146,7 +147,11 @@ void launch_pcg_dir(const int32_t* rowptr, const int32_t* col, const double* val
                     hipStream_t st);
 void launch_pcg_update(double* x, double* r, const double* p, const double* q, const double* part_pq,
                        double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st);
-void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, hipStream_t st);
+// hdone: mapped pinned host word set to 1 when the solve ends (may be null)
+void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, int* hdone, hipStream_t st);
+// out: mapped pinned host memory of 5 + 3 n doubles
+void launch_pack_readback(const PcgScalars* sc, const double* rr_true, int seg, int n, double* out,
+                          hipStream_t st);
 void launch_dot(const double* a, const double* b, double* part, int64_t n, const int* done, hipStream_t st);
 void launch_finish_dot(const double* part, double* out, hipStream_t st);
 void launch_elem_grad(const MeshDevHost& m, const double* lam, const double* u, double* g, int64_t nel,

@@ -1272,7 +1272,14 @@ __global__ __launch_bounds__(VBLK) void pcg_update_kernel(double* x, double* r, 
 
 // finalise rr (convergence / breakdown decision) in a single block; later kernels
 // of the iteration see sc->done
-__global__ __launch_bounds__(VBLK) void pcg_check_kernel(const double* part_rr, PcgScalars* sc, int it) {
+// Tells the host that the solve has ended (a word of mapped pinned host memory;
+// a system-scope store, visible to the host once the kernel has completed).
+__device__ __forceinline__ void signal_host(int* hdone) {
+  if (hdone) __hip_atomic_store(hdone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ __launch_bounds__(VBLK) void pcg_check_kernel(const double* part_rr, PcgScalars* sc, int it,
+                                                         int* hdone) {
   __shared__ double sh[VBLK / 64];
   if (sc->done) return;
   const double rr = reduce_partials(part_rr, VGRID, sh);
@@ -1283,8 +1290,10 @@ __global__ __launch_bounds__(VBLK) void pcg_check_kernel(const double* part_rr, 
     if (!(pq > 0.0) || !(rz > 0.0) || !(rr == rr)) {
       sc->done = 2;
       sc->iters = it;     // the update of this iteration was not applied
+      signal_host(hdone);
     } else if (rr <= sc->tol2) {
       sc->done = 1;
+      signal_host(hdone);
     }
   }
 }
@@ -1335,8 +1344,35 @@ void launch_pcg_update(double* x, double* r, const double* p, const double* q, c
                        double* part_rr, PcgScalars* sc, int it, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(pcg_update_kernel, dim3(VGRID), dim3(VBLK), 0, st, x, r, p, q, part_pq, part_rr, sc, it, n);
 }
-void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, hipStream_t st) {
-  hipLaunchKernelGGL(pcg_check_kernel, dim3(1), dim3(VBLK), 0, st, part_rr, sc, it);
+// End of a CG segment: the scalars the host reads, written straight into mapped
+// pinned host memory (one launch instead of several copies): out[0..3] = tol2,
+// bb, rr0, (done, iters) as two ints; out[4] = the true r.r; then alpha, beta and
+// rr of iterations seg .. seg+n-1.
+__global__ void pack_readback_kernel(const PcgScalars* sc, const double* rr_true, int seg, int n, double* out) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    out[0] = sc->tol2;
+    out[1] = sc->bb;
+    out[2] = sc->rr0;
+    int* w = reinterpret_cast<int*>(out + 3);
+    w[0] = sc->done;
+    w[1] = sc->iters;
+    out[4] = *rr_true;
+  }
+  for (int i = t; i < n; i += blockDim.x) {
+    out[5 + i] = sc->alpha[seg + i];
+    out[5 + n + i] = sc->beta[seg + i];
+    out[5 + 2 * n + i] = sc->rr[seg + i];
+  }
+}
+
+void launch_pack_readback(const PcgScalars* sc, const double* rr_true, int seg, int n, double* out,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(pack_readback_kernel, dim3(1), dim3(256), 0, st, sc, rr_true, seg, n, out);
+}
+
+void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, int* hdone, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_check_kernel, dim3(1), dim3(VBLK), 0, st, part_rr, sc, it, hdone);
 }
 void launch_dot(const double* a, const double* b, double* part, int64_t n, const int* done, hipStream_t st) {
   hipLaunchKernelGGL(dot_kernel, dim3(VGRID), dim3(VBLK), 0, st, a, b, part, n, done);
@@ -1688,6 +1724,7 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
       sc->iters = bad ? it : it + 1;   // a breakdown leaves this iteration's update unapplied
       if (bad) sc->done = 2;
       else if (conv) sc->done = 1;
+      if (bad || conv) signal_host(A.hdone);
     }
     if (bad || conv) return;
   }
