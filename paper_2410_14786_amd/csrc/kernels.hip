@@ -35,6 +35,10 @@ __device__ __forceinline__ V stream_load(const V* p) {
   return __builtin_nontemporal_load(p);
 }
 
+// Offset of element (r, c) inside an FP32 interface-matrix tile: four blocks of
+// 16 columns, each 64 rows x 16 columns row-major (64 bytes per row).
+__host__ __device__ __forceinline__ int sym_f32_off(int r, int c) { return (c >> 4) * (NB * 16) + r * 16 + (c & 15); }
+
 template <typename T> struct Traits;
 template <> struct Traits<double> {
   using U = unsigned long long;
@@ -1593,7 +1597,7 @@ __global__ __launch_bounds__(256) void sym_build_kernel(const MatDesc* mats, con
         double v = acc[p][q][it];
         const int R = ii * NB + r, C = jj * NB + c;
         if (MODE == SYM_OP && R >= p0 && R < p1 && C >= p0 && C < p1) v += m[(R - p0) * MAX_NCI + (C - p0)];
-        o[r * NB + c] = TO(v);
+        o[sizeof(TO) == 4 ? sym_f32_off(r, c) : r * NB + c] = TO(v);
       }
 }
 
@@ -1760,14 +1764,18 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
     const int row = inf >> 8, d = inf & 255;
     V b[KR];
     {
-      const T* p = mat + t * (NB * NB) + rg * NB + col;
+      // FP64 tiles are row-major (a wave's 16 columns of a row: one 128-byte
+      // line); FP32 tiles are stored by 16-column blocks (sym_f32_off), so that a
+      // wave reads whole lines of its own block
+      constexpr int RS = sizeof(T) == 4 ? 16 : NB;   // row stride
+      const T* p = mat + t * (NB * NB) + (sizeof(T) == 4 ? sym_f32_off(0, 16 * w) + VEC * cp : col) + rg * RS;
       // rows kept: r < h, outside [z0, z1), and (diagonal tile) r >= 16 w
       const int h = rws & 255, z0 = (rws >> 8) & 255, z1 = rws >> 16;
       const int rmin = d == 0 ? 16 * w : 0;
       for (int k = 0; k < KR; ++k) {
         const int r = rg + RG * k;
         V v = V(T(0));
-        if (r < h && r >= rmin && (r < z0 || r >= z1)) v = stream_load(reinterpret_cast<const V*>(p + k * RG * NB));
+        if (r < h && r >= rmin && (r < z0 || r >= z1)) v = stream_load(reinterpret_cast<const V*>(p + k * RG * RS));
         b[k] = v;
       }
     }
@@ -1913,7 +1921,8 @@ __global__ __launch_bounds__(256) void pc_finish_kernel(IfaceArgs A) {
     for (int c = w; c < nci; c += 4) {
       const int R = nG + c;
       const int64_t e = (D.sg_off + tri_tile(R / NB, ii)) * int64_t(NB * NB) + (R % NB) * NB + lane;
-      v += (A.m32 ? double(static_cast<const float*>(A.m)[e]) : static_cast<const double*>(A.m)[e]) * cf[c];
+      const int64_t ef = e - (R % NB) * NB - lane + sym_f32_off(R % NB, lane);
+      v += (A.m32 ? double(static_cast<const float*>(A.m)[ef]) : static_cast<const double*>(A.m)[e]) * cf[c];
     }
     s_red[w][lane] += v;
   }
