@@ -1487,19 +1487,29 @@ __global__ __launch_bounds__(256) void coarse_gemv_kernel(const double* ainv, in
   if (done && *done) return;
   const int s = blockIdx.y;
   const int j0 = s * cs, j1 = min(nc, j0 + cs);
+  // one row per wave (the rows are independent, so many short chains in flight);
+  // the row is loaded while the coarse residual is assembled
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + w;
+  constexpr int PER_LANE = COARSE_SPLIT_COLS / 64;
+  double rv[PER_LANE];
+  {
+    const double* row = ainv + int64_t(min(i, nc - 1)) * nc;
+    for (int q = 0; q < PER_LANE; ++q) {
+      const int j = j0 + lane + 64 * q;
+      rv[q] = j < j1 ? row[j] : 0.0;
+    }
+  }
   for (int j = j0 + threadIdx.x; j < j1; j += 256) {
     double v = 0.0;
     for (int q = cinv_ptr[j]; q < cinv_ptr[j + 1]; ++q) v += gbuf[cinv[q]];
     rcs[j - j0] = v;
   }
   __syncthreads();
-  // one row per wave: the rows are independent, so many short chains in flight
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + w;
   if (i >= nc) return;
-  const double* row = ainv + int64_t(i) * nc;
   double v = 0.0;
-  for (int j = j0 + lane; j < j1; j += 64) v += row[j] * rcs[j - j0];
+  for (int q = 0; q < PER_LANE; ++q)
+    if (j0 + lane + 64 * q < j1) v += rv[q] * rcs[lane + 64 * q];
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   if (lane == 0) upart[int64_t(s) * nc + i] = v;
 }
@@ -1717,10 +1727,10 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
     // the convergence decision of CG iteration check_it, taken by every
     // workgroup from the same partial sums of r.r (workgroup 0 records it)
     __shared__ double sh[VBLK / 64];
-    const double rr = reduce_partials(A.part_rr, A.nparts_rr, sh);
     const int it = A.check_it;
     PcgScalars* sc = const_cast<PcgScalars*>(A.sc);
     const double pq = sc->pq[it], rz = sc->rz[it];
+    const double rr = reduce_partials(A.part_rr, A.nparts_rr, sh);
     const bool bad = !(pq > 0.0) || !(rz > 0.0) || !(rr == rr);
     const bool conv = rr <= sc->tol2;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1855,13 +1865,14 @@ __global__ __launch_bounds__(256) void op_finish_kernel(IfaceArgs A) {
   const int s = A.tasks[2 * blockIdx.x], ii = A.tasks[2 * blockIdx.x + 1];
   const MatDesc D = A.mats[s];
   const int TS = sym_tile_rows(D), nG = D.n_R - D.n_I, tid = threadIdx.x;
+  const int r = ii * NB + tid;
+  const double ds = tid < NB && r < nG ? A.dsc[D.loc_off + D.n_I + r] : 1.0;
   sum_row(A, D, ii, TS, s_red);
   __syncthreads();
   if (tid >= NB) return;
   const double y = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
-  const int r = ii * NB + tid;
   if (r < nG) {
-    A.sploc[D.loc_off + D.n_I + r] = y / A.dsc[D.loc_off + D.n_I + r];
+    A.sploc[D.loc_off + D.n_I + r] = y / ds;
   } else if (r - nG >= D.n_A && r - nG < D.n_ci) {
     A.sploc[D.loc_off + D.n_R + (r - nG - D.n_A)] = y;
   }
@@ -1885,8 +1896,29 @@ __global__ __launch_bounds__(256) void pc_finish_kernel(IfaceArgs A) {
   const bool rows = ii * NB < nG;   // uniform: this tile row holds interface rows
   if (!rows && ii != 0) return;
   const int nA = D.n_A, nP = D.n_P, nci = D.n_ci;
-  // partial sums of the output row first (independent of the coarse solution)
-  if (rows) sum_row(A, D, ii, TS, s_red);
+  // Everything that does not depend on the coarse solution is loaded first: the
+  // partial sums of the output row, the constraint rows M(n_G + c, r) for
+  // c = w, w + 4, ... (M(n_G + c, r) lies in tile ((n_G + c) / 64, ii)), the
+  // output weight.
+  constexpr int CPW = MAX_NCI / 4;
+  double mc[CPW];
+  double wdr = 0.0;
+  const int r_out = ii * NB + lane;
+  if (rows) {
+    sum_row(A, D, ii, TS, s_red);
+    for (int q = 0; q < CPW; ++q) {
+      const int c = w + 4 * q;
+      double m = 0.0;
+      if (c < nci) {
+        const int R = nG + c;
+        const int64_t t = (D.sg_off + tri_tile(R / NB, ii)) * int64_t(NB * NB);
+        m = A.m32 ? double(static_cast<const float*>(A.m)[t + sym_f32_off(R % NB, lane)])
+                  : static_cast<const double*>(A.m)[t + (R % NB) * NB + lane];
+      }
+      mc[q] = m;
+    }
+    if (w == 0 && r_out < nG) wdr = A.wd[D.loc_off + D.n_I + r_out];
+  }
   if (tid < nci) {
     const int pc = A.rc[D.coarse_off + tid];
     double v = 0.0;
@@ -1914,24 +1946,18 @@ __global__ __launch_bounds__(256) void pc_finish_kernel(IfaceArgs A) {
   }
   if (!rows) return;
   __syncthreads();
-  // constraint rows: wave w takes c = w, w+4, ...; M(nG + c, r) lies in tile
-  // ((nG + c) / 64, ii)
+  // constraint rows: wave w takes c = w, w+4, ...
   {
     double v = 0.0;
-    for (int c = w; c < nci; c += 4) {
-      const int R = nG + c;
-      const int64_t e = (D.sg_off + tri_tile(R / NB, ii)) * int64_t(NB * NB) + (R % NB) * NB + lane;
-      const int64_t ef = e - (R % NB) * NB - lane + sym_f32_off(R % NB, lane);
-      v += (A.m32 ? double(static_cast<const float*>(A.m)[ef]) : static_cast<const double*>(A.m)[e]) * cf[c];
-    }
+    for (int q = 0; q < CPW; ++q)
+      if (w + 4 * q < nci) v += mc[q] * cf[w + 4 * q];
     s_red[w][lane] += v;
   }
   __syncthreads();
   if (tid >= NB) return;
-  const int r = ii * NB + tid;
-  if (r < nG) {
+  if (r_out < nG) {
     const double x = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
-    A.ww[D.loc_off + D.n_I + r] = A.wd[D.loc_off + D.n_I + r] * x;
+    A.ww[D.loc_off + D.n_I + r_out] = wdr * x;
   }
 }
 
@@ -2005,6 +2031,24 @@ __global__ __launch_bounds__(VBLK) void gather_sp_ifc_kernel(IfcArgs A) {
   __shared__ double sh[VBLK / 64];
   PcgScalars* sc = A.sc;
   if (sc->done) return;
+  // the data of an interface dof does not depend on beta: the loads of the
+  // thread's first dof are issued before the reduction of the r.z partial sums
+  const int64_t k0 = blockIdx.x * int64_t(VBLK) + threadIdx.x, ks = int64_t(gridDim.x) * VBLK;
+  int g = 0;
+  double v = 0.0, zv = 0.0, pv0 = 0.0, qv0 = 0.0;
+  auto load = [&](int64_t k) {
+    g = A.g[k];
+    const IfcCopies l = load_copies(A.l, k);
+    v = 0.0;
+    for (int c = 0; c < IFC_MAXC; ++c)
+      if (l.l[c] >= 0) v += A.sploc[l.l[c]];
+    zv = A.z[g];
+    if (!A.fresh) {
+      pv0 = A.p[g];
+      qv0 = A.q[g];
+    }
+  };
+  if (k0 < A.n) load(k0);
   const double rz = reduce_partials(A.part_in, gridDim.x, sh);
   const double beta = A.fresh ? 0.0 : rz / sc->rz[A.it - 1];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -2012,14 +2056,10 @@ __global__ __launch_bounds__(VBLK) void gather_sp_ifc_kernel(IfcArgs A) {
     if (!A.fresh) sc->beta[A.it - 1] = beta;
   }
   double pq = 0.0;
-  for (int64_t k = blockIdx.x * int64_t(VBLK) + threadIdx.x; k < A.n; k += int64_t(gridDim.x) * VBLK) {
-    const int g = A.g[k];
-    const IfcCopies l = load_copies(A.l, k);
-    double v = 0.0;
-    for (int c = 0; c < IFC_MAXC; ++c)
-      if (l.l[c] >= 0) v += A.sploc[l.l[c]];
-    const double pv = A.fresh ? A.z[g] : A.z[g] + beta * A.p[g];
-    const double qv = A.fresh ? v : v + beta * A.q[g];
+  for (int64_t k = k0; k < A.n; k += ks) {
+    if (k != k0) load(k);
+    const double pv = A.fresh ? zv : zv + beta * pv0;
+    const double qv = A.fresh ? v : v + beta * qv0;
     A.p[g] = pv;
     A.q[g] = qv;
     pq += pv * qv;
@@ -2034,8 +2074,29 @@ __global__ __launch_bounds__(VBLK) void pcg_update_ifc_kernel(IfcArgs A) {
   __shared__ double sh[VBLK / 64];
   PcgScalars* sc = A.sc;
   if (sc->done) return;
-  const double pq = reduce_partials(A.part_in, gridDim.x, sh);
+  // the thread's first interface dof is loaded before the reduction of the p.q
+  // partial sums (its data does not depend on alpha)
+  const int64_t k0 = blockIdx.x * int64_t(VBLK) + threadIdx.x, ks = int64_t(gridDim.x) * VBLK;
+  int g = 0;
+  IfcCopies sf;
+  double xv = 0.0, pv = 0.0, rv0 = 0.0, qv = 0.0, wd[IFC_MAXC];
+  auto load = [&](int64_t k) {
+    g = A.g[k];
+    sf = load_copies(A.slotf, k);
+    xv = A.x[g];
+    pv = A.p[g];
+    rv0 = A.r[g];
+    qv = A.q[g];
+    const d2v* wp = reinterpret_cast<const d2v*>(A.wd + k * IFC_MAXC);
+    for (int c = 0; c < IFC_MAXC; c += 2) {
+      const d2v w2 = wp[c / 2];
+      wd[c] = w2[0];
+      wd[c + 1] = w2[1];
+    }
+  };
   const double rz = sc->rz[A.it];
+  if (k0 < A.n) load(k0);
+  const double pq = reduce_partials(A.part_in, gridDim.x, sh);
   const double alpha = rz / pq;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc->pq[A.it] = pq;
@@ -2043,15 +2104,14 @@ __global__ __launch_bounds__(VBLK) void pcg_update_ifc_kernel(IfcArgs A) {
   }
   double rr = 0.0;
   if (pq > 0.0 && rz > 0.0) {
-    for (int64_t k = blockIdx.x * int64_t(VBLK) + threadIdx.x; k < A.n; k += int64_t(gridDim.x) * VBLK) {
-      const int g = A.g[k];
-      const IfcCopies sf = load_copies(A.slotf, k);
-      A.x[g] += alpha * A.p[g];
-      const double rv = A.r[g] - alpha * A.q[g];
+    for (int64_t k = k0; k < A.n; k += ks) {
+      if (k != k0) load(k);
+      A.x[g] = xv + alpha * pv;
+      const double rv = rv0 - alpha * qv;
       A.r[g] = rv;
       rr += rv * rv;
       for (int c = 0; c < IFC_MAXC; ++c)
-        if (sf.l[c] >= 0) A.fpad[sf.l[c]] = A.wd[k * IFC_MAXC + c] * rv;
+        if (sf.l[c] >= 0) A.fpad[sf.l[c]] = wd[c] * rv;
     }
   }
   const double t = block_sum(rr, sh);
