@@ -306,6 +306,14 @@ void* pub_slot(bddc_ctx* c, int i) {
 }
 
 int trsv_grid(bddc_ctx* c, int ntasks) { return std::max(1, std::min(ntasks, c->grid_trsv)); }
+// Interior passes: one chain of tile rows per subdomain, each task waiting on the
+// previous rows of its own chain; about four tasks in flight per chain keep
+// every chain busy, and more workgroups only add polling traffic (measured on
+// the 64^3 workload: 64 chains, 256 workgroups beat 512 and 768).
+int trsv_grid_ii(bddc_ctx* c, int ntasks) {
+  const int want = std::max(c->cus, 4 * c->plan.nsubs);
+  return std::max(1, std::min(ntasks, std::min(want, c->grid_trsv)));
+}
 
 // z = M^{-1} r (paper Sec. 2): v1 + v2 through the forward solve, the coarse
 // problem and the backward solve, then v3 on subdomain interiors.
@@ -392,7 +400,7 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   {
     hipEvent_t k0, k1;
     c->kernel_events("trsv_fwd_ii", &k0, &k1);
-    launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st, k0, k1);
+    launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st, k0, k1);
   }
   a = base_args(c);
   a.done = done;
@@ -407,7 +415,7 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   {
     hipEvent_t k0, k1;
     c->kernel_events("trsv_bwd_ii", &k0, &k1);
-    launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st, k0, k1);
+    launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st, k0, k1);
   }
   c->end("apply", ea);
 }
@@ -533,13 +541,12 @@ void enqueue_schur(bddc_ctx* c, int it, bool fresh, const double* part_rz, doubl
 }
 
 // x = P_I b: interior solves of b, zero on the interface
-void enqueue_interior_guess(bddc_ctx* c, const double* b, double* x) {
+// (zero: optional vector set to zero by the same first launch)
+void enqueue_interior_guess(bddc_ctx* c, const double* b, double* x, double* zero = nullptr) {
   const Plan& P = c->plan;
   hipStream_t st = c->st;
-  if (c->fp32) launch_fill_sentinel<float>(static_cast<float*>(pub_slot(c, 2)), 2 * P.n_vec, st);
-  else launch_fill_sentinel<double>(static_cast<double*>(pub_slot(c, 2)), 2 * P.n_vec, st);
-  launch_fill<unsigned>(c->tickets, 0u, 8, st);
-  launch_zero_interface(c->kappa, x, P.n_free, st);
+  launch_reset(c->fp32, pub_slot(c, 2), 2 * P.n_vec, nullptr, 0, c->tickets, nullptr, st, c->kappa, x, zero,
+               P.n_free);
   TrsvArgs a = base_args(c);
   a.tasks = c->t_fwd_ii;
   a.fcol = c->fcol_ii;
@@ -547,7 +554,7 @@ void enqueue_interior_guess(bddc_ctx* c, const double* b, double* x) {
   a.ticket = c->tickets + 2;
   a.sol = pub_slot(c, 2);
   a.rin = b;
-  launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
+  launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st);
   a = base_args(c);
   a.tasks = c->t_bwd_ii;
   a.lrow = c->lrow_ii;
@@ -556,7 +563,7 @@ void enqueue_interior_guess(bddc_ctx* c, const double* b, double* x) {
   a.sol = pub_slot(c, 3);
   a.src = pub_slot(c, 2);
   a.zout = x;
-  launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
+  launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st);
 }
 
 // one PCG iteration it (fresh: first of a segment, p = z)
@@ -645,7 +652,7 @@ void enqueue_interior_complete(bddc_ctx* c, const double* b, const double* xt, d
   a.sol = pub_slot(c, 2);
   a.rin = b;
   a.v12 = xt;
-  launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
+  launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st);
   a = base_args(c);
   a.tasks = c->t_bwd_ii;
   a.lrow = c->lrow_ii;
@@ -655,7 +662,7 @@ void enqueue_interior_complete(bddc_ctx* c, const double* b, const double* xt, d
   a.src = pub_slot(c, 2);
   a.zout = out;
   a.base = xt;
-  launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid(c, a.ntasks), st);
+  launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st);
 }
 
 int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
@@ -1015,8 +1022,7 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
       launch_zero_interior(c->kappa, x, n, st);
       enqueue_interior_complete(c, b, x, c->tmp);
     } else {
-      launch_fill<double>(x, 0.0, n, st);
-      enqueue_interior_guess(c, b, c->tmp);
+      enqueue_interior_guess(c, b, c->tmp, x);
     }
     launch_residual(c->rowptr, c->col, c->val, c->tmp, b, c->r, c->part_a, c->part_b, n, st, c->kappa);
   } else {

@@ -159,8 +159,12 @@ void launch_elem_grad(const MeshDevHost& m, const double* lam, const double* u, 
 
 constexpr int VEC_GRID = 1024;   // partial-sum count of the vector kernels
 
+// Before the triangular passes: sentinels into the published-solution buffers,
+// tickets to zero, and (n > 0) zero_all[i] = 0 and zero_iface[i] = 0 where
+// kappa[i] > 1 (either may be null).
 void launch_reset(bool fp32, void* pub, int64_t n_pub, double* pubc, int64_t n_pubc, unsigned* tickets,
-                  const int* done, hipStream_t st);
+                  const int* done, hipStream_t st, const uint8_t* kappa = nullptr, double* zero_iface = nullptr,
+                  double* zero_all = nullptr, int64_t n = 0);
 
 
 

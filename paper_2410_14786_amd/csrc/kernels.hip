@@ -2155,7 +2155,8 @@ void launch_scatter_f_ifc(const IfcArgs& a, hipStream_t st) {
 // sentinel fill of the published buffers and zero tickets, one launch
 template <typename T>
 __global__ void reset_kernel(T* pub, int64_t n_pub, double* pubc, int64_t n_pubc, unsigned* tickets,
-                             const int* done) {
+                             const int* done, const uint8_t* kappa, double* zero_iface, double* zero_all,
+                             int64_t n) {
   if (done && *done) return;
   using U = typename Traits<T>::U;
   U* q = reinterpret_cast<U*>(pub);
@@ -2165,17 +2166,24 @@ __global__ void reset_kernel(T* pub, int64_t n_pub, double* pubc, int64_t n_pubc
   for (int64_t i = i0; i < n_pub; i += stride) q[i] = Traits<T>::SENT;
   for (int64_t i = i0; i < n_pubc; i += stride) qc[i] = Traits<double>::SENT;
   if (i0 < 8) tickets[i0] = 0u;
+  for (int64_t i = i0; i < n; i += stride) {
+    if (zero_all) zero_all[i] = 0.0;
+    if (zero_iface && kappa[i] > 1) zero_iface[i] = 0.0;
+  }
 }
 
 void launch_reset(bool fp32, void* pub, int64_t n_pub, double* pubc, int64_t n_pubc, unsigned* tickets,
-                  const int* done, hipStream_t st) {
-  const int g = grid_for(n_pub > n_pubc ? n_pub : n_pubc, 256, 2048);
+                  const int* done, hipStream_t st, const uint8_t* kappa, double* zero_iface, double* zero_all,
+                  int64_t n) {
+  int64_t m = n_pub > n_pubc ? n_pub : n_pubc;
+  if (n > m) m = n;
+  const int g = grid_for(m, 256, 2048);
   if (fp32)
     hipLaunchKernelGGL(reset_kernel<float>, dim3(g), dim3(256), 0, st, (float*)pub, n_pub, pubc, n_pubc, tickets,
-                       done);
+                       done, kappa, zero_iface, zero_all, n);
   else
     hipLaunchKernelGGL(reset_kernel<double>, dim3(g), dim3(256), 0, st, (double*)pub, n_pub, pubc, n_pubc, tickets,
-                       done);
+                       done, kappa, zero_iface, zero_all, n);
 }
 
 
