@@ -998,7 +998,7 @@ __global__ __launch_bounds__(64) void coarse_prep_kernel(const MatDesc* mats, co
                                                          const int32_t* gmap, const double* wgt, const double* r,
                                                          double* gbuf, double* mu, const int* done,
                                                          const double* rowp, int64_t ntiles, int nwg) {
-  if (done && *done) return;
+  const int dn = done ? *done : 0;   // tested once the loads are in flight
   const int s = blockIdx.x;
   const MatDesc D = mats[s];
   const int tid = threadIdx.x;
@@ -1017,6 +1017,7 @@ __global__ __launch_bounds__(64) void coarse_prep_kernel(const MatDesc* mats, co
     }
     h[tid] = v;
   }
+  if (dn) return;
   __syncthreads();
   const double* so = sainv + int64_t(s) * MAX_NCI * MAX_NCI;
   const double* se = sainve + int64_t(s) * MAX_NCI * MAX_NCI;
@@ -1484,7 +1485,7 @@ __global__ __launch_bounds__(256) void coarse_gemv_kernel(const double* ainv, in
                                                           const int32_t* cinv_ptr, const int32_t* cinv,
                                                           const double* gbuf, double* upart, const int* done) {
   __shared__ double rcs[COARSE_SPLIT_COLS];
-  if (done && *done) return;
+  const int dn = done ? *done : 0;   // tested once the loads are in flight
   const int s = blockIdx.y;
   const int j0 = s * cs, j1 = min(nc, j0 + cs);
   // one row per wave (the rows are independent, so many short chains in flight);
@@ -1505,6 +1506,7 @@ __global__ __launch_bounds__(256) void coarse_gemv_kernel(const double* ainv, in
     for (int q = cinv_ptr[j]; q < cinv_ptr[j + 1]; ++q) v += gbuf[cinv[q]];
     rcs[j - j0] = v;
   }
+  if (dn) return;
   __syncthreads();
   if (i >= nc) return;
   double v = 0.0;
@@ -1861,13 +1863,14 @@ __device__ __forceinline__ void sum_row(const IfaceArgs& A, const MatDesc& D, in
 // corners.
 __global__ __launch_bounds__(256) void op_finish_kernel(IfaceArgs A) {
   __shared__ double s_red[4][NB];
-  if (A.sc->done) return;
+  const int dn = A.sc->done;   // tested once the loads are in flight
   const int s = A.tasks[2 * blockIdx.x], ii = A.tasks[2 * blockIdx.x + 1];
   const MatDesc D = A.mats[s];
   const int TS = sym_tile_rows(D), nG = D.n_R - D.n_I, tid = threadIdx.x;
   const int r = ii * NB + tid;
   const double ds = tid < NB && r < nG ? A.dsc[D.loc_off + D.n_I + r] : 1.0;
   sum_row(A, D, ii, TS, s_red);
+  if (dn) return;
   __syncthreads();
   if (tid >= NB) return;
   const double y = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
@@ -1888,7 +1891,7 @@ __global__ __launch_bounds__(256) void pc_finish_kernel(IfaceArgs A) {
   __shared__ double u[MAX_NCI];
   __shared__ double cf[MAX_NCI];
   __shared__ double s_red[4][NB];
-  if (A.sc->done) return;
+  const int dn = A.sc->done;   // tested once the loads are in flight
   const int s = A.tasks[2 * blockIdx.x], ii = A.tasks[2 * blockIdx.x + 1];
   const MatDesc D = A.mats[s];
   const int TS = sym_tile_rows(D), nG = D.n_R - D.n_I, tid = threadIdx.x;
@@ -1925,6 +1928,7 @@ __global__ __launch_bounds__(256) void pc_finish_kernel(IfaceArgs A) {
     for (int q = 0; q < A.nsplit; ++q) v += A.uc[int64_t(q) * A.nc + pc];
     u[tid] = v;
   }
+  if (dn) return;
   __syncthreads();
   {
     // coefficient c = tid / 4, lanes tid % 4 split its terms
@@ -2008,16 +2012,28 @@ __global__ void ifc_setup_kernel(const int32_t* ifc_l, const double* dsc, const 
 // input, partial sums of r.z
 __global__ __launch_bounds__(VBLK) void gather_z_ifc_kernel(IfcArgs A) {
   __shared__ double sh[VBLK / 64];
-  if (A.sc->done) return;
-  double rz = 0.0;
-  for (int64_t k = blockIdx.x * int64_t(VBLK) + threadIdx.x; k < A.n; k += int64_t(gridDim.x) * VBLK) {
-    const int g = A.g[k];
-    const IfcCopies l = load_copies(A.l, k), sz = load_copies(A.slotz, k);
-    double v = 0.0;
+  // the end-of-solve word is tested once the thread's first loads are in flight
+  const int dn = A.sc->done;
+  const int64_t k0 = blockIdx.x * int64_t(VBLK) + threadIdx.x, ks = int64_t(gridDim.x) * VBLK;
+  int g = 0;
+  IfcCopies sz;
+  double v = 0.0, rv = 0.0;
+  auto load = [&](int64_t k) {
+    g = A.g[k];
+    const IfcCopies l = load_copies(A.l, k);
+    sz = load_copies(A.slotz, k);
+    v = 0.0;
     for (int c = 0; c < IFC_MAXC; ++c)
       if (l.l[c] >= 0) v += A.ww[l.l[c]];
+    rv = A.r[g];
+  };
+  if (k0 < A.n) load(k0);
+  if (dn) return;
+  double rz = 0.0;
+  for (int64_t k = k0; k < A.n; k += ks) {
+    if (k != k0) load(k);
     A.z[g] = v;
-    rz += A.r[g] * v;
+    rz += rv * v;
     for (int c = 0; c < IFC_MAXC; ++c)
       if (sz.l[c] >= 0) A.zpad[sz.l[c]] = v / A.dsc[k * IFC_MAXC + c];
   }
@@ -2030,7 +2046,7 @@ __global__ __launch_bounds__(VBLK) void gather_z_ifc_kernel(IfcArgs A) {
 __global__ __launch_bounds__(VBLK) void gather_sp_ifc_kernel(IfcArgs A) {
   __shared__ double sh[VBLK / 64];
   PcgScalars* sc = A.sc;
-  if (sc->done) return;
+  const int dn = sc->done;   // tested once the first loads are in flight
   // the data of an interface dof does not depend on beta: the loads of the
   // thread's first dof are issued before the reduction of the r.z partial sums
   const int64_t k0 = blockIdx.x * int64_t(VBLK) + threadIdx.x, ks = int64_t(gridDim.x) * VBLK;
@@ -2049,6 +2065,7 @@ __global__ __launch_bounds__(VBLK) void gather_sp_ifc_kernel(IfcArgs A) {
     }
   };
   if (k0 < A.n) load(k0);
+  if (dn) return;
   const double rz = reduce_partials(A.part_in, gridDim.x, sh);
   const double beta = A.fresh ? 0.0 : rz / sc->rz[A.it - 1];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -2073,7 +2090,7 @@ __global__ __launch_bounds__(VBLK) void gather_sp_ifc_kernel(IfcArgs A) {
 __global__ __launch_bounds__(VBLK) void pcg_update_ifc_kernel(IfcArgs A) {
   __shared__ double sh[VBLK / 64];
   PcgScalars* sc = A.sc;
-  if (sc->done) return;
+  const int dn = sc->done;   // tested once the first loads are in flight
   // the thread's first interface dof is loaded before the reduction of the p.q
   // partial sums (its data does not depend on alpha)
   const int64_t k0 = blockIdx.x * int64_t(VBLK) + threadIdx.x, ks = int64_t(gridDim.x) * VBLK;
@@ -2096,6 +2113,7 @@ __global__ __launch_bounds__(VBLK) void pcg_update_ifc_kernel(IfcArgs A) {
   };
   const double rz = sc->rz[A.it];
   if (k0 < A.n) load(k0);
+  if (dn) return;
   const double pq = reduce_partials(A.part_in, gridDim.x, sh);
   const double alpha = rz / pq;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
