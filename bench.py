@@ -144,8 +144,10 @@ def run_gpu(w, steps, warmup, local_bits, use_graph=False, full_space=False, aut
     elapsed = time.perf_counter() - t0
     fam = {f: S.kernel_time(f) for f in families + ["apply"]}
     S.set_timing(False)
+    flops, factor_ms = S.setup_stats()
     res = {"setup_s": setup_s, "elapsed_s": elapsed, "iters": iters, "info": info, "kernels": fam,
-           "dev_bytes": S.dev_bytes, "families": families, "tuning": tune}
+           "dev_bytes": S.dev_bytes, "families": families, "tuning": tune, "factor_flops": flops,
+           "factor_ms": factor_ms}
     S.close()
     del S
     torch.cuda.empty_cache()
@@ -235,6 +237,17 @@ def main():
         print(f"[bench] {name}: {1000 * r['elapsed_s'] / args.steps:.2f} ms/solve, iters {r['iters'][-1]}, "
               f"setup {r['setup_s']:.2f} s", file=sys.stderr, flush=True)
 
+    def factor_roofline(r, bits):
+        """The setup's batched local Cholesky (MFMA-bound): its envelope flops over
+        its stream-event time, against the dense MFMA peak of its precision (the
+        interface form factors in FP64 for either local precision)."""
+        fp32_factors = bits == 32 and r["families"] == FULL_FAMILIES
+        peak = 157.3 if fp32_factors else 78.6
+        ach = r["factor_flops"] / (r["factor_ms"] * 1e-3) / 1e12 if r["factor_ms"] > 0 else None
+        return {"bound": "mfma", "achieved": round(ach, 2) if ach else None, "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4) if ach else None, "flops": r["factor_flops"],
+                "ms": round(r["factor_ms"], 3), "dtype": "f32" if fp32_factors else "f64"}
+
     def summarize(r, bits):
         lb = 8 if bits == 64 else 4
         algo = algorithmic_bytes(w, lb)
@@ -289,6 +302,7 @@ def main():
     for k in ["applies_per_s", "kernel_ms", "streamed_hbm_frac"]:
         out[k] = timed[k]
     out["roofline"] = timed["roofline"]
+    out["setup_factor_roofline"] = factor_roofline(runs["main"], main_bits)
     if "graph" in runs:
         out["graph"] = summarize(runs["graph"], main_bits)
     if "full_space" in runs:
@@ -302,6 +316,7 @@ def main():
             f[k] = f["timed"][k]
         if "fp32_local_full_space" in runs:
             f["full_space"] = summarize(runs["fp32_local_full_space"], 32)
+            f["full_space"]["setup_factor_roofline"] = factor_roofline(runs["fp32_local_full_space"], 32)
             f["full_space"]["local_precision"] = "FP32 local factors and triangular solves"
         out["fp32_local"] = f
     if not args.no_cpu_baseline:

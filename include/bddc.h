@@ -166,6 +166,14 @@ int bddc_spmv(bddc_ctx* ctx, const double* x, double* y);
  * Asynchronous. */
 int bddc_elem_grad(bddc_ctx* ctx, const double* lam, const double* u, double* g);
 
+/* Setup statistics (for the factorisation's compute roofline): the floating-
+ * point operations of the batched local tile Cholesky inside the factors'
+ * envelope (diagonal factor 64^3/3, panel solve 64^3, off-diagonal update 2*64^3,
+ * diagonal update 64^3 per tile operation) and its GPU time at setup in ms
+ * (measured with stream events around the factorisation launches).  Either
+ * pointer may be NULL.  Errors: EINVAL (NULL ctx). */
+int bddc_setup_stats(bddc_ctx* c, double* factor_flops, double* factor_ms);
+
 /* Sizes: free dofs, subdomains, global coarse dofs, device bytes held.
  * Any output pointer may be NULL. */
 int bddc_query(bddc_ctx* ctx, int64_t* n_free, int32_t* n_sub, int32_t* n_coarse,

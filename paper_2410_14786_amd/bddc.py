@@ -46,7 +46,7 @@ class PcgInfo(ctypes.Structure):
 
 EXPORTS = ["bddc_setup", "bddc_apply", "bddc_pcg_solve", "bddc_spmv", "bddc_elem_grad", "bddc_query",
            "bddc_plan_stats", "bddc_set_timing", "bddc_kernel_time", "bddc_destroy", "bddc_strerror",
-           "bddc_last_error", "bddc_debug_read", "bddc_set_tuning", "bddc_autotune"]
+           "bddc_last_error", "bddc_debug_read", "bddc_set_tuning", "bddc_autotune", "bddc_setup_stats"]
 
 _lib = None
 
@@ -77,6 +77,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bddc_set_tuning.restype = ctypes.c_int
     lib.bddc_autotune.argtypes = [vp, ctypes.POINTER(i32), i32, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     lib.bddc_autotune.restype = ctypes.c_int
+    lib.bddc_setup_stats.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    lib.bddc_setup_stats.restype = ctypes.c_int
     lib.bddc_destroy.argtypes = [vp]
     lib.bddc_destroy.restype = None
     lib.bddc_strerror.argtypes = [ctypes.c_int]
@@ -245,6 +247,13 @@ class Solver:
         if n < 0:
             _check(int(n), "bddc_debug_read")
         return buf[:n]
+
+    def setup_stats(self):
+        """Floating-point operations of the batched local factorisation (inside the
+        factors' envelope) and its GPU time at setup in ms."""
+        fl, ms = ctypes.c_double(), ctypes.c_double()
+        _check(self.lib.bddc_setup_stats(self.ctx, ctypes.byref(fl), ctypes.byref(ms)), "bddc_setup_stats")
+        return fl.value, ms.value
 
     def set_tuning(self, wg_per_cu: int):
         _check(self.lib.bddc_set_tuning(self.ctx, int(wg_per_cu)), "bddc_set_tuning")

@@ -148,6 +148,7 @@ struct bddc_ctx {
   PcgScalars* sc = nullptr;
   int* err = nullptr;
   double t_setup_ms = 0.0;
+  double factor_ms = 0.0;           // GPU time of the batched local factorisation at setup
 
   // HIP graphs of chunks of PCG iterations (use_graph): graph k holds iterations
   // [k*GRAPH_CHUNK, (k+1)*GRAPH_CHUNK) of a solve, replayed on gst, which is
@@ -765,7 +766,12 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->alloc(c->ifc_dsc, int64_t(P.ifc_l.size()) + 1))) return rc_;
   if ((rc_ = c->alloc(c->ifc_wd, int64_t(P.ifc_l.size()) + 1))) return rc_;
   launch_ifc_setup(c->ifc_l, c->dsc, c->wd, c->ifc_dsc, c->ifc_wd, int64_t(P.ifc_g.size()), st);
+  hipEvent_t f0 = nullptr, f1 = nullptr;
+  HIP_TRY(hipEventCreate(&f0));
+  HIP_TRY(hipEventCreate(&f1));
+  HIP_TRY(hipEventRecord(f0, st));
   launch_factor(c->mats, P.nsubs, P.maxT, P.maxTx, c->tiles, c->dinv, c->fp32, c->fcol, c->err + 1, st);
+  HIP_TRY(hipEventRecord(f1, st));
   if ((rc_ = c->alloc(c->cpp, small))) return rc_;
   launch_local_small(c->mats, P.nsubs, c->tiles, c->fp32, c->app, c->sainv, c->sainve, c->aci, c->cpp, c->err + 1,
                      st);
@@ -866,6 +872,13 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   int herr[4] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(herr, c->err, sizeof(herr), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, f0, f1));
+    c->factor_ms = ms;
+    hipEventDestroy(f0);
+    hipEventDestroy(f1);
+  }
   if (herr[0] & 1) return fail(BDDC_ENOTSPD, "conductivity must be positive and finite");
   if (herr[0] & 4) return fail(BDDC_EINVAL, "internal: CSR row count mismatch");
   if (herr[1]) return fail(BDDC_ENOTSPD, "a local factorisation met a non-positive pivot (flags " +
@@ -1133,6 +1146,13 @@ int bddc_query(bddc_ctx* c, int64_t* n_free, int32_t* n_sub, int32_t* n_coarse, 
   if (n_sub) *n_sub = c->plan.nsubs;
   if (n_coarse) *n_coarse = c->plan.n_coarse;
   if (dev_bytes) *dev_bytes = c->dev_bytes;
+  return BDDC_OK;
+}
+
+int bddc_setup_stats(bddc_ctx* c, double* factor_flops, double* factor_ms) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  if (factor_flops) *factor_flops = c->plan.factor_flops;
+  if (factor_ms) *factor_ms = c->factor_ms;
   return BDDC_OK;
 }
 

@@ -100,6 +100,9 @@ struct Plan {
   // outside [z0, z1)); the operator skips its zero average-constraint rows
   std::vector<int32_t> trows_op, trows_pc;
   int64_t n_symrows = 0;
+  // floating-point operations of the batched tile Cholesky inside the envelope
+  // (diagonal factor 64^3/3, panel solve 64^3, update 2*64^3, diagonal update 64^3)
+  double factor_flops = 0.0;
   // interface dofs (kappa >= 2): global index and IFC_MAXC local copies each
   // (local dof, operator slot, preconditioner slot; -1 past the last copy)
   std::vector<int32_t> ifc_g, ifc_l, ifc_slotz, ifc_slotf;

@@ -307,6 +307,21 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
       }
       P.fcol.insert(P.fcol.end(), fc.begin(), fc.end());
       P.fcol_ii.insert(P.fcol_ii.end(), fi.begin(), fi.end());
+      {
+        // the tile operations the factorisation runs: tile (i, k) is zero when
+        // k < fc[i] (the bordering row T, if any, is dense)
+        const double b3 = double(NB) * NB * NB;
+        auto nz = [&](int i, int k) { return i >= D.T || fc[i] <= k; };
+        for (int k = 0; k < D.T; ++k) {
+          P.factor_flops += b3 / 3.0;
+          for (int i = k + 1; i < D.Tx; ++i) {
+            if (!nz(i, k)) continue;
+            P.factor_flops += b3;
+            for (int j = k + 1; j <= i; ++j)
+              if (nz(j, k)) P.factor_flops += j == i ? b3 : 2.0 * b3;
+          }
+        }
+      }
     }
     // local coarse order [averages | corners]
     for (auto& a : avgs) P.rc.push_back(a.first);

@@ -87,3 +87,25 @@ def test_local_setup_against_numpy(case, bits):
         rtol = 1e-10 if bits == 64 else 1e-4
         assert np.allclose(ev_gpu, ev_orc, rtol=rtol, atol=rtol * ev_orc.max())
     S.close()
+
+
+def test_setup_stats_factor_flops_bounded_by_dense_count():
+    """The factorisation's flop count covers the tile operations inside the
+    envelope: positive, at most the dense tile Cholesky of every factor, and
+    the factorisation took GPU time."""
+    from paper_2410_14786_amd import bddc
+    w = W.make_workload("t", 3, (16, 16, 16), (2, 2, 2), theta="lognormal", seed=0)
+    S = bddc.Solver(w.dim, w.nel, w.cuts, w.theta, w.constraints)
+    flops, ms = S.setup_stats()
+    b3 = 64.0 ** 3
+    dense = 0.0
+    for sub in range(S.n_sub):
+        nR, nI, nA, nP, T, ni = S.debug_read("sizes", sub).astype(int)
+        Tx = T + (1 if nA + nP > 0 else 0)
+        for k in range(T):
+            m = Tx - k - 1
+            dense += b3 / 3 + m * b3 + m * b3 + (m * (m - 1) // 2) * 2 * b3
+    print("factor flops", flops, "dense", dense, "ms", ms, flush=True)
+    assert 0 < flops <= dense
+    assert ms > 0
+    S.close()
