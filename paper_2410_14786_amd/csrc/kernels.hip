@@ -380,31 +380,43 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const MatDesc* mats, T*
   for (int i = tid; i < NB * NB; i += 256) a[(i / NB) * LDT + (i % NB)] = tile[i];
   if (tid == 0) bad = 0;
   __syncthreads();
+  // Right-looking, one barrier per column: the trailing update uses the unscaled
+  // column j (l_ij l_cj = a_ij a_cj / a_jj); column j is scaled afterwards, and
+  // no later step reads it.
   for (int j = 0; j < NB; ++j) {
-    if (tid == 0) {
-      T p = a[j * LDT + j];
-      if (!(p > T(0)) || !(p < T(3e38))) { bad = 1; p = T(1); }
-      a[j * LDT + j] = sqrt(p);
+    T p = a[j * LDT + j];
+    if (!(p > T(0)) || !(p < T(3e38))) {
+      if (tid == 0) bad = 1;
+      p = T(1);
+    }
+    const T inv_p = T(1) / p;
+    {
+      // four threads per row i, each every fourth column c in (j, i]
+      const int i = tid >> 2, q = tid & 3;
+      if (i > j) {
+        const T f = a[i * LDT + j] * inv_p;
+        for (int c = j + 1 + ((q - j - 1) & 3); c <= i; c += 4) a[i * LDT + c] -= f * a[c * LDT + j];
+      }
     }
     __syncthreads();
-    const T ljj = a[j * LDT + j];
-    for (int i = j + 1 + tid; i < NB; i += 256) a[i * LDT + j] /= ljj;
-    __syncthreads();
-    const int m = NB - 1 - j;
-    for (int idx = tid; idx < m * m; idx += 256) {
-      int i = j + 1 + idx / m, c = j + 1 + idx % m;
-      if (c <= i) a[i * LDT + c] -= a[i * LDT + j] * a[c * LDT + j];
+    if (tid >= j && tid < NB) {
+      const T ljj = sqrt(p);
+      a[tid * LDT + j] = tid == j ? ljj : a[tid * LDT + j] / ljj;
     }
-    __syncthreads();
   }
-  // inverse of the lower-triangular factor, one column per thread
-  if (tid < NB) {
-    const int c = tid;
-    for (int i = 0; i < c; ++i) x[i * LDT + c] = T(0);
+  __syncthreads();
+  // inverse of the lower-triangular factor by forward substitution: four lanes
+  // per column c split each row's sum, the lane of row i's residue class stores
+  // x(i, c) (LDS operations of one wave complete in order)
+  {
+    const int c = tid >> 2, q = tid & 3;
+    for (int i = q; i < c; i += 4) x[i * LDT + c] = T(0);
     for (int i = c; i < NB; ++i) {
-      T s = (i == c) ? T(1) : T(0);
-      for (int j = c; j < i; ++j) s -= a[i * LDT + j] * x[j * LDT + c];
-      x[i * LDT + c] = s / a[i * LDT + i];
+      T s = T(0);
+      for (int j = c + q; j < i; j += 4) s += a[i * LDT + j] * x[j * LDT + c];
+      s += __shfl_xor(s, 1, 4);
+      s += __shfl_xor(s, 2, 4);
+      if (q == (i & 3)) x[i * LDT + c] = ((i == c ? T(1) : T(0)) - s) / a[i * LDT + i];
     }
   }
   __syncthreads();
