@@ -125,6 +125,10 @@ void launch_coarse_assembly(const int32_t* src_ptr, const int32_t* src, const in
 // t0 / t1: optional events recorded by the dispatch itself at kernel start / end
 void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st, hipEvent_t t0 = nullptr,
                  hipEvent_t t1 = nullptr);
+// interior passes (TRSV_FWD_II, TRSV_BWD_II; launch_trsv routes them here): two
+// tile rows per task, one workgroup per CU
+void launch_trsv2(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st, hipEvent_t t0 = nullptr,
+                  hipEvent_t t1 = nullptr);
 void launch_coarse_prep(const MatDesc* mats, int nmats, const double* part, const double* sainv,
                         const double* sainve, const int32_t* gmap, const double* wgt, const double* r,
                         double* gbuf, double* mu, const int* done, const double* rowp, int64_t ntiles, int nwg,

@@ -723,7 +723,8 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
   constexpr int LPR = NB / VEC;      // lanes per tile row
   constexpr int RPI = 64 / LPR;      // tile rows per wave instruction
   constexpr int NI = 16 / RPI;       // instructions per 16-row slab
-  constexpr bool FWD = (MODE == TRSV_FWD_RR || MODE == TRSV_FWD_II || MODE == TRSV_FWD_C);
+  constexpr bool FWD = (MODE == TRSV_FWD_RR || MODE == TRSV_FWD_C);
+  static_assert(MODE != TRSV_FWD_II && MODE != TRSV_BWD_II, "interior passes: trsv2_kernel");
 
   __shared__ T s_rhs[NB];
   __shared__ T s_v[NB];
@@ -758,38 +759,20 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     if (task >= A.ntasks) return;
     const int s = A.tasks[2 * task], k = A.tasks[2 * task + 1];
     const MatDesc D = A.mats[s];
-    const int T_rows = (MODE == TRSV_FWD_II || MODE == TRSV_BWD_II) ? D.TI : D.T;
-    const int nlim = (MODE == TRSV_FWD_II || MODE == TRSV_BWD_II) ? D.n_I : D.n_R;
+    const int T_rows = D.T;
+    const int nlim = D.n_R;
     const int nlo = 0, j0 = 0;
     const int64_t tbase = D.tile_off;
     T* my_sol = sol + D.vec_off;
 
     // ---------------- prologue: right-hand side of tile row k ----------------
-    if (MODE == TRSV_FWD_II && A.v12) {
-      // interior rows of r - A v12: four lanes per CSR row
-      const int row = tid >> 2, sl = tid & 3;
-      const int a = k * NB + row;
-      double v = 0.0;
-      int64_t l = 0;
-      int g = 0;
-      if (a < nlim) {
-        l = D.loc_off + a;
-        g = A.gmap[l];
-        for (int j = A.rowptr[g] + sl; j < A.rowptr[g + 1]; j += 4) v += A.vals[j] * A.v12[A.colind[j]];
-      }
-      v += __shfl_xor(v, 1, 4);
-      v += __shfl_xor(v, 2, 4);
-      if (sl == 0) s_rhs[row] = a < nlim ? T(A.dsc[l] * (A.rin[g] - v)) : T(0);
-    } else if (tid < NB) {
+    if (tid < NB) {
       const int a = k * NB + tid;
       double rhs = 0.0;
       if (a >= nlo && a < nlim) {
         if (MODE == TRSV_FWD_RR) {
           const int64_t l = D.loc_off + a;
           rhs = A.wd[l] * A.rin[A.gmap[l]];
-        } else if (MODE == TRSV_FWD_II) {
-          const int64_t l = D.loc_off + a;
-          rhs = A.dsc[l] * A.rin[A.gmap[l]];
         } else if (MODE == TRSV_FWD_C) {
           double v = 0.0;
           for (int j = A.cinv_ptr[a]; j < A.cinv_ptr[a + 1]; ++j) v += A.gbuf[A.cinv[j]];
@@ -930,15 +913,6 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
           A.ww[l] = A.wd[l] * double(s_out[tid]);
         }
       }
-    } else if (MODE == TRSV_BWD_II) {
-      if (tid < NB) {
-        const int a = k * NB + tid;
-        if (a < D.n_I) {
-          const int64_t l = D.loc_off + a;
-          const int g = A.gmap[l];
-          A.zout[g] = (A.base ? A.base[g] : 0.0) + A.dsc[l] * double(s_out[tid]);
-        }
-      }
     } else if (MODE == TRSV_BWD_C) {
       if (tid < NB) {
         const int a = k * NB + tid;
@@ -959,14 +933,269 @@ static void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t st, hipEve
     hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
 }
 
+// Interior passes with two tile rows per task (the task list holds every second
+// row: forward k = 0, 2, 4, ... for rows k and k+1; backward k = T-1, T-3, ...
+// for rows k and k-1).  A pass is a chain of tasks per subdomain, each link a
+// publish to device memory and a poll by another workgroup (about 3 us); with
+// two rows per task the second row takes the first row's block from LDS, so
+// the chain has half as many links.  Everything a task multiplies before its
+// last wait is in registers when that wait ends: both rows' inverse diagonal
+// tiles, the tile coupling the two rows, and both rows' tiles of the next
+// published block (double-buffered).  The register layouts, the envelope, the
+// published values and the right-hand sides are those of trsv_kernel.  The
+// kernel needs about 290 registers per lane: one workgroup per CU.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
+  using V = typename Traits<T>::V;
+  constexpr int VEC = Traits<T>::VEC;
+  constexpr int LPR = NB / VEC;
+  constexpr int RPI = 64 / LPR;
+  constexpr int NI = 16 / RPI;
+  constexpr bool FWD = MODE == TRSV_FWD_II;
+  static_assert(MODE == TRSV_FWD_II || MODE == TRSV_BWD_II, "interior passes only");
+  constexpr int CPL = 16 / VEC, RG = 64 / CPL;
+  constexpr int NACC = FWD ? NI : VEC;
+
+  __shared__ T s_rhs[2][NB];
+  __shared__ T s_v[NB];
+  __shared__ T s_out[NB];
+  __shared__ T s_red[4][NB];
+  __shared__ int s_task;
+
+  if (A.done && *A.done) return;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int lr = lane / LPR, lc = lane % LPR;
+  const int rg = lane / CPL, cp = lane % CPL;
+  const int64_t lane_off = FWD ? (int64_t(rg) * NB + 16 * w + VEC * cp) : (int64_t(16 * w + lr) * NB + VEC * lc);
+  constexpr int64_t STEP = FWD ? RG * NB : RPI * NB;
+  const T* tiles = reinterpret_cast<const T*>(A.tiles);
+  const T* dinv = reinterpret_cast<const T*>(A.dinv);
+  T* sol = reinterpret_cast<T*>(A.sol);
+  const T* src = reinterpret_cast<const T*>(A.src);
+
+  for (;;) {
+    if (tid == 0) s_task = atomicAdd(A.ticket, 1u);
+    __syncthreads();
+    const int task = s_task;
+    __syncthreads();
+    if (task >= A.ntasks) return;
+    const int s = A.tasks[2 * task], k0 = A.tasks[2 * task + 1];
+    const MatDesc D = A.mats[s];
+    const int TI = D.TI, nlim = D.n_I;
+    const int64_t tbase = D.tile_off;
+    T* my_sol = sol + D.vec_off;
+    const int nr = FWD ? (k0 + 1 < TI ? 2 : 1) : (k0 >= 1 ? 2 : 1);
+    const int kr0 = k0, kr1 = FWD ? k0 + 1 : k0 - 1;
+    auto tptr = [&](int k, int j) -> const T* {
+      // forward: tile (k, j), j < k; backward: tile (j, k), j > k
+      const int64_t t = FWD ? tri_tile(k, j) : tri_tile(j, k);
+      return tiles + (tbase + t) * int64_t(NB * NB) + lane_off;
+    };
+    auto load = [&](const T* p, V (&t)[NI]) {
+      for (int i = 0; i < NI; ++i) t[i] = stream_load(reinterpret_cast<const V*>(p + i * STEP));
+    };
+
+    // blocks published by other tasks: forward row k reads tiles (k, lo..k-1),
+    // backward row k reads tiles (k+1..hi, k); the external blocks of the task
+    // are the union of both rows' ranges without the first row's own block
+    int lo[2], hi[2];
+    for (int q = 0; q < 2; ++q) {
+      const int k = q == 0 ? kr0 : kr1;
+      if (q < nr) {
+        if (FWD) {
+          lo[q] = A.fcol ? int(A.fcol[D.vec_off / NB + k]) : 0;
+          hi[q] = k - 1;
+        } else {
+          lo[q] = k + 1;
+          hi[q] = A.lrow ? int(A.lrow[D.vec_off / NB + k]) : TI - 1;
+        }
+      } else {
+        lo[q] = 1;
+        hi[q] = 0;
+      }
+    }
+    const bool inner = nr > 1 && kr0 >= lo[1] && kr0 <= hi[1];
+    const int ext_lo = FWD ? min(lo[0], nr > 1 ? lo[1] : lo[0]) : kr0 + 1;
+    const int ext_hi = FWD ? kr0 - 1 : max(hi[0], nr > 1 ? hi[1] : hi[0]);
+    const int nt = ext_hi - ext_lo + 1;
+    auto blk = [&](int jj) -> int { return FWD ? ext_lo + jj : ext_hi - jj; };
+
+    // everything independent of other tasks first: both inverse diagonal tiles,
+    // the coupling tile, the first external block's tiles
+    V dv0[NI], dv1[NI], ti[NI], c0[NI], c1[NI], n0[NI], n1[NI];
+    load(dinv + (D.dinv_off + kr0) * int64_t(NB * NB) + lane_off, dv0);
+    if (nr > 1) load(dinv + (D.dinv_off + kr1) * int64_t(NB * NB) + lane_off, dv1);
+    if (inner) load(tptr(kr1, kr0), ti);
+    if (nt > 0) {
+      const int j = blk(0);
+      if (j >= lo[0] && j <= hi[0]) load(tptr(kr0, j), c0);
+      if (j >= lo[1] && j <= hi[1]) load(tptr(kr1, j), c1);
+    }
+
+    // right-hand sides of the task's rows
+    for (int q = 0; q < nr; ++q) {
+      const int k = q == 0 ? kr0 : kr1;
+      if (FWD && A.v12) {
+        // interior rows of r - A v12: four lanes per CSR row
+        const int row = tid >> 2, sl = tid & 3;
+        const int a = k * NB + row;
+        double v = 0.0;
+        int64_t l = 0;
+        int g = 0;
+        if (a < nlim) {
+          l = D.loc_off + a;
+          g = A.gmap[l];
+          for (int j = A.rowptr[g] + sl; j < A.rowptr[g + 1]; j += 4) v += A.vals[j] * A.v12[A.colind[j]];
+        }
+        v += __shfl_xor(v, 1, 4);
+        v += __shfl_xor(v, 2, 4);
+        if (sl == 0) s_rhs[q][row] = a < nlim ? T(A.dsc[l] * (A.rin[g] - v)) : T(0);
+      } else if (tid < NB) {
+        const int a = k * NB + tid;
+        double rhs = 0.0;
+        if (a < nlim) {
+          if (FWD) {
+            const int64_t l = D.loc_off + a;
+            rhs = A.dsc[l] * A.rin[A.gmap[l]];
+          } else {
+            rhs = double(src[D.vec_off + a]);   // the forward solution
+          }
+        }
+        s_rhs[q][tid] = T(rhs);
+      }
+    }
+
+    T acc0[NACC], acc1[NACC];
+    for (int i = 0; i < NACC; ++i) {
+      acc0[i] = T(0);
+      acc1[i] = T(0);
+    }
+    auto mac = [&](T (&acc)[NACC], const V (&t)[NI], const T* xv) {
+      if (FWD) {
+        for (int i = 0; i < NI; ++i)
+          for (int e = 0; e < VEC; ++e) acc[i] += t[i][e] * xv[e];
+      } else {
+        for (int i = 0; i < NI; ++i)
+          for (int e = 0; e < VEC; ++e) acc[e] += t[i][e] * xv[i];
+      }
+    };
+    for (int jj = 0; jj < nt; ++jj) {
+      const int j = blk(jj);
+      if (jj + 1 < nt) {
+        const int jn = blk(jj + 1);
+        if (jn >= lo[0] && jn <= hi[0]) load(tptr(kr0, jn), n0);
+        if (jn >= lo[1] && jn <= hi[1]) load(tptr(kr1, jn), n1);
+      }
+      const T* ys = my_sol + j * NB;
+      T xv[FWD ? VEC : NI];
+      if (FWD) {
+        for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + 16 * w + VEC * cp + e);
+      } else {
+        for (int i = 0; i < NI; ++i) xv[i] = poll_published(ys + 16 * w + RPI * i + lr);
+      }
+      if (j >= lo[0] && j <= hi[0]) mac(acc0, c0, xv);
+      if (j >= lo[1] && j <= hi[1]) mac(acc1, c1, xv);
+      for (int i = 0; i < NI; ++i) {
+        c0[i] = n0[i];
+        c1[i] = n1[i];
+      }
+    }
+
+    // finish one row: reduce the partial sums, subtract from the right-hand
+    // side, multiply by the inverse diagonal tile, publish, write the output
+    auto finish = [&](int q, int k, const T (&acc)[NACC], const V (&dvq)[NI]) {
+      if (FWD) {
+        for (int i = 0; i < NI; ++i) {
+          T v = acc[i];
+          for (int off = 1; off < CPL; off <<= 1) v += __shfl_xor(v, off, CPL);
+          if (cp == 0) s_red[w][rg + RG * i] = v;
+        }
+      } else {
+        for (int e = 0; e < VEC; ++e) {
+          T v = acc[e];
+          for (int off = LPR; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+          if (lr == 0) s_red[w][VEC * lc + e] = v;
+        }
+      }
+      __syncthreads();
+      if (tid < NB) {
+        const T red = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
+        s_v[tid] = k * NB + tid < nlim ? (s_rhs[q][tid] - red) : T(0);
+      }
+      __syncthreads();
+      if (FWD) {
+        for (int i = 0; i < NI; ++i) {
+          T v = T(0);
+          for (int e = 0; e < VEC; ++e) v += dvq[i][e] * s_v[16 * w + VEC * cp + e];
+          for (int off = 1; off < CPL; off <<= 1) v += __shfl_xor(v, off, CPL);
+          if (cp == 0) s_red[w][rg + RG * i] = v;
+        }
+      } else {
+        T a2[VEC];
+        for (int e = 0; e < VEC; ++e) a2[e] = T(0);
+        for (int i = 0; i < NI; ++i)
+          for (int e = 0; e < VEC; ++e) a2[e] += dvq[i][e] * s_v[16 * w + RPI * i + lr];
+        for (int e = 0; e < VEC; ++e) {
+          T v = a2[e];
+          for (int off = LPR; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+          if (lr == 0) s_red[w][VEC * lc + e] = v;
+        }
+      }
+      __syncthreads();
+      if (tid < NB) {
+        T o = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
+        if (k * NB + tid >= nlim) o = T(0);
+        s_out[tid] = o;
+        store_published(my_sol + k * NB + tid, o);
+        if (!FWD) {
+          const int a = k * NB + tid;
+          if (a < nlim) {
+            const int64_t l = D.loc_off + a;
+            const int g = A.gmap[l];
+            A.zout[g] = (A.base ? A.base[g] : 0.0) + A.dsc[l] * double(o);
+          }
+        }
+      }
+      __syncthreads();
+    };
+
+    finish(0, kr0, acc0, dv0);
+    if (nr > 1) {
+      if (inner) {
+        // the first row's block, from LDS
+        T xv[FWD ? VEC : NI];
+        if (FWD) {
+          for (int e = 0; e < VEC; ++e) xv[e] = s_out[16 * w + VEC * cp + e];
+        } else {
+          for (int i = 0; i < NI; ++i) xv[i] = s_out[16 * w + RPI * i + lr];
+        }
+        mac(acc1, ti, xv);
+      }
+      __syncthreads();   // s_out is overwritten by the second row
+      finish(1, kr1, acc1, dv1);
+    }
+  }
+}
+
+template <typename T>
+static void launch_trsv2_t(int mode, const TrsvArgs& a, int grid, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
+  const dim3 g(grid), b(256);
+  if (mode == TRSV_FWD_II) launch_timed(trsv2_kernel<T, TRSV_FWD_II>, g, b, st, t0, t1, a);
+  else launch_timed(trsv2_kernel<T, TRSV_BWD_II>, g, b, st, t0, t1, a);
+}
+
+void launch_trsv2(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
+  if (a.ntasks <= 0) return;
+  if (fp32) launch_trsv2_t<float>(mode, a, grid, st, t0, t1);
+  else launch_trsv2_t<double>(mode, a, grid, st, t0, t1);
+}
+
 template <typename T>
 static void launch_trsv_t(int mode, const TrsvArgs& a, int grid, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
   const dim3 g(grid), b(256);
   switch (mode) {
     case TRSV_FWD_RR: launch_timed(trsv_kernel<T, TRSV_FWD_RR>, g, b, st, t0, t1, a); break;
     case TRSV_BWD_RR: launch_timed(trsv_kernel<T, TRSV_BWD_RR>, g, b, st, t0, t1, a); break;
-    case TRSV_FWD_II: launch_timed(trsv_kernel<T, TRSV_FWD_II>, g, b, st, t0, t1, a); break;
-    case TRSV_BWD_II: launch_timed(trsv_kernel<T, TRSV_BWD_II>, g, b, st, t0, t1, a); break;
     case TRSV_FWD_C: launch_timed(trsv_kernel<T, TRSV_FWD_C>, g, b, st, t0, t1, a); break;
     case TRSV_BWD_C: launch_timed(trsv_kernel<T, TRSV_BWD_C>, g, b, st, t0, t1, a); break;
   }
@@ -974,6 +1203,10 @@ static void launch_trsv_t(int mode, const TrsvArgs& a, int grid, hipStream_t st,
 
 void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
   if (a.ntasks <= 0) return;
+  if (mode == TRSV_FWD_II || mode == TRSV_BWD_II) {
+    launch_trsv2(mode, fp32, a, grid, st, t0, t1);
+    return;
+  }
   if (fp32 && mode != TRSV_FWD_C && mode != TRSV_BWD_C)
     launch_trsv_t<float>(mode, a, grid, st, t0, t1);
   else

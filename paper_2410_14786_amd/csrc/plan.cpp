@@ -448,9 +448,11 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
   }
 
   // ---- task lists: forward passes by tile row, backward passes from the bottom ----
+  // (interior passes: two tile rows per task, the task names the first)
   auto make_tasks = [&](std::vector<int32_t>& out, bool interior_only, bool backward) {
     int maxT = interior_only ? P.maxTI : P.maxT;
-    for (int d = 0; d < maxT; ++d)
+    const int step = interior_only ? 2 : 1;
+    for (int d = 0; d < maxT; d += step)
       for (int s = 0; s < P.nsubs; ++s) {
         int T = interior_only ? P.subs[s].TI : P.subs[s].T;
         if (d < T) {
