@@ -46,6 +46,12 @@ notes):
     residual is zero on subdomain-interior dofs, where the three-part
     preconditioner is symmetric;
   * stopping test ||r_k||_2 <= rtol ||b||_2, confirmed on the true residual.
+
+Beyond the paper (which fixes w = 1/kappa): coefficient-aware weights
+(`weights="rho"`, rho-scaling): rho_i(x) is the largest conductivity among the
+elements of subdomain i that contain node x, and w_i(x) = rho_i(x) / sum_j
+rho_j(x) over the subdomains j sharing x.  They form a partition of unity and
+equal 1/kappa when theta is constant.  The rest of the method is unchanged.
 """
 from __future__ import annotations
 
@@ -255,7 +261,7 @@ class BDDC:
     """The BDDC preconditioner of the paper (Sec. 2) on a box partition."""
 
     def __init__(self, dim: int, nel: Sequence[int], cuts: Sequence[np.ndarray],
-                 theta: np.ndarray, constraints: int):
+                 theta: np.ndarray, constraints: int, weights: str = "kappa"):
         self.mesh = Mesh(dim, tuple(int(n) for n in nel))
         self.cuts = [np.asarray(c, dtype=np.int64) for c in cuts]
         self.theta = np.asarray(theta, dtype=np.float64)
@@ -282,9 +288,33 @@ class BDDC:
         for s in self.subs:
             s.W = 1.0 / self.kappa[s.R]
             s.interior = np.nonzero(self.kappa[s.R] == 1)[0]
+        if weights == "rho":
+            self._rho_weights()
+        elif weights != "kappa":
+            raise ValueError("weights must be 'kappa' or 'rho'")
         self.classes = classify_interface(self.mesh, self.subs)
         self._build_constraints()
         self._build_coarse()
+
+    def _rho_weights(self):
+        """rho-scaling: rho_i(x) = max theta over subdomain i's elements that
+        contain x; w_i(x) = rho_i(x) / sum_j rho_j(x)."""
+        rho = []
+        for s in self.subs:
+            d = self.mesh.element_dofs(s.elems)          # (n_elems, corners), -1 for Dirichlet
+            r = np.zeros(len(s.R))
+            for e in range(len(s.elems)):
+                th = self.theta[s.elems[e]]
+                for g in d[e]:
+                    if g >= 0:
+                        k = np.searchsorted(s.R, g)
+                        r[k] = max(r[k], th)
+            rho.append(r)
+        total = np.zeros(self.n)
+        for s, r in zip(self.subs, rho):
+            np.add.at(total, s.R, r)
+        for s, r in zip(self.subs, rho):
+            s.W = r / total[s.R]
 
     # -- constraints C_i (Sec. 2) -------------------------------------------------
     def _active(self, cl: InterfaceClass) -> bool:

@@ -476,3 +476,48 @@ def test_planted_transposed_coarse_basis_is_caught():
     sym = np.abs(M - M.T).max() / np.abs(M).max()
     ev = np.sort(np.real(np.linalg.eigvals(M @ S)))
     assert sym > 1e-6 or ev[0] < 1 - 1e-6
+
+
+# -- coefficient-aware weights (rho-scaling, an extension beyond the paper) --------------
+
+def test_rho_weights_partition_of_unity_and_kappa_limit():
+    """rho weights sum to one over the subdomains sharing each dof, and with a
+    constant conductivity they are exactly the paper's 1/kappa."""
+    w = W.make_workload("t", 3, (8, 6, 7), cuts=[[0, 3, 8], [0, 2, 6], [0, 4, 7]], theta="lognormal", seed=2)
+    P = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints, weights="rho")
+    tot = np.zeros(P.n)
+    for s in P.subs:
+        np.add.at(tot, s.R, s.W)
+    assert np.abs(tot - 1.0).max() <= 1e-14
+    c = O.BDDC(w.dim, w.nel, w.cuts, np.full_like(w.theta, 2.5), w.constraints, weights="rho")
+    for s in c.subs:
+        assert np.array_equal(s.W, 1.0 / c.kappa[s.R])
+
+
+def test_rho_weights_two_box_values():
+    """Two boxes side by side with conductivities 1 and 4: a node on the cut gets
+    the weights 1/5 and 4/5 (largest conductivity among each box's elements at
+    the node), nodes elsewhere weight 1."""
+    nel, cuts = (6, 4), [np.array([0, 3, 6]), np.array([0, 4])]
+    mesh = O.Mesh(2, nel)
+    ec = mesh.element_coords()
+    theta = np.where(ec[:, 0] < 3, 1.0, 4.0)
+    P = O.BDDC(2, nel, cuts, theta, W.CORNERS | W.EDGES, weights="rho")
+    for i, s in enumerate(P.subs):
+        on_cut = P.kappa[s.R] == 2
+        assert on_cut.sum() == 3            # the free nodes x = 3, y = 1..3
+        assert np.allclose(s.W[on_cut], 0.2 if i == 0 else 0.8, rtol=0, atol=1e-15)
+        assert np.all(s.W[~on_cut] == 1.0)
+
+
+def test_rho_weights_pcg_solves_the_system():
+    """BDDC-PCG with rho weights still converges to the sparse-direct solution, in
+    no more iterations than with 1/kappa on a lognormal coefficient."""
+    w = W.make_workload("t", 3, (8, 8, 8), (2, 2, 2), theta="lognormal", seed=1)
+    Pr = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints, weights="rho")
+    Pk = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints)
+    x_ref = spla.spsolve(Pr.A.tocsc(), w.b)
+    rr = O.bddc_pcg(Pr, w.b, 1e-10)
+    rk = O.bddc_pcg(Pk, w.b, 1e-10)
+    assert np.linalg.norm(rr.x - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+    assert rr.iters <= rk.iters
