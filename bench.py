@@ -116,13 +116,15 @@ def load_traffic(kernel, workload, local_bits):
     return None
 
 
-def run_gpu(w, steps, warmup, local_bits, use_graph=False, full_space=False, autotune=True, timing=True):
+def run_gpu(w, steps, warmup, local_bits, use_graph=False, full_space=False, autotune=True, timing=True,
+            rho_scaling=False):
     import torch
     from paper_2410_14786_amd import bddc
     families = FULL_FAMILIES if full_space else IFACE_FAMILIES
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    S = bddc.solver_for(w, local_bits=local_bits, use_graph=use_graph, full_space=full_space)
+    S = bddc.solver_for(w, local_bits=local_bits, use_graph=use_graph, full_space=full_space,
+                        rho_scaling=rho_scaling)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     tune = S.autotune(cache="") if autotune else None
@@ -195,6 +197,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the run that replays captured HIP graphs")
     ap.add_argument("--local-bits", type=int, default=64)
+    ap.add_argument("--no-rho", action="store_true", help="skip the run with coefficient-aware weights")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 512 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -228,6 +231,8 @@ def main():
         runs["graph"] = run_gpu(w, args.steps, args.warmup, main_bits, use_graph=True, timing=False)
     if not args.no_full_space:
         runs["full_space"] = run_gpu(w, args.steps, args.warmup, main_bits, full_space=True)
+    if not args.no_rho:
+        runs["rho_scaling"] = run_gpu(w, args.steps, args.warmup, main_bits, timing=False, rho_scaling=True)
     if not args.no_fp32 and main_bits == 64:
         runs["fp32_local"] = run_gpu(w, args.steps, args.warmup, 32, timing=False)
         runs["fp32_local_timed"] = run_gpu(w, args.steps, args.warmup, 32)
@@ -307,6 +312,9 @@ def main():
         out["graph"] = summarize(runs["graph"], main_bits)
     if "full_space" in runs:
         out["full_space"] = summarize(runs["full_space"], main_bits)
+    if "rho_scaling" in runs:
+        out["rho_scaling"] = summarize(runs["rho_scaling"], main_bits)
+        out["rho_scaling"]["weights"] = "rho-scaling (coefficient-aware; the paper fixes 1/kappa)"
     if "fp32_local" in runs:
         f = summarize(runs["fp32_local"], 32)
         f["cg_space"] = "interface"

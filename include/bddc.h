@@ -81,6 +81,14 @@ enum { BDDC_SETUP_KEEP_ON_ERROR = 1 };
  * interface matrices) in FP32; see bddc_options.local_bits. */
 enum { BDDC_SETUP_FULL_SPACE = 2 };
 
+/* Setup option flag, beyond the paper (which fixes w = 1/kappa, Sec. 2):
+ * coefficient-aware weights (rho-scaling).  rho_i(x) is the largest
+ * conductivity among subdomain i's elements that contain node x and
+ * w_i(x) = rho_i(x) / sum_j rho_j(x) over the subdomains sharing x: a partition
+ * of unity that equals 1/kappa for a constant conductivity.  Only the weights
+ * W_i change; every step of the method is otherwise the same. */
+enum { BDDC_SETUP_RHO_SCALING = 4 };
+
 /* Solve flags. */
 enum { BDDC_X0_GIVEN = 1 /* use x on entry as the initial guess */ };
 
@@ -122,7 +130,8 @@ typedef struct {
   int32_t use_graph;    /* 1: replay PCG iterations from a captured HIP graph   */
   int32_t nb_override;  /* 0 = default tile size (64); other values: ENOTIMPL   */
   void* stream;         /* hipStream_t for all work of this ctx                 */
-  int32_t flags;        /* BDDC_SETUP_FULL_SPACE and/or BDDC_SETUP_KEEP_ON_ERROR */
+  int32_t flags;        /* BDDC_SETUP_FULL_SPACE, BDDC_SETUP_RHO_SCALING and/or
+                           BDDC_SETUP_KEEP_ON_ERROR */
 } bddc_options;
 
 typedef struct {

@@ -96,6 +96,7 @@ struct bddc_ctx {
   hipStream_t st = nullptr;
   bool fp32 = false;                // local factors and triangular solves in FP32
   bool pc32 = false;                // interface form: preconditioner matrices in FP32
+  bool rho_scaling = false;         // coefficient-aware weights instead of 1/kappa
   bool use_graph = false;
   bool iface = true;                // interface-restricted CG (see bddc.h)
   MeshDevHost mesh{};
@@ -761,6 +762,12 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   launch_fill<double>(c->aci, 0.0, small, st);
   int max_ni = 1;
   for (auto& D : P.subs) max_ni = std::max(max_ni, int(D.n_i));
+  if (c->rho_scaling) {
+    double* rho;
+    if ((rc_ = c->alloc(rho, P.n_loc))) return rc_;
+    launch_rho_weights(c->mesh, c->theta, c->mats, P.nsubs, max_ni, c->gmap, c->inv_ptr, c->inv, P.n_free, rho,
+                       c->wgt, st);
+  }
   launch_local_assembly(c->mesh, c->theta, c->mats, P.nsubs, max_ni, c->gmap, c->lmap, c->wgt, c->dsc, c->wd,
                         c->avg_of, c->avg_coef, c->tiles, c->fp32, c->app, c->err + 1, st);
   if ((rc_ = c->alloc(c->ifc_dsc, int64_t(P.ifc_l.size()) + 1))) return rc_;
@@ -925,7 +932,7 @@ int bddc_setup(const bddc_mesh* mesh, const bddc_partition* part, const bddc_coe
   if (!opts) return fail(BDDC_EINVAL, "options are NULL");
   if (opts->local_bits != 32 && opts->local_bits != 64) return fail(BDDC_EINVAL, "local_bits must be 32 or 64");
   if (opts->nb_override != 0 && opts->nb_override != NB) return fail(BDDC_ENOTIMPL, "only 64-wide tiles are built");
-  if (opts->flags & ~(BDDC_SETUP_KEEP_ON_ERROR | BDDC_SETUP_FULL_SPACE))
+  if (opts->flags & ~(BDDC_SETUP_KEEP_ON_ERROR | BDDC_SETUP_FULL_SPACE | BDDC_SETUP_RHO_SCALING))
     return fail(BDDC_EINVAL, "unknown options.flags bits");
   bddc_ctx* c = new (std::nothrow) bddc_ctx();
   if (!c) return fail(BDDC_ENOMEM, "host allocation failed");
@@ -948,6 +955,7 @@ int bddc_setup(const bddc_mesh* mesh, const bddc_partition* part, const bddc_coe
   }
   c->st = static_cast<hipStream_t>(opts->stream);
   c->use_graph = opts->use_graph != 0;
+  c->rho_scaling = (opts->flags & BDDC_SETUP_RHO_SCALING) != 0;
   c->iface = !(opts->flags & BDDC_SETUP_FULL_SPACE);
   // the interface mat-vec packs a tile's row distance into 8 bits: at most
   // IFACE_MAX_TS tile rows per subdomain; larger boxes iterate on the whole space

@@ -110,6 +110,10 @@ template <typename T> void launch_fill_sentinel(T* p, int64_t n, hipStream_t st)
 void launch_check_theta(const double* theta, int64_t n, int* err, hipStream_t st);
 void launch_assemble_csr(const MeshDevHost& m, const double* theta, const int32_t* rowptr, int32_t* col,
                          double* val, int64_t n, int* err, hipStream_t st);
+// rho-scaling weights into wgt (per local dof); rho: scratch of n_loc doubles
+void launch_rho_weights(const MeshDevHost& m, const double* theta, const MatDesc* mats, int nmats, int max_ni,
+                        const int32_t* gmap, const int32_t* inv_ptr, const int32_t* inv, int64_t n_free,
+                        double* rho, double* wgt, hipStream_t st);
 void launch_local_assembly(const MeshDevHost& m, const double* theta, const MatDesc* mats, int nmats, int max_ni,
                            const int32_t* gmap, const int32_t* lmap, const double* wgt, double* dsc, double* wd,
                            const int32_t* avg_of, const double* avg_coef, void* tiles, bool fp32, double* app,

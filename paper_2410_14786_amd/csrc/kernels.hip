@@ -246,6 +246,42 @@ void launch_check_theta(const double* theta, int64_t n, int* err, hipStream_t st
 // Local (subdomain) assembly into equilibrated tiles
 // ---------------------------------------------------------------------------
 
+// Coefficient-aware weights (rho-scaling, an option beyond the paper's 1/kappa):
+// rho_i(x) = the largest conductivity among subdomain i's elements that contain
+// node x, w_i(x) = rho_i(x) / sum_j rho_j(x) over the subdomains sharing x.
+__global__ void rho_local_kernel(MeshDev M, const double* theta, const MatDesc* mats, const int32_t* gmap,
+                                 double* rho) {
+  const MatDesc D = mats[blockIdx.y];
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.n_i) return;
+  int c[3];
+  free_coords(M, gmap[D.loc_off + a], c);
+  int e0[3], e1[3];
+  for (int d = 0; d < 3; ++d) {
+    if (d >= M.dim) {
+      e0[d] = e1[d] = 0;
+      continue;
+    }
+    e0[d] = max(c[d] - 1, int(D.box_lo[d]));
+    e1[d] = min(c[d], int(D.box_lo[d] + D.box_len[d]) - 1);
+  }
+  double r = 0.0;
+  for (int ez = e0[2]; ez <= e1[2]; ++ez)
+    for (int ey = e0[1]; ey <= e1[1]; ++ey)
+      for (int ex = e0[0]; ex <= e1[0]; ++ex)
+        r = fmax(r, theta[ex + int64_t(M.nel[0]) * (ey + int64_t(M.nel[1]) * ez)]);
+  rho[D.loc_off + a] = r;
+}
+
+__global__ void rho_normalize_kernel(const int32_t* inv_ptr, const int32_t* inv, const double* rho, double* wgt,
+                                     int64_t n) {
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x) {
+    double t = 0.0;
+    for (int q = inv_ptr[g]; q < inv_ptr[g + 1]; ++q) t += rho[inv[q]];
+    for (int q = inv_ptr[g]; q < inv_ptr[g + 1]; ++q) wgt[inv[q]] = rho[inv[q]] / t;
+  }
+}
+
 // local dof a of matrix s -> box-local node coordinates
 __device__ __forceinline__ void local_node(const MeshDev& M, const MatDesc& D, const int32_t* gmap, int a,
                                            int c[3]) {
@@ -333,6 +369,16 @@ __global__ void pad_identity_kernel(const MatDesc* mats, T* tiles) {
   if (D.T == 0 || r >= D.T * NB) return;
   int64_t t = D.tile_off + tri_tile(D.T - 1, D.T - 1);
   tiles[t * NB * NB + (r % NB) * NB + (r % NB)] = T(1);
+}
+
+void launch_rho_weights(const MeshDevHost& m, const double* theta, const MatDesc* mats, int nmats, int max_ni,
+                        const int32_t* gmap, const int32_t* inv_ptr, const int32_t* inv, int64_t n_free,
+                        double* rho, double* wgt, hipStream_t st) {
+  MeshDev M{m.dim, {m.nel[0], m.nel[1], m.nel[2]}, {m.h[0], m.h[1], m.h[2]}};
+  hipLaunchKernelGGL(rho_local_kernel, dim3((max_ni + 255) / 256, nmats), dim3(256), 0, st, M, theta, mats, gmap,
+                     rho);
+  hipLaunchKernelGGL(rho_normalize_kernel, dim3(grid_for(n_free, 256, 4096)), dim3(256), 0, st, inv_ptr, inv, rho,
+                     wgt, n_free);
 }
 
 void launch_local_assembly(const MeshDevHost& mh, const double* theta, const MatDesc* mats, int nmats,

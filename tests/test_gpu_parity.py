@@ -340,3 +340,41 @@ def test_autotune_keeps_results_bitwise(full_space, tmp_path):
         assert same(host(x2), x0)
     S.close()
     S2.close()
+
+
+_rho_oracles = {}
+
+
+def rho_oracle_for(name):
+    if name not in _rho_oracles:
+        w = CASES[name]()
+        _rho_oracles[name] = (w, O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints, weights="rho"))
+    return _rho_oracles[name]
+
+
+@pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
+@pytest.mark.parametrize("name", ["3d_12x10x14_uneven", "3d_24_3x3x3_inclusions", "2d_20x24_uneven"])
+def test_rho_scaling_matches_oracle(name, full_space):
+    """Coefficient-aware weights (rho-scaling, beyond the paper): the same
+    preconditioner as the oracle's with weights="rho" (apply to 1e-10), the same
+    PCG iterates after a fixed number of steps, iteration count and Lanczos
+    estimate."""
+    w, P = rho_oracle_for(name)
+    S = bd().solver_for(w, full_space=full_space, rho_scaling=True)
+    r = np.random.default_rng(11).standard_normal(P.n)
+    e = rel(host(S.apply(dev(r))), P.apply(r))
+    say(name, "rho apply rel err", e)
+    assert e <= 1e-10
+    ref = O.bddc_pcg(P, w.b, w.rtol)
+    K = max(ref.iters - 2, 1)
+    refK = O.bddc_pcg(P, w.b, 1e-300, maxit=K)
+    xK, info = S.solve(dev(w.b), 1e-15, maxit=K, raise_on_noconv=False)
+    e = rel(host(xK), refK.x)
+    say(name, "rho K", K, "iterate rel err", e)
+    assert info["iters"] == K and e <= 1e-10
+    x, info = S.solve(dev(w.b), w.rtol)
+    say(name, "rho iters gpu", info["iters"], "oracle", ref.iters, "cond", info["cond_est"], ref.cond_est)
+    assert abs(info["iters"] - ref.iters) <= 1
+    assert info["relres_true"] <= w.rtol
+    assert abs(info["cond_est"] - ref.cond_est) <= 1e-6 * ref.cond_est + 1e-8
+    S.close()
