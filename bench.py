@@ -117,14 +117,14 @@ def load_traffic(kernel, workload, local_bits):
 
 
 def run_gpu(w, steps, warmup, local_bits, use_graph=False, full_space=False, autotune=True, timing=True,
-            rho_scaling=False):
+            rho_scaling=False, coarse_cg=False):
     import torch
     from paper_2410_14786_amd import bddc
     families = FULL_FAMILIES if full_space else IFACE_FAMILIES
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S = bddc.solver_for(w, local_bits=local_bits, use_graph=use_graph, full_space=full_space,
-                        rho_scaling=rho_scaling)
+                        rho_scaling=rho_scaling, coarse_cg=coarse_cg)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     tune = S.autotune(cache="") if autotune else None
@@ -198,6 +198,7 @@ def main():
                     help="skip the run that replays captured HIP graphs")
     ap.add_argument("--local-bits", type=int, default=64)
     ap.add_argument("--no-rho", action="store_true", help="skip the run with coefficient-aware weights")
+    ap.add_argument("--no-coarse-cg", action="store_true", help="skip the run with the coarse problem by CG")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 512 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -233,6 +234,8 @@ def main():
         runs["full_space"] = run_gpu(w, args.steps, args.warmup, main_bits, full_space=True)
     if not args.no_rho:
         runs["rho_scaling"] = run_gpu(w, args.steps, args.warmup, main_bits, timing=False, rho_scaling=True)
+    if not args.no_coarse_cg:
+        runs["coarse_cg"] = run_gpu(w, args.steps, args.warmup, main_bits, timing=False, coarse_cg=True)
     if not args.no_fp32 and main_bits == 64:
         runs["fp32_local"] = run_gpu(w, args.steps, args.warmup, 32, timing=False)
         runs["fp32_local_timed"] = run_gpu(w, args.steps, args.warmup, 32)
@@ -315,6 +318,9 @@ def main():
     if "rho_scaling" in runs:
         out["rho_scaling"] = summarize(runs["rho_scaling"], main_bits)
         out["rho_scaling"]["weights"] = "rho-scaling (coefficient-aware; the paper fixes 1/kappa)"
+    if "coarse_cg" in runs:
+        out["coarse_cg"] = summarize(runs["coarse_cg"], main_bits)
+        out["coarse_cg"]["coarse_solve"] = "Jacobi-preconditioned CG to 1e-13 (the paper's choice) at every apply"
     if "fp32_local" in runs:
         f = summarize(runs["fp32_local"], 32)
         f["cg_space"] = "interface"

@@ -89,6 +89,14 @@ enum { BDDC_SETUP_FULL_SPACE = 2 };
  * W_i change; every step of the method is otherwise the same. */
 enum { BDDC_SETUP_RHO_SCALING = 4 };
 
+/* Setup option flag: solve the coarse problem of eq. (2) by CG, as the paper
+ * does (Sec. 3), instead of the dense FP64 Cholesky factor (whole space) or its
+ * explicit inverse (interface form): Jacobi-preconditioned CG on the assembled
+ * A_c from zero to a relative residual of 1e-13 (at most 2000 iterations) in
+ * one workgroup at every application of the preconditioner.  The explicit
+ * forms are faster on one GPU; this one follows the paper. */
+enum { BDDC_SETUP_COARSE_CG = 8 };
+
 /* Solve flags. */
 enum { BDDC_X0_GIVEN = 1 /* use x on entry as the initial guess */ };
 
@@ -130,8 +138,8 @@ typedef struct {
   int32_t use_graph;    /* 1: replay PCG iterations from a captured HIP graph   */
   int32_t nb_override;  /* 0 = default tile size (64); other values: ENOTIMPL   */
   void* stream;         /* hipStream_t for all work of this ctx                 */
-  int32_t flags;        /* BDDC_SETUP_FULL_SPACE, BDDC_SETUP_RHO_SCALING and/or
-                           BDDC_SETUP_KEEP_ON_ERROR */
+  int32_t flags;        /* BDDC_SETUP_FULL_SPACE, BDDC_SETUP_RHO_SCALING,
+                           BDDC_SETUP_COARSE_CG and/or BDDC_SETUP_KEEP_ON_ERROR */
 } bddc_options;
 
 typedef struct {

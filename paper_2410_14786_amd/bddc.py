@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libbddc.so")
 
 CORNERS, EDGES, FACES, ALL_PRIMAL = 1, 2, 4, 8
 X0_GIVEN = 1
-SETUP_KEEP_ON_ERROR, SETUP_FULL_SPACE, SETUP_RHO_SCALING = 1, 2, 4
+SETUP_KEEP_ON_ERROR, SETUP_FULL_SPACE, SETUP_RHO_SCALING, SETUP_COARSE_CG = 1, 2, 4, 8
 
 OK, EINVAL, ENOTSPD, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, ENOTIMPL = 0, -1, -2, -3, -4, -5, -6, -7
 
@@ -141,7 +141,7 @@ class Solver:
 
     def __init__(self, dim: int, nel: Sequence[int], cuts: Sequence[Sequence[int]], theta, constraints: int,
                  local_bits: int = 64, use_graph: bool = False, stream=None, keep_on_error: bool = False,
-                 full_space: bool = False, rho_scaling: bool = False):
+                 full_space: bool = False, rho_scaling: bool = False, coarse_cg: bool = False):
         import torch
         self.lib = load_library()
         self.dim = dim
@@ -166,7 +166,7 @@ class Solver:
         opt.nb_override = 0
         opt.stream = stream.cuda_stream
         opt.flags = ((SETUP_KEEP_ON_ERROR if keep_on_error else 0) | (SETUP_FULL_SPACE if full_space else 0)
-                     | (SETUP_RHO_SCALING if rho_scaling else 0))
+                     | (SETUP_RHO_SCALING if rho_scaling else 0) | (SETUP_COARSE_CG if coarse_cg else 0))
         ctx = ctypes.c_void_p()
         code = self.lib.bddc_setup(ctypes.byref(m), ctypes.byref(p), ctypes.byref(co), constraints,
                                    ctypes.byref(opt), ctypes.byref(ctx))
@@ -183,7 +183,8 @@ class Solver:
         box = sorted({tuple(int(c[i + 1] - c[i]) for i in range(len(c) - 1)) for c in
                       (np.asarray(cc) for cc in cuts[:dim])})
         self.tune_key = (f"dim{dim}|nel{'x'.join(map(str, self.nel))}|boxes{box}|bits{local_bits}|"
-                         f"{'full' if full_space else 'iface'}|graph{int(use_graph)}|rho{int(rho_scaling)}")
+                         f"{'full' if full_space else 'iface'}|graph{int(use_graph)}|rho{int(rho_scaling)}|"
+                         f"ccg{int(coarse_cg)}")
 
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
@@ -306,11 +307,11 @@ class Solver:
 
 
 def solver_for(w, local_bits: Optional[int] = None, use_graph: bool = False, full_space: bool = False,
-               rho_scaling: bool = False) -> Solver:
+               rho_scaling: bool = False, coarse_cg: bool = False) -> Solver:
     """Solver for a workloads.Workload."""
     return Solver(w.dim, w.nel, w.cuts, w.theta, w.constraints,
                   local_bits=w.local_bits if local_bits is None else local_bits, use_graph=use_graph,
-                  full_space=full_space, rho_scaling=rho_scaling)
+                  full_space=full_space, rho_scaling=rho_scaling, coarse_cg=coarse_cg)
 
 
 def _autograd_function():

@@ -18,6 +18,11 @@
 using namespace bddc;
 
 namespace {
+constexpr double COARSE_CG_TOL = 1e-13;   // coarse CG: relative residual
+constexpr int COARSE_CG_MAXIT = 2000;
+}  // namespace
+
+namespace {
 
 thread_local std::string g_last_error;
 
@@ -97,6 +102,9 @@ struct bddc_ctx {
   bool fp32 = false;                // local factors and triangular solves in FP32
   bool pc32 = false;                // interface form: preconditioner matrices in FP32
   bool rho_scaling = false;         // coefficient-aware weights instead of 1/kappa
+  bool coarse_cg = false;           // coarse problem by CG instead of the dense factor / inverse
+  int32_t *ac_rowptr = nullptr, *ac_fcol = nullptr, *ac_fsrc = nullptr;   // full CSR of A_c (coarse CG)
+  double* ccg_work = nullptr;       // coarse CG vectors (3 n_c)
   bool use_graph = false;
   bool iface = true;                // interface-restricted CG (see bddc.h)
   MeshDevHost mesh{};
@@ -361,13 +369,18 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
     cf.cinv = c->cinv;
     cf.gbuf = c->gbuf;
     cf.dc = c->dc;
-    launch_trsv(TRSV_FWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
-    cf.tasks = c->ctask_bwd;
-    cf.ticket = c->tickets + 5;
-    cf.src = c->pub_coarse;
-    cf.sol = c->pub_coarse + int64_t(c->Tc) * NB;
-    cf.uc = c->uc;
-    launch_trsv(TRSV_BWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
+    if (c->coarse_cg) {
+      launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fsrc, c->ac_val, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
+                       c->gbuf, c->uc, c->ccg_work, COARSE_CG_TOL, COARSE_CG_MAXIT, done, st);
+    } else {
+      launch_trsv(TRSV_FWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
+      cf.tasks = c->ctask_bwd;
+      cf.ticket = c->tickets + 5;
+      cf.src = c->pub_coarse;
+      cf.sol = c->pub_coarse + int64_t(c->Tc) * NB;
+      cf.uc = c->uc;
+      launch_trsv(TRSV_BWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
+    }
     launch_coarse_coef(c->mats, P.nsubs, c->rc, c->uc, c->mu, c->sainv, c->sainve, c->wgt, c->coef, c->ww, done,
                        st);
   }
@@ -494,7 +507,11 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
   if (P.n_coarse > 0) {
     launch_coarse_prep(c->mats, P.nsubs, nullptr, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done,
                        c->rowp, a.ntiles, a.nwg, st);
-    launch_coarse_gemv(c->cainv, P.n_coarse, c->csplit, c->cinv_ptr, c->cinv, c->gbuf, c->upart, done, st);
+    if (c->coarse_cg)
+      launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fsrc, c->ac_val, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
+                       c->gbuf, c->upart, c->ccg_work, COARSE_CG_TOL, COARSE_CG_MAXIT, done, st);
+    else
+      launch_coarse_gemv(c->cainv, P.n_coarse, c->csplit, c->cinv_ptr, c->cinv, c->gbuf, c->upart, done, st);
   }
   a.uc = c->upart;
   a.nc = P.n_coarse;
@@ -810,6 +827,27 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   std::vector<MatDesc> cm(1, c->cmat_host);
   if ((rc_ = c->upload(c->cmat, cm))) return rc_;
   if ((rc_ = c->alloc(c->ac_val, int64_t(P.ac_row.size())))) return rc_;
+  if (c->coarse_cg) {
+    // CSR of the full symmetric A_c over its stored lower-triangle entries
+    struct FE { int32_t r, q, e; };
+    std::vector<FE> fe;
+    for (size_t e = 0; e < P.ac_row.size(); ++e) {
+      fe.push_back({P.ac_row[e], P.ac_col[e], int32_t(e)});
+      if (P.ac_row[e] != P.ac_col[e]) fe.push_back({P.ac_col[e], P.ac_row[e], int32_t(e)});
+    }
+    std::sort(fe.begin(), fe.end(), [](const FE& x, const FE& y) { return x.r != y.r ? x.r < y.r : x.q < y.q; });
+    std::vector<int32_t> rp(nc + 1, 0), fc, fs;
+    for (const FE& f : fe) {
+      ++rp[f.r + 1];
+      fc.push_back(f.q);
+      fs.push_back(f.e);
+    }
+    for (int p = 0; p < nc; ++p) rp[p + 1] += rp[p];
+    if ((rc_ = c->upload(c->ac_rowptr, rp))) return rc_;
+    if ((rc_ = c->upload(c->ac_fcol, fc))) return rc_;
+    if ((rc_ = c->upload(c->ac_fsrc, fs))) return rc_;
+    if ((rc_ = c->alloc(c->ccg_work, 3 * int64_t(nc) + 1))) return rc_;
+  }
   if ((rc_ = c->alloc(c->dc, nc))) return rc_;
   if ((rc_ = c->alloc(c->ctiles, tri_tile(c->Tc, 0) * NB * NB))) return rc_;
   if ((rc_ = c->alloc(c->cdinv, int64_t(c->Tc) * NB * NB))) return rc_;
@@ -833,7 +871,7 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
       // A_c^{-1} = D X^T X D, X = inverse of the coarse Cholesky factor
       if ((rc_ = c->alloc(c->cxg, tri_tile(c->Tc, 0) * NB * NB))) return rc_;
       if ((rc_ = c->alloc(c->cainv, int64_t(nc) * nc))) return rc_;
-      c->csplit = (nc + COARSE_SPLIT_COLS - 1) / COARSE_SPLIT_COLS;
+      c->csplit = c->coarse_cg ? 1 : (nc + COARSE_SPLIT_COLS - 1) / COARSE_SPLIT_COLS;
       if ((rc_ = c->alloc(c->upart, int64_t(c->csplit) * nc))) return rc_;
       launch_trailing_inverse(c->cmat, 1, c->Tc, c->ctiles, c->cdinv, c->cxg, st);
       launch_coarse_inverse(c->cxg, c->dc, nc, c->cainv, st);
@@ -932,7 +970,8 @@ int bddc_setup(const bddc_mesh* mesh, const bddc_partition* part, const bddc_coe
   if (!opts) return fail(BDDC_EINVAL, "options are NULL");
   if (opts->local_bits != 32 && opts->local_bits != 64) return fail(BDDC_EINVAL, "local_bits must be 32 or 64");
   if (opts->nb_override != 0 && opts->nb_override != NB) return fail(BDDC_ENOTIMPL, "only 64-wide tiles are built");
-  if (opts->flags & ~(BDDC_SETUP_KEEP_ON_ERROR | BDDC_SETUP_FULL_SPACE | BDDC_SETUP_RHO_SCALING))
+  if (opts->flags &
+      ~(BDDC_SETUP_KEEP_ON_ERROR | BDDC_SETUP_FULL_SPACE | BDDC_SETUP_RHO_SCALING | BDDC_SETUP_COARSE_CG))
     return fail(BDDC_EINVAL, "unknown options.flags bits");
   bddc_ctx* c = new (std::nothrow) bddc_ctx();
   if (!c) return fail(BDDC_ENOMEM, "host allocation failed");
@@ -956,6 +995,7 @@ int bddc_setup(const bddc_mesh* mesh, const bddc_partition* part, const bddc_coe
   c->st = static_cast<hipStream_t>(opts->stream);
   c->use_graph = opts->use_graph != 0;
   c->rho_scaling = (opts->flags & BDDC_SETUP_RHO_SCALING) != 0;
+  c->coarse_cg = (opts->flags & BDDC_SETUP_COARSE_CG) != 0;
   c->iface = !(opts->flags & BDDC_SETUP_FULL_SPACE);
   // the interface mat-vec packs a tile's row distance into 8 bits: at most
   // IFACE_MAX_TS tile rows per subdomain; larger boxes iterate on the whole space

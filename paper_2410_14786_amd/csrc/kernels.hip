@@ -1815,6 +1815,88 @@ void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* c
                      cinv, gbuf, upart, done);
 }
 
+// The coarse problem by CG (the paper's choice; an option beside the explicit
+// inverse): A_c u_c = r_c with r_c = sum of the subdomain shares gbuf over the
+// coarse inverse map, Jacobi-preconditioned CG (diag(A_c)^{-1} = dc^2) from
+// u_c = 0 until ||r|| <= tol ||r_c|| or maxit iterations, in one workgroup.  A_c
+// is stored as its lower-triangle entries val; the CSR (rowptr, col) of the full
+// symmetric matrix names for every entry its stored value val[src[k]].  work
+// holds 3 nc doubles.
+constexpr int CCG_BLK = 1024;
+__device__ __forceinline__ double ccg_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < CCG_BLK / 64; ++i) t += sh[i];
+  return t;
+}
+
+__global__ __launch_bounds__(CCG_BLK) void coarse_cg_kernel(const int32_t* rowptr, const int32_t* col,
+                                                           const int32_t* src, const double* val,
+                                                           const double* dc, int nc,
+                                                           const int32_t* cinv_ptr, const int32_t* cinv,
+                                                           const double* gbuf, double* u, double* work, double tol2,
+                                                           int maxit, const int* done) {
+  __shared__ double sh[CCG_BLK / 64];
+  if (done && *done) return;
+  double* r = work;
+  double* p = work + nc;
+  double* q = work + 2 * nc;
+  const int t = threadIdx.x;
+  double bb = 0.0, rz = 0.0;
+  for (int i = t; i < nc; i += CCG_BLK) {
+    double v = 0.0;
+    for (int k = cinv_ptr[i]; k < cinv_ptr[i + 1]; ++k) v += gbuf[cinv[k]];
+    r[i] = v;
+    const double z = dc[i] * dc[i] * v;
+    p[i] = z;
+    u[i] = 0.0;
+    bb += v * v;
+    rz += v * z;
+  }
+  bb = ccg_sum(bb, sh);
+  rz = ccg_sum(rz, sh);
+  if (!(bb > 0.0)) return;
+  for (int it = 0; it < maxit; ++it) {
+    __syncthreads();   // p complete
+    double pq = 0.0;
+    for (int i = t; i < nc; i += CCG_BLK) {
+      double v = 0.0;
+      for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) v += val[src[k]] * p[col[k]];
+      q[i] = v;
+      pq += p[i] * v;
+    }
+    pq = ccg_sum(pq, sh);
+    if (!(pq > 0.0)) break;
+    const double alpha = rz / pq;
+    double rr = 0.0, rzn = 0.0;
+    for (int i = t; i < nc; i += CCG_BLK) {
+      u[i] += alpha * p[i];
+      const double rv = r[i] - alpha * q[i];
+      r[i] = rv;
+      rr += rv * rv;
+      rzn += rv * dc[i] * dc[i] * rv;
+    }
+    rr = ccg_sum(rr, sh);
+    rzn = ccg_sum(rzn, sh);
+    if (rr <= tol2 * bb) break;
+    const double beta = rzn / rz;
+    rz = rzn;
+    for (int i = t; i < nc; i += CCG_BLK) p[i] = dc[i] * dc[i] * r[i] + beta * p[i];
+  }
+}
+
+void launch_coarse_cg(const int32_t* rowptr, const int32_t* col, const int32_t* src, const double* val,
+                      const double* dc, int nc, const int32_t* cinv_ptr, const int32_t* cinv, const double* gbuf,
+                      double* u, double* work, double tol, int maxit, const int* done, hipStream_t st) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(coarse_cg_kernel, dim3(1), dim3(CCG_BLK), 0, st, rowptr, col, src, val, dc, nc, cinv_ptr, cinv,
+                     gbuf, u, work, tol * tol, maxit, done);
+}
+
 // Symmetric interface matrices of a subdomain, lower tile triangle over
 // sym_tile_rows tile rows.  Rows (and columns) 0..n_G-1 are the interface rows
 // (local dofs n_I + r), rows n_G + c the constraints c < n_ci.  M = K K^T with

@@ -113,7 +113,7 @@ def test_setup_validates_before_any_device_work(lib):
     th = np.ones(64)
     assert _setup_raw(lib, th, local_bits=16)[0] == bddc.EINVAL
     assert _setup_raw(lib, th, nb=32)[0] == bddc.ENOTIMPL
-    assert _setup_raw(lib, th, flags=8)[0] == bddc.EINVAL
+    assert _setup_raw(lib, th, flags=16)[0] == bddc.EINVAL
     assert _setup_raw(lib, th, on_device=2)[0] == bddc.EINVAL
     assert _setup_raw(lib, th, cuts=((0, 7, 8), (0, 8)))[0] == bddc.EINVAL
     bad = th.copy()
