@@ -104,7 +104,9 @@ struct bddc_ctx {
   bool rho_scaling = false;         // coefficient-aware weights instead of 1/kappa
   bool coarse_cg = false;           // coarse problem by CG instead of the dense factor / inverse
   int32_t *ac_rowptr = nullptr, *ac_fcol = nullptr, *ac_fsrc = nullptr;   // full CSR of A_c (coarse CG)
-  double* ccg_work = nullptr;       // coarse CG vectors (3 n_c)
+  double* ac_fval = nullptr;        // its values
+  int ac_nfull = 0;
+  double* ccg_work = nullptr;       // coarse CG vectors (5 n_c)
   bool use_graph = false;
   bool iface = true;                // interface-restricted CG (see bddc.h)
   MeshDevHost mesh{};
@@ -370,7 +372,7 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
     cf.gbuf = c->gbuf;
     cf.dc = c->dc;
     if (c->coarse_cg) {
-      launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fsrc, c->ac_val, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
+      launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fval, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
                        c->gbuf, c->uc, c->ccg_work, COARSE_CG_TOL, COARSE_CG_MAXIT, done, st);
     } else {
       launch_trsv(TRSV_FWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
@@ -508,7 +510,7 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
     launch_coarse_prep(c->mats, P.nsubs, nullptr, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done,
                        c->rowp, a.ntiles, a.nwg, st);
     if (c->coarse_cg)
-      launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fsrc, c->ac_val, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
+      launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fval, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
                        c->gbuf, c->upart, c->ccg_work, COARSE_CG_TOL, COARSE_CG_MAXIT, done, st);
     else
       launch_coarse_gemv(c->cainv, P.n_coarse, c->csplit, c->cinv_ptr, c->cinv, c->gbuf, c->upart, done, st);
@@ -846,11 +848,14 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
     if ((rc_ = c->upload(c->ac_rowptr, rp))) return rc_;
     if ((rc_ = c->upload(c->ac_fcol, fc))) return rc_;
     if ((rc_ = c->upload(c->ac_fsrc, fs))) return rc_;
-    if ((rc_ = c->alloc(c->ccg_work, 3 * int64_t(nc) + 1))) return rc_;
+    c->ac_nfull = int(fs.size());
+    if ((rc_ = c->alloc(c->ac_fval, int64_t(fs.size())))) return rc_;
+    if ((rc_ = c->alloc(c->ccg_work, 5 * int64_t(nc) + 1))) return rc_;
   }
   if ((rc_ = c->alloc(c->dc, nc))) return rc_;
-  if ((rc_ = c->alloc(c->ctiles, tri_tile(c->Tc, 0) * NB * NB))) return rc_;
-  if ((rc_ = c->alloc(c->cdinv, int64_t(c->Tc) * NB * NB))) return rc_;
+  // (the coarse CG needs no dense coarse factor)
+  if ((rc_ = c->alloc(c->ctiles, c->coarse_cg ? 1 : tri_tile(c->Tc, 0) * NB * NB))) return rc_;
+  if ((rc_ = c->alloc(c->cdinv, c->coarse_cg ? 1 : int64_t(c->Tc) * NB * NB))) return rc_;
   if ((rc_ = c->alloc(c->pub_coarse, 2 * int64_t(c->Tc) * NB))) return rc_;
   std::vector<int32_t> cf, cb;
   for (int k = 0; k < c->Tc; ++k) {
@@ -861,7 +866,12 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   }
   if ((rc_ = c->upload(c->ctask_fwd, cf))) return rc_;
   if ((rc_ = c->upload(c->ctask_bwd, cb))) return rc_;
-  if (nc > 0) {
+  if (nc > 0 && c->coarse_cg) {
+    launch_coarse_assembly(c->ac_src_ptr, c->ac_src, c->ac_row, c->ac_col, c->ac_diag, int(P.ac_row.size()), nc,
+                           c->aci, c->ac_val, c->dc, nullptr, c->err + 2, st);
+    launch_coarse_cg_matrix(c->ac_fsrc, c->ac_val, c->ac_fval, c->ac_nfull, st);
+    if (c->iface && (rc_ = c->alloc(c->upart, nc))) return rc_;
+  } else if (nc > 0) {
     launch_fill<double>(c->ctiles, 0.0, tri_tile(c->Tc, 0) * NB * NB, st);
     launch_pad_identity(c->cmat, 1, c->ctiles, false, st);
     launch_coarse_assembly(c->ac_src_ptr, c->ac_src, c->ac_row, c->ac_col, c->ac_diag, int(P.ac_row.size()), nc,
@@ -871,7 +881,7 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
       // A_c^{-1} = D X^T X D, X = inverse of the coarse Cholesky factor
       if ((rc_ = c->alloc(c->cxg, tri_tile(c->Tc, 0) * NB * NB))) return rc_;
       if ((rc_ = c->alloc(c->cainv, int64_t(nc) * nc))) return rc_;
-      c->csplit = c->coarse_cg ? 1 : (nc + COARSE_SPLIT_COLS - 1) / COARSE_SPLIT_COLS;
+      c->csplit = (nc + COARSE_SPLIT_COLS - 1) / COARSE_SPLIT_COLS;
       if ((rc_ = c->alloc(c->upart, int64_t(c->csplit) * nc))) return rc_;
       launch_trailing_inverse(c->cmat, 1, c->Tc, c->ctiles, c->cdinv, c->cxg, st);
       launch_coarse_inverse(c->cxg, c->dc, nc, c->cainv, st);

@@ -750,8 +750,9 @@ void launch_coarse_assembly(const int32_t* src_ptr, const int32_t* src, const in
   hipLaunchKernelGGL(coarse_entries_kernel, dim3((nentries + 255) / 256), dim3(256), 0, st, src_ptr, src, aci,
                      val, nentries);
   hipLaunchKernelGGL(coarse_scale_kernel, dim3((nc + 255) / 256), dim3(256), 0, st, diag, val, dc, nc, err);
-  hipLaunchKernelGGL(coarse_write_kernel, dim3((nentries + 255) / 256), dim3(256), 0, st, row, col, val, dc,
-                     tiles, nentries);
+  if (tiles)
+    hipLaunchKernelGGL(coarse_write_kernel, dim3((nentries + 255) / 256), dim3(256), 0, st, row, col, val, dc,
+                       tiles, nentries);
 }
 
 // ---------------------------------------------------------------------------
@@ -1818,83 +1819,123 @@ void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* c
 // The coarse problem by CG (the paper's choice; an option beside the explicit
 // inverse): A_c u_c = r_c with r_c = sum of the subdomain shares gbuf over the
 // coarse inverse map, Jacobi-preconditioned CG (diag(A_c)^{-1} = dc^2) from
-// u_c = 0 until ||r|| <= tol ||r_c|| or maxit iterations, in one workgroup.  A_c
-// is stored as its lower-triangle entries val; the CSR (rowptr, col) of the full
-// symmetric matrix names for every entry its stored value val[src[k]].  work
-// holds 3 nc doubles.
+// u_c = 0 until ||r|| <= tol ||r_c|| or maxit iterations, in one workgroup.  fval
+// is the full symmetric A_c in CSR (rowptr, col), gathered once at setup from the
+// stored lower triangle.  A group of CCG_G lanes forms each row's product and the
+// group's first lane owns that row in every vector operation, so p is the only
+// vector that threads share.  With nc <= CCG_LDS_N the five vectors (r, p, q,
+// dc^2, u) live in LDS, else in work (5 nc doubles).
 constexpr int CCG_BLK = 1024;
-__device__ __forceinline__ double ccg_sum(double v, double* sh) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+constexpr int CCG_G = 16;
+constexpr int CCG_NG = CCG_BLK / CCG_G;
+constexpr int CCG_LDS_N = 1536;
+
+__device__ __forceinline__ void ccg_sum2(double& a, double& b, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
-  if (lane == 0) sh[w] = v;
+  if (lane == 0) {
+    sh[2 * w] = a;
+    sh[2 * w + 1] = b;
+  }
   __syncthreads();
-  double t = 0.0;
-  for (int i = 0; i < CCG_BLK / 64; ++i) t += sh[i];
-  return t;
+  a = 0.0;
+  b = 0.0;
+  for (int i = 0; i < CCG_BLK / 64; ++i) {
+    a += sh[2 * i];
+    b += sh[2 * i + 1];
+  }
 }
 
+template <bool SH>
 __global__ __launch_bounds__(CCG_BLK) void coarse_cg_kernel(const int32_t* rowptr, const int32_t* col,
-                                                           const int32_t* src, const double* val,
-                                                           const double* dc, int nc,
+                                                           const double* fval, const double* dc, int nc,
                                                            const int32_t* cinv_ptr, const int32_t* cinv,
                                                            const double* gbuf, double* u, double* work, double tol2,
                                                            int maxit, const int* done) {
-  __shared__ double sh[CCG_BLK / 64];
+  __shared__ double sh[2 * (CCG_BLK / 64)];
+  __shared__ double sv[SH ? 5 * CCG_LDS_N : 1];
   if (done && *done) return;
-  double* r = work;
-  double* p = work + nc;
-  double* q = work + 2 * nc;
-  const int t = threadIdx.x;
+  const int ld = SH ? CCG_LDS_N : nc;
+  double* r = SH ? sv : work;
+  double* p = r + ld;
+  double* q = r + 2 * ld;
+  double* dd = r + 3 * ld;
+  double* uu = r + 4 * ld;
+  const int t = threadIdx.x, g = t / CCG_G, l = t % CCG_G;
+  const bool own = (l == 0);
   double bb = 0.0, rz = 0.0;
-  for (int i = t; i < nc; i += CCG_BLK) {
-    double v = 0.0;
-    for (int k = cinv_ptr[i]; k < cinv_ptr[i + 1]; ++k) v += gbuf[cinv[k]];
-    r[i] = v;
-    const double z = dc[i] * dc[i] * v;
-    p[i] = z;
-    u[i] = 0.0;
-    bb += v * v;
-    rz += v * z;
-  }
-  bb = ccg_sum(bb, sh);
-  rz = ccg_sum(rz, sh);
-  if (!(bb > 0.0)) return;
-  for (int it = 0; it < maxit; ++it) {
-    __syncthreads();   // p complete
-    double pq = 0.0;
-    for (int i = t; i < nc; i += CCG_BLK) {
+  if (own)
+    for (int i = g; i < nc; i += CCG_NG) {
       double v = 0.0;
-      for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) v += val[src[k]] * p[col[k]];
-      q[i] = v;
-      pq += p[i] * v;
+      for (int k = cinv_ptr[i]; k < cinv_ptr[i + 1]; ++k) v += gbuf[cinv[k]];
+      const double d2 = dc[i] * dc[i];
+      r[i] = v;
+      dd[i] = d2;
+      p[i] = d2 * v;
+      uu[i] = 0.0;
+      bb += v * v;
+      rz += v * d2 * v;
     }
-    pq = ccg_sum(pq, sh);
+  ccg_sum2(bb, rz, sh);
+  for (int it = 0; it < maxit && bb > 0.0; ++it) {
+    __syncthreads();   // p complete
+    double pq = 0.0, unused = 0.0;
+    for (int i = g; i < nc; i += CCG_NG) {
+      double v = 0.0;
+      for (int k = rowptr[i] + l; k < rowptr[i + 1]; k += CCG_G) v += fval[k] * p[col[k]];
+      for (int o = CCG_G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, CCG_G);
+      if (own) {
+        q[i] = v;
+        pq += p[i] * v;
+      }
+    }
+    ccg_sum2(pq, unused, sh);
     if (!(pq > 0.0)) break;
     const double alpha = rz / pq;
     double rr = 0.0, rzn = 0.0;
-    for (int i = t; i < nc; i += CCG_BLK) {
-      u[i] += alpha * p[i];
-      const double rv = r[i] - alpha * q[i];
-      r[i] = rv;
-      rr += rv * rv;
-      rzn += rv * dc[i] * dc[i] * rv;
-    }
-    rr = ccg_sum(rr, sh);
-    rzn = ccg_sum(rzn, sh);
+    if (own)
+      for (int i = g; i < nc; i += CCG_NG) {
+        uu[i] += alpha * p[i];
+        const double rv = r[i] - alpha * q[i];
+        r[i] = rv;
+        rr += rv * rv;
+        rzn += rv * dd[i] * rv;
+      }
+    ccg_sum2(rr, rzn, sh);
     if (rr <= tol2 * bb) break;
     const double beta = rzn / rz;
     rz = rzn;
-    for (int i = t; i < nc; i += CCG_BLK) p[i] = dc[i] * dc[i] * r[i] + beta * p[i];
+    if (own)
+      for (int i = g; i < nc; i += CCG_NG) p[i] = dd[i] * r[i] + beta * p[i];
   }
+  if (own)
+    for (int i = g; i < nc; i += CCG_NG) u[i] = uu[i];
 }
 
-void launch_coarse_cg(const int32_t* rowptr, const int32_t* col, const int32_t* src, const double* val,
-                      const double* dc, int nc, const int32_t* cinv_ptr, const int32_t* cinv, const double* gbuf,
-                      double* u, double* work, double tol, int maxit, const int* done, hipStream_t st) {
+__global__ void coarse_cg_matrix_kernel(const int32_t* fsrc, const double* val, double* fval, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) fval[k] = val[fsrc[k]];
+}
+
+void launch_coarse_cg_matrix(const int32_t* fsrc, const double* val, double* fval, int nnz, hipStream_t st) {
+  if (nnz <= 0) return;
+  hipLaunchKernelGGL(coarse_cg_matrix_kernel, dim3((nnz + 255) / 256), dim3(256), 0, st, fsrc, val, fval, nnz);
+}
+
+void launch_coarse_cg(const int32_t* rowptr, const int32_t* col, const double* fval, const double* dc, int nc,
+                      const int32_t* cinv_ptr, const int32_t* cinv, const double* gbuf, double* u, double* work,
+                      double tol, int maxit, const int* done, hipStream_t st) {
   if (nc <= 0) return;
-  hipLaunchKernelGGL(coarse_cg_kernel, dim3(1), dim3(CCG_BLK), 0, st, rowptr, col, src, val, dc, nc, cinv_ptr, cinv,
-                     gbuf, u, work, tol * tol, maxit, done);
+  if (nc <= CCG_LDS_N)
+    hipLaunchKernelGGL(coarse_cg_kernel<true>, dim3(1), dim3(CCG_BLK), 0, st, rowptr, col, fval, dc, nc, cinv_ptr,
+                       cinv, gbuf, u, work, tol * tol, maxit, done);
+  else
+    hipLaunchKernelGGL(coarse_cg_kernel<false>, dim3(1), dim3(CCG_BLK), 0, st, rowptr, col, fval, dc, nc, cinv_ptr,
+                       cinv, gbuf, u, work, tol * tol, maxit, done);
 }
 
 // Symmetric interface matrices of a subdomain, lower tile triangle over
