@@ -90,11 +90,14 @@ enum { BDDC_SETUP_FULL_SPACE = 2 };
 enum { BDDC_SETUP_RHO_SCALING = 4 };
 
 /* Setup option flag: solve the coarse problem of eq. (2) by CG, as the paper
- * does (Sec. 3), instead of the dense FP64 Cholesky factor (whole space) or its
- * explicit inverse (interface form): Jacobi-preconditioned CG on the assembled
- * A_c from zero to a relative residual of 1e-13 (at most 2000 iterations) in
- * one workgroup at every application of the preconditioner.  The explicit
- * forms are faster on one GPU; this one follows the paper. */
+ * does (Sec. 2), instead of the dense FP64 Cholesky factor (whole space) or its
+ * explicit inverse (interface form): CG on the assembled A_c with its diagonal
+ * as preconditioner (the paper's CG is unpreconditioned), from zero to a
+ * relative residual of 1e-13 (at most 2000 iterations), in one workgroup at
+ * every application of the preconditioner.  No dense coarse factor or inverse
+ * is formed; A_c is checked for a positive diagonal only, and a coarse matrix
+ * that is not positive definite ends that inner CG early instead of failing
+ * setup.  The explicit forms are faster on one GPU. */
 enum { BDDC_SETUP_COARSE_CG = 8 };
 
 /* Solve flags. */
