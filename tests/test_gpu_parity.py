@@ -62,6 +62,8 @@ CASES = {
                                                   constraints=W.CORNERS | W.EDGES),
     "3d_8_corners_only": lambda: W.make_workload("t", 3, (8, 8, 8), (2, 2, 2), theta="lognormal", seed=8,
                                                  constraints=W.CORNERS),
+    # 576 boxes of 3x3 elements: n_c = 1633, more coarse unknowns than the coarse CG keeps in LDS
+    "2d_72_24x24_many": lambda: W.make_workload("t", 2, (72, 72), (24, 24), theta="lognormal", seed=5),
 }
 
 _oracles = {}
@@ -381,7 +383,8 @@ def test_rho_scaling_matches_oracle(name, full_space):
 
 
 @pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
-@pytest.mark.parametrize("name", ["2d_64_4x4_theta1", "3d_12x10x14_uneven", "3d_24_3x3x3_inclusions"])
+@pytest.mark.parametrize("name", ["2d_64_4x4_theta1", "3d_12x10x14_uneven", "3d_24_3x3x3_inclusions",
+                                  "2d_72_24x24_many"])
 def test_coarse_cg_matches_oracle(name, full_space):
     """The coarse problem by CG (the paper's choice) to a relative residual of
     1e-13: the oracle's preconditioner (exact coarse solve) to 1e-10, the same
@@ -393,7 +396,10 @@ def test_coarse_cg_matches_oracle(name, full_space):
     say(name, "coarse-CG apply rel err", e)
     assert e <= 1e-10
     ref = O.bddc_pcg(P, w.b, w.rtol)
-    K = max(ref.iters - 2, 1)
+    # at most 10 steps: on 2d_72_24x24_many the oracle's own iterate after 19
+    # steps moves by 3e-9 when each preconditioner output is perturbed by 1e-14
+    # relative, after 10 steps by 2e-14 under 1e-13
+    K = max(min(ref.iters - 2, 10), 1)
     refK = O.bddc_pcg(P, w.b, 1e-300, maxit=K)
     xK, info = S.solve(dev(w.b), 1e-15, maxit=K, raise_on_noconv=False)
     e = rel(host(xK), refK.x)
