@@ -50,7 +50,7 @@ typedef enum {
   BDDC_EHIP = -4,        /* a HIP runtime call failed                             */
   BDDC_ENOCONV = -5,     /* maxit reached; x and info are still filled            */
   BDDC_EBREAKDOWN = -6,  /* CG breakdown: (p, A p) <= 0 or (r, z) <= 0 or NaN     */
-  BDDC_ENOTIMPL = -7     /* a valid request this build does not support           */
+  BDDC_ENOTIMPL = -7     /* a valid request the library does not support          */
 } bddc_status;
 
 /* Constraint selection (paper Sec. 2: corner values, edge and face averages).
