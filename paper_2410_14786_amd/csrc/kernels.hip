@@ -1826,7 +1826,7 @@ void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* c
 // vector that threads share.  With nc <= CCG_LDS_N the five vectors (r, p, q,
 // dc^2, u) live in LDS, else in work (5 nc doubles).
 constexpr int CCG_BLK = 1024;
-constexpr int CCG_G = 16;
+constexpr int CCG_G = 8;
 constexpr int CCG_NG = CCG_BLK / CCG_G;
 constexpr int CCG_LDS_N = 1536;
 
@@ -1886,6 +1886,7 @@ __global__ __launch_bounds__(CCG_BLK) void coarse_cg_kernel(const int32_t* rowpt
     double pq = 0.0, unused = 0.0;
     for (int i = g; i < nc; i += CCG_NG) {
       double v = 0.0;
+#pragma unroll 4
       for (int k = rowptr[i] + l; k < rowptr[i + 1]; k += CCG_G) v += fval[k] * p[col[k]];
       for (int o = CCG_G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, CCG_G);
       if (own) {
