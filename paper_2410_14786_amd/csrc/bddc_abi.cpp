@@ -106,7 +106,7 @@ struct bddc_ctx {
   int32_t *ac_rowptr = nullptr, *ac_fcol = nullptr, *ac_fsrc = nullptr;   // full CSR of A_c (coarse CG)
   double* ac_fval = nullptr;        // its values
   int ac_nfull = 0;
-  double* ccg_work = nullptr;       // coarse CG vectors (5 n_c)
+  double* ccg_work = nullptr;       // coarse CG vectors (7 n_c)
   bool use_graph = false;
   bool iface = true;                // interface-restricted CG (see bddc.h)
   MeshDevHost mesh{};
@@ -372,7 +372,7 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
     cf.gbuf = c->gbuf;
     cf.dc = c->dc;
     if (c->coarse_cg) {
-      launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fval, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
+      launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fval, c->ac_nfull, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
                        c->gbuf, c->uc, c->ccg_work, COARSE_CG_TOL, COARSE_CG_MAXIT, done, st);
     } else {
       launch_trsv(TRSV_FWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
@@ -510,7 +510,7 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
     launch_coarse_prep(c->mats, P.nsubs, nullptr, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done,
                        c->rowp, a.ntiles, a.nwg, st);
     if (c->coarse_cg)
-      launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fval, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
+      launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fval, c->ac_nfull, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
                        c->gbuf, c->upart, c->ccg_work, COARSE_CG_TOL, COARSE_CG_MAXIT, done, st);
     else
       launch_coarse_gemv(c->cainv, P.n_coarse, c->csplit, c->cinv_ptr, c->cinv, c->gbuf, c->upart, done, st);
@@ -850,7 +850,7 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
     if ((rc_ = c->upload(c->ac_fsrc, fs))) return rc_;
     c->ac_nfull = int(fs.size());
     if ((rc_ = c->alloc(c->ac_fval, int64_t(fs.size())))) return rc_;
-    if ((rc_ = c->alloc(c->ccg_work, 5 * int64_t(nc) + 1))) return rc_;
+    if ((rc_ = c->alloc(c->ccg_work, 7 * int64_t(nc) + 1))) return rc_;
   }
   if ((rc_ = c->alloc(c->dc, nc))) return rc_;
   // (the coarse CG needs no dense coarse factor)

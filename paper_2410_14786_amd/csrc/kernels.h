@@ -223,10 +223,10 @@ void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* c
 // relative residual tol); work: 3 nc doubles
 // full symmetric A_c in CSR for the coarse CG: fval[k] = val[fsrc[k]]
 void launch_coarse_cg_matrix(const int32_t* fsrc, const double* val, double* fval, int nnz, hipStream_t st);
-// (work: 5 nc doubles)
-void launch_coarse_cg(const int32_t* rowptr, const int32_t* col, const double* fval, const double* dc, int nc,
-                      const int32_t* cinv_ptr, const int32_t* cinv, const double* gbuf, double* u, double* work,
-                      double tol, int maxit, const int* done, hipStream_t st);
+// (work: 7 nc doubles)
+void launch_coarse_cg(const int32_t* rowptr, const int32_t* col, const double* fval, int nnz, const double* dc,
+                      int nc, const int32_t* cinv_ptr, const int32_t* cinv, const double* gbuf, double* u,
+                      double* work, double tol, int maxit, const int* done, hipStream_t st);
 void launch_trailing_inverse(const MatDesc* mats, int nmats, int maxTG, const double* tiles, const double* dinv,
                              double* xg, hipStream_t st);
 

@@ -1818,56 +1818,84 @@ void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* c
 
 // The coarse problem by CG (the paper's choice; an option beside the explicit
 // inverse): A_c u_c = r_c with r_c = sum of the subdomain shares gbuf over the
-// coarse inverse map, Jacobi-preconditioned CG (diag(A_c)^{-1} = dc^2) from
-// u_c = 0 until ||r|| <= tol ||r_c|| or maxit iterations, in one workgroup.  fval
+// coarse inverse map, CG preconditioned by diag(A_c)^{-1} = dc^2 from u_c = 0
+// until ||r|| <= tol ||r_c|| or maxit mat-vecs, in one workgroup.  The iteration
+// is the single-reduction form of Chronopoulos and Gear (same iterates as CG in
+// exact arithmetic): with u = M r and w = A u, gamma = (r, u), delta = (w, u),
+// beta = gamma / gamma_old, alpha = gamma / (delta - beta gamma / alpha_old),
+// p = u + beta p, s = w + beta s (= A p), x += alpha p, r -= alpha s, so that one
+// block reduction (gamma, delta and ||r||^2 together) serves an iteration.  fval
 // is the full symmetric A_c in CSR (rowptr, col), gathered once at setup from the
 // stored lower triangle.  A group of CCG_G lanes forms each row's product and the
-// group's first lane owns that row in every vector operation, so p is the only
-// vector that threads share.  With nc <= CCG_LDS_N the five vectors (r, p, q,
-// dc^2, u) live in LDS, else in work (5 nc doubles).
+// group's first lane owns that row in every vector operation, so u is the only
+// vector that threads share.  When the seven vectors (r, u, p, s, w, dc^2, x) and
+// the CSR fit in CCG_LDS_DBL doubles of LDS they are all kept there (the CSR is
+// copied in once per launch, so an iteration touches no global memory); else the
+// vectors live in work (7 nc doubles) and the CSR is read through L2.
 constexpr int CCG_BLK = 1024;
 constexpr int CCG_G = 8;
 constexpr int CCG_NG = CCG_BLK / CCG_G;
-constexpr int CCG_LDS_N = 1536;
+constexpr int CCG_LDS_DBL = 19200;   // 150 KB of the 160 KB of LDS of a CDNA4 compute unit
 
-__device__ __forceinline__ void ccg_sum2(double& a, double& b, double* sh) {
+__device__ __forceinline__ void ccg_sum3(double& a, double& b, double& c, double* sh) {
   for (int off = 32; off > 0; off >>= 1) {
     a += __shfl_xor(a, off, 64);
     b += __shfl_xor(b, off, 64);
+    c += __shfl_xor(c, off, 64);
   }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
   if (lane == 0) {
-    sh[2 * w] = a;
-    sh[2 * w + 1] = b;
+    sh[3 * w] = a;
+    sh[3 * w + 1] = b;
+    sh[3 * w + 2] = c;
   }
   __syncthreads();
   a = 0.0;
   b = 0.0;
+  c = 0.0;
   for (int i = 0; i < CCG_BLK / 64; ++i) {
-    a += sh[2 * i];
-    b += sh[2 * i + 1];
+    a += sh[3 * i];
+    b += sh[3 * i + 1];
+    c += sh[3 * i + 2];
   }
 }
 
 template <bool SH>
-__global__ __launch_bounds__(CCG_BLK) void coarse_cg_kernel(const int32_t* rowptr, const int32_t* col,
-                                                           const double* fval, const double* dc, int nc,
+__global__ __launch_bounds__(CCG_BLK) void coarse_cg_kernel(const int32_t* rowptr_g, const int32_t* col_g,
+                                                           const double* fval_g, int nnz, const double* dc, int nc,
                                                            const int32_t* cinv_ptr, const int32_t* cinv,
-                                                           const double* gbuf, double* u, double* work, double tol2,
+                                                           const double* gbuf, double* uc, double* work, double tol2,
                                                            int maxit, const int* done) {
-  __shared__ double sh[2 * (CCG_BLK / 64)];
-  __shared__ double sv[SH ? 5 * CCG_LDS_N : 1];
+  __shared__ double sh[3 * (CCG_BLK / 64)];
+  __shared__ double sv[SH ? CCG_LDS_DBL : 1];
   if (done && *done) return;
-  const int ld = SH ? CCG_LDS_N : nc;
+  const int ld = nc;
   double* r = SH ? sv : work;
-  double* p = r + ld;
-  double* q = r + 2 * ld;
-  double* dd = r + 3 * ld;
-  double* uu = r + 4 * ld;
+  const double* fval = fval_g;
+  const int32_t* col = col_g;
+  const int32_t* rowptr = rowptr_g;
+  if (SH) {
+    double* fs = sv + 7 * int64_t(nc);
+    int32_t* cs = reinterpret_cast<int32_t*>(fs + nnz);
+    int32_t* rs = cs + nnz;
+    for (int k = threadIdx.x; k < nnz; k += CCG_BLK) {
+      fs[k] = fval_g[k];
+      cs[k] = col_g[k];
+    }
+    for (int k = threadIdx.x; k <= nc; k += CCG_BLK) rs[k] = rowptr_g[k];
+    fval = fs;
+    col = cs;
+    rowptr = rs;
+  }
+  double* u = r + ld;
+  double* p = r + 2 * ld;
+  double* s = r + 3 * ld;
+  double* w = r + 4 * ld;
+  double* dd = r + 5 * ld;
+  double* x = r + 6 * ld;
   const int t = threadIdx.x, g = t / CCG_G, l = t % CCG_G;
   const bool own = (l == 0);
-  double bb = 0.0, rz = 0.0;
   if (own)
     for (int i = g; i < nc; i += CCG_NG) {
       double v = 0.0;
@@ -1875,46 +1903,48 @@ __global__ __launch_bounds__(CCG_BLK) void coarse_cg_kernel(const int32_t* rowpt
       const double d2 = dc[i] * dc[i];
       r[i] = v;
       dd[i] = d2;
-      p[i] = d2 * v;
-      uu[i] = 0.0;
-      bb += v * v;
-      rz += v * d2 * v;
+      u[i] = d2 * v;
+      x[i] = 0.0;
     }
-  ccg_sum2(bb, rz, sh);
-  for (int it = 0; it < maxit && bb > 0.0; ++it) {
-    __syncthreads();   // p complete
-    double pq = 0.0, unused = 0.0;
+  double bb = 0.0, gam_old = 1.0, alpha = 1.0;
+  for (int it = 0; it <= maxit; ++it) {
+    __syncthreads();   // u complete
+    double gam = 0.0, del = 0.0, rr = 0.0;
     for (int i = g; i < nc; i += CCG_NG) {
       double v = 0.0;
 #pragma unroll 4
-      for (int k = rowptr[i] + l; k < rowptr[i + 1]; k += CCG_G) v += fval[k] * p[col[k]];
+      for (int k = rowptr[i] + l; k < rowptr[i + 1]; k += CCG_G) v += fval[k] * u[col[k]];
       for (int o = CCG_G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, CCG_G);
       if (own) {
-        q[i] = v;
-        pq += p[i] * v;
+        w[i] = v;
+        const double ui = u[i], ri = r[i];
+        gam += ri * ui;
+        del += v * ui;
+        rr += ri * ri;
       }
     }
-    ccg_sum2(pq, unused, sh);
-    if (!(pq > 0.0)) break;
-    const double alpha = rz / pq;
-    double rr = 0.0, rzn = 0.0;
+    ccg_sum3(gam, del, rr, sh);
+    if (it == 0) bb = rr;
+    if (!(bb > 0.0) || rr <= tol2 * bb || it == maxit) break;
+    const double beta = it == 0 ? 0.0 : gam / gam_old;
+    const double den = del - beta * gam / alpha;
+    if (!(gam > 0.0) || !(den > 0.0)) break;
+    alpha = gam / den;
+    gam_old = gam;
     if (own)
       for (int i = g; i < nc; i += CCG_NG) {
-        uu[i] += alpha * p[i];
-        const double rv = r[i] - alpha * q[i];
-        r[i] = rv;
-        rr += rv * rv;
-        rzn += rv * dd[i] * rv;
+        const double pi = it == 0 ? u[i] : u[i] + beta * p[i];
+        const double si = it == 0 ? w[i] : w[i] + beta * s[i];
+        p[i] = pi;
+        s[i] = si;
+        x[i] += alpha * pi;
+        const double ri = r[i] - alpha * si;
+        r[i] = ri;
+        u[i] = dd[i] * ri;
       }
-    ccg_sum2(rr, rzn, sh);
-    if (rr <= tol2 * bb) break;
-    const double beta = rzn / rz;
-    rz = rzn;
-    if (own)
-      for (int i = g; i < nc; i += CCG_NG) p[i] = dd[i] * r[i] + beta * p[i];
   }
   if (own)
-    for (int i = g; i < nc; i += CCG_NG) u[i] = uu[i];
+    for (int i = g; i < nc; i += CCG_NG) uc[i] = x[i];
 }
 
 __global__ void coarse_cg_matrix_kernel(const int32_t* fsrc, const double* val, double* fval, int n) {
@@ -1927,16 +1957,18 @@ void launch_coarse_cg_matrix(const int32_t* fsrc, const double* val, double* fva
   hipLaunchKernelGGL(coarse_cg_matrix_kernel, dim3((nnz + 255) / 256), dim3(256), 0, st, fsrc, val, fval, nnz);
 }
 
-void launch_coarse_cg(const int32_t* rowptr, const int32_t* col, const double* fval, const double* dc, int nc,
-                      const int32_t* cinv_ptr, const int32_t* cinv, const double* gbuf, double* u, double* work,
-                      double tol, int maxit, const int* done, hipStream_t st) {
+void launch_coarse_cg(const int32_t* rowptr, const int32_t* col, const double* fval, int nnz, const double* dc,
+                      int nc, const int32_t* cinv_ptr, const int32_t* cinv, const double* gbuf, double* u,
+                      double* work, double tol, int maxit, const int* done, hipStream_t st) {
   if (nc <= 0) return;
-  if (nc <= CCG_LDS_N)
-    hipLaunchKernelGGL(coarse_cg_kernel<true>, dim3(1), dim3(CCG_BLK), 0, st, rowptr, col, fval, dc, nc, cinv_ptr,
-                       cinv, gbuf, u, work, tol * tol, maxit, done);
+  // LDS bytes of the resident variant: 7 nc + nnz doubles, nnz + nc + 1 ints
+  const int64_t need = 8 * (7 * int64_t(nc) + nnz) + 4 * (int64_t(nnz) + nc + 1);
+  if (need <= 8 * int64_t(CCG_LDS_DBL))
+    hipLaunchKernelGGL(coarse_cg_kernel<true>, dim3(1), dim3(CCG_BLK), 0, st, rowptr, col, fval, nnz, dc, nc,
+                       cinv_ptr, cinv, gbuf, u, work, tol * tol, maxit, done);
   else
-    hipLaunchKernelGGL(coarse_cg_kernel<false>, dim3(1), dim3(CCG_BLK), 0, st, rowptr, col, fval, dc, nc, cinv_ptr,
-                       cinv, gbuf, u, work, tol * tol, maxit, done);
+    hipLaunchKernelGGL(coarse_cg_kernel<false>, dim3(1), dim3(CCG_BLK), 0, st, rowptr, col, fval, nnz, dc, nc,
+                       cinv_ptr, cinv, gbuf, u, work, tol * tol, maxit, done);
 }
 
 // Symmetric interface matrices of a subdomain, lower tile triangle over
