@@ -141,10 +141,11 @@ def test_solution_matches_sparse_direct(name, full_space):
     S.close()
 
 
+@pytest.mark.parametrize("coarse_cg", [False, True], ids=["coarse_direct", "coarse_cg"])
 @pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
-def test_single_subdomain_is_direct(full_space):
+def test_single_subdomain_is_direct(full_space, coarse_cg):
     w = W.make_workload("t", 3, (9, 10, 11), (1, 1, 1), theta="lognormal", seed=9)
-    S = bd().solver_for(w, full_space=full_space)
+    S = bd().solver_for(w, full_space=full_space, coarse_cg=coarse_cg)
     assert S.n_coarse == 0
     x, info = S.solve(dev(w.b), 1e-12)
     P = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints)
@@ -160,6 +161,21 @@ def test_all_primal_converges_in_one_iteration(full_space):
     S = bd().solver_for(w, full_space=full_space)
     x, info = S.solve(dev(w.b), 1e-12)
     assert info["iters"] == 1
+    S.close()
+
+
+@pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
+def test_all_primal_with_coarse_cg(full_space):
+    """With every interface dof primal the preconditioner is A^{-1} up to the
+    coarse CG's own tolerance (1e-13 relative residual on A_c), so the outer CG
+    stops after at most two steps at the direct solution."""
+    w = W.make_workload("t", 2, (8, 8), (2, 2), theta="lognormal", constraints=W.ALL_PRIMAL, seed=10)
+    S = bd().solver_for(w, full_space=full_space, coarse_cg=True)
+    x, info = S.solve(dev(w.b), 1e-12)
+    P = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints)
+    import scipy.sparse.linalg as spla
+    assert info["iters"] <= 2
+    assert rel(host(x), spla.spsolve(P.A.tocsc(), w.b)) <= 1e-10
     S.close()
 
 
