@@ -2375,17 +2375,30 @@ __global__ __launch_bounds__(256) void pc_finish_kernel(IfaceArgs A) {
     for (int q = 0; q < A.nsplit; ++q) v += A.uc[int64_t(q) * A.nc + pc];
     u[tid] = v;
   }
+  // the first terms of the coefficient rows (S_A^{-1} and S_A^{-1} E, coefficient
+  // c = tid / 4, lanes tid % 4 split its terms) do not depend on u either
+  constexpr int SPO = 8, SPE = 2;
+  const int c = tid >> 2, l4 = tid & 3;
+  const double* so = A.sainv + int64_t(s) * MAX_NCI * MAX_NCI + c * MAX_NCI;
+  const double* se = A.sainve + int64_t(s) * MAX_NCI * MAX_NCI + c * MAX_NCI;
+  double sov[SPO], sev[SPE];
+#pragma unroll
+  for (int k = 0; k < SPO; ++k) sov[k] = (c < nA && l4 + 4 * k < nA) ? so[l4 + 4 * k] : 0.0;
+#pragma unroll
+  for (int k = 0; k < SPE; ++k) sev[k] = (c < nA && l4 + 4 * k < nP) ? se[l4 + 4 * k] : 0.0;
   if (dn) return;
   __syncthreads();
   {
-    // coefficient c = tid / 4, lanes tid % 4 split its terms
-    const int c = tid >> 2, l4 = tid & 3;
     double v = 0.0;
     if (c < nA) {
-      const double* so = A.sainv + int64_t(s) * MAX_NCI * MAX_NCI + c * MAX_NCI;
-      const double* se = A.sainve + int64_t(s) * MAX_NCI * MAX_NCI + c * MAX_NCI;
-      for (int t = l4; t < nA; t += 4) v += so[t] * u[t];
-      for (int q = l4; q < nP; q += 4) v += se[q] * u[nA + q];
+#pragma unroll
+      for (int k = 0; k < SPO; ++k)
+        if (l4 + 4 * k < nA) v += sov[k] * u[l4 + 4 * k];
+      for (int t = l4 + 4 * SPO; t < nA; t += 4) v += so[t] * u[t];
+#pragma unroll
+      for (int k = 0; k < SPE; ++k)
+        if (l4 + 4 * k < nP) v += sev[k] * u[nA + l4 + 4 * k];
+      for (int q = l4 + 4 * SPE; q < nP; q += 4) v += se[q] * u[nA + q];
     }
     v += __shfl_xor(v, 1, 4);
     v += __shfl_xor(v, 2, 4);
