@@ -172,17 +172,22 @@ def cpu_baseline(full_iters):
     ctx = threadpool_limits(1) if threadpool_limits else None
     try:
         P = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints)
-        t0 = time.perf_counter()
-        res = O.bddc_pcg(P, w.b, w.rtol)
-        t = time.perf_counter() - t0
+        # repeat the sample solve until about 10 s of solve time has accumulated
+        reps, total = 0, 0.0
+        while reps < 60 and (reps == 0 or total < 10.0):
+            t0 = time.perf_counter()
+            res = O.bddc_pcg(P, w.b, w.rtol)
+            total += time.perf_counter() - t0
+            reps += 1
+        t = total / reps
     finally:
         if ctx is not None:
             ctx.__exit__(None, None, None)
     scale = (64 / 8) * (full_iters / max(res.iters, 1))
     return {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle BDDC-PCG on 32^3 elements, 2x2x2 boxes of 16^3 (8 of the 64 subdomains), "
-                      f"{res.iters} iterations in {t:.2f} s, scaled x8 for subdomains and x{full_iters}/{res.iters} "
-                      f"for iterations; setup excluded"}
+                      f"{res.iters} iterations, {reps} solves in {total:.1f} s ({t:.2f} s each), scaled x8 for "
+                      f"subdomains and x{full_iters}/{res.iters} for iterations; setup excluded"}
 
 
 def main():
