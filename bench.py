@@ -156,6 +156,82 @@ def run_gpu(w, steps, warmup, local_bits, use_graph=False, full_space=False, aut
     return res
 
 
+def element_free_dofs(nel, e):
+    """Free dofs of Q1 element e of the structured cube (elements and free nodes
+    numbered x fastest; boundary nodes are not free)."""
+    nx, ny, nz = nel
+    ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+    out = []
+    for c in (0, 1):
+        for b in (0, 1):
+            for a in (0, 1):
+                ix, iy, iz = ex + a, ey + b, ez + c
+                if 1 <= ix <= nx - 1 and 1 <= iy <= ny - 1 and 1 <= iz <= nz - 1:
+                    out.append((ix - 1) + (nx - 1) * ((iy - 1) + (ny - 1) * (iz - 1)))
+    return out
+
+
+def adjoint_report(n_fd=4, h=1e-6):
+    """Gradient of J = |u - u_obs|^2 / 2 with respect to the element
+    conductivities on the 96^3 adjoint workload (6^3 boxes of 16^3, FP32 local
+    factors): the differentiable solve (setup, forward and adjoint BDDC-PCG, the
+    element kernel) timed from the host; the Euler identity (A is linear in theta,
+    so theta . dJ/dtheta = -(u - u_obs) . u); and central differences on n_fd
+    seeded elements without cancellation: A(theta +- h e_k) u_+- = b is solved as
+    the correction delta = -+ h A^{-1} K_k (u + delta) (a contraction for small h;
+    K_k v is read off the element-gradient kernel with unit vectors), and
+    J(+-) - J = delta . (u - u_obs) + |delta|^2 / 2."""
+    import torch
+    from paper_2410_14786_amd import bddc
+    from paper_2410_14786_amd import workloads as W
+    w = W.cfg_3d_96_adjoint(n_fd=n_fd)
+    dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")
+    b = dev(w.b)
+    S_obs = bddc.Solver(w.dim, w.nel, w.cuts, w.theta_obs, w.constraints, local_bits=64)
+    u_obs, _ = S_obs.solve(b, 1e-12)
+    S_obs.close()
+    th = dev(w.theta).requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = bddc.bddc_solve(th, b, 3, w.nel, w.cuts, w.constraints, rtol=1e-10, local_bits=32)
+    loss = 0.5 * torch.sum((u - u_obs) ** 2)
+    loss.backward()
+    torch.cuda.synchronize()
+    grad_s = time.perf_counter() - t0
+    g = th.grad.detach().cpu().numpy()
+    u_h, uo_h = u.detach().cpu().numpy(), u_obs.cpu().numpy()
+    lhs, rhs = float(w.theta @ g), -float((u_h - uo_h) @ u_h)
+    S = bddc.Solver(w.dim, w.nel, w.cuts, w.theta, w.constraints, local_bits=64)
+    uu, _ = S.solve(b, 1e-13)
+    uu_h = uu.cpu().numpy()
+    unit = torch.zeros_like(b)
+    worst, scale = 0.0, 0.0
+    for e in w.fd_elements:
+        dofs = element_free_dofs(w.nel, int(e))
+        de = {}
+        for sign in (+1, -1):
+            delta = np.zeros_like(uu_h)
+            for _ in range(3):
+                v = dev(uu_h + delta)
+                rhs_v = np.zeros_like(uu_h)
+                for d in dofs:
+                    unit[d] = 1.0
+                    # elem_grad gives -unit_e^T K_e v_e, i.e. -(K_e v)_d
+                    rhs_v[d] = sign * h * float(S.elem_grad(unit, v)[int(e)])
+                    unit[d] = 0.0
+                dn, _ = S.solve(dev(rhs_v), 1e-13, maxit=2000)
+                delta = dn.cpu().numpy()
+            de[sign] = delta @ (uu_h - uo_h) + 0.5 * delta @ delta
+        fd = (de[+1] - de[-1]) / (2 * h)
+        worst = max(worst, abs(fd - g[int(e)]))
+        scale = max(scale, abs(fd))
+    S.close()
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "n_free": int(w.n_free), "local_bits": 32, "grad_s_with_setup": grad_s,
+            "euler_rel": abs(lhs - rhs) / abs(rhs), "fd_elements": len(w.fd_elements), "fd_h": h,
+            "fd_rel_worst": worst / scale if scale > 0 else None}
+
+
 def cpu_baseline(full_iters):
     """The oracle on a bounded sample: the same 16^3 boxes and coefficient law,
     2x2x2 boxes (32^3 elements) instead of 4x4x4; its solve time is scaled by
@@ -204,6 +280,7 @@ def main():
     ap.add_argument("--local-bits", type=int, default=64)
     ap.add_argument("--no-rho", action="store_true", help="skip the run with coefficient-aware weights")
     ap.add_argument("--no-coarse-cg", action="store_true", help="skip the run with the coarse problem by CG")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient check on the 96^3 adjoint workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 512 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -338,6 +415,8 @@ def main():
             f["full_space"]["setup_factor_roofline"] = factor_roofline(runs["fp32_local_full_space"], 32)
             f["full_space"]["local_precision"] = "FP32 local factors and triangular solves"
         out["fp32_local"] = f
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_report()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m["iters"])
     print(json.dumps(out), flush=True)
