@@ -1833,7 +1833,7 @@ void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* c
 // copied in once per launch, so an iteration touches no global memory); else the
 // vectors live in work (7 nc doubles) and the CSR is read through L2.
 constexpr int CCG_BLK = 1024;
-constexpr int CCG_G = 8;
+constexpr int CCG_G = 2;
 constexpr int CCG_NG = CCG_BLK / CCG_G;
 constexpr int CCG_LDS_DBL = 19200;   // 150 KB of the 160 KB of LDS of a CDNA4 compute unit
 
