@@ -257,11 +257,45 @@ def classify_interface(mesh: Mesh, subs: List[Subdomain]) -> List[InterfaceClass
     return classes
 
 
+def factor_kkt(s: Subdomain):
+    """Sparse LU of the saddle-point matrix [A_i C_i^T; C_i 0] of eqs. (1) and (4)
+    (of A_i alone when the subdomain has no constraint)."""
+    nci = s.C.shape[0]
+    kkt = sp.bmat([[s.A, s.C.T], [s.C, None]], format="csc") if nci else s.A.tocsc()
+    return spla.splu(kkt)
+
+
+def factor_interior(s: Subdomain):
+    """Sparse LU of the interior block A_II = R_Ii A_i R_Ii^T of eq. (5), or None."""
+    ii = s.interior
+    return spla.splu(s.A[ii][:, ii].tocsc()) if len(ii) else None
+
+
+def setup_subdomain(s: Subdomain) -> None:
+    """Local setup of one subdomain: [Phi_i; Lambda_i] from eq. (1) with right-hand
+    side [0; I], A_ci = Phi_i^T A_i Phi_i (Sec. 2), and the factors used by the
+    preconditioner (eq. (4): the same KKT matrix; eq. (5): A_II)."""
+    ni = len(s.R)
+    nci = s.C.shape[0]
+    s.kkt_lu = factor_kkt(s)
+    if nci:
+        rhs = np.zeros((ni + nci, nci))
+        rhs[ni:, :] = np.eye(nci)
+        sol = s.kkt_lu.solve(rhs)
+        s.Phi = sol[:ni, :]
+        s.Lam = sol[ni:, :]
+    else:
+        s.Phi = np.zeros((ni, 0))
+        s.Lam = np.zeros((0, 0))
+    s.Ac = s.Phi.T @ (s.A @ s.Phi)
+    s.Aii_lu = factor_interior(s)
+
+
 class BDDC:
     """The BDDC preconditioner of the paper (Sec. 2) on a box partition."""
 
     def __init__(self, dim: int, nel: Sequence[int], cuts: Sequence[np.ndarray],
-                 theta: np.ndarray, constraints: int, weights: str = "kappa"):
+                 theta: np.ndarray, constraints: int, weights: str = "kappa", factor: bool = True):
         self.mesh = Mesh(dim, tuple(int(n) for n in nel))
         self.cuts = [np.asarray(c, dtype=np.int64) for c in cuts]
         self.theta = np.asarray(theta, dtype=np.float64)
@@ -286,15 +320,23 @@ class BDDC:
         for s in self.subs:
             self.kappa[s.R] += 1
         for s in self.subs:
-            s.W = 1.0 / self.kappa[s.R]
             s.interior = np.nonzero(self.kappa[s.R] == 1)[0]
+        self._kappa_weights()
         if weights == "rho":
             self._rho_weights()
         elif weights != "kappa":
             raise ValueError("weights must be 'kappa' or 'rho'")
         self.classes = classify_interface(self.mesh, self.subs)
         self._build_constraints()
-        self._build_coarse()
+        # factor=False stops before the local factorisations: a driver that runs
+        # setup_subdomain in worker processes (oracle/parallel.py) finishes it
+        if factor:
+            self._build_coarse()
+
+    def _kappa_weights(self):
+        """w = 1/kappa on every local dof (Sec. 2)."""
+        for s in self.subs:
+            s.W = 1.0 / self.kappa[s.R]
 
     def _rho_weights(self):
         """rho-scaling: rho_i(x) = max theta over subdomain i's elements that
@@ -361,23 +403,11 @@ class BDDC:
     # -- coarse basis (eq. (1)) and coarse matrix ----------------------------------
     def _build_coarse(self):
         for s in self.subs:
-            ni = len(s.R)
-            nci = s.C.shape[0]
-            kkt = sp.bmat([[s.A, s.C.T], [s.C, None]], format="csc") if nci else s.A.tocsc()
-            s.kkt_lu = spla.splu(kkt)
-            if nci:
-                rhs = np.zeros((ni + nci, nci))
-                rhs[ni:, :] = np.eye(nci)
-                sol = s.kkt_lu.solve(rhs)
-                s.Phi = sol[:ni, :]
-                s.Lam = sol[ni:, :]
-            else:
-                s.Phi = np.zeros((ni, 0))
-                s.Lam = np.zeros((0, 0))
-            s.Ac = s.Phi.T @ (s.A @ s.Phi)
-            ii = s.interior
-            if len(ii):
-                s.Aii_lu = spla.splu(s.A[ii][:, ii].tocsc())
+            setup_subdomain(s)
+        self.assemble_coarse()
+
+    def assemble_coarse(self):
+        """A_c = sum_i R_ci^T A_ci R_ci (Sec. 2) and its dense Cholesky factor."""
         Ac = np.zeros((self.n_coarse, self.n_coarse))
         for s in self.subs:
             Ac[np.ix_(s.Rc, s.Rc)] += s.Ac
@@ -392,39 +422,48 @@ class BDDC:
         return scipy.linalg.solve_triangular(L.T, y, lower=False)
 
     # -- the three parts of M^{-1} r (Sec. 2, eqs. (2)-(5)) -------------------------
-    def coarse_residual(self, r: np.ndarray) -> np.ndarray:
+    def coarse_residual(self, r: np.ndarray, subs=None) -> np.ndarray:
         rc = np.zeros(self.n_coarse)
-        for s in self.subs:
+        for s in self.subs if subs is None else subs:
             np.add.at(rc, s.Rc, s.Phi.T @ (s.W * r[s.R]))
         return rc
 
     def v1(self, r: np.ndarray) -> np.ndarray:
-        uc = self.coarse_solve(self.coarse_residual(r))
+        return self.coarse_interpolation(self.coarse_solve(self.coarse_residual(r)))
+
+    def coarse_interpolation(self, uc: np.ndarray, subs=None) -> np.ndarray:
+        """sum_i R_i^T W_i Phi_i R_ci u_c (eq. (2))."""
         v = np.zeros(self.n)
-        for s in self.subs:
+        for s in self.subs if subs is None else subs:
             np.add.at(v, s.R, s.W * (s.Phi @ uc[s.Rc]))
         return v
 
-    def local_z(self, s: Subdomain, r: np.ndarray) -> np.ndarray:
+    def local_z(self, s: Subdomain, r: np.ndarray, lu=None) -> np.ndarray:
         ni = len(s.R)
         rhs = np.zeros(ni + s.C.shape[0])
         rhs[:ni] = s.W * r[s.R]
-        return s.kkt_lu.solve(rhs)[:ni]
+        return (s.kkt_lu if lu is None else lu).solve(rhs)[:ni]
 
-    def v2(self, r: np.ndarray) -> np.ndarray:
+    def v2(self, r: np.ndarray, subs=None, refactor: bool = False) -> np.ndarray:
+        """sum_i R_i^T W_i z_i with z_i from eq. (4) (eq. (3)); refactor=True
+        factors each KKT matrix afresh instead of using the stored factor."""
         v = np.zeros(self.n)
-        for s in self.subs:
-            np.add.at(v, s.R, s.W * self.local_z(s, r))
+        for s in self.subs if subs is None else subs:
+            lu = factor_kkt(s) if refactor else None
+            np.add.at(v, s.R, s.W * self.local_z(s, r, lu))
         return v
 
-    def interior_correction(self, r1: np.ndarray) -> np.ndarray:
+    def interior_correction(self, r1: np.ndarray, subs=None, refactor: bool = False) -> np.ndarray:
         """sum_i R_i^T R_Ii^T (R_Ii A_i R_Ii^T)^{-1} R_Ii R_i r1 (eq. (5)); also
-        the operator P_I used for the initial guess."""
+        the operator P_I used for the initial guess.  refactor=True factors each
+        A_II afresh instead of using the stored factor (same arithmetic, for
+        drivers that do not keep every factor in memory)."""
         v = np.zeros(self.n)
-        for s in self.subs:
+        for s in self.subs if subs is None else subs:
             ii = s.interior
             if len(ii):
-                np.add.at(v, s.R[ii], s.Aii_lu.solve(r1[s.R[ii]]))
+                lu = factor_interior(s) if refactor else s.Aii_lu
+                np.add.at(v, s.R[ii], lu.solve(r1[s.R[ii]]))
         return v
 
     def apply(self, r: np.ndarray) -> np.ndarray:
@@ -474,8 +513,10 @@ def lanczos_condition(alphas: Sequence[float], betas: Sequence[float]) -> float:
     return float(ev[-1] / ev[0])
 
 
-def pcg(A, b: np.ndarray, prec, rtol: float, maxit: int = 1000, x0: Optional[np.ndarray] = None) -> PCGResult:
-    """Hestenes-Stiefel preconditioned CG; stop when ||r||_2 <= rtol ||b||_2."""
+def pcg(A, b: np.ndarray, prec, rtol: float, maxit: int = 1000, x0: Optional[np.ndarray] = None,
+        callback=None) -> PCGResult:
+    """Hestenes-Stiefel preconditioned CG; stop when ||r||_2 <= rtol ||b||_2.
+    callback(k, x), if given, sees the iterate after each step k (read only)."""
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
     r = b - A @ x
@@ -495,6 +536,8 @@ def pcg(A, b: np.ndarray, prec, rtol: float, maxit: int = 1000, x0: Optional[np.
             r -= alpha * q
             alphas.append(alpha)
             it += 1
+            if callback is not None:
+                callback(it, x)
             if np.linalg.norm(r) <= rtol * bnorm:
                 converged = True
                 break

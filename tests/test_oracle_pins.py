@@ -117,24 +117,36 @@ def test_subassembly_invariant(case):
 # weights and interface classes (Sec. 2)
 # ---------------------------------------------------------------------------
 
-def test_weights_partition_of_unity():
-    w = W.make_workload("t", 3, (9, 7, 8), cuts=[[0, 4, 9], [0, 3, 7], [0, 2, 5, 8]], theta="one")
-    P = build(w)
+def partition_of_unity_error(P):
+    """max |sum_i R_i^T W_i R_i 1 - 1| (the weights must form a partition of unity)."""
     tot = np.zeros(P.n)
     for s in P.subs:
         np.add.at(tot, s.R, s.W)
-    assert np.all(np.abs(tot - 1) < 1e-15)
-    assert set(np.unique(P.kappa)) <= {1, 2, 4, 8}
+    return np.abs(tot - 1).max()
 
 
-def test_weights_paper_2d_values():
-    w = W.cfg_2d_64()
-    P = build(w)
+def paper_2d_weights_hold(P):
+    """The weight values the paper lists for the 2D 4x4 partition (Sec. 2),
+    stored in tests/golden/weights_2d_64_4x4.txt: 1 inside, 1/2 on edges, 1/4 at
+    cross points."""
     data = np.loadtxt(os.path.join(GOLDEN, "weights_2d_64_4x4.txt"))
     for x, y, want in data:
         g = int(x - 1) + 63 * int(y - 1)
         ws = [s.W[np.searchsorted(s.R, g)] for s in P.subs if g in set(s.R.tolist())]
-        assert all(abs(v - want) < 1e-15 for v in ws) and len(ws) == round(1 / want)
+        if not (all(abs(v - want) < 1e-15 for v in ws) and len(ws) == round(1 / want)):
+            return False
+    return True
+
+
+def test_weights_partition_of_unity():
+    w = W.make_workload("t", 3, (9, 7, 8), cuts=[[0, 4, 9], [0, 3, 7], [0, 2, 5, 8]], theta="one")
+    P = build(w)
+    assert partition_of_unity_error(P) < 1e-15
+    assert set(np.unique(P.kappa)) <= {1, 2, 4, 8}
+
+
+def test_weights_paper_2d_values():
+    assert paper_2d_weights_hold(build(W.cfg_2d_64()))
 
 
 @pytest.mark.parametrize("K", [2, 3, 4])
@@ -163,9 +175,13 @@ def small3d():
     return build(W.make_workload("t", 3, (8, 8, 8), (2, 2, 2), theta="lognormal", seed=5))
 
 
+def constraint_error(P):
+    """max_i |C_i Phi_i - I| (eq. (1): the coarse basis reproduces the constraints)."""
+    return max(np.abs(s.C @ s.Phi - np.eye(s.C.shape[0])).max() for s in P.subs)
+
+
 def test_constraints_reproduced(small3d):
-    for s in small3d.subs:
-        assert np.abs(s.C @ s.Phi - np.eye(s.C.shape[0])).max() < 1e-10
+    assert constraint_error(small3d) < 1e-10
 
 
 def test_saddle_point_first_row(small3d):
@@ -429,14 +445,15 @@ def test_adjoint_matches_dense_adjoint():
 # ---------------------------------------------------------------------------
 
 def test_planted_weight_mistake_is_caught(monkeypatch):
-    w = W.make_workload("t", 2, (8, 8), (2, 2), theta="one")
-    P = build(w)
-    for s in P.subs:
-        s.W = s.W ** 2      # 1/kappa^2 instead of 1/kappa
-    tot = np.zeros(P.n)
-    for s in P.subs:
-        np.add.at(tot, s.R, s.W)
-    assert np.abs(tot - 1).max() > 0.1
+    """The oracle's weight step planted with 1/kappa^2: the partition-of-unity
+    pin and the paper's 2D values both fail on the oracle built with it."""
+    def squared(self):
+        for s in self.subs:
+            s.W = 1.0 / self.kappa[s.R] ** 2
+    monkeypatch.setattr(O.BDDC, "_kappa_weights", squared)
+    w = W.make_workload("t", 3, (9, 7, 8), cuts=[[0, 4, 9], [0, 3, 7], [0, 2, 5, 8]], theta="one")
+    assert partition_of_unity_error(build(w)) > 0.1
+    assert not paper_2d_weights_hold(build(W.cfg_2d_64()))
 
 
 def test_planted_dropped_v3_is_caught(monkeypatch):
@@ -459,10 +476,28 @@ def test_planted_r1_sign_mistake_is_caught():
     assert np.abs((P.A @ bad_apply(r))[I] - r[I]).max() > 1e-3
 
 
-def test_planted_transposed_coarse_basis_is_caught():
+def test_planted_coarse_basis_rhs_mistake_is_caught(monkeypatch):
+    """The oracle's eq. (1) planted with the identity in the wrong block of the
+    right-hand side ([I; 0] instead of [0; I]): the C Phi = I pin fails on the
+    oracle built with it."""
+    def bad_setup(s):
+        ni, nci = len(s.R), s.C.shape[0]
+        s.kkt_lu = O.factor_kkt(s)
+        rhs = np.zeros((ni + nci, nci))
+        rhs[:nci, :] = np.eye(nci)
+        sol = s.kkt_lu.solve(rhs)
+        s.Phi, s.Lam = sol[:ni, :], sol[ni:, :]
+        s.Ac = s.Phi.T @ (s.A @ s.Phi)
+        s.Aii_lu = O.factor_interior(s)
+    monkeypatch.setattr(O, "setup_subdomain", bad_setup)
+    P = build(W.make_workload("t", 3, (8, 8, 8), (2, 2, 2), theta="lognormal", seed=5))
+    assert constraint_error(P) > 0.1
+
+
+def test_planted_unweighted_coarse_residual_is_caught():
+    """The oracle's coarse residual planted without the weights W_i: the pins on
+    the preconditioned interface operator (symmetric, spectrum >= 1) fail."""
     P = build(W.make_workload("t", 2, (12, 12), (3, 3), theta="lognormal", seed=4))
-    # use Phi from a neighbouring subdomain's solve with the wrong weights side:
-    # coarse residual without the weights W_i breaks the lower bound 1
     orig = P.coarse_residual
 
     def bad_coarse_residual(r):
