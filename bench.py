@@ -1,21 +1,25 @@
 """Benchmark: BDDC-PCG solves/s on one MI355X.
 
-Workload (default): 3D Q1 diffusion on a 64^3 element grid, 4x4x4 = 64 box
-subdomains of 16^3 elements, lognormal(0,1) per-element conductivity, corner +
-edge + face constraints, uniform[-1,1] right-hand side, solved to relative
-residual 1e-8.  A step is one warm BDDC-PCG solve (the preconditioner is set up
-once beforehand, as when the matrix is reused across time steps); inputs are
-resident in HBM when the timed region starts.
+Workload (default): 3D Q1 diffusion on a 128^3 element grid cut by seeded
+random axis-aligned splits into 8^3 = 512 tensor boxes with edges of 8-24
+elements (729-15625 dofs per box), one 1e-3 ellipsoid inclusion per box,
+corner + edge + face constraints, uniform[-1,1] right-hand side, solved to
+relative residual 1e-8.  A step is one warm BDDC-PCG solve (the preconditioner
+is set up once beforehand, as when the matrix is reused across time steps);
+inputs are resident in HBM when the timed region starts.
 
 Prints one JSON line with the FP64 solve rate as `value` (CG restricted to the
-interface dofs, the default of bddc_pcg_solve, kernels launched from the host),
-the same solves with per-kernel timing events, replayed from captured HIP graphs,
-and with CG on the whole space (the three-part preconditioner applied as
-written), the FP32-local
-rates beside it (interface form with the preconditioner's local solves in
-FP32, and whole-space form with FP32 local factors), the roofline of the
-dominant kernel (algorithmic bytes per launch over its HIP-event-timed average
-duration) and a CPU-oracle baseline on a bounded sample of the same workload.
+interface dofs, the default of bddc_pcg_solve, kernels launched from the
+host) and beside it: the FP32-local forms (FP32 local Cholesky factors and
+triangular solves on the whole space, and the interface variant with the
+preconditioner's local solves in FP32), the FP64 whole-space form (the
+three-part preconditioner applied as written), graph replay, the setup
+options (rho-scaling weights, coarse problem by CG), each with its iteration
+count, true residual and error against stored oracle values; the roofline of
+the dominant kernel (algorithmic bytes per launch over its HIP-event-timed
+average duration); the 64^3 workload's rate as a secondary figure; the
+adjoint-gradient check on the 96^3 workload; and a CPU-oracle baseline on a
+bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -31,6 +35,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FULL_FAMILIES = ["trsv_fwd_rr", "trsv_bwd_rr", "trsv_fwd_ii", "trsv_bwd_ii"]
+GOLDEN = {"3d_128_uneven": "3d_128_uneven_sampled.json", "3d_64": "3d_64_sampled.json"}
+TILE = 64 * 64
 IFACE_FAMILIES = ["op", "pc"]
 NB = 64
 
@@ -68,19 +74,47 @@ def sub_sizes(w):
     return out
 
 
-def algorithmic_bytes(w, local_bytes):
-    """Bytes each triangular-solve family must stream per launch: the lower
-    triangle of the factor it uses plus the border rows where they are read,
-    plus its vectors (FP64 input/output)."""
+def envelope_tiles(env, sizes):
+    """Tiles each pass of one subdomain streams: the lower tiles of L_RR inside
+    the factor's envelope (tile (k, j) for fcol[k] <= j <= k, k < T) and of its
+    interior block (fcol_ii[k] <= j <= k, k < TI); tiles left of the envelope are
+    zero and neither stored into nor read."""
+    n_R, n_I = sizes[0], sizes[1]
+    T = (n_R + 63) // 64
+    TI = (n_I + 63) // 64
+    fc, fi = env[:T], env[T:2 * T]
+    rr = int(sum(k - fc[k] + 1 for k in range(T)))
+    ii = int(sum(k - fi[k] + 1 for k in range(TI)))
+    return rr, ii, T
+
+
+def algorithmic_bytes(w, local_bytes, env=None):
+    """Bytes each kernel family must stream per launch.  Triangular passes: the
+    tiles inside each factor's envelope (``env``: per subdomain the tile counts
+    from envelope_tiles; without it the dense lower triangle), the border tile
+    row (constraint rows) where it is read, and the vectors.  Interface form:
+    the packed symmetric matrices and their FP64 input and output."""
     fam = {}
     s = sub_sizes(w)
     tri = lambda n: n * (n + 1) // 2
-    fam["trsv_fwd_rr"] = sum(tri(nR) * local_bytes + nci * nR * local_bytes + nR * (8 + 8 + 4 + local_bytes)
-                             for nR, nI, nci, nP in s)
-    fam["trsv_bwd_rr"] = sum(tri(nR) * local_bytes + nci * nR * local_bytes + nR * (8 + 2 * local_bytes)
-                             for nR, nI, nci, nP in s)
-    fam["trsv_fwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 4 + local_bytes) for nR, nI, nci, nP in s)
-    fam["trsv_bwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 8 + 4 + local_bytes) for nR, nI, nci, nP in s)
+    tb = TILE * local_bytes
+    if env is not None:
+        rr_t = [e[0] for e in env]
+        ii_t = [e[1] for e in env]
+        border = [e[2] if nci else 0 for e, (nR, nI, nci, nP) in zip(env, s)]
+        fam["trsv_fwd_rr"] = sum(rr * tb + bt * tb + nR * (8 + 8 + 4 + local_bytes)
+                                 for rr, bt, (nR, nI, nci, nP) in zip(rr_t, border, s))
+        fam["trsv_bwd_rr"] = sum(rr * tb + bt * tb + nR * (8 + 2 * local_bytes)
+                                 for rr, bt, (nR, nI, nci, nP) in zip(rr_t, border, s))
+        fam["trsv_fwd_ii"] = sum(ii * tb + nI * (8 + 4 + local_bytes) for ii, (nR, nI, nci, nP) in zip(ii_t, s))
+        fam["trsv_bwd_ii"] = sum(ii * tb + nI * (8 + 8 + 4 + local_bytes) for ii, (nR, nI, nci, nP) in zip(ii_t, s))
+    else:
+        fam["trsv_fwd_rr"] = sum(tri(nR) * local_bytes + nci * nR * local_bytes + nR * (8 + 8 + 4 + local_bytes)
+                                 for nR, nI, nci, nP in s)
+        fam["trsv_bwd_rr"] = sum(tri(nR) * local_bytes + nci * nR * local_bytes + nR * (8 + 2 * local_bytes)
+                                 for nR, nI, nci, nP in s)
+        fam["trsv_fwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 4 + local_bytes) for nR, nI, nci, nP in s)
+        fam["trsv_bwd_ii"] = sum(tri(nI) * local_bytes + nI * (8 + 8 + 4 + local_bytes) for nR, nI, nci, nP in s)
     # interface form: the operator (always FP64) streams the lower triangle of
     # the local Schur complement on n_G + n_P rows (n_G = n_R - n_I interface
     # rows, n_P corners), the preconditioner (local precision) that of X^T X on
@@ -116,11 +150,34 @@ def load_traffic(kernel, workload, local_bits):
     return None
 
 
+def load_golden(workload):
+    name = GOLDEN.get(workload)
+    if name is None:
+        return None
+    path = os.path.join(ROOT, "tests", "golden", name)
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def golden_error(x, golden):
+    """Error of a solution against the oracle's converged solution on the
+    stored sample dofs: norm-wise over the sample and entry-wise against the
+    oracle vector's largest magnitude."""
+    if golden is None:
+        return None
+    smp = np.array(golden["sample"])
+    ref = np.array(golden["pcg"]["values"])
+    d = x[smp] - ref
+    mx = golden["pcg"].get("maxabs", float(np.abs(ref).max()))
+    return {"sampled_rel": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            "sampled_entrywise": float(np.abs(d).max() / mx), "oracle_iters": golden["pcg"]["iters"],
+            "samples": int(len(smp))}
+
+
 def run_gpu(w, steps, warmup, local_bits, use_graph=False, full_space=False, autotune=True, timing=True,
-            rho_scaling=False, coarse_cg=False):
+            rho_scaling=False, coarse_cg=False, golden=None):
     import torch
     from paper_2410_14786_amd import bddc
-    families = FULL_FAMILIES if full_space else IFACE_FAMILIES
+    families = FULL_FAMILIES if full_space else IFACE_FAMILIES + ["trsv_fwd_ii", "trsv_bwd_ii"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S = bddc.solver_for(w, local_bits=local_bits, use_graph=use_graph, full_space=full_space,
@@ -128,6 +185,10 @@ def run_gpu(w, steps, warmup, local_bits, use_graph=False, full_space=False, aut
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     tune = S.autotune(cache="") if autotune else None
+    env = []
+    for i in range(S.n_sub):
+        sz = S.debug_read("sizes", i)
+        env.append(envelope_tiles(S.debug_read("envelope", i).astype(np.int64), (int(sz[0]), int(sz[1]))))
     b = torch.as_tensor(w.b, dtype=torch.float64, device="cuda")
     x = torch.empty_like(b)
     info = None
@@ -147,9 +208,11 @@ def run_gpu(w, steps, warmup, local_bits, use_graph=False, full_space=False, aut
     fam = {f: S.kernel_time(f) for f in families + ["apply"]}
     S.set_timing(False)
     flops, factor_ms = S.setup_stats()
+    xh = x.cpu().numpy()
     res = {"setup_s": setup_s, "elapsed_s": elapsed, "iters": iters, "info": info, "kernels": fam,
            "dev_bytes": S.dev_bytes, "families": families, "tuning": tune, "factor_flops": flops,
-           "factor_ms": factor_ms}
+           "factor_ms": factor_ms, "env": env, "full_space": full_space,
+           "err_vs_oracle": golden_error(xh, golden)}
     S.close()
     del S
     torch.cuda.empty_cache()
@@ -232,38 +295,68 @@ def adjoint_report(n_fd=4, h=1e-6):
             "fd_rel_worst": worst / scale if scale > 0 else None}
 
 
-def cpu_baseline(full_iters):
-    """The oracle on a bounded sample: the same 16^3 boxes and coefficient law,
-    2x2x2 boxes (32^3 elements) instead of 4x4x4; its solve time is scaled by
-    the subdomain count (64/8) and by the iteration ratio to give solves/s for
-    the full workload.  Setup is excluded, as for the GPU rate."""
-    try:
-        from threadpoolctl import threadpool_limits
-    except Exception:
-        threadpool_limits = None
-    from oracle import bddc_oracle as O
+def cpu_baseline(w_full, full_iters, workers=None):
+    """The oracle on a bounded sample of the workload, one worker process per
+    host core (oracle/parallel.py runs the oracle's per-subdomain steps in
+    forked workers, BLAS limited to one thread each).  128^3 workload: the
+    4x4x4 block of boxes at the origin (64 of the 512 subdomains, the same cut
+    positions and the same inclusion coefficients), as a problem of its own
+    with a fresh uniform[-1,1] right-hand side; 64^3: 2x2x2 boxes of 16^3 with
+    the same lognormal law.  The sample's solve time (setup excluded, as for
+    the GPU rate) is scaled by the subdomain count and by the iteration ratio to
+    give solves/s for the full workload."""
+    import platform
+    from oracle import parallel as OP
     from paper_2410_14786_amd import workloads as W
-    w = W.make_workload("sample_3d_32cubed_2x2x2_lognormal", 3, (32, 32, 32), (2, 2, 2), theta="lognormal",
-                        rtol=1e-8, seed=0)
-    ctx = threadpool_limits(1) if threadpool_limits else None
+    nsub_full = int(np.prod(w_full.nsub))
+    if w_full.name.startswith("3d_q1_128"):
+        k = 4
+        cuts = [np.asarray(c[:k + 1], dtype=np.int64) for c in w_full.cuts]
+        nel = tuple(int(c[-1]) for c in cuts)
+        full_nel = w_full.nel
+        ex, ey, ez = np.meshgrid(np.arange(nel[0]), np.arange(nel[1]), np.arange(nel[2]), indexing="ij")
+        eidx = (ex + full_nel[0] * (ey + full_nel[1] * ez)).transpose(2, 1, 0).ravel()
+        theta = w_full.theta[eidx]
+        rng = np.random.default_rng(99)
+        b = rng.uniform(-1.0, 1.0, int(np.prod([n - 1 for n in nel])))
+        what = (f"oracle BDDC-PCG on the 4x4x4 block of boxes at the origin of the 128^3 workload "
+                f"({nel[0]}x{nel[1]}x{nel[2]} elements, 64 of the 512 subdomains, same cuts and inclusions)")
+        dim, cons, rtol = 3, w_full.constraints, w_full.rtol
+    else:
+        ws = W.make_workload("sample", 3, (32, 32, 32), (2, 2, 2), theta="lognormal", rtol=1e-8, seed=0)
+        cuts, nel, theta, b = ws.cuts, ws.nel, ws.theta, ws.b
+        what = "oracle BDDC-PCG on 32^3 elements, 2x2x2 boxes of 16^3 (8 of the 64 subdomains)"
+        dim, cons, rtol = 3, ws.constraints, ws.rtol
+    nsub_s = int(np.prod([len(c) - 1 for c in cuts]))
+    workers = workers or min(os.cpu_count() or 1, 16, nsub_s)
+    t0 = time.perf_counter()
+    Q = OP.ParallelBDDC(dim, nel, cuts, theta, cons, workers=workers, keep_factors=True)
+    setup = time.perf_counter() - t0
     try:
-        P = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints)
-        # repeat the sample solve until about 10 s of solve time has accumulated
         reps, total = 0, 0.0
-        while reps < 60 and (reps == 0 or total < 10.0):
+        while reps < 20 and (reps == 0 or total < 10.0):
             t0 = time.perf_counter()
-            res = O.bddc_pcg(P, w.b, w.rtol)
+            res = Q.pcg(b, rtol)
             total += time.perf_counter() - t0
             reps += 1
-        t = total / reps
     finally:
-        if ctx is not None:
-            ctx.__exit__(None, None, None)
-    scale = (64 / 8) * (full_iters / max(res.iters, 1))
-    return {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle BDDC-PCG on 32^3 elements, 2x2x2 boxes of 16^3 (8 of the 64 subdomains), "
-                      f"{res.iters} iterations, {reps} solves in {total:.1f} s ({t:.2f} s each), scaled x8 for "
-                      f"subdomains and x{full_iters}/{res.iters} for iterations; setup excluded"}
+        Q.close()
+    t = total / reps
+    scale = (nsub_full / nsub_s) * (full_iters / max(res.iters, 1))
+    cpu = platform.processor() or platform.machine()
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                cpu = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": Q.workers, "kind": "oracle",
+            "cpu": cpu, "host_cpus": os.cpu_count(),
+            "sample": f"{what}; {res.iters} iterations; {reps} solves in {total:.1f} s ({t:.2f} s each) with "
+                      f"{Q.workers} worker processes (one per core, BLAS 1 thread each; oracle setup {setup:.1f} s "
+                      f"not timed); scaled x{nsub_full / nsub_s:g} for subdomains and x{full_iters}/{res.iters} "
+                      f"for iterations"}
 
 
 def main():
@@ -271,7 +364,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="3d_64")
+    ap.add_argument("--workload", default="3d_128_uneven")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-full-space", action="store_true")
@@ -281,6 +374,11 @@ def main():
     ap.add_argument("--no-rho", action="store_true", help="skip the run with coefficient-aware weights")
     ap.add_argument("--no-coarse-cg", action="store_true", help="skip the run with the coarse problem by CG")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient check on the 96^3 adjoint workload")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 64^3 workload's secondary rate")
+    ap.add_argument("--only-main", action="store_true",
+                    help="only the main runs (untimed and timed); for profiling")
+    ap.add_argument("--main-form", choices=["interface", "full"], default="interface",
+                    help="iteration form of the main runs (full: CG on the whole space)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 512 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -288,6 +386,9 @@ def main():
         print(f"bench.py runs on one GPU only (the whole problem lives on one MI355X); --gpus {args.gpus} "
               f"is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.only_main:
+        args.no_cpu_baseline = args.no_fp32 = args.no_full_space = args.no_graph = True
+        args.no_rho = args.no_coarse_cg = args.no_adjoint = args.no_secondary = True
     import torch
     from paper_2410_14786_amd import workloads as W
     if args.copy_calibration:
@@ -299,39 +400,46 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = W.WORKLOADS[args.workload]()
+    golden = load_golden(args.workload)
     print(f"[bench] workload {w.name}: n_free {w.n_free}, {int(np.prod(w.nsub))} subdomains", file=sys.stderr,
           flush=True)
     main_bits = args.local_bits
     runs = {}
+
+    def run(name, *a, **k):
+        print(f"[bench] run {name}", file=sys.stderr, flush=True)
+        runs[name] = run_gpu(w, args.steps, args.warmup, *a, golden=golden, **k)
+        r = runs[name]
+        print(f"[bench] {name}: {1000 * r['elapsed_s'] / args.steps:.2f} ms/solve, iters {r['iters'][-1]}, "
+              f"setup {r['setup_s']:.2f} s", file=sys.stderr, flush=True)
+
     # `value`: kernels launched from the host with no timing events (the host
     # stays ahead of the GPU, and eager launches read their arguments from device
     # memory, which graph kernel nodes on this ROCm do not); the same solves with
     # dispatch-recorded events give the per-kernel times and the roofline; the
     # graph-replay rate is reported beside them
-    runs["main"] = run_gpu(w, args.steps, args.warmup, main_bits, timing=False)
-    runs["timed"] = run_gpu(w, args.steps, args.warmup, main_bits)
-    if not args.no_graph:
-        runs["graph"] = run_gpu(w, args.steps, args.warmup, main_bits, use_graph=True, timing=False)
-    if not args.no_full_space:
-        runs["full_space"] = run_gpu(w, args.steps, args.warmup, main_bits, full_space=True)
-    if not args.no_rho:
-        runs["rho_scaling"] = run_gpu(w, args.steps, args.warmup, main_bits, timing=False, rho_scaling=True)
-    if not args.no_coarse_cg:
-        runs["coarse_cg"] = run_gpu(w, args.steps, args.warmup, main_bits, timing=False, coarse_cg=True)
+    main_full = args.main_form == "full"
+    run("main", main_bits, timing=False, full_space=main_full)
+    run("timed", main_bits, full_space=main_full)
     if not args.no_fp32 and main_bits == 64:
-        runs["fp32_local"] = run_gpu(w, args.steps, args.warmup, 32, timing=False)
-        runs["fp32_local_timed"] = run_gpu(w, args.steps, args.warmup, 32)
         if not args.no_full_space:
-            runs["fp32_local_full_space"] = run_gpu(w, args.steps, args.warmup, 32, full_space=True)
-    for name, r in runs.items():
-        print(f"[bench] {name}: {1000 * r['elapsed_s'] / args.steps:.2f} ms/solve, iters {r['iters'][-1]}, "
-              f"setup {r['setup_s']:.2f} s", file=sys.stderr, flush=True)
+            run("fp32_local_full_space", 32, full_space=True)
+        run("fp32_local", 32, timing=False)
+        run("fp32_local_timed", 32)
+    if not args.no_full_space:
+        run("full_space", main_bits, full_space=True)
+    if not args.no_graph:
+        run("graph", main_bits, use_graph=True, timing=False)
+    if not args.no_rho:
+        run("rho_scaling", main_bits, timing=False, rho_scaling=True)
+    if not args.no_coarse_cg:
+        run("coarse_cg", main_bits, timing=False, coarse_cg=True)
 
     def factor_roofline(r, bits):
         """The setup's batched local Cholesky (MFMA-bound): its envelope flops over
         its stream-event time, against the dense MFMA peak of its precision (the
         interface form factors in FP64 for either local precision)."""
-        fp32_factors = bits == 32 and r["families"] == FULL_FAMILIES
+        fp32_factors = bits == 32 and r["full_space"]
         peak = 157.3 if fp32_factors else 78.6
         ach = r["factor_flops"] / (r["factor_ms"] * 1e-3) / 1e12 if r["factor_ms"] > 0 else None
         return {"bound": "mfma", "achieved": round(ach, 2) if ach else None, "peak": peak, "unit": "TFLOP/s",
@@ -339,15 +447,23 @@ def main():
                 "ms": round(r["factor_ms"], 3), "dtype": "f32" if fp32_factors else "f64"}
 
     def summarize(r, bits):
+        # element size of each family's matrices: the interface form keeps FP64
+        # factors (interior passes) and an FP64 operator whatever local_bits is
         lb = 8 if bits == 64 else 4
-        algo = algorithmic_bytes(w, lb)
+        algo = algorithmic_bytes(w, lb, r["env"])
+        if not r["full_space"]:
+            a8 = algorithmic_bytes(w, 8, r["env"])
+            algo["trsv_fwd_ii"], algo["trsv_bwd_ii"] = a8["trsv_fwd_ii"], a8["trsv_bwd_ii"]
         fams = {f: r["kernels"][f] for f in r["families"]}
+        out = {"value": round(args.steps / r["elapsed_s"], 3), "unit": "solves/s",
+               "ms_per_step": round(1000 * r["elapsed_s"] / args.steps, 3), "iters": r["iters"][-1],
+               "relres_true": r["info"]["relres_true"], "cond_est": r["info"]["cond_est"],
+               "err_vs_oracle": r["err_vs_oracle"], "setup_s": round(r["setup_s"], 3),
+               "dev_bytes": r["dev_bytes"], "autotune": r["tuning"]}
         if not any(v[0] for v in fams.values()):
-            return {"value": round(args.steps / r["elapsed_s"], 3), "unit": "solves/s",
-                    "ms_per_step": round(1000 * r["elapsed_s"] / args.steps, 3), "iters": r["iters"][-1],
-                    "relres_true": r["info"]["relres_true"], "cond_est": r["info"]["cond_est"],
-                    "setup_s": round(r["setup_s"], 3), "dev_bytes": r["dev_bytes"], "autotune": r["tuning"]}
-        dom = max(fams, key=lambda f: fams[f][1])
+            return out
+        main_fams = FULL_FAMILIES if r["full_space"] else IFACE_FAMILIES
+        dom = max(main_fams, key=lambda f: fams[f][1])
         n_l, tot_ms = fams[dom]
         avg_s = tot_ms / 1000.0 / max(n_l, 1)
         achieved = algo[dom] / avg_s / 1e9
@@ -355,17 +471,21 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": load_traffic(dom, args.workload, bits),
                 "bytes_per_launch": algo[dom], "avg_launch_ms": round(avg_s * 1e3, 4), "launches": n_l}
-        fam_bytes = sum(algo[f] for f in r["families"])
-        fam_ms = sum(fams[f][1] / max(fams[f][0], 1) for f in r["families"])
+        # bytes every family streams per solve (launch counts of the timed run)
+        solve_bytes = sum(algo[f] * fams[f][0] for f in r["families"]) / args.steps
+        fam_rates = {f: round(algo[f] / (fams[f][1] / 1e3 / fams[f][0]) / 1e9 / HBM_PEAK_GBS, 4)
+                     for f in r["families"] if fams[f][0]}
         n_a, ms_a = r["kernels"]["apply"]
-        return {"value": round(args.steps / r["elapsed_s"], 3), "unit": "solves/s",
-                "ms_per_step": round(1000 * r["elapsed_s"] / args.steps, 3), "iters": r["iters"][-1],
-                "relres_true": r["info"]["relres_true"], "cond_est": r["info"]["cond_est"],
-                "setup_s": round(r["setup_s"], 3),
-                "applies_per_s": round(n_a / (ms_a / 1e3), 2) if n_a else None,
-                "kernel_ms": {f: round(fams[f][1] / max(fams[f][0], 1), 4) for f in fams},
-                "streamed_hbm_frac": round(fam_bytes / (fam_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if fam_ms else None,
-                "roofline": roof, "dev_bytes": r["dev_bytes"], "autotune": r["tuning"]}
+        out.update({
+            "applies_per_s": round(n_a / (ms_a / 1e3), 2) if n_a else None,
+            "kernel_ms": {f: round(fams[f][1] / max(fams[f][0], 1), 4) for f in fams},
+            "launches_per_solve": {f: fams[f][0] / args.steps for f in fams},
+            "kernel_hbm_frac": fam_rates,
+            "bytes_per_solve": int(solve_bytes),
+            # the streams of every family over the whole solve time (timed run)
+            "solve_hbm_frac": round(solve_bytes / (r["elapsed_s"] / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+            "roofline": roof})
+        return out
 
     m = summarize(runs["main"], main_bits)
     out = {
@@ -382,43 +502,65 @@ def main():
         "dtype": "f64" if main_bits == 64 else "f64-outer/f32-local",
         "data": "synthetic",
         "config": {"workload": w.name, "n_free": w.n_free, "subdomains": int(np.prod(w.nsub)),
-                   "rtol": w.rtol, "local_bits": main_bits, "cg_space": "interface",
-                   "launch": "eager"},
+                   "rtol": w.rtol, "local_bits": main_bits,
+                   "cg_space": "whole space" if main_full else "interface", "launch": "eager"},
     }
-    for k in ["iters", "relres_true", "cond_est", "setup_s", "dev_bytes", "autotune"]:
+    for k in ["iters", "relres_true", "cond_est", "err_vs_oracle", "setup_s", "dev_bytes", "autotune"]:
         out[k] = m[k]
     out["timed"] = timed = summarize(runs["timed"], main_bits)
-    out["roofline_measured_in"] = "timed run: the same solves with dispatch-recorded events around the mat-vecs"
-    for k in ["applies_per_s", "kernel_ms", "streamed_hbm_frac"]:
+    out["roofline_measured_in"] = "timed run: the same solves with dispatch-recorded events around the kernels"
+    for k in ["applies_per_s", "kernel_ms", "kernel_hbm_frac", "bytes_per_solve", "solve_hbm_frac"]:
         out[k] = timed[k]
     out["roofline"] = timed["roofline"]
     out["setup_factor_roofline"] = factor_roofline(runs["main"], main_bits)
-    if "graph" in runs:
-        out["graph"] = summarize(runs["graph"], main_bits)
+    if "fp32_local" in runs or "fp32_local_full_space" in runs:
+        f = {}
+        if "fp32_local_full_space" in runs:
+            # the FP32-local form as the workload defines it: FP32 local Cholesky
+            # factors and triangular solves, FP64 outer CG, r1 and coarse problem
+            f = summarize(runs["fp32_local_full_space"], 32)
+            f["cg_space"] = "whole space"
+            f["local_precision"] = "FP32 local Cholesky factors and triangular solves (MFMA f32)"
+            f["setup_factor_roofline"] = factor_roofline(runs["fp32_local_full_space"], 32)
+            f["speedup_vs_fp64_full_space"] = None
+        if "fp32_local" in runs:
+            v = summarize(runs["fp32_local"], 32)
+            v["cg_space"] = "interface"
+            v["local_precision"] = "FP32 preconditioner matrices (FP64 factors, operator and interior solves)"
+            v["timed"] = summarize(runs["fp32_local_timed"], 32)
+            for k in ["applies_per_s", "kernel_ms", "kernel_hbm_frac", "solve_hbm_frac", "roofline"]:
+                v[k] = v["timed"].get(k)
+            v["speedup_vs_fp64"] = round(v["value"] / m["value"], 4)
+            f["interface_variant"] = v
+        out["fp32_local"] = f
     if "full_space" in runs:
         out["full_space"] = summarize(runs["full_space"], main_bits)
+        out["full_space"]["setup_factor_roofline"] = factor_roofline(runs["full_space"], main_bits)
+        if out.get("fp32_local", {}).get("value"):
+            out["fp32_local"]["speedup_vs_fp64_full_space"] = round(
+                out["fp32_local"]["value"] / out["full_space"]["value"], 4)
+    if "graph" in runs:
+        out["graph"] = summarize(runs["graph"], main_bits)
     if "rho_scaling" in runs:
         out["rho_scaling"] = summarize(runs["rho_scaling"], main_bits)
         out["rho_scaling"]["weights"] = "rho-scaling (coefficient-aware; the paper fixes 1/kappa)"
     if "coarse_cg" in runs:
         out["coarse_cg"] = summarize(runs["coarse_cg"], main_bits)
         out["coarse_cg"]["coarse_solve"] = "Jacobi-preconditioned CG to 1e-13 (the paper's choice) at every apply"
-    if "fp32_local" in runs:
-        f = summarize(runs["fp32_local"], 32)
-        f["cg_space"] = "interface"
-        f["local_precision"] = "FP32 preconditioner matrices (FP64 factors, operator and interior solves)"
-        f["timed"] = summarize(runs["fp32_local_timed"], 32)
-        for k in ["applies_per_s", "kernel_ms", "streamed_hbm_frac", "roofline"]:
-            f[k] = f["timed"][k]
-        if "fp32_local_full_space" in runs:
-            f["full_space"] = summarize(runs["fp32_local_full_space"], 32)
-            f["full_space"]["setup_factor_roofline"] = factor_roofline(runs["fp32_local_full_space"], 32)
-            f["full_space"]["local_precision"] = "FP32 local factors and triangular solves"
-        out["fp32_local"] = f
+    if not args.no_secondary and args.workload != "3d_64":
+        w64 = W.cfg_3d_64()
+        r64 = run_gpu(w64, args.steps, args.warmup, main_bits, timing=False, golden=load_golden("3d_64"))
+        out["secondary_3d_64"] = {"workload": w64.name, "value": round(args.steps / r64["elapsed_s"], 3),
+                                  "unit": "solves/s", "ms_per_step": round(1000 * r64["elapsed_s"] / args.steps, 3),
+                                  "iters": r64["iters"][-1], "relres_true": r64["info"]["relres_true"],
+                                  "err_vs_oracle": r64["err_vs_oracle"]}
+        print(f"[bench] secondary 3d_64: {1000 * r64['elapsed_s'] / args.steps:.2f} ms/solve", file=sys.stderr,
+              flush=True)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_report()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(m["iters"])
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, m["iters"])
     print(json.dumps(out), flush=True)
 
 

@@ -231,6 +231,10 @@ int bddc_kernel_time(bddc_ctx* ctx, const char* family, int64_t* launches,
  *       "schur"  -> the bordering diagonal tile (-W^T W), 64 x 64;
  *       "aci"    -> A_ci = Phi_i^T A_i Phi_i, 64 x 64 (constraint order: averages
  *                   then corners);
+ *       "envelope" -> 2T values: for each tile row k of the factor, the first tile
+ *                   column holding a nonzero (tiles left of it are zero and are
+ *                   never stored into or read), then the same over the interior
+ *                   rows only (meaningful for k < ceil(n_I / 64));
  *       "gmap"   -> global free dof of each local dof (n_i values);
  *       "dscale" -> equilibration factor of each local dof (n_i values).
  * Returns the number of values written (<= cap) or a negative status. */

@@ -234,7 +234,7 @@ class Solver:
 
     def debug_read(self, what: str, sub: int) -> np.ndarray:
         """One subdomain's setup data (test access): sizes, factor, border, schur,
-        aci, gmap, dscale."""
+        aci, gmap, dscale, envelope."""
         cap = 64 * 1024 * 1024
         sizes = np.zeros(6)
         n = self.lib.bddc_debug_read(self.ctx, b"sizes", sub, sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 6)
@@ -242,7 +242,7 @@ class Solver:
             _check(int(n), "bddc_debug_read")
         T = int(sizes[4])
         need = {"sizes": 6, "factor": (T * 64) ** 2, "border": 64 * T * 64, "schur": 4096, "aci": 4096,
-                "gmap": int(sizes[5]), "dscale": int(sizes[5])}[what]
+                "gmap": int(sizes[5]), "dscale": int(sizes[5]), "envelope": 2 * T}[what]
         buf = np.zeros(min(need, cap))
         n = self.lib.bddc_debug_read(self.ctx, what.encode(), sub, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      len(buf))

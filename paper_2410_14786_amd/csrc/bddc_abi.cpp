@@ -575,7 +575,9 @@ void enqueue_interior_guess(bddc_ctx* c, const double* b, double* x, double* zer
   a.ticket = c->tickets + 2;
   a.sol = pub_slot(c, 2);
   a.rin = b;
-  launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st);
+  hipEvent_t k0, k1;
+  c->kernel_events("trsv_fwd_ii", &k0, &k1);
+  launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st, k0, k1);
   a = base_args(c);
   a.tasks = c->t_bwd_ii;
   a.lrow = c->lrow_ii;
@@ -584,7 +586,8 @@ void enqueue_interior_guess(bddc_ctx* c, const double* b, double* x, double* zer
   a.sol = pub_slot(c, 3);
   a.src = pub_slot(c, 2);
   a.zout = x;
-  launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st);
+  c->kernel_events("trsv_bwd_ii", &k0, &k1);
+  launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st, k0, k1);
 }
 
 // one PCG iteration it (fresh: first of a segment, p = z)
@@ -673,7 +676,9 @@ void enqueue_interior_complete(bddc_ctx* c, const double* b, const double* xt, d
   a.sol = pub_slot(c, 2);
   a.rin = b;
   a.v12 = xt;
-  launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st);
+  hipEvent_t k0, k1;
+  c->kernel_events("trsv_fwd_ii", &k0, &k1);
+  launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st, k0, k1);
   a = base_args(c);
   a.tasks = c->t_bwd_ii;
   a.lrow = c->lrow_ii;
@@ -683,7 +688,8 @@ void enqueue_interior_complete(bddc_ctx* c, const double* b, const double* xt, d
   a.src = pub_slot(c, 2);
   a.zout = out;
   a.base = xt;
-  launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st);
+  c->kernel_events("trsv_bwd_ii", &k0, &k1);
+  launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st, k0, k1);
 }
 
 int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
@@ -1303,6 +1309,15 @@ int64_t bddc_debug_read(bddc_ctx* c, const char* what, int32_t sub, double* out,
   } else if (w == "gmap") {
     res.resize(D.n_i);
     for (int a = 0; a < D.n_i; ++a) res[a] = c->plan.gmap[D.loc_off + a];
+  } else if (w == "envelope") {
+    // per tile row k < T: first tile column of the factor's envelope (all rows),
+    // then the same over the interior rows (rows k < TI only)
+    const int64_t base = D.vec_off / NB;
+    res.resize(2 * int64_t(D.T));
+    for (int k = 0; k < D.T; ++k) {
+      res[k] = c->plan.fcol[base + k];
+      res[D.T + k] = c->plan.fcol_ii[base + k];
+    }
   } else if (w == "dscale") {
     res.resize(D.n_i);
     HIP_TRY(hipMemcpy(res.data(), c->dsc + D.loc_off, res.size() * 8, hipMemcpyDeviceToHost));

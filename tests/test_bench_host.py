@@ -29,3 +29,38 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_envelope_tile_count():
+    """Tile counts of the triangular passes: a dense envelope (first column 0 in
+    every tile row) gives the whole lower tile triangle; a band of half-width b
+    tiles gives the band's tiles; the interior count covers ceil(n_I/64) rows."""
+    T, TI = 5, 3
+    n_R, n_I = 64 * T - 10, 64 * TI - 7
+    dense = np.zeros(2 * T, dtype=np.int64)
+    assert bench.envelope_tiles(dense, (n_R, n_I)) == (T * (T + 1) // 2, TI * (TI + 1) // 2, T)
+    band = np.array([max(0, k - 1) for k in range(T)] * 2)
+    rr, ii, t = bench.envelope_tiles(band, (n_R, n_I))
+    assert rr == 1 + 2 * (T - 1) and ii == 1 + 2 * (TI - 1) and t == T
+
+
+def test_envelope_bytes_never_exceed_dense_tiles():
+    """Bytes counted from the envelope are at most those of the dense tile
+    triangle (same vectors), and equal to them for a dense envelope."""
+    from paper_2410_14786_amd import workloads as W
+    w = W.make_workload("t", 3, (20, 18, 16), cuts=[[0, 9, 20], [0, 8, 18], [0, 16]], theta="one")
+    sizes = bench.sub_sizes(w)
+    dense_env, band_env = [], []
+    for nR, nI, nci, nP in sizes:
+        T = (nR + 63) // 64
+        dense_env.append(bench.envelope_tiles(np.zeros(2 * T, dtype=np.int64), (nR, nI)))
+        band_env.append(bench.envelope_tiles(np.array([max(0, k - 2) for k in range(T)] * 2), (nR, nI)))
+    for lb in (4, 8):
+        d = bench.algorithmic_bytes(w, lb, dense_env)
+        b = bench.algorithmic_bytes(w, lb, band_env)
+        for f in bench.FULL_FAMILIES:
+            assert b[f] <= d[f]
+        # the dense tile triangle holds at least the element triangle
+        e = bench.algorithmic_bytes(w, lb)
+        for f in bench.FULL_FAMILIES:
+            assert d[f] >= e[f] - sum(nR * 64 * lb for nR, _, _, _ in sizes)

@@ -3,8 +3,14 @@
 * 64^3, 64 boxes (the benchmark workload): sampled parity with stored oracle
   values (tests/golden/3d_64_sampled.json, written by make_golden.py from the
   oracle only): M^{-1} b, the iterate after K PCG steps and the iteration count.
-* 128^3, 512 uneven boxes with inclusions, FP64 and FP32-local: the true
-  relative residual recomputed on the CPU from an independently assembled A.
+* 128^3, 512 uneven boxes with inclusions (the headline workload): sampled
+  parity with stored oracle values (tests/golden/3d_128_uneven_sampled.json,
+  written by make_golden_128.py from the oracle only, 6 dofs of every box):
+  M^{-1} b and the iterate after K PCG steps, element by element, in both
+  iteration forms; the iteration count and Lanczos estimate; and, for the
+  FP32-local forms (interface variant and FP32 local factors on the whole
+  space), the true relative residual recomputed on the CPU from an
+  independently assembled A and the error against the oracle's solution.
 * 96^3, 216 boxes, adjoint gradient: the Euler identity (exact at any size) and
   central finite differences on 16 seeded elements.
 """
@@ -52,24 +58,36 @@ def golden64():
     return json.load(open(os.path.join(GOLDEN, "3d_64_sampled.json")))
 
 
+@pytest.fixture(scope="module")
+def golden128():
+    return json.load(open(os.path.join(GOLDEN, "3d_128_uneven_sampled.json")))
+
+
+def sampled_close(v, g, key, tol):
+    """Sampled entries of v against the stored oracle values: norm-wise over the
+    sample, entry-wise against the oracle vector's largest magnitude, and the
+    full vector's norm."""
+    smp_vals = np.array(g[key]["values"])
+    vs = v[np.array(g["sample"])]
+    en = np.linalg.norm(vs - smp_vals) / np.linalg.norm(smp_vals)
+    ee = np.abs(vs - smp_vals).max() / g[key]["maxabs"] if "maxabs" in g[key] else \
+        np.abs(vs - smp_vals).max() / np.abs(smp_vals).max()
+    enorm = abs(np.linalg.norm(v) - g[key]["norm"]) / g[key]["norm"]
+    assert en <= tol and ee <= tol and enorm <= tol, (key, en, ee, enorm)
+    return en, ee, enorm
+
+
 def test_3d_64_sampled_parity_fp64(golden64):
     g = golden64
     w = W.cfg_3d_64()
     S = bd().solver_for(w)
-    smp = np.array(g["sample"])
     z = host(S.apply(dev(w.b)))
-    zs = np.array(g["apply_b"]["values"])
-    e = np.linalg.norm(z[smp] - zs) / np.linalg.norm(zs)
-    en = abs(np.linalg.norm(z) - g["apply_b"]["norm"]) / g["apply_b"]["norm"]
-    say("3d_64 apply sampled rel err", e, "norm rel err", en)
-    assert e <= 1e-10 and en <= 1e-10
+    say("3d_64 apply sampled rel err / entry-wise / norm", *sampled_close(z, g, "apply_b", 1e-10))
     K = g["pcg_K"]["K"]
     xK, info = S.solve(dev(w.b), 1e-15, maxit=K, raise_on_noconv=False)
-    xK = host(xK)
-    xs = np.array(g["pcg_K"]["values"])
-    e = np.linalg.norm(xK[smp] - xs) / np.linalg.norm(xs)
-    say("3d_64 PCG iterate K", K, "sampled rel err", e)
-    assert info["iters"] == K and e <= 1e-10
+    assert info["iters"] == K
+    say("3d_64 PCG iterate K", K, "sampled rel err / entry-wise / norm",
+        *sampled_close(host(xK), g, "pcg_K", 1e-10))
     x, info = S.solve(dev(w.b), w.rtol)
     say("3d_64 iters", info["iters"], "oracle", g["pcg"]["iters"], "relres", info["relres_true"],
         "cond", info["cond_est"], g["pcg"]["cond_est"])
@@ -98,16 +116,54 @@ def true_relres_cpu(w, x):
     return np.linalg.norm(w.b - A @ x) / np.linalg.norm(w.b)
 
 
-@pytest.mark.parametrize("bits", [64, 32])
-def test_3d_128_uneven_inclusions(bits):
-    w = W.cfg_3d_128_uneven(local_bits=bits)
-    S = bd().solver_for(w)
-    say("3d_128 device GB", S.dev_bytes / 1e9)
+@pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
+def test_3d_128_sampled_parity_fp64(golden128, full_space):
+    """The 128^3 workload (boxes of 8-24 elements per side) against the oracle:
+    M^{-1} b and the K-step iterate on 6 sampled dofs of every box, element by
+    element to 1e-10, the iteration count (+-1) and the Lanczos estimate."""
+    g = golden128
+    w = W.cfg_3d_128_uneven()
+    S = bd().solver_for(w, full_space=full_space)
+    say("3d_128 device GB", S.dev_bytes / 1e9, "full space", full_space)
+    z = host(S.apply(dev(w.b)))
+    say("3d_128 apply sampled rel err / entry-wise / norm", *sampled_close(z, g, "apply_b", 1e-10))
+    K = g["pcg_K"]["K"]
+    xK, info = S.solve(dev(w.b), 1e-15, maxit=K, raise_on_noconv=False)
+    assert info["iters"] == K
+    say("3d_128 PCG iterate K", K, "sampled rel err / entry-wise / norm",
+        *sampled_close(host(xK), g, "pcg_K", 1e-10))
     x, info = S.solve(dev(w.b), w.rtol, maxit=1000)
     rr = true_relres_cpu(w, host(x))
-    say("3d_128 fp%d iters" % bits, info["iters"], "relres_true gpu", info["relres_true"], "cpu", rr,
-        "cond", info["cond_est"], "setup ms", info["t_setup_ms"], "solve ms", info["t_solve_ms"])
+    say("3d_128 fp64 iters", info["iters"], "oracle", g["pcg"]["iters"], "relres_true gpu", info["relres_true"],
+        "cpu", rr, "cond", info["cond_est"], g["pcg"]["cond_est"], "solve ms", info["t_solve_ms"])
+    assert abs(info["iters"] - g["pcg"]["iters"]) <= 1
     assert rr <= w.rtol * 1.01
+    assert abs(info["cond_est"] - g["pcg"]["cond_est"]) <= 1e-6 * g["pcg"]["cond_est"]
+    S.close()
+
+
+@pytest.mark.parametrize("full_space", [False, True], ids=["interface_fp32_pc", "full_space_fp32_factors"])
+def test_3d_128_fp32_local(golden128, full_space):
+    """FP32 local solves on the 128^3 workload: full_space=True is the form with
+    FP32 local Cholesky factors and FP32 triangular solves (FP64 CG, r1 and
+    coarse problem); the interface variant keeps FP64 factors and applies the
+    preconditioner's local solves in FP32.  No exact counterpart exists (parity
+    unpinned): the true residual recomputed on the CPU must reach 1e-8, and the
+    error against the oracle's converged solution on the sampled dofs is
+    reported and bounded by 1e-5 (both solutions carry a 1e-8 residual)."""
+    g = golden128
+    w = W.cfg_3d_128_uneven(local_bits=32)
+    S = bd().solver_for(w, full_space=full_space)
+    x, info = S.solve(dev(w.b), w.rtol, maxit=1000)
+    xh = host(x)
+    rr = true_relres_cpu(w, xh)
+    xs = np.array(g["pcg"]["values"])
+    e = np.linalg.norm(xh[np.array(g["sample"])] - xs) / np.linalg.norm(xs)
+    say("3d_128 fp32-local full_space", full_space, "iters", info["iters"], "oracle", g["pcg"]["iters"],
+        "relres_true gpu", info["relres_true"], "cpu", rr, "sampled err vs oracle", e,
+        "solve ms", info["t_solve_ms"])
+    assert rr <= w.rtol * 1.01
+    assert e <= 1e-5
     S.close()
 
 

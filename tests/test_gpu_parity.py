@@ -1,9 +1,11 @@
 """Parity of the HIP library (through the C ABI) with the CPU oracle.
 
 Tolerances: FP64 local solves must match the oracle's preconditioner and PCG
-iterates to 1e-10 relative (norm-wise); the FP32-local form has no exact
-counterpart and is checked by the true residual it reaches and by its error
-against the oracle's solution, reported and bounded.
+iterates to 1e-10 relative, both norm-wise and element by element
+(max_k |a_k - b_k| <= 1e-10 max_k |b_k|, so that an error confined to a few
+entries or one subdomain cannot hide in the norm); the FP32-local form has no
+exact counterpart and is checked by the true residual it reaches and by its
+error against the oracle's solution, reported and bounded.
 """
 import os
 import sys
@@ -43,6 +45,18 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+def elem(a, b):
+    """Largest entry-wise difference relative to the largest entry of b."""
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def close(a, b, tol):
+    """Norm-wise and entry-wise agreement to tol; returns both errors."""
+    en, ee = rel(a, b), elem(a, b)
+    assert en <= tol and ee <= tol, (en, ee)
+    return en, ee
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
@@ -62,6 +76,11 @@ CASES = {
                                                   constraints=W.CORNERS | W.EDGES),
     "3d_8_corners_only": lambda: W.make_workload("t", 3, (8, 8, 8), (2, 2, 2), theta="lognormal", seed=8,
                                                  constraints=W.CORNERS),
+    # boxes of 8 and 24 elements per side (the extremes of the 128^3 workload's box
+    # lengths), inclusions; the middle box has 15 625 dofs, 216 factor tile rows
+    # and 3458 interface rows (55 tile rows of interface matrix), all six faces shared
+    "3d_40_boxes_8_24_inclusions": lambda: W.make_workload("t", 3, (40, 40, 40), cuts=[[0, 8, 32, 40]] * 3,
+                                                           theta="inclusions", seed=13),
     # 576 boxes of 3x3 elements: n_c = 1633, more coarse unknowns than the coarse CG keeps in LDS
     "2d_72_24x24_many": lambda: W.make_workload("t", 2, (72, 72), (24, 24), theta="lognormal", seed=5),
 }
@@ -88,9 +107,8 @@ def test_apply_parity_fp64(name):
     for vec in (r, rf, w.b):
         z = host(S.apply(dev(vec)))
         zo = P.apply(vec)
-        e = rel(z, zo)
-        say("  apply rel err", e)
-        assert e <= 1e-10
+        en, ee = close(z, zo, 1e-10)
+        say("  apply rel err", en, "entry-wise", ee)
     S.close()
 
 
@@ -100,13 +118,13 @@ def test_spmv_parity(name):
     S = bd().solver_for(w)
     x = np.random.default_rng(1).standard_normal(P.n)
     y = host(S.spmv(dev(x)))
-    assert rel(y, P.A @ x) <= 1e-14
+    close(y, P.A @ x, 1e-14)
     S.close()
 
 
 @pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
 @pytest.mark.parametrize("name", ["2d_64_4x4_theta1", "3d_12x10x14_uneven", "3d_24_3x3x3_inclusions",
-                                  "2d_20x24_uneven", "3d_8_corners_only"])
+                                  "2d_20x24_uneven", "3d_8_corners_only", "3d_40_boxes_8_24_inclusions"])
 def test_pcg_iterates_match_oracle(name, full_space):
     """Same number K of iterations from the same x0 = P_I b: iterates agree, for
     the CG run on the whole space and the one restricted to interface dofs."""
@@ -116,10 +134,9 @@ def test_pcg_iterates_match_oracle(name, full_space):
     K = max(ref.iters - 2, 1)
     refK = O.bddc_pcg(P, w.b, 1e-300, maxit=K)
     xK, info = S.solve(dev(w.b), 1e-15, maxit=K, raise_on_noconv=False)
-    e = rel(host(xK), refK.x)
-    say(name, "K", K, "iterate rel err", e, "status", info["status"])
     assert info["iters"] == K
-    assert e <= 1e-10
+    en, ee = close(host(xK), refK.x, 1e-10)
+    say(name, "K", K, "iterate rel err", en, "entry-wise", ee, "status", info["status"])
     x, info = S.solve(dev(w.b), w.rtol)
     say(name, "iters gpu", info["iters"], "oracle", ref.iters, "relres", info["relres_true"],
         "cond", info["cond_est"], ref.cond_est)
@@ -137,7 +154,7 @@ def test_solution_matches_sparse_direct(name, full_space):
     S = bd().solver_for(w, full_space=full_space)
     x, info = S.solve(dev(w.b), 1e-13)
     xs = spla.spsolve(P.A.tocsc(), w.b)
-    assert rel(host(x), xs) <= 1e-10
+    close(host(x), xs, 1e-10)
     S.close()
 
 
@@ -151,7 +168,7 @@ def test_single_subdomain_is_direct(full_space, coarse_cg):
     P = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints)
     import scipy.sparse.linalg as spla
     assert info["iters"] == 0
-    assert rel(host(x), spla.spsolve(P.A.tocsc(), w.b)) <= 1e-12
+    close(host(x), spla.spsolve(P.A.tocsc(), w.b), 1e-12)
     S.close()
 
 
@@ -175,7 +192,7 @@ def test_all_primal_with_coarse_cg(full_space):
     P = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints)
     import scipy.sparse.linalg as spla
     assert info["iters"] <= 2
-    assert rel(host(x), spla.spsolve(P.A.tocsc(), w.b)) <= 1e-10
+    close(host(x), spla.spsolve(P.A.tocsc(), w.b), 1e-10)
     S.close()
 
 
@@ -202,7 +219,8 @@ def test_warm_start_flag(full_space):
 
 
 @pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
-@pytest.mark.parametrize("name", ["3d_16_2x2x2", "3d_24_3x3x3_inclusions", "2d_20x24_uneven"])
+@pytest.mark.parametrize("name", ["3d_16_2x2x2", "3d_24_3x3x3_inclusions", "2d_20x24_uneven",
+                                  "3d_40_boxes_8_24_inclusions"])
 def test_fp32_local_reaches_true_residual(name, full_space):
     w, P = oracle_for(name)
     ref = O.bddc_pcg(P, w.b, 1e-12)
@@ -258,7 +276,7 @@ def test_element_gradient_kernel():
     rng = np.random.default_rng(4)
     lam, u = rng.standard_normal(P.n), rng.standard_normal(P.n)
     g = host(S.elem_grad(dev(lam), dev(u)))
-    assert rel(g, O.element_gradient(P.mesh, lam, u)) <= 1e-13
+    close(g, O.element_gradient(P.mesh, lam, u), 1e-13)
     S.close()
 
 
@@ -380,16 +398,15 @@ def test_rho_scaling_matches_oracle(name, full_space):
     w, P = rho_oracle_for(name)
     S = bd().solver_for(w, full_space=full_space, rho_scaling=True)
     r = np.random.default_rng(11).standard_normal(P.n)
-    e = rel(host(S.apply(dev(r))), P.apply(r))
-    say(name, "rho apply rel err", e)
-    assert e <= 1e-10
+    en, ee = close(host(S.apply(dev(r))), P.apply(r), 1e-10)
+    say(name, "rho apply rel err", en, "entry-wise", ee)
     ref = O.bddc_pcg(P, w.b, w.rtol)
     K = max(ref.iters - 2, 1)
     refK = O.bddc_pcg(P, w.b, 1e-300, maxit=K)
     xK, info = S.solve(dev(w.b), 1e-15, maxit=K, raise_on_noconv=False)
-    e = rel(host(xK), refK.x)
-    say(name, "rho K", K, "iterate rel err", e)
-    assert info["iters"] == K and e <= 1e-10
+    assert info["iters"] == K
+    en, ee = close(host(xK), refK.x, 1e-10)
+    say(name, "rho K", K, "iterate rel err", en, "entry-wise", ee)
     x, info = S.solve(dev(w.b), w.rtol)
     say(name, "rho iters gpu", info["iters"], "oracle", ref.iters, "cond", info["cond_est"], ref.cond_est)
     assert abs(info["iters"] - ref.iters) <= 1
@@ -408,19 +425,20 @@ def test_coarse_cg_matches_oracle(name, full_space):
     w, P = oracle_for(name)
     S = bd().solver_for(w, full_space=full_space, coarse_cg=True)
     r = np.random.default_rng(12).standard_normal(P.n)
-    e = rel(host(S.apply(dev(r))), P.apply(r))
-    say(name, "coarse-CG apply rel err", e)
-    assert e <= 1e-10
+    en, ee = close(host(S.apply(dev(r))), P.apply(r), 1e-10)
+    say(name, "coarse-CG apply rel err", en, "entry-wise", ee)
     ref = O.bddc_pcg(P, w.b, w.rtol)
-    # at most 10 steps: on 2d_72_24x24_many the oracle's own iterate after 19
-    # steps moves by 3e-9 when each preconditioner output is perturbed by 1e-14
-    # relative, after 10 steps by 2e-14 under 1e-13
-    K = max(min(ref.iters - 2, 10), 1)
+    K = max(ref.iters - 2, 1)
+    if name == "2d_72_24x24_many":
+        # on this case alone the oracle's own iterate after 19 steps moves by
+        # 3e-9 when each preconditioner output is perturbed by 1e-14 relative
+        # (after 10 steps by 2e-14 under 1e-13): compare after at most 10 steps
+        K = min(K, 10)
     refK = O.bddc_pcg(P, w.b, 1e-300, maxit=K)
     xK, info = S.solve(dev(w.b), 1e-15, maxit=K, raise_on_noconv=False)
-    e = rel(host(xK), refK.x)
-    say(name, "coarse-CG K", K, "iterate rel err", e)
-    assert info["iters"] == K and e <= 1e-10
+    assert info["iters"] == K
+    en, ee = close(host(xK), refK.x, 1e-10)
+    say(name, "coarse-CG K", K, "iterate rel err", en, "entry-wise", ee)
     x, info = S.solve(dev(w.b), w.rtol)
     assert abs(info["iters"] - ref.iters) <= 1 and info["relres_true"] <= w.rtol
     S.close()
