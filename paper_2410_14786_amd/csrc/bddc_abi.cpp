@@ -152,6 +152,8 @@ struct bddc_ctx {
   void* pub_local = nullptr;   // 4 * n_vec entries of the local precision
   double* pub_coarse = nullptr;
   unsigned* tickets = nullptr;
+  int* fready = nullptr;            // per tile ready words of the persistent factorisation
+  unsigned* fticket = nullptr;
   double *part = nullptr, *gbuf = nullptr, *mu = nullptr, *coef = nullptr, *ww = nullptr, *v12 = nullptr,
          *uc = nullptr;
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *tmp = nullptr;
@@ -802,7 +804,16 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   HIP_TRY(hipEventCreate(&f0));
   HIP_TRY(hipEventCreate(&f1));
   HIP_TRY(hipEventRecord(f0, st));
-  launch_factor(c->mats, P.nsubs, P.maxT, P.maxTx, c->tiles, c->dinv, c->fp32, c->fcol, c->err + 1, st);
+  {
+    // one persistent launch factors every local matrix (two workgroups per CU:
+    // each holds two tiles in LDS)
+    int32_t* ftasks = nullptr;
+    if ((rc_ = c->upload(ftasks, P.factor_tasks))) return rc_;
+    if ((rc_ = c->alloc(c->fready, P.n_tiles))) return rc_;
+    if ((rc_ = c->alloc(c->fticket, 1))) return rc_;
+    launch_factor_persistent(c->mats, c->tiles, c->dinv, c->fp32, c->fcol, ftasks, int(P.factor_tasks.size() / 3),
+                             c->fticket, c->fready, P.n_tiles, 2 * c->cus, c->err + 1, st);
+  }
   HIP_TRY(hipEventRecord(f1, st));
   if ((rc_ = c->alloc(c->cpp, small))) return rc_;
   launch_local_small(c->mats, P.nsubs, c->tiles, c->fp32, c->app, c->sainv, c->sainve, c->aci, c->cpp, c->err + 1,
@@ -882,7 +893,17 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
     launch_pad_identity(c->cmat, 1, c->ctiles, false, st);
     launch_coarse_assembly(c->ac_src_ptr, c->ac_src, c->ac_row, c->ac_col, c->ac_diag, int(P.ac_row.size()), nc,
                            c->aci, c->ac_val, c->dc, c->ctiles, c->err + 2, st);
-    launch_factor(c->cmat, 1, c->Tc, c->Tc, c->ctiles, c->cdinv, false, nullptr, c->err + 2, st);
+    {
+      std::vector<int32_t> ct;
+      std::string terr;
+      if ((rc_ = make_factor_tasks(cm, nullptr, ct, terr))) return fail(rc_, terr);
+      int32_t* ctasks = nullptr;
+      int* cready = nullptr;
+      if ((rc_ = c->upload(ctasks, ct))) return rc_;
+      if ((rc_ = c->alloc(cready, tri_tile(c->Tc, 0)))) return rc_;
+      launch_factor_persistent(c->cmat, c->ctiles, c->cdinv, false, nullptr, ctasks, int(ct.size() / 3), c->fticket,
+                               cready, tri_tile(c->Tc, 0), 2 * c->cus, c->err + 2, st);
+    }
     if (c->iface) {
       // A_c^{-1} = D X^T X D, X = inverse of the coarse Cholesky factor
       if ((rc_ = c->alloc(c->cxg, tri_tile(c->Tc, 0) * NB * NB))) return rc_;
@@ -942,6 +963,7 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   }
   if (herr[0] & 1) return fail(BDDC_ENOTSPD, "conductivity must be positive and finite");
   if (herr[0] & 4) return fail(BDDC_EINVAL, "internal: CSR row count mismatch");
+  if ((herr[1] | herr[2]) & 8) return fail(BDDC_EHIP, "a factorisation task waited too long for a tile it reads");
   if (herr[1]) return fail(BDDC_ENOTSPD, "a local factorisation met a non-positive pivot (flags " +
                                             std::to_string(herr[1]) + ")");
   if (herr[2]) return fail(BDDC_ENOTSPD, "the coarse matrix is not positive definite (flags " +

@@ -89,6 +89,8 @@ struct Plan {
 
   // ticket-ordered task lists of the triangular solves, (matrix, tile row)
   std::vector<int32_t> fwd_rr, bwd_rr, fwd_ii, bwd_ii;
+  // ticket-ordered tile tasks of the persistent factorisation, (matrix, i, j)
+  std::vector<int32_t> factor_tasks;
   // interface form: the symmetric interface matrices of all subdomains form one
   // stream of n_sg tiles (sg_off order) and n_symrows tile rows (sym_row order).
   // symfin = (matrix, ii) per row; tinfo per tile = (global row << 8) | (ii - jj);
@@ -112,6 +114,12 @@ struct Plan {
   int maxTG = 0, maxTS = 0;
   int max_nci = 0;
 };
+
+// Tile tasks (matrix, i, j) of the persistent left-looking factorisation in
+// ticket order; fcol: per tile row (vec_off / NB + i) first envelope column, or
+// null for dense matrices.  Checks that every tile a task reads comes earlier.
+int make_factor_tasks(const std::vector<MatDesc>& mats, const std::vector<int32_t>* fcol, std::vector<int32_t>& out,
+                      std::string& err);
 
 // Validates and plans; returns a bddc_status, with a message in err.
 int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constraints,

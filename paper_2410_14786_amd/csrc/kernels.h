@@ -119,8 +119,12 @@ void launch_local_assembly(const MeshDevHost& m, const double* theta, const MatD
                            const int32_t* avg_of, const double* avg_coef, void* tiles, bool fp32, double* app,
                            int* err, hipStream_t st);
 void launch_pad_identity(const MatDesc* mats, int nmats, void* tiles, bool fp32, hipStream_t st);
-void launch_factor(const MatDesc* mats, int nmats, int maxT, int maxTx, void* tiles, void* dinv, bool fp32,
-                   const int32_t* fcol, int* err, hipStream_t st);
+// One persistent launch factors every matrix (left-looking, tile tasks in the
+// order of make_factor_tasks); ready: nready ints of scratch, ticket: 1 counter.
+// err bits: 2 non-positive pivot, 8 a dependency wait gave up.
+void launch_factor_persistent(const MatDesc* mats, void* tiles, void* dinv, bool fp32, const int32_t* fcol,
+                              const int32_t* tasks, int ntasks, unsigned* ticket, int* ready, int64_t nready,
+                              int grid, int* err, hipStream_t st);
 void launch_local_small(const MatDesc* mats, int nmats, const void* tiles, bool fp32, const double* app,
                         double* sainv, double* sainve, double* aci, double* cpp, int* err, hipStream_t st);
 void launch_coarse_assembly(const int32_t* src_ptr, const int32_t* src, const int32_t* row, const int32_t* col,

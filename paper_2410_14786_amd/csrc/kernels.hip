@@ -406,74 +406,10 @@ void launch_pad_identity(const MatDesc* mats, int nmats, void* tiles, bool fp32,
 }
 
 // ---------------------------------------------------------------------------
-// Batched right-looking tile Cholesky
+// Tile algebra on MFMA shared by the factorisation and the setup kernels
 // ---------------------------------------------------------------------------
 
 constexpr int LDT = NB + 1;   // padded LDS row stride
-
-// Factor the diagonal tile (k, k) of every matrix with T > k in LDS, write L_kk and
-// its inverse (the inverse-diagonal tile used by the panel step and the solves).
-template <typename T>
-__global__ __launch_bounds__(256) void potrf_diag_kernel(const MatDesc* mats, T* tiles, T* dinv, int k,
-                                                         int* err) {
-  const MatDesc D = mats[blockIdx.x];
-  if (k >= D.T) return;
-  __shared__ T a[NB * LDT];
-  __shared__ T x[NB * LDT];
-  __shared__ int bad;
-  const int tid = threadIdx.x;
-  T* tile = tiles + (D.tile_off + tri_tile(k, k)) * int64_t(NB * NB);
-  for (int i = tid; i < NB * NB; i += 256) a[(i / NB) * LDT + (i % NB)] = tile[i];
-  if (tid == 0) bad = 0;
-  __syncthreads();
-  // Right-looking, one barrier per column: the trailing update uses the unscaled
-  // column j (l_ij l_cj = a_ij a_cj / a_jj); column j is scaled afterwards, and
-  // no later step reads it.
-  for (int j = 0; j < NB; ++j) {
-    T p = a[j * LDT + j];
-    if (!(p > T(0)) || !(p < T(3e38))) {
-      if (tid == 0) bad = 1;
-      p = T(1);
-    }
-    const T inv_p = T(1) / p;
-    {
-      // four threads per row i, each every fourth column c in (j, i]
-      const int i = tid >> 2, q = tid & 3;
-      if (i > j) {
-        const T f = a[i * LDT + j] * inv_p;
-        for (int c = j + 1 + ((q - j - 1) & 3); c <= i; c += 4) a[i * LDT + c] -= f * a[c * LDT + j];
-      }
-    }
-    __syncthreads();
-    if (tid >= j && tid < NB) {
-      const T ljj = sqrt(p);
-      a[tid * LDT + j] = tid == j ? ljj : a[tid * LDT + j] / ljj;
-    }
-  }
-  __syncthreads();
-  // inverse of the lower-triangular factor by forward substitution: four lanes
-  // per column c split each row's sum, the lane of row i's residue class stores
-  // x(i, c) (LDS operations of one wave complete in order)
-  {
-    const int c = tid >> 2, q = tid & 3;
-    for (int i = q; i < c; i += 4) x[i * LDT + c] = T(0);
-    for (int i = c; i < NB; ++i) {
-      T s = T(0);
-      for (int j = c + q; j < i; j += 4) s += a[i * LDT + j] * x[j * LDT + c];
-      s += __shfl_xor(s, 1, 4);
-      s += __shfl_xor(s, 2, 4);
-      if (q == (i & 3)) x[i * LDT + c] = ((i == c ? T(1) : T(0)) - s) / a[i * LDT + i];
-    }
-  }
-  __syncthreads();
-  T* dt = dinv + (D.dinv_off + k) * int64_t(NB * NB);
-  for (int i = tid; i < NB * NB; i += 256) {
-    int r = i / NB, c = i % NB;
-    tile[i] = (c <= r) ? a[r * LDT + c] : T(0);
-    dt[i] = (c <= r) ? x[r * LDT + c] : T(0);
-  }
-  if (tid == 0 && bad) atomicOr(err, 2);
-}
 
 // MFMA 16x16x4 wrappers: a operand = A[row0 + lane%16][k + lane/16], b operand =
 // B[col0 + lane%16][k + lane/16].  Accumulator item i of lane l holds column
@@ -514,104 +450,251 @@ __device__ __forceinline__ void gemm_nt_tile(const T* A, const T* B, typename Ac
   }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent left-looking tile Cholesky: one launch for all matrices
+// ---------------------------------------------------------------------------
+// A task is one tile (i, j), j <= i, of one matrix inside its envelope.  It sums
+// P = sum_k L_ik L_jk^T over the columns k < j where both tiles can be nonzero
+// (k >= max(fcol_i, fcol_j)), keeping P in MFMA accumulators, and then
+//   i == j < T : factors A_jj - P = L_jj L_jj^T and inverts L_jj (Dinv_j);
+//   i == j == T: stores A_TT - P (the bordering tile, -W^T W);
+//   i > j      : L_ij = (A_ij - P) Dinv_j^T.
+// Tasks are taken from one ticket counter in an order where every tile a task
+// reads belongs to an earlier ticket (host: make_factor_tasks), so a task only
+// waits for tasks already taken by running workgroups: no deadlock for any
+// grid size.  A finished tile is announced by a per-tile ready word; tile values
+// that other tasks read (off-diagonal L, Dinv) are written and read with
+// device-scope (agent) atomic accesses, which are coherent across the XCDs'
+// L2 caches, and the ready word is stored after every value has landed.
+
+// Bounded wait for a ready word; gives up after about a second and records
+// FACTOR_ERR_WAIT so that a broken dependency order cannot hang the GPU.
+constexpr int FACTOR_ERR_PIVOT = 2;
+constexpr int FACTOR_ERR_WAIT = 8;
+__device__ __forceinline__ void wait_ready(const int* flag, int* err) {
+  if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  for (long n = 0; n < (1L << 24); ++n) {
+    __builtin_amdgcn_s_sleep(4);
+    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  }
+  atomicOr(err, FACTOR_ERR_WAIT);
+}
+
 template <typename T>
-__device__ __forceinline__ void load_tile_lds(T* dst, const T* src) {
-  for (int i = threadIdx.x; i < NB * NB; i += 256) dst[(i / NB) * LDT + (i % NB)] = src[i];
+__device__ __forceinline__ T load_agent(const T* p) {
+  using U = typename Traits<T>::U;
+  return __builtin_bit_cast(T, __hip_atomic_load(reinterpret_cast<const U*>(p), __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT));
 }
-
-// L_ik = A_ik * Dinv_k^T for tile rows i in (k, Tx) (the border row included).
-// Tiles outside the envelope (fcol, per tile row; the border row is dense) are
-// zero in A and stay zero in L, so the panel and update steps skip them.
-__device__ __forceinline__ bool tile_zero(const int32_t* fcol, const MatDesc& D, int i, int k) {
-  return fcol && i < D.T && fcol[D.vec_off / NB + i] > k;
-}
-
 template <typename T>
-__global__ __launch_bounds__(256) void trsm_panel_kernel(const MatDesc* mats, T* tiles, const T* dinv, int k,
-                                                          const int32_t* fcol) {
-  const MatDesc D = mats[blockIdx.y];
-  const int i = k + 1 + blockIdx.x;
-  if (k >= D.T || i >= D.Tx || tile_zero(fcol, D, i, k)) return;
-  __shared__ T sa[NB * LDT];
-  __shared__ T sb[NB * LDT];
-  T* tik = tiles + (D.tile_off + tri_tile(i, k)) * int64_t(NB * NB);
-  load_tile_lds(sa, tik);
-  load_tile_lds(sb, dinv + (D.dinv_off + k) * int64_t(NB * NB));
-  __syncthreads();
-  typename Acc4<T>::type acc[2][2];
-  for (int p = 0; p < 2; ++p)
-    for (int q = 0; q < 2; ++q) acc[p][q] = typename Acc4<T>::type(0);
-  gemm_nt_tile<T>(sa, sb, acc);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
-  for (int p = 0; p < 2; ++p)
-    for (int q = 0; q < 2; ++q)
-      for (int it = 0; it < 4; ++it) {
-        int r = r0 + 16 * p + Acc4<T>::row(lane, it), c = c0 + 16 * q + (lane & 15);
-        tik[r * NB + c] = acc[p][q][it];
-      }
+__device__ __forceinline__ void store_agent(T* p, T v) {
+  using U = typename Traits<T>::U;
+  __hip_atomic_store(reinterpret_cast<U*>(p), __builtin_bit_cast(U, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// A_ij -= L_ik L_jk^T for k < j <= i < Tx (pairs enumerated row by row).
+// a published tile (row-major, NB x NB) into LDS (stride LDT)
 template <typename T>
-__global__ __launch_bounds__(256) void syrk_update_kernel(const MatDesc* mats, T* tiles, int k, const int32_t* fcol) {
-  const MatDesc D = mats[blockIdx.y];
-  if (k >= D.T) return;
-  const int m = D.Tx - k - 1;                 // tile rows below k
-  const int64_t pidx = blockIdx.x;
-  if (pidx >= int64_t(m) * (m + 1) / 2) return;
-  int ii = int((sqrt(8.0 * double(pidx) + 1.0) - 1.0) * 0.5);
-  while (int64_t(ii) * (ii + 1) / 2 > pidx) --ii;
-  while (int64_t(ii + 1) * (ii + 2) / 2 <= pidx) ++ii;
-  const int jj = int(pidx - int64_t(ii) * (ii + 1) / 2);
-  const int i = k + 1 + ii, j = k + 1 + jj;
-  if (tile_zero(fcol, D, i, k) || tile_zero(fcol, D, j, k)) return;
-  __shared__ T sa[NB * LDT];
-  __shared__ T sb[NB * LDT];
-  const T* lik = tiles + (D.tile_off + tri_tile(i, k)) * int64_t(NB * NB);
-  const T* ljk = tiles + (D.tile_off + tri_tile(j, k)) * int64_t(NB * NB);
-  T* aij = tiles + (D.tile_off + tri_tile(i, j)) * int64_t(NB * NB);
-  load_tile_lds(sa, lik);
-  if (i != j) load_tile_lds(sb, ljk);
-  __syncthreads();
-  typename Acc4<T>::type acc[2][2];
-  for (int p = 0; p < 2; ++p)
-    for (int q = 0; q < 2; ++q) acc[p][q] = typename Acc4<T>::type(0);
-  gemm_nt_tile<T>(sa, i != j ? sb : sa, acc);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
-  for (int p = 0; p < 2; ++p)
-    for (int q = 0; q < 2; ++q)
-      for (int it = 0; it < 4; ++it) {
-        int r = r0 + 16 * p + Acc4<T>::row(lane, it), c = c0 + 16 * q + (lane & 15);
-        aij[r * NB + c] -= acc[p][q][it];
-      }
+__device__ __forceinline__ void load_tile_agent(T* dst, const T* src) {
+  for (int i = threadIdx.x; i < NB * NB; i += 256) dst[(i / NB) * LDT + (i % NB)] = load_agent(src + i);
 }
 
-void launch_factor(const MatDesc* mats, int nmats, int maxT, int maxTx, void* tiles, void* dinv, bool fp32,
-                   const int32_t* fcol, int* err, hipStream_t st) {
-  for (int k = 0; k < maxT; ++k) {
-    const int below = maxTx - k - 1;
-    if (fp32) {
-      hipLaunchKernelGGL(potrf_diag_kernel<float>, dim3(nmats), dim3(256), 0, st, mats, (float*)tiles,
-                         (float*)dinv, k, err);
-      if (below > 0) {
-        hipLaunchKernelGGL(trsm_panel_kernel<float>, dim3(below, nmats), dim3(256), 0, st, mats, (float*)tiles,
-                           (const float*)dinv, k, fcol);
-        hipLaunchKernelGGL(syrk_update_kernel<float>, dim3(int64_t(below) * (below + 1) / 2, nmats), dim3(256),
-                           0, st, mats, (float*)tiles, k, fcol);
+// Cholesky factor and inverse of the 64 x 64 SPD tile in a (LDS, stride LDT):
+// on return a = L (upper part zero) and x = L^{-1}.  Thread t holds the 4 x 4
+// block of rows 4 (t & 15).., columns 4 (t >> 4).. in registers; the 16 threads
+// that own a column block form one wave's quarter, so the pivot reaches them by
+// a lane shuffle.  Right-looking, one barrier per column for the factor and one
+// per row for the inverse (column / row broadcast through double-buffered LDS).
+// Returns false on a non-positive or non-finite pivot (replaced by 1).
+template <typename T>
+__device__ bool tile_potrf_inv(T* a, T* x, T* bc /* 2 x NB */, T* dg /* NB */) {
+  const int t = threadIdx.x;
+  const int r0 = 4 * (t & 15), c0 = 4 * (t >> 4);
+  T v[4][4];
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q) v[p][q] = a[(r0 + p) * LDT + c0 + q];
+  bool ok = true;
+  for (int jb = 0; jb < NB / 4; ++jb) {
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int j = 4 * jb + jj;
+      T* col = bc + (j & 1) * NB;
+      if ((t >> 4) == jb) {
+        // the pivot sits with the thread of row block jb in this column block
+        const int src = (16 * jb + jb) & 63;
+        T d = __shfl(v[jj][jj], src);
+        if (!(d > T(0)) || !(d < T(3e38))) {
+          ok = false;
+          d = T(1);
+        }
+        const T ljj = sqrt(d);
+        const T rinv = T(1) / ljj;
+        for (int p = 0; p < 4; ++p) {
+          const int r = r0 + p;
+          const T l = r > j ? v[p][jj] * rinv : (r == j ? ljj : T(0));
+          v[p][jj] = l;
+          col[r] = l;
+        }
+        if ((t & 15) == jb) dg[j] = rinv;
       }
-    } else {
-      hipLaunchKernelGGL(potrf_diag_kernel<double>, dim3(nmats), dim3(256), 0, st, mats, (double*)tiles,
-                         (double*)dinv, k, err);
-      if (below > 0) {
-        hipLaunchKernelGGL(trsm_panel_kernel<double>, dim3(below, nmats), dim3(256), 0, st, mats,
-                           (double*)tiles, (const double*)dinv, k, fcol);
-        hipLaunchKernelGGL(syrk_update_kernel<double>, dim3(int64_t(below) * (below + 1) / 2, nmats),
-                           dim3(256), 0, st, mats, (double*)tiles, k, fcol);
+      __syncthreads();
+      if (c0 + 3 > j) {
+        T lc[4], lr[4];
+        for (int q = 0; q < 4; ++q) lc[q] = col[c0 + q];
+        for (int p = 0; p < 4; ++p) lr[p] = col[r0 + p];
+        for (int p = 0; p < 4; ++p)
+          for (int q = 0; q < 4; ++q)
+            if (c0 + q > j) v[p][q] -= lr[p] * lc[q];
       }
     }
   }
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q) a[(r0 + p) * LDT + c0 + q] = v[p][q];
+  // X = L^{-1} by elimination on [L | I], row j at step j: x_j /= l_jj, then
+  // x_r -= l_rj x_j for r > j
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q) v[p][q] = (r0 + p == c0 + q) ? T(1) : T(0);
+  __syncthreads();
+  for (int jb = 0; jb < NB / 4; ++jb) {
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int j = 4 * jb + jj;
+      T* row = bc + (j & 1) * NB;
+      if ((t & 15) == jb) {
+        const T s = dg[j];
+        for (int q = 0; q < 4; ++q) {
+          v[jj][q] *= s;
+          row[c0 + q] = v[jj][q];
+        }
+      }
+      __syncthreads();
+      if (r0 + 3 > j) {
+        T lr[4], xc[4];
+        for (int p = 0; p < 4; ++p) lr[p] = a[(r0 + p) * LDT + j];
+        for (int q = 0; q < 4; ++q) xc[q] = row[c0 + q];
+        for (int p = 0; p < 4; ++p)
+          if (r0 + p > j)
+            for (int q = 0; q < 4; ++q) v[p][q] -= lr[p] * xc[q];
+      }
+    }
+  }
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q) x[(r0 + p) * LDT + c0 + q] = v[p][q];
+  return ok;
+}
+
+struct FactorArgs {
+  const MatDesc* mats;
+  void* tiles;
+  void* dinv;
+  const int32_t* fcol;    // per tile row (vec_off / NB + i): first envelope column; null: dense
+  const int32_t* tasks;   // (matrix, i, j) per ticket
+  int ntasks;
+  unsigned* ticket;
+  int* ready;             // per stored tile (tile_off + tri_tile(i, j)), zero before the launch
+  int* err;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void factor_persistent_kernel(FactorArgs F) {
+  __shared__ T sa[NB * LDT];
+  __shared__ T sb[NB * LDT];
+  __shared__ T bc[2 * NB];
+  __shared__ T dg[NB];
+  __shared__ int s_task;
+  T* tiles = static_cast<T*>(F.tiles);
+  T* dinv = static_cast<T*>(F.dinv);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int qr0 = 32 * (w >> 1), qc0 = 32 * (w & 1);
+  using AccT = typename Acc4<T>::type;
+  for (;;) {
+    if (tid == 0) s_task = int(atomicAdd(F.ticket, 1u));
+    __syncthreads();
+    // the same value in every lane: read it as a scalar so that the compiler
+    // keeps the loop (and the barriers in it) uniform across the workgroup
+    const int task = __builtin_amdgcn_readfirstlane(s_task);
+    __syncthreads();
+    if (task >= F.ntasks) return;
+    const int m = F.tasks[3 * task], i = F.tasks[3 * task + 1], j = F.tasks[3 * task + 2];
+    const MatDesc D = F.mats[m];
+    const int64_t rbase = D.vec_off / NB;
+    auto first_col = [&](int r) { return (F.fcol == nullptr || r >= D.T) ? 0 : F.fcol[rbase + r]; };
+    const int kf = max(first_col(i), first_col(j));
+    AccT acc[2][2];
+    for (int p = 0; p < 2; ++p)
+      for (int q = 0; q < 2; ++q) acc[p][q] = AccT(0);
+    for (int k = kf; k < j; ++k) {
+      if (tid == 0) {
+        wait_ready(F.ready + D.tile_off + tri_tile(i, k), F.err);
+        if (i != j) wait_ready(F.ready + D.tile_off + tri_tile(j, k), F.err);
+      }
+      __syncthreads();
+      load_tile_agent(sa, tiles + (D.tile_off + tri_tile(i, k)) * int64_t(NB * NB));
+      if (i != j) load_tile_agent(sb, tiles + (D.tile_off + tri_tile(j, k)) * int64_t(NB * NB));
+      __syncthreads();
+      gemm_nt_tile<T>(sa, i != j ? sb : sa, acc);
+      __syncthreads();
+    }
+    // R = A_ij - P into LDS (sa)
+    T* tij = tiles + (D.tile_off + tri_tile(i, j)) * int64_t(NB * NB);
+    for (int p = 0; p < 2; ++p)
+      for (int q = 0; q < 2; ++q)
+        for (int it = 0; it < 4; ++it) {
+          const int r = qr0 + 16 * p + Acc4<T>::row(lane, it), c = qc0 + 16 * q + (lane & 15);
+          sa[r * LDT + c] = tij[r * NB + c] - acc[p][q][it];
+        }
+    if (i == j && i < D.T) {
+      __syncthreads();
+      const bool ok = tile_potrf_inv<T>(sa, sb, bc, dg);
+      __syncthreads();
+      T* dt = dinv + (D.dinv_off + j) * int64_t(NB * NB);
+      for (int e = tid; e < NB * NB; e += 256) {
+        const int r = e / NB, c = e % NB;
+        tij[e] = sa[r * LDT + c];
+        store_agent(dt + e, sb[r * LDT + c]);
+      }
+      if (!ok && tid == 0) atomicOr(F.err, FACTOR_ERR_PIVOT);
+    } else if (i == j) {
+      __syncthreads();
+      for (int e = tid; e < NB * NB; e += 256) tij[e] = sa[(e / NB) * LDT + (e % NB)];
+    } else {
+      if (tid == 0) wait_ready(F.ready + D.tile_off + tri_tile(j, j), F.err);
+      __syncthreads();
+      load_tile_agent(sb, dinv + (D.dinv_off + j) * int64_t(NB * NB));
+      __syncthreads();
+      for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q) acc[p][q] = AccT(0);
+      gemm_nt_tile<T>(sa, sb, acc);
+      for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q)
+          for (int it = 0; it < 4; ++it) {
+            const int r = qr0 + 16 * p + Acc4<T>::row(lane, it), c = qc0 + 16 * q + (lane & 15);
+            store_agent(tij + r * NB + c, acc[p][q][it]);
+          }
+    }
+    // every value of this tile has landed before its ready word is set
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(F.ready + D.tile_off + tri_tile(i, j), 1, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+    // end the body with a barrier: the thread-0 regions at the end of one task
+    // and at the start of the next must not be merged into one region that
+    // the other lanes loop around (they would re-run the task without a ticket)
+    __syncthreads();
+  }
+}
+
+void launch_factor_persistent(const MatDesc* mats, void* tiles, void* dinv, bool fp32, const int32_t* fcol,
+                              const int32_t* tasks, int ntasks, unsigned* ticket, int* ready, int64_t nready,
+                              int grid, int* err, hipStream_t st) {
+  launch_fill<int>(ready, 0, nready, st);
+  launch_fill<unsigned>(ticket, 0u, 1, st);
+  FactorArgs F{mats, tiles, dinv, fcol, tasks, ntasks, ticket, ready, err};
+  grid = std::max(1, std::min(grid, ntasks));
+  if (fp32)
+    hipLaunchKernelGGL(factor_persistent_kernel<float>, dim3(grid), dim3(256), 0, st, F);
+  else
+    hipLaunchKernelGGL(factor_persistent_kernel<double>, dim3(grid), dim3(256), 0, st, F);
 }
 
 // ---------------------------------------------------------------------------

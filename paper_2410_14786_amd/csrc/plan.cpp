@@ -475,6 +475,76 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
       }
     }
   }
+  if (int rc_ = make_factor_tasks(P.subs, &P.fcol, P.factor_tasks, err)) return rc_;
+  return BDDC_OK;
+}
+
+int make_factor_tasks(const std::vector<MatDesc>& mats, const std::vector<int32_t>* fcol, std::vector<int32_t>& out,
+                      std::string& err) {
+  // tile (i, k) of matrix m can be nonzero: border row, or inside the envelope
+  auto nz = [&](const MatDesc& D, int i, int k) {
+    return i >= D.T || fcol == nullptr || (*fcol)[D.vec_off / NB + i] <= k;
+  };
+  auto first_col = [&](const MatDesc& D, int r) {
+    return (fcol == nullptr || r >= D.T) ? 0 : (*fcol)[D.vec_off / NB + r];
+  };
+  // per matrix: its tasks in step order (step s: the diagonal tile (s, s), the
+  // tiles (i, s - 1) for i > s, then (s + 1, s), which the next diagonal tile waits for)
+  std::vector<std::vector<std::vector<int32_t>>> steps(mats.size());
+  int max_steps = 0;
+  for (size_t m = 0; m < mats.size(); ++m) {
+    const MatDesc& D = mats[m];
+    steps[m].resize(D.Tx);
+    max_steps = std::max(max_steps, int(D.Tx));
+    for (int st = 0; st < D.Tx; ++st) {
+      auto& v = steps[m][st];
+      v.push_back(st);
+      v.push_back(st);
+      if (st >= 1)
+        for (int i = st + 1; i < D.Tx; ++i)
+          if (nz(D, i, st - 1)) {
+            v.push_back(i);
+            v.push_back(st - 1);
+          }
+      if (st < D.T && st + 1 < D.Tx && nz(D, st + 1, st)) {
+        v.push_back(st + 1);
+        v.push_back(st);
+      }
+    }
+    // check the order: every tile a task reads (L_ik, L_jk for k in
+    // [max(first_col(i), first_col(j)), j), and Dinv_j) comes earlier, and every
+    // tile of the envelope appears exactly once
+    std::vector<int32_t> pos(tri_tile(D.Tx, 0), -1);
+    int32_t n = 0;
+    for (auto& v : steps[m])
+      for (size_t q = 0; q < v.size(); q += 2) {
+        int32_t& p = pos[tri_tile(v[q], v[q + 1])];
+        if (p >= 0) { err = "internal: factor task listed twice"; return BDDC_EINVAL; }
+        p = n++;
+      }
+    for (int i = 0; i < D.Tx; ++i)
+      for (int j = 0; j <= i; ++j) {
+        const int32_t p = pos[tri_tile(i, j)];
+        if ((p >= 0) != (i == j || nz(D, i, j))) { err = "internal: factor tasks do not cover the envelope"; return BDDC_EINVAL; }
+        if (p < 0) continue;
+        const int kf = std::max(first_col(D, i), first_col(D, j));
+        for (int k = kf; k < j; ++k) {
+          const int32_t a = pos[tri_tile(i, k)], b = pos[tri_tile(j, k)];
+          if (a < 0 || b < 0 || a >= p || b >= p) { err = "internal: factor task order"; return BDDC_EINVAL; }
+        }
+        if (i != j && pos[tri_tile(j, j)] >= p) { err = "internal: factor task order"; return BDDC_EINVAL; }
+      }
+  }
+  for (int st = 0; st < max_steps; ++st)
+    for (size_t m = 0; m < mats.size(); ++m) {
+      if (st >= mats[m].Tx) continue;
+      const auto& v = steps[m][st];
+      for (size_t q = 0; q < v.size(); q += 2) {
+        out.push_back(int32_t(m));
+        out.push_back(v[q]);
+        out.push_back(v[q + 1]);
+      }
+    }
   return BDDC_OK;
 }
 
