@@ -1,0 +1,46 @@
+// Host-only driver of the planner (plan.cpp), built with the address and
+// undefined-behaviour sanitizers by the CPU test suite: it plans the partitions
+// given on stdin and prints the sizes and invariants of each plan, so that any
+// out-of-bounds access or undefined operation in the host stage of bddc_setup
+// stops the run.  Needs no GPU and no HIP runtime.
+//
+// stdin, one case per line:  dim nel0 nel1 nel2 constraints n0 cuts0... n1 cuts1... n2 cuts2...
+//   (n_a cut positions per axis, 0 ... nel_a; nel2 = 1 and n2 = 2 "0 1" in 2D)
+// stdout, per case: status n_free n_sub n_coarse sum_ni max_nci n_tiles factor_tasks
+#include <cstdio>
+#include <iostream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "bddc_internal.h"
+
+int main() {
+  std::string line;
+  while (std::getline(std::cin, line)) {
+    if (line.empty()) continue;
+    std::istringstream in(line);
+    bddc_mesh mesh{};
+    uint32_t cons = 0;
+    in >> mesh.dim >> mesh.nel[0] >> mesh.nel[1] >> mesh.nel[2] >> cons;
+    std::vector<int64_t> cuts[3];
+    bddc_partition part{};
+    for (int a = 0; a < 3; ++a) {
+      int n = 0;
+      in >> n;
+      cuts[a].resize(n);
+      for (int q = 0; q < n; ++q) in >> cuts[a][q];
+      part.nsub[a] = n - 1;
+      part.cuts[a] = cuts[a].data();
+    }
+    bddc::Plan P;
+    std::string err;
+    const int rc = bddc::make_plan(&mesh, &part, cons, P, err);
+    int64_t sum_ni = 0;
+    for (auto& D : P.subs) sum_ni += D.n_i;
+    std::printf("%d %lld %d %d %lld %d %lld %lld\n", rc, (long long)P.n_free, P.nsubs, P.n_coarse,
+                (long long)sum_ni, P.max_nci, (long long)P.n_tiles, (long long)(P.factor_tasks.size() / 3));
+    if (rc) std::fprintf(stderr, "case failed: %s\n", err.c_str());
+  }
+  return 0;
+}
