@@ -46,7 +46,8 @@ class PcgInfo(ctypes.Structure):
 
 EXPORTS = ["bddc_setup", "bddc_apply", "bddc_pcg_solve", "bddc_spmv", "bddc_elem_grad", "bddc_query",
            "bddc_plan_stats", "bddc_set_timing", "bddc_kernel_time", "bddc_destroy", "bddc_strerror",
-           "bddc_last_error", "bddc_debug_read", "bddc_set_tuning", "bddc_autotune", "bddc_setup_stats"]
+           "bddc_last_error", "bddc_debug_read", "bddc_set_tuning", "bddc_autotune", "bddc_setup_stats",
+           "bddc_apply_noalloc"]
 
 _lib = None
 
@@ -62,6 +63,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bddc_setup.argtypes = [ctypes.POINTER(Mesh), ctypes.POINTER(Partition), ctypes.POINTER(Coefficients),
                                ctypes.c_uint32, ctypes.POINTER(Options), ctypes.POINTER(vp)]
     lib.bddc_apply.argtypes = [vp, vp, vp]
+    lib.bddc_apply_noalloc.argtypes = [vp, vp, vp]
     lib.bddc_pcg_solve.argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(PcgInfo)]
     lib.bddc_spmv.argtypes = [vp, vp, vp]
     lib.bddc_elem_grad.argtypes = [vp, vp, vp, vp]
@@ -85,7 +87,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bddc_strerror.restype = ctypes.c_char_p
     lib.bddc_last_error.argtypes = []
     lib.bddc_last_error.restype = ctypes.c_char_p
-    for name in ["bddc_setup", "bddc_apply", "bddc_pcg_solve", "bddc_spmv", "bddc_elem_grad", "bddc_query",
+    for name in ["bddc_setup", "bddc_apply", "bddc_apply_noalloc", "bddc_pcg_solve", "bddc_spmv", "bddc_elem_grad", "bddc_query",
                  "bddc_plan_stats", "bddc_set_timing", "bddc_kernel_time"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -205,6 +207,12 @@ class Solver:
         z = self._new(self.n_free) if out is None else out
         _check(self.lib.bddc_apply(self.ctx, _dev_ptr(r, "r"), _dev_ptr(z, "z")), "bddc_apply")
         return z
+
+    def apply_noalloc(self, r, out):
+        """z = M^{-1} r through bddc_apply_noalloc (fixed device workspace; the
+        caller provides z)."""
+        _check(self.lib.bddc_apply_noalloc(self.ctx, _dev_ptr(r, "r"), _dev_ptr(out, "z")), "bddc_apply_noalloc")
+        return out
 
     def spmv(self, x, out=None):
         y = self._new(self.n_free) if out is None else out

@@ -154,6 +154,7 @@ struct bddc_ctx {
   unsigned* tickets = nullptr;
   int* fready = nullptr;            // per tile ready words of the persistent factorisation
   unsigned* fticket = nullptr;
+  void* static_scratch = nullptr;   // this device's fixed workspace (bddc_apply_noalloc)
   double *part = nullptr, *gbuf = nullptr, *mu = nullptr, *coef = nullptr, *ww = nullptr, *v12 = nullptr,
          *uc = nullptr;
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *tmp = nullptr;
@@ -319,6 +320,13 @@ void* pub_slot(bddc_ctx* c, int i) {
   return static_cast<char*>(c->pub_local) + size_t(i) * size_t(c->plan.n_vec) * es;
 }
 
+// Buffers of one preconditioner application that start over at every call.
+struct ApplyWs {
+  void* pub_local;      // 4 * n_vec entries of the local precision
+  double* pub_coarse;   // 2 * Tc * NB doubles
+  unsigned* tickets;    // 8 counters
+};
+
 int trsv_grid(bddc_ctx* c, int ntasks) { return std::max(1, std::min(ntasks, c->grid_trsv)); }
 // Interior passes: one chain of tile rows per subdomain, each task waiting on the
 // previous rows of its own chain; about four tasks in flight per chain keep
@@ -331,14 +339,23 @@ int trsv_grid_ii(bddc_ctx* c, int ntasks) {
 
 // z = M^{-1} r (paper Sec. 2): v1 + v2 through the forward solve, the coarse
 // problem and the backward solve, then v3 on subdomain interiors.
-void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
+// ws: where the per-application buffers live (published solutions, coarse
+// solutions, tickets); NULL: the ctx's own.  With ws no event is recorded.
+void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done, const ApplyWs* ws = nullptr) {
   const Plan& P = c->plan;
   hipStream_t st = c->st;
-  hipEvent_t ea = c->begin("apply");
-  if (c->fp32) launch_fill_sentinel<float>(static_cast<float*>(c->pub_local), 4 * P.n_vec, st);
-  else launch_fill_sentinel<double>(static_cast<double*>(c->pub_local), 4 * P.n_vec, st);
-  if (c->Tc > 0) launch_fill_sentinel<double>(c->pub_coarse, 2 * int64_t(c->Tc) * NB, st);
-  launch_fill<unsigned>(c->tickets, 0u, 8, st);
+  ApplyWs own{c->pub_local, c->pub_coarse, c->tickets};
+  const ApplyWs& W = ws ? *ws : own;
+  const bool events = ws == nullptr;
+  auto slot = [&](int i) -> void* {
+    const size_t es = c->fp32 ? sizeof(float) : sizeof(double);
+    return static_cast<char*>(W.pub_local) + size_t(i) * size_t(P.n_vec) * es;
+  };
+  hipEvent_t ea = events ? c->begin("apply") : nullptr;
+  if (c->fp32) launch_fill_sentinel<float>(static_cast<float*>(W.pub_local), 4 * P.n_vec, st);
+  else launch_fill_sentinel<double>(static_cast<double*>(W.pub_local), 4 * P.n_vec, st);
+  if (c->Tc > 0) launch_fill_sentinel<double>(W.pub_coarse, 2 * int64_t(c->Tc) * NB, st);
+  launch_fill<unsigned>(W.tickets, 0u, 8, st);
 
   // forward solve with A_RR: t = L^{-1} D W_i R_i r, border partials W^T t
   TrsvArgs a = base_args(c);
@@ -346,13 +363,13 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   a.tasks = c->t_fwd_rr;
   a.fcol = c->fcol;
   a.ntasks = int(P.fwd_rr.size() / 2);
-  a.ticket = c->tickets + 0;
-  a.sol = pub_slot(c, 0);
+  a.ticket = W.tickets + 0;
+  a.sol = slot(0);
   a.rin = r;
   a.part = c->part;
   {
-    hipEvent_t k0, k1;
-    c->kernel_events("trsv_fwd_rr", &k0, &k1);
+    hipEvent_t k0 = nullptr, k1 = nullptr;
+    if (events) c->kernel_events("trsv_fwd_rr", &k0, &k1);
     launch_trsv(TRSV_FWD_RR, c->fp32, a, trsv_grid(c, a.ntasks), st, k0, k1);
   }
 
@@ -367,8 +384,8 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
     cf.done = done;
     cf.tasks = c->ctask_fwd;
     cf.ntasks = c->Tc;
-    cf.ticket = c->tickets + 4;
-    cf.sol = c->pub_coarse;
+    cf.ticket = W.tickets + 4;
+    cf.sol = W.pub_coarse;
     cf.cinv_ptr = c->cinv_ptr;
     cf.cinv = c->cinv;
     cf.gbuf = c->gbuf;
@@ -379,9 +396,9 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
     } else {
       launch_trsv(TRSV_FWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
       cf.tasks = c->ctask_bwd;
-      cf.ticket = c->tickets + 5;
-      cf.src = c->pub_coarse;
-      cf.sol = c->pub_coarse + int64_t(c->Tc) * NB;
+      cf.ticket = W.tickets + 5;
+      cf.src = W.pub_coarse;
+      cf.sol = W.pub_coarse + int64_t(c->Tc) * NB;
       cf.uc = c->uc;
       launch_trsv(TRSV_BWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
     }
@@ -394,14 +411,14 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   a.tasks = c->t_bwd_rr;
   a.lrow = c->lrow_rr;
   a.ntasks = int(P.bwd_rr.size() / 2);
-  a.ticket = c->tickets + 1;
-  a.sol = pub_slot(c, 1);
-  a.src = pub_slot(c, 0);
+  a.ticket = W.tickets + 1;
+  a.sol = slot(1);
+  a.src = slot(0);
   a.coef = c->coef;
   a.ww = c->ww;
   {
-    hipEvent_t k0, k1;
-    c->kernel_events("trsv_bwd_rr", &k0, &k1);
+    hipEvent_t k0 = nullptr, k1 = nullptr;
+    if (events) c->kernel_events("trsv_bwd_rr", &k0, &k1);
     launch_trsv(TRSV_BWD_RR, c->fp32, a, trsv_grid(c, a.ntasks), st, k0, k1);
   }
   // v1 + v2 = sum_i R_i^T W_i w_i
@@ -412,13 +429,13 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   a.tasks = c->t_fwd_ii;
   a.fcol = c->fcol_ii;
   a.ntasks = int(P.fwd_ii.size() / 2);
-  a.ticket = c->tickets + 2;
-  a.sol = pub_slot(c, 2);
+  a.ticket = W.tickets + 2;
+  a.sol = slot(2);
   a.rin = r;
   a.v12 = c->v12;
   {
-    hipEvent_t k0, k1;
-    c->kernel_events("trsv_fwd_ii", &k0, &k1);
+    hipEvent_t k0 = nullptr, k1 = nullptr;
+    if (events) c->kernel_events("trsv_fwd_ii", &k0, &k1);
     launch_trsv(TRSV_FWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st, k0, k1);
   }
   a = base_args(c);
@@ -426,17 +443,17 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done) {
   a.tasks = c->t_bwd_ii;
   a.lrow = c->lrow_ii;
   a.ntasks = int(P.bwd_ii.size() / 2);
-  a.ticket = c->tickets + 3;
-  a.sol = pub_slot(c, 3);
-  a.src = pub_slot(c, 2);
+  a.ticket = W.tickets + 3;
+  a.sol = slot(3);
+  a.src = slot(2);
   a.zout = z;
   a.base = c->v12;
   {
-    hipEvent_t k0, k1;
-    c->kernel_events("trsv_bwd_ii", &k0, &k1);
+    hipEvent_t k0 = nullptr, k1 = nullptr;
+    if (events) c->kernel_events("trsv_bwd_ii", &k0, &k1);
     launch_trsv(TRSV_BWD_II, c->fp32, a, trsv_grid_ii(c, a.ntasks), st, k0, k1);
   }
-  c->end("apply", ea);
+  if (events) c->end("apply", ea);
 }
 
 IfcArgs ifc_args(bddc_ctx* c) {
@@ -1031,6 +1048,9 @@ int bddc_setup(const bddc_mesh* mesh, const bddc_partition* part, const bddc_coe
       }
   }
   c->st = static_cast<hipStream_t>(opts->stream);
+  // the fixed workspace of bddc_apply_noalloc on the current device (looked up
+  // once per device; a failed lookup only disables that entry point)
+  if (static_scratch_address(&c->static_scratch) != 0) c->static_scratch = nullptr;
   c->use_graph = opts->use_graph != 0;
   c->rho_scaling = (opts->flags & BDDC_SETUP_RHO_SCALING) != 0;
   c->coarse_cg = (opts->flags & BDDC_SETUP_COARSE_CG) != 0;
@@ -1071,6 +1091,26 @@ int bddc_apply(bddc_ctx* c, const double* r, double* z) {
   if (int rc_ = check_ctx(c)) return rc_;
   if (!r || !z || r == z) return fail(BDDC_EINVAL, "r and z must be distinct non-NULL device pointers");
   enqueue_apply(c, r, z, nullptr);
+  HIP_TRY(hipGetLastError());
+  return BDDC_OK;
+}
+
+int bddc_apply_noalloc(bddc_ctx* c, const double* r, double* z) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  if (!r || !z || r == z) return fail(BDDC_EINVAL, "r and z must be distinct non-NULL device pointers");
+  if (!c->static_scratch) return fail(BDDC_EHIP, "the fixed device workspace has no address on this device");
+  const Plan& P = c->plan;
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t es = c->fp32 ? sizeof(float) : sizeof(double);
+  const size_t b_pub = up(size_t(4) * size_t(P.n_vec) * es);
+  const size_t b_coarse = up(size_t(2) * size_t(std::max(c->Tc, 0)) * NB * sizeof(double));
+  const size_t need = b_pub + b_coarse + up(8 * sizeof(unsigned));
+  if (need > STATIC_SCRATCH_BYTES)
+    return fail(BDDC_EINVAL, "this problem needs " + std::to_string(need) + " bytes of apply workspace; the fixed "
+                             "workspace of bddc_apply_noalloc holds " + std::to_string(STATIC_SCRATCH_BYTES));
+  char* base = static_cast<char*>(c->static_scratch);
+  ApplyWs ws{base, reinterpret_cast<double*>(base + b_pub), reinterpret_cast<unsigned*>(base + b_pub + b_coarse)};
+  enqueue_apply(c, r, z, nullptr, &ws);
   HIP_TRY(hipGetLastError());
   return BDDC_OK;
 }

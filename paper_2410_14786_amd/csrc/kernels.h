@@ -231,6 +231,11 @@ void launch_coarse_cg_matrix(const int32_t* fsrc, const double* val, double* fva
 void launch_coarse_cg(const int32_t* rowptr, const int32_t* col, const double* fval, int nnz, const double* dc,
                       int nc, const int32_t* cinv_ptr, const int32_t* cinv, const double* gbuf, double* u,
                       double* work, double tol, int maxit, const int* done, hipStream_t st);
+// Size of the fixed device workspace of the allocation-free apply, and its
+// address on the current device (looked up once per device; 0 on success).
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(64) << 20;
+int static_scratch_address(void** ptr);
+
 void launch_trailing_inverse(const MatDesc* mats, int nmats, int maxTG, const double* tiles, const double* dinv,
                              double* xg, hipStream_t st);
 

@@ -17,6 +17,8 @@
 #include <hip/hip_ext.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 
 #include "bddc_internal.h"
 #include "kernels.h"
@@ -2790,6 +2792,33 @@ void launch_elem_grad(const MeshDevHost& mh, const double* lam, const double* u,
                       hipStream_t st) {
   MeshDev M{mh.dim, {mh.nel[0], mh.nel[1], mh.nel[2]}, {mh.h[0], mh.h[1], mh.h[2]}};
   hipLaunchKernelGGL(elem_grad_kernel, dim3(grid_for(nel)), dim3(256), 0, st, M, lam, u, g, nel);
+}
+
+// Fixed device workspace of the allocation-free apply (bddc_apply_noalloc):
+// the published-solution buffers, coarse solution buffers and ticket counters
+// of one preconditioner application.  Every GPU the library runs on holds its
+// own copy for the life of the process.  In host code `scratch` names a
+// host-side stand-in, never the device memory: kernels get the per-device
+// address that static_scratch_address obtains from the runtime.
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+int static_scratch_address(void** ptr) {
+  static std::mutex mtx;
+  static std::map<int, void*> by_device;
+  *ptr = nullptr;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  std::lock_guard<std::mutex> lock(mtx);
+  auto it = by_device.find(dev);
+  if (it != by_device.end()) {
+    *ptr = it->second;
+    return 0;
+  }
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -1;
+  by_device[dev] = p;
+  *ptr = p;
+  return 0;
 }
 
 }  // namespace bddc
