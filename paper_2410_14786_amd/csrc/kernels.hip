@@ -494,12 +494,6 @@ __device__ __forceinline__ void store_agent(T* p, T v) {
   __hip_atomic_store(reinterpret_cast<U*>(p), __builtin_bit_cast(U, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// a published tile (row-major, NB x NB) into LDS (stride LDT)
-template <typename T>
-__device__ __forceinline__ void load_tile_agent(T* dst, const T* src) {
-  for (int i = threadIdx.x; i < NB * NB; i += 256) dst[(i / NB) * LDT + (i % NB)] = load_agent(src + i);
-}
-
 // Cholesky factor and inverse of the 64 x 64 SPD tile in a (LDS, stride LDT):
 // on return a = L (upper part zero) and x = L^{-1}.  Thread t holds the 4 x 4
 // block of rows 4 (t & 15).., columns 4 (t >> 4).. in registers; the 16 threads
@@ -597,7 +591,7 @@ struct FactorArgs {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void factor_persistent_kernel(FactorArgs F) {
+__global__ __launch_bounds__(256, 2) void factor_persistent_kernel(FactorArgs F) {
   __shared__ T sa[NB * LDT];
   __shared__ T sb[NB * LDT];
   __shared__ T bc[2 * NB];
@@ -625,15 +619,31 @@ __global__ __launch_bounds__(256) void factor_persistent_kernel(FactorArgs F) {
     AccT acc[2][2];
     for (int p = 0; p < 2; ++p)
       for (int q = 0; q < 2; ++q) acc[p][q] = AccT(0);
+    // L_ik and L_jk of the next column are loaded into registers while the
+    // product of the current column runs from LDS; every lane checks the
+    // ready words itself (one request per wave), so no barrier sits between the
+    // wait and the loads
+    constexpr int PER = NB * NB / 256;
+    T ra[PER], rb[PER];
+    auto fetch = [&](int k) {
+      wait_ready(F.ready + D.tile_off + tri_tile(i, k), F.err);
+      if (i != j) wait_ready(F.ready + D.tile_off + tri_tile(j, k), F.err);
+      const T* pa = tiles + (D.tile_off + tri_tile(i, k)) * int64_t(NB * NB);
+      const T* pb = tiles + (D.tile_off + tri_tile(j, k)) * int64_t(NB * NB);
+      for (int q = 0; q < PER; ++q) ra[q] = load_agent(pa + tid + 256 * q);
+      if (i != j)
+        for (int q = 0; q < PER; ++q) rb[q] = load_agent(pb + tid + 256 * q);
+    };
+    if (kf < j) fetch(kf);
     for (int k = kf; k < j; ++k) {
-      if (tid == 0) {
-        wait_ready(F.ready + D.tile_off + tri_tile(i, k), F.err);
-        if (i != j) wait_ready(F.ready + D.tile_off + tri_tile(j, k), F.err);
+      // LDS is free: the previous product ended with a barrier
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        sa[(e / NB) * LDT + (e % NB)] = ra[q];
+        if (i != j) sb[(e / NB) * LDT + (e % NB)] = rb[q];
       }
       __syncthreads();
-      load_tile_agent(sa, tiles + (D.tile_off + tri_tile(i, k)) * int64_t(NB * NB));
-      if (i != j) load_tile_agent(sb, tiles + (D.tile_off + tri_tile(j, k)) * int64_t(NB * NB));
-      __syncthreads();
+      if (k + 1 < j) fetch(k + 1);
       gemm_nt_tile<T>(sa, i != j ? sb : sa, acc);
       __syncthreads();
     }
@@ -660,9 +670,13 @@ __global__ __launch_bounds__(256) void factor_persistent_kernel(FactorArgs F) {
       __syncthreads();
       for (int e = tid; e < NB * NB; e += 256) tij[e] = sa[(e / NB) * LDT + (e % NB)];
     } else {
-      if (tid == 0) wait_ready(F.ready + D.tile_off + tri_tile(j, j), F.err);
-      __syncthreads();
-      load_tile_agent(sb, dinv + (D.dinv_off + j) * int64_t(NB * NB));
+      wait_ready(F.ready + D.tile_off + tri_tile(j, j), F.err);
+      const T* dj = dinv + (D.dinv_off + j) * int64_t(NB * NB);
+      for (int q = 0; q < PER; ++q) rb[q] = load_agent(dj + tid + 256 * q);
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        sb[(e / NB) * LDT + (e % NB)] = rb[q];
+      }
       __syncthreads();
       for (int p = 0; p < 2; ++p)
         for (int q = 0; q < 2; ++q) acc[p][q] = AccT(0);
