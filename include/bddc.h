@@ -257,6 +257,26 @@ int bddc_kernel_time(bddc_ctx* ctx, const char* family, int64_t* launches,
  * Returns the number of values written (<= cap) or a negative status. */
 int64_t bddc_debug_read(bddc_ctx* ctx, const char* what, int32_t sub, double* host_out, int64_t cap);
 
+/* Device-side limits, mainly for tests of the failure paths:
+ *   "wait_polls"      polls of a published value before a triangular-solve task
+ *                     gives up (default 4194304, about a second); the task then
+ *                     uses 0, finishes normally and marks the ctx's device status
+ *                     word; a negative value makes every wait give up at once;
+ *   "coarse_cg_maxit" iteration limit of the coarse CG (BDDC_SETUP_COARSE_CG,
+ *                     default 2000); a coarse CG that stops at it (or breaks
+ *                     down) marks the device status word.
+ * A marked status word is reported, and cleared, by the next bddc_pcg_solve
+ * (EHIP for a wait that gave up, ENOCONV for the coarse CG; x and info are
+ * still filled) or bddc_sync.  Captured graphs are dropped.
+ * Errors: EINVAL (unknown name, negative coarse_cg_maxit). */
+int bddc_set_limit(bddc_ctx* ctx, const char* what, int32_t value);
+
+/* Waits for all work queued on the ctx stream and reports the device status
+ * word since it was last reported: OK, EHIP (a triangular-solve wait gave up,
+ * e.g. in an asynchronous bddc_apply) or ENOCONV (the coarse CG did not
+ * converge); the word is cleared. */
+int bddc_sync(bddc_ctx* ctx);
+
 /* Launch shape of the persistent kernels (triangular solves and tile
  * mat-vecs): wg_per_cu resident workgroups per compute unit, 1..16 (default
  * 4).  Captured graphs are dropped and recaptured with the new shape. */

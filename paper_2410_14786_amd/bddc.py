@@ -47,7 +47,7 @@ class PcgInfo(ctypes.Structure):
 EXPORTS = ["bddc_setup", "bddc_apply", "bddc_pcg_solve", "bddc_spmv", "bddc_elem_grad", "bddc_query",
            "bddc_plan_stats", "bddc_set_timing", "bddc_kernel_time", "bddc_destroy", "bddc_strerror",
            "bddc_last_error", "bddc_debug_read", "bddc_set_tuning", "bddc_autotune", "bddc_setup_stats",
-           "bddc_apply_noalloc"]
+           "bddc_apply_noalloc", "bddc_set_limit", "bddc_sync"]
 
 _lib = None
 
@@ -64,6 +64,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                ctypes.c_uint32, ctypes.POINTER(Options), ctypes.POINTER(vp)]
     lib.bddc_apply.argtypes = [vp, vp, vp]
     lib.bddc_apply_noalloc.argtypes = [vp, vp, vp]
+    lib.bddc_set_limit.argtypes = [vp, ctypes.c_char_p, i32]
+    lib.bddc_sync.argtypes = [vp]
     lib.bddc_pcg_solve.argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(PcgInfo)]
     lib.bddc_spmv.argtypes = [vp, vp, vp]
     lib.bddc_elem_grad.argtypes = [vp, vp, vp, vp]
@@ -87,7 +89,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bddc_strerror.restype = ctypes.c_char_p
     lib.bddc_last_error.argtypes = []
     lib.bddc_last_error.restype = ctypes.c_char_p
-    for name in ["bddc_setup", "bddc_apply", "bddc_apply_noalloc", "bddc_pcg_solve", "bddc_spmv", "bddc_elem_grad", "bddc_query",
+    for name in ["bddc_setup", "bddc_apply", "bddc_apply_noalloc", "bddc_set_limit", "bddc_sync", "bddc_pcg_solve", "bddc_spmv", "bddc_elem_grad", "bddc_query",
                  "bddc_plan_stats", "bddc_set_timing", "bddc_kernel_time"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -213,6 +215,15 @@ class Solver:
         caller provides z)."""
         _check(self.lib.bddc_apply_noalloc(self.ctx, _dev_ptr(r, "r"), _dev_ptr(out, "z")), "bddc_apply_noalloc")
         return out
+
+    def set_limit(self, what: str, value: int):
+        """Device-side limits for failure-path tests: "wait_polls", "coarse_cg_maxit"."""
+        _check(self.lib.bddc_set_limit(self.ctx, what.encode(), int(value)), "bddc_set_limit")
+
+    def sync(self):
+        """Wait for the ctx stream; raise BDDCError if a device-side wait gave up or the
+        coarse CG did not converge since the last report."""
+        _check(self.lib.bddc_sync(self.ctx), "bddc_sync")
 
     def spmv(self, x, out=None):
         y = self._new(self.n_free) if out is None else out

@@ -31,6 +31,13 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+// status of the device status word (bits DEV_*)
+int device_status_error(int w) {
+  if (w & DEV_WAIT_GAVE_UP)
+    return fail(BDDC_EHIP, "a triangular-solve task gave up waiting for a published value (wait_polls limit)");
+  return fail(BDDC_ENOCONV, "the coarse CG stopped at its iteration limit or broke down");
+}
+
 #define HIP_TRY(expr)                                                                  \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
@@ -153,6 +160,8 @@ struct bddc_ctx {
   double* pub_coarse = nullptr;
   unsigned* tickets = nullptr;
   int* fready = nullptr;            // per tile ready words of the persistent factorisation
+  int wait_polls = 1 << 22;         // polls of a published value before a solve task gives up
+  int coarse_maxit = COARSE_CG_MAXIT;
   unsigned* fticket = nullptr;
   void* static_scratch = nullptr;   // this device's fixed workspace (bddc_apply_noalloc)
   double *part = nullptr, *gbuf = nullptr, *mu = nullptr, *coef = nullptr, *ww = nullptr, *v12 = nullptr,
@@ -312,6 +321,8 @@ TrsvArgs base_args(bddc_ctx* c) {
   a.rowptr = c->rowptr;
   a.colind = c->col;
   a.vals = c->val;
+  a.werr = c->err + 3;
+  a.spin = c->wait_polls;
   return a;
 }
 
@@ -390,9 +401,11 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done, con
     cf.cinv = c->cinv;
     cf.gbuf = c->gbuf;
     cf.dc = c->dc;
+    cf.werr = c->err + 3;
+    cf.spin = c->wait_polls;
     if (c->coarse_cg) {
       launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fval, c->ac_nfull, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
-                       c->gbuf, c->uc, c->ccg_work, COARSE_CG_TOL, COARSE_CG_MAXIT, done, st);
+                       c->gbuf, c->uc, c->ccg_work, COARSE_CG_TOL, c->coarse_maxit, done, c->err + 3, st);
     } else {
       launch_trsv(TRSV_FWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
       cf.tasks = c->ctask_bwd;
@@ -530,7 +543,7 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
                        c->rowp, a.ntiles, a.nwg, st);
     if (c->coarse_cg)
       launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fval, c->ac_nfull, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
-                       c->gbuf, c->upart, c->ccg_work, COARSE_CG_TOL, COARSE_CG_MAXIT, done, st);
+                       c->gbuf, c->upart, c->ccg_work, COARSE_CG_TOL, c->coarse_maxit, done, c->err + 3, st);
     else
       launch_coarse_gemv(c->cainv, P.n_coarse, c->csplit, c->cinv_ptr, c->cinv, c->gbuf, c->upart, done, st);
   }
@@ -959,7 +972,7 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hdone), sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
   HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hdone_dev), c->hdone, 0));
   *c->hdone = 0;
-  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hback), (5 + 3 * size_t(MAX_PCG_IT)) * sizeof(double),
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hback), (6 + 3 * size_t(MAX_PCG_IT)) * sizeof(double),
                         hipHostMallocMapped | hipHostMallocCoherent));
   HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hback_dev), c->hback, 0));
   for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreateWithFlags(&c->snap_ev[i], hipEventDisableTiming));
@@ -1171,6 +1184,7 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
   launch_pcg_init(c->part_a, c->part_b, c->sc, rtol * rtol, st);
 
   struct HostScalars { double tol2, bb, rr0; int done, iters; } hs{};
+  int devstat = 0;   // device status word (DEV_* bits) read back with the scalars
   std::vector<double> alphas, betas;
   int it = 0;            // iteration slot
   int restarts = 0;
@@ -1222,17 +1236,19 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
     if (iface) enqueue_interior_complete(c, b, x, x);
     launch_residual(c->rowptr, c->col, c->val, x, b, c->tmp, c->part_a, c->part_b, n, st);
     launch_finish_dot(c->part_a, c->scal, st);
-    launch_pack_readback(c->sc, c->scal, 0, it, c->hback_dev, st);
+    launch_pack_readback(c->sc, c->scal, c->err + 3, 0, it, c->hback_dev, st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
     const double* hb = c->hback;
     std::memcpy(&hs, hb, sizeof(hs));
     const int iters = hs.iters;
+    std::memcpy(&devstat, hb + 5, sizeof(int));
     if (iters > seg_start && restarts == 0) {
-      alphas.assign(hb + 5, hb + 5 + iters);
-      betas.assign(hb + 5 + it, hb + 5 + it + iters - 1);
+      alphas.assign(hb + 6, hb + 6 + iters);
+      betas.assign(hb + 6 + it, hb + 6 + it + iters - 1);
     }
-    const double rr = iters > 0 ? hb[5 + 2 * it + iters - 1] : hs.rr0;
+    const double rr = iters > 0 ? hb[6 + 2 * it + iters - 1] : hs.rr0;
+    if (devstat) break;
     relres_rec = hs.bb > 0 ? std::sqrt(rr / hs.bb) : 0.0;
     relres_true = hs.bb > 0 ? std::sqrt(hb[4] / hs.bb) : 0.0;
     if (hs.done == 2) { status = BDDC_EBREAKDOWN; break; }
@@ -1260,6 +1276,11 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
     info->cond_est = lanczos_cond(alphas, betas);
     info->t_setup_ms = c->t_setup_ms;
     info->t_solve_ms = now_ms() - t0;
+  }
+  if (devstat) {
+    launch_fill<int>(c->err + 3, 0, 1, st);
+    HIP_TRY(hipStreamSynchronize(st));
+    return device_status_error(devstat);
   }
   if (status == BDDC_EBREAKDOWN) return fail(status, "CG breakdown: (p, A p) <= 0, (r, z) <= 0 or NaN");
   if (status == BDDC_ENOCONV) return fail(status, "maximum iterations reached");
@@ -1410,6 +1431,36 @@ void drop_graphs(bddc_ctx* c) {
   c->graph_pending.clear();
 }
 }  // namespace
+
+int bddc_set_limit(bddc_ctx* c, const char* what, int32_t value) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  if (!what) return fail(BDDC_EINVAL, "limit name is NULL");
+  const std::string w(what);
+  if (w == "wait_polls") {
+    drop_graphs(c);   // captured kernel arguments hold the old limit
+    c->wait_polls = value;
+  } else if (w == "coarse_cg_maxit") {
+    if (value < 0) return fail(BDDC_EINVAL, "coarse_cg_maxit must be >= 0");
+    drop_graphs(c);
+    c->coarse_maxit = value;
+  } else {
+    return fail(BDDC_EINVAL, "unknown limit (wait_polls, coarse_cg_maxit)");
+  }
+  return BDDC_OK;
+}
+
+int bddc_sync(bddc_ctx* c) {
+  if (int rc_ = check_ctx(c)) return rc_;
+  int w = 0;
+  HIP_TRY(hipMemcpyAsync(&w, c->err + 3, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  if (w) {
+    launch_fill<int>(c->err + 3, 0, 1, c->st);
+    HIP_TRY(hipStreamSynchronize(c->st));
+    return device_status_error(w);
+  }
+  return BDDC_OK;
+}
 
 int bddc_set_tuning(bddc_ctx* c, int32_t wg_per_cu) {
   if (int rc_ = check_ctx(c)) return rc_;

@@ -56,7 +56,14 @@ struct TrsvArgs {
   double* uc;
   const int32_t* fcol;   // per tile row: first nonzero tile column (null: dense)
   const int32_t* lrow;   // backward passes, per tile column k: last tile row to read (null: dense)
+  int* werr;             // device status word: DEV_WAIT_GAVE_UP when a wait gives up
+  int spin;              // polls of a published value before giving up (< 0: give up at once)
 };
+
+// bits of the device status word of a ctx (set by kernels, read and cleared by
+// the host at the end of a solve or by bddc_sync)
+constexpr int DEV_WAIT_GAVE_UP = 1;     // a triangular-solve task stopped waiting for a value
+constexpr int DEV_COARSE_NOCONV = 2;    // the coarse CG stopped at its iteration limit or broke down
 
 
 struct PcgScalars {
@@ -162,8 +169,8 @@ void launch_pcg_update(double* x, double* r, const double* p, const double* q, c
 // hdone: mapped pinned host word set to 1 when the solve ends (may be null)
 void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, int* hdone, hipStream_t st);
 // out: mapped pinned host memory of 5 + 3 n doubles
-void launch_pack_readback(const PcgScalars* sc, const double* rr_true, int seg, int n, double* out,
-                          hipStream_t st);
+void launch_pack_readback(const PcgScalars* sc, const double* rr_true, const int* werr, int seg, int n,
+                          double* out, hipStream_t st);
 void launch_dot(const double* a, const double* b, double* part, int64_t n, const int* done, hipStream_t st);
 void launch_finish_dot(const double* part, double* out, hipStream_t st);
 void launch_elem_grad(const MeshDevHost& m, const double* lam, const double* u, double* g, int64_t nel,
@@ -230,7 +237,7 @@ void launch_coarse_cg_matrix(const int32_t* fsrc, const double* val, double* fva
 // (work: 7 nc doubles)
 void launch_coarse_cg(const int32_t* rowptr, const int32_t* col, const double* fval, int nnz, const double* dc,
                       int nc, const int32_t* cinv_ptr, const int32_t* cinv, const double* gbuf, double* u,
-                      double* work, double tol, int maxit, const int* done, hipStream_t st);
+                      double* work, double tol, int maxit, const int* done, int* werr, hipStream_t st);
 // Size of the fixed device workspace of the allocation-free apply, and its
 // address on the current device (looked up once per device; 0 on success).
 constexpr size_t STATIC_SCRATCH_BYTES = size_t(64) << 20;

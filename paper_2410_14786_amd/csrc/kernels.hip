@@ -68,14 +68,20 @@ __device__ __forceinline__ bool is_sentinel(T v) {
   return __builtin_bit_cast(U, v) == Traits<T>::SENT;
 }
 
+// Wait for a published value; after `spin` polls (at once for spin < 0) give up,
+// record DEV_WAIT_GAVE_UP in the status word and use 0, so that the kernel
+// still finishes (the host then reports the failure).
 template <typename T>
-__device__ __forceinline__ T poll_published(const T* p) {
-  T v = load_published(p);
-  while (is_sentinel(v)) {
+__device__ __forceinline__ T poll_published(const T* p, int spin, int* werr) {
+  T v = spin < 0 ? T(0) : load_published(p);
+  if (spin >= 0 && !is_sentinel(v)) return v;
+  for (int n = 0; n < spin; ++n) {
     __builtin_amdgcn_s_sleep(2);
     v = load_published(p);
+    if (!is_sentinel(v)) return v;
   }
-  return v;
+  atomicOr(werr, DEV_WAIT_GAVE_UP);
+  return T(0);
 }
 
 template <typename T>
@@ -973,9 +979,9 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
         const T* ys = my_sol + sol_row(jj) * NB;
         T xv[FWD ? VEC : NI];
         if (FWD) {
-          for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + 16 * w + VEC * cp + e);
+          for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + 16 * w + VEC * cp + e, A.spin, A.werr);
         } else {
-          for (int i = 0; i < NI; ++i) xv[i] = poll_published(ys + 16 * w + RPI * i + lr);
+          for (int i = 0; i < NI; ++i) xv[i] = poll_published(ys + 16 * w + RPI * i + lr, A.spin, A.werr);
         }
         if (jj + 1 < nt) {
           const T* p = tile_ptr(jj + 1);
@@ -1235,9 +1241,9 @@ __global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
       const T* ys = my_sol + j * NB;
       T xv[FWD ? VEC : NI];
       if (FWD) {
-        for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + 16 * w + VEC * cp + e);
+        for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + 16 * w + VEC * cp + e, A.spin, A.werr);
       } else {
-        for (int i = 0; i < NI; ++i) xv[i] = poll_published(ys + 16 * w + RPI * i + lr);
+        for (int i = 0; i < NI; ++i) xv[i] = poll_published(ys + 16 * w + RPI * i + lr, A.spin, A.werr);
       }
       if (j >= lo[0] && j <= hi[0]) mac(acc0, c0, xv);
       if (j >= lo[1] && j <= hi[1]) mac(acc1, c1, xv);
@@ -1742,9 +1748,10 @@ void launch_pcg_update(double* x, double* r, const double* p, const double* q, c
 }
 // End of a CG segment: the scalars the host reads, written straight into mapped
 // pinned host memory (one launch instead of several copies): out[0..3] = tol2,
-// bb, rr0, (done, iters) as two ints; out[4] = the true r.r; then alpha, beta and
-// rr of iterations seg .. seg+n-1.
-__global__ void pack_readback_kernel(const PcgScalars* sc, const double* rr_true, int seg, int n, double* out) {
+// bb, rr0, (done, iters) as two ints; out[4] = the true r.r; out[5] = the device
+// status word (as an int); then alpha, beta and rr of iterations seg .. seg+n-1.
+__global__ void pack_readback_kernel(const PcgScalars* sc, const double* rr_true, const int* werr, int seg, int n,
+                                     double* out) {
   const int t = threadIdx.x;
   if (t == 0) {
     out[0] = sc->tol2;
@@ -1754,17 +1761,20 @@ __global__ void pack_readback_kernel(const PcgScalars* sc, const double* rr_true
     w[0] = sc->done;
     w[1] = sc->iters;
     out[4] = *rr_true;
+    int* e = reinterpret_cast<int*>(out + 5);
+    e[0] = *werr;
+    e[1] = 0;
   }
   for (int i = t; i < n; i += blockDim.x) {
-    out[5 + i] = sc->alpha[seg + i];
-    out[5 + n + i] = sc->beta[seg + i];
-    out[5 + 2 * n + i] = sc->rr[seg + i];
+    out[6 + i] = sc->alpha[seg + i];
+    out[6 + n + i] = sc->beta[seg + i];
+    out[6 + 2 * n + i] = sc->rr[seg + i];
   }
 }
 
-void launch_pack_readback(const PcgScalars* sc, const double* rr_true, int seg, int n, double* out,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(pack_readback_kernel, dim3(1), dim3(256), 0, st, sc, rr_true, seg, n, out);
+void launch_pack_readback(const PcgScalars* sc, const double* rr_true, const int* werr, int seg, int n,
+                          double* out, hipStream_t st) {
+  hipLaunchKernelGGL(pack_readback_kernel, dim3(1), dim3(256), 0, st, sc, rr_true, werr, seg, n, out);
 }
 
 void launch_pcg_check(const double* part_rr, PcgScalars* sc, int it, int* hdone, hipStream_t st) {
@@ -1965,7 +1975,7 @@ __global__ __launch_bounds__(CCG_BLK) void coarse_cg_kernel(const int32_t* rowpt
                                                            const double* fval_g, int nnz, const double* dc, int nc,
                                                            const int32_t* cinv_ptr, const int32_t* cinv,
                                                            const double* gbuf, double* uc, double* work, double tol2,
-                                                           int maxit, const int* done) {
+                                                           int maxit, const int* done, int* werr) {
   __shared__ double sh[3 * (CCG_BLK / 64)];
   __shared__ double sv[SH ? CCG_LDS_DBL : 1];
   if (done && *done) return;
@@ -2024,10 +2034,14 @@ __global__ __launch_bounds__(CCG_BLK) void coarse_cg_kernel(const int32_t* rowpt
     }
     ccg_sum3(gam, del, rr, sh);
     if (it == 0) bb = rr;
-    if (!(bb > 0.0) || rr <= tol2 * bb || it == maxit) break;
+    if (!(bb > 0.0) || rr <= tol2 * bb) break;
     const double beta = it == 0 ? 0.0 : gam / gam_old;
     const double den = del - beta * gam / alpha;
-    if (!(gam > 0.0) || !(den > 0.0)) break;
+    if (it == maxit || !(gam > 0.0) || !(den > 0.0)) {
+      // not converged: iteration limit or breakdown (A_c not positive definite)
+      if (threadIdx.x == 0) atomicOr(werr, DEV_COARSE_NOCONV);
+      break;
+    }
     alpha = gam / den;
     gam_old = gam;
     if (own)
@@ -2058,16 +2072,16 @@ void launch_coarse_cg_matrix(const int32_t* fsrc, const double* val, double* fva
 
 void launch_coarse_cg(const int32_t* rowptr, const int32_t* col, const double* fval, int nnz, const double* dc,
                       int nc, const int32_t* cinv_ptr, const int32_t* cinv, const double* gbuf, double* u,
-                      double* work, double tol, int maxit, const int* done, hipStream_t st) {
+                      double* work, double tol, int maxit, const int* done, int* werr, hipStream_t st) {
   if (nc <= 0) return;
   // LDS bytes of the resident variant: 7 nc + nnz doubles, nnz + nc + 1 ints
   const int64_t need = 8 * (7 * int64_t(nc) + nnz) + 4 * (int64_t(nnz) + nc + 1);
   if (need <= 8 * int64_t(CCG_LDS_DBL))
     hipLaunchKernelGGL(coarse_cg_kernel<true>, dim3(1), dim3(CCG_BLK), 0, st, rowptr, col, fval, nnz, dc, nc,
-                       cinv_ptr, cinv, gbuf, u, work, tol * tol, maxit, done);
+                       cinv_ptr, cinv, gbuf, u, work, tol * tol, maxit, done, werr);
   else
     hipLaunchKernelGGL(coarse_cg_kernel<false>, dim3(1), dim3(CCG_BLK), 0, st, rowptr, col, fval, nnz, dc, nc,
-                       cinv_ptr, cinv, gbuf, u, work, tol * tol, maxit, done);
+                       cinv_ptr, cinv, gbuf, u, work, tol * tol, maxit, done, werr);
 }
 
 // Symmetric interface matrices of a subdomain, lower tile triangle over
