@@ -147,6 +147,7 @@ struct bddc_ctx {
   int32_t *ifc_g = nullptr, *ifc_l = nullptr, *ifc_slotz = nullptr, *ifc_slotf = nullptr;   // interface dofs
   double *ifc_dsc = nullptr, *ifc_wd = nullptr;
   int32_t *fcol = nullptr, *fcol_ii = nullptr, *lrow_rr = nullptr, *lrow_ii = nullptr;   // factor envelopes
+  int32_t *bptr = nullptr, *brows = nullptr;   // rows of each factor column inside the envelope
   double* xg = nullptr;                        // inverses of the trailing factor blocks
   double *sg = nullptr, *hg = nullptr;         // interface form: Schur complements, X^T X (+ border rows)
   float* hg32 = nullptr;                       // X^T X (+ border rows) in FP32 (pc32, instead of hg)
@@ -423,6 +424,8 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done, con
   a.done = done;
   a.tasks = c->t_bwd_rr;
   a.lrow = c->lrow_rr;
+  a.bptr = c->bptr;
+  a.brows = c->brows;
   a.ntasks = int(P.bwd_rr.size() / 2);
   a.ticket = W.tickets + 1;
   a.sol = slot(1);
@@ -780,6 +783,8 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->upload(c->fcol, P.fcol))) return rc_;
   if ((rc_ = c->upload(c->fcol_ii, P.fcol_ii))) return rc_;
   if ((rc_ = c->upload(c->lrow_rr, P.lrow_rr))) return rc_;
+  if ((rc_ = c->upload(c->bptr, P.bptr))) return rc_;
+  if ((rc_ = c->upload(c->brows, P.brows))) return rc_;
   if ((rc_ = c->upload(c->lrow_ii, P.lrow_ii))) return rc_;
   if ((rc_ = c->upload(c->t_symfin, P.symfin))) return rc_;
 

@@ -86,6 +86,9 @@ struct Plan {
   // (j < T with fcol[j] <= k, resp. j < TI with fcol_ii[j] <= k), the rows a
   // backward pass over column k reads
   std::vector<int32_t> fcol, fcol_ii, lrow_rr, lrow_ii;
+  // per tile column k (vec_off / NB + k, one extra end entry): the rows j > k
+  // of L_RR whose envelope reaches column k, in descending order
+  std::vector<int32_t> bptr, brows;
 
   // ticket-ordered task lists of the triangular solves, (matrix, tile row)
   std::vector<int32_t> fwd_rr, bwd_rr, fwd_ii, bwd_ii;

@@ -56,6 +56,8 @@ struct TrsvArgs {
   double* uc;
   const int32_t* fcol;   // per tile row: first nonzero tile column (null: dense)
   const int32_t* lrow;   // backward passes, per tile column k: last tile row to read (null: dense)
+  const int32_t* bptr;   // whole-space backward pass, per tile column k (vec_off / NB + k): its
+  const int32_t* brows;  //   rows j > k inside the envelope, descending, brows[bptr[.]..bptr[.+1]) (null: range)
   int* werr;             // device status word: DEV_WAIT_GAVE_UP when a wait gives up
   int spin;              // polls of a published value before giving up (< 0: give up at once)
 };

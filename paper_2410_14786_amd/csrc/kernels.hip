@@ -960,16 +960,22 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     for (int i = 0; i < (FWD ? NI : VEC); ++i) acc[i] = T(0);
     // only the tiles inside the envelope: forward reads (k, jlo..k-1), backward
     // reads (jhi..k+1, k); the tiles outside are zero
+    // (a column of the factor is not contiguous: below the band of the interior
+    // rows, only the interface rows whose envelope reaches back to column k hold
+    // nonzero tiles; the backward pass with a row list reads just those)
     const int jlo = (FWD && A.fcol) ? max(j0, int(A.fcol[D.vec_off / NB + k])) : j0;
     const int jhi = (!FWD && A.lrow) ? int(A.lrow[D.vec_off / NB + k]) : T_rows - 1;
-    const int nt = FWD ? k - jlo : (jhi - k);
+    const bool list = !FWD && A.bptr != nullptr;
+    const int b0 = list ? A.bptr[D.vec_off / NB + k] : 0;
+    const int nt = FWD ? k - jlo : (list ? A.bptr[D.vec_off / NB + k + 1] - b0 : jhi - k);
     if (nt > 0) {
+      auto sol_row = [&](int jj) -> int { return FWD ? jlo + jj : (list ? int(A.brows[b0 + jj]) : jhi - jj); };
       auto tile_ptr = [&](int jj) -> const T* {
-        // forward: tile (k, jlo + jj), jj = 0..k-jlo-1; backward: tile (j, k), j = jhi .. k+1
-        int64_t t = FWD ? tri_tile(k, jlo + jj) : tri_tile(jhi - jj, k);
+        // forward: tile (k, jlo + jj), jj = 0..k-jlo-1; backward: tile (j, k) for the
+        // listed rows j (or j = jhi .. k+1)
+        int64_t t = FWD ? tri_tile(k, jlo + jj) : tri_tile(sol_row(jj), k);
         return tiles + (tbase + t) * int64_t(NB * NB) + lane_off;
       };
-      auto sol_row = [&](int jj) -> int { return FWD ? jlo + jj : (jhi - jj); };
       V cur[NI], nxt[NI];
       {
         const T* p = tile_ptr(0);

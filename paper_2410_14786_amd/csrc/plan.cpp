@@ -304,6 +304,9 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
         }
         P.lrow_rr.push_back(lr);
         P.lrow_ii.push_back(li);
+        P.bptr.push_back(int32_t(P.brows.size()));
+        for (int j = D.T - 1; j > k; --j)
+          if (fc[j] <= k) P.brows.push_back(j);
       }
       P.fcol.insert(P.fcol.end(), fc.begin(), fc.end());
       P.fcol_ii.insert(P.fcol_ii.end(), fi.begin(), fi.end());
@@ -377,6 +380,7 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
     }
   }
   P.n_tiles = tile_off;
+  P.bptr.push_back(int32_t(P.brows.size()));
   P.n_dinv = dinv_off;
   P.n_vec = vec_off;
   P.n_loc = loc_off;
