@@ -147,7 +147,9 @@ struct bddc_ctx {
   int32_t *ifc_g = nullptr, *ifc_l = nullptr, *ifc_slotz = nullptr, *ifc_slotf = nullptr;   // interface dofs
   double *ifc_dsc = nullptr, *ifc_wd = nullptr;
   int32_t *fcol = nullptr, *fcol_ii = nullptr, *lrow_rr = nullptr, *lrow_ii = nullptr;   // factor envelopes
-  int32_t *bptr = nullptr, *brows = nullptr;   // rows of each factor column inside the envelope
+  int32_t *bptr = nullptr, *brows = nullptr, *btile = nullptr;   // rows of each factor column in the envelope
+  EnvRow* envrow = nullptr;                     // envelope storage of each tile row
+  std::vector<MatDesc> mats_dev;                // host image of the device descriptors
   double* xg = nullptr;                        // inverses of the trailing factor blocks
   double *sg = nullptr, *hg = nullptr;         // interface form: Schur complements, X^T X (+ border rows)
   float* hg32 = nullptr;                       // X^T X (+ border rows) in FP32 (pc32, instead of hg)
@@ -426,6 +428,7 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done, con
   a.lrow = c->lrow_rr;
   a.bptr = c->bptr;
   a.brows = c->brows;
+  a.btile = c->btile;
   a.ntasks = int(P.bwd_rr.size() / 2);
   a.ticket = W.tickets + 1;
   a.sol = slot(1);
@@ -751,7 +754,14 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->alloc(c->col, P.nnz))) return rc_;
   if ((rc_ = c->alloc(c->val, P.nnz))) return rc_;
   if ((rc_ = c->upload(c->kappa, P.kappa))) return rc_;
-  if ((rc_ = c->upload(c->mats, P.subs))) return rc_;
+  // descriptors with device copies of the envelope tables (uploaded below)
+  if ((rc_ = c->upload(c->fcol, P.fcol))) return rc_;
+  if ((rc_ = c->upload(c->envrow, P.envrow))) return rc_;
+  c->mats_dev = P.subs;
+  for (auto& D : c->mats_dev) {
+    D.env = c->envrow + D.vec_off / NB;
+  }
+  if ((rc_ = c->upload(c->mats, c->mats_dev))) return rc_;
   if ((rc_ = c->upload(c->gmap, P.gmap))) return rc_;
   if ((rc_ = c->upload(c->lmap, P.lmap))) return rc_;
   if ((rc_ = c->upload(c->avg_of, P.avg_of))) return rc_;
@@ -780,11 +790,11 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->upload(c->ifc_l, P.ifc_l))) return rc_;
   if ((rc_ = c->upload(c->ifc_slotz, P.ifc_slotz))) return rc_;
   if ((rc_ = c->upload(c->ifc_slotf, P.ifc_slotf))) return rc_;
-  if ((rc_ = c->upload(c->fcol, P.fcol))) return rc_;
   if ((rc_ = c->upload(c->fcol_ii, P.fcol_ii))) return rc_;
   if ((rc_ = c->upload(c->lrow_rr, P.lrow_rr))) return rc_;
   if ((rc_ = c->upload(c->bptr, P.bptr))) return rc_;
   if ((rc_ = c->upload(c->brows, P.brows))) return rc_;
+  if ((rc_ = c->upload(c->btile, P.btile))) return rc_;
   if ((rc_ = c->upload(c->lrow_ii, P.lrow_ii))) return rc_;
   if ((rc_ = c->upload(c->t_symfin, P.symfin))) return rc_;
 
@@ -1372,7 +1382,7 @@ int64_t bddc_debug_read(bddc_ctx* c, const char* what, int32_t sub, double* out,
     std::vector<double> t;
     for (int i = 0; i < D.T; ++i)
       for (int j = 0; j <= i; ++j) {
-        if (int rc_ = tile_to_double(D.tile_off + tri_tile(i, j), t)) return rc_;
+        if (int rc_ = tile_to_double(env_tile(D, i, j), t)) return rc_;
         for (int r = 0; r < NB; ++r)
           for (int q = 0; q < NB; ++q) res[(i * NB + r) * n + j * NB + q] = t[r * NB + q];
       }
@@ -1380,13 +1390,13 @@ int64_t bddc_debug_read(bddc_ctx* c, const char* what, int32_t sub, double* out,
     if (D.n_ci == 0) return 0;
     std::vector<double> t;
     if (w == "schur") {
-      if (int rc_ = tile_to_double(D.tile_off + tri_tile(D.T, D.T), t)) return rc_;
+      if (int rc_ = tile_to_double(env_tile(D, D.T, D.T), t)) return rc_;
       res = t;
     } else {
       const int64_t n = int64_t(D.T) * NB;
       res.assign(NB * n, 0.0);
       for (int j = 0; j < D.T; ++j) {
-        if (int rc_ = tile_to_double(D.tile_off + tri_tile(D.T, j), t)) return rc_;
+        if (int rc_ = tile_to_double(env_tile(D, D.T, j), t)) return rc_;
         for (int r = 0; r < NB; ++r)
           for (int q = 0; q < NB; ++q) res[r * n + j * NB + q] = t[r * NB + q];
       }

@@ -13,6 +13,14 @@ constexpr int NB = 64;        // tile edge (rows and columns) of every dense fac
 constexpr int MAX_NCI = 64;   // constraints per subdomain (one extra tile row)
 constexpr int IFC_MAXC = 8;   // subdomains sharing one dof (2^dim at most for box partitions)
 
+// Envelope storage of one tile row of a factor: its first stored column fc (the
+// tiles left of it are zero) and rd = (its first stored tile, counted from the
+// matrix's first tile) - fc, so that tile (i, j) is tile_off + rd + j.
+struct EnvRow {
+  int32_t fc;
+  int32_t rd;
+};
+
 // Per-matrix descriptor used by the factorisation and the triangular solves.
 // A "matrix" is a subdomain's equilibrated A_RR bordered by one extra tile row
 // holding (D B)^T with B = [C_AR^T | A_RPi], or the coarse matrix A_c.
@@ -37,6 +45,14 @@ struct MatDesc {
   int32_t sym_row;    // global index of this matrix's first row of symmetric interface tiles
   int64_t xg_off;     // first tile of the inverse of the trailing block (tile rows n_I/NB .. T-1)
   int64_t sg_off;     // first tile of the symmetric interface matrices (sym_tile_rows tile rows)
+  // Envelope storage of the factor: tile row i < T holds only its tiles env[i].fc
+  // .. i (those left of the envelope are zero), tile (i, j) at tile_off +
+  // env[i].rd + j; the border row T holds all tiles 0 .. T from tile_off + tb.
+  // env points to this matrix's rows of the per-row table (the host copy in the
+  // plan, the device copy in the uploaded descriptors); null: every row dense.
+  const EnvRow* env;
+  int64_t tb;
+  int64_t ztile;      // the shared all-zero tile, read for any tile left of the envelope
 };
 
 // Host-side plan: everything bddc_setup derives from the mesh and partition
@@ -86,9 +102,12 @@ struct Plan {
   // (j < T with fcol[j] <= k, resp. j < TI with fcol_ii[j] <= k), the rows a
   // backward pass over column k reads
   std::vector<int32_t> fcol, fcol_ii, lrow_rr, lrow_ii;
+  // per tile row (vec_off / NB + i): the envelope storage of that row
+  std::vector<EnvRow> envrow;
   // per tile column k (vec_off / NB + k, one extra end entry): the rows j > k
-  // of L_RR whose envelope reaches column k, in descending order
-  std::vector<int32_t> bptr, brows;
+  // of L_RR whose envelope reaches column k, in descending order, and the index
+  // of tile (j, k) counted from the matrix's tile_off
+  std::vector<int32_t> bptr, brows, btile;
 
   // ticket-ordered task lists of the triangular solves, (matrix, tile row)
   std::vector<int32_t> fwd_rr, bwd_rr, fwd_ii, bwd_ii;
@@ -136,6 +155,22 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
 
 // Tile index of tile (i, j), j <= i, inside a matrix's packed lower storage.
 BDDC_HD inline int64_t tri_tile(int64_t i, int64_t j) { return i * (i + 1) / 2 + j; }
+
+// Index of stored tile (i, j), j <= i, of a matrix's factor (see MatDesc).
+BDDC_HD inline int64_t env_tile(const MatDesc& D, int i, int j) {
+  if (i >= D.T) return D.tile_off + D.tb + j;
+  if (D.env == nullptr) return D.tile_off + tri_tile(i, j);
+  const EnvRow e = D.env[i];
+  return j < e.fc ? D.ztile : D.tile_off + e.rd + j;
+}
+
+// Tile (i, j) of row i is row_origin(D, i) + j for every j inside the row's
+// envelope (and the border row): one lookup per row for loops along a row.
+BDDC_HD inline int64_t row_origin(const MatDesc& D, int i) {
+  if (i >= D.T) return D.tile_off + D.tb;
+  if (D.env == nullptr) return D.tile_off + tri_tile(i, 0);
+  return D.tile_off + D.env[i].rd;
+}
 
 // Symmetric interface matrices of a subdomain: rows 0..n_G-1 are its interface
 // rows (local dofs n_I..n_R-1), rows n_G..n_G+n_ci-1 its constraints; tile rows:

@@ -58,6 +58,7 @@ struct TrsvArgs {
   const int32_t* lrow;   // backward passes, per tile column k: last tile row to read (null: dense)
   const int32_t* bptr;   // whole-space backward pass, per tile column k (vec_off / NB + k): its
   const int32_t* brows;  //   rows j > k inside the envelope, descending, brows[bptr[.]..bptr[.+1]) (null: range)
+  const int32_t* btile;  //   and the tile (j, k) of each, counted from the matrix's tile_off
   int* werr;             // device status word: DEV_WAIT_GAVE_UP when a wait gives up
   int spin;              // polls of a published value before giving up (< 0: give up at once)
 };

@@ -331,7 +331,6 @@ __global__ void local_assemble_kernel(MeshDev M, const double* theta, const MatD
   int lo[3] = {D.box_lo[0], D.box_lo[1], D.box_lo[2]};
   int len[3] = {D.box_len[0], D.box_len[1], M.dim == 3 ? D.box_len[2] : 1};
   const int n1x = D.box_len[0] + 1, n1y = D.box_len[1] + 1;
-  T* mt = tiles + D.tile_off * int64_t(NB * NB);
   const double da = dsc[D.loc_off + a];
   const int zr = M.dim == 3 ? 1 : 0;
   for (int dz = -zr; dz <= zr; ++dz)
@@ -347,14 +346,14 @@ __global__ void local_assemble_kernel(MeshDev M, const double* theta, const MatD
         if (a < D.n_R && b < D.n_R) {
           if (b > a) continue;
           double v = stiff_entry(M, theta, c, nb, lo, len) * da * dsc[D.loc_off + b];
-          int64_t t = tri_tile(a / NB, b / NB);
-          mt[t * NB * NB + (a % NB) * NB + (b % NB)] = T(v);
+          const int64_t t = env_tile(D, a / NB, b / NB);   // inside the envelope by its definition
+          tiles[t * NB * NB + (a % NB) * NB + (b % NB)] = T(v);
         } else if (a < D.n_R && b >= D.n_R) {
           // border row: (D A_R,Pi)^T, constraint row n_A + corner index
           double v = stiff_entry(M, theta, c, nb, lo, len) * da;
           int row = D.n_A + (b - D.n_R);
-          int64_t t = tri_tile(D.T, a / NB);
-          mt[t * NB * NB + row * NB + (a % NB)] = T(v);
+          const int64_t t = env_tile(D, D.T, a / NB);
+          tiles[t * NB * NB + row * NB + (a % NB)] = T(v);
         } else if (a >= D.n_R && b >= D.n_R) {
           double v = stiff_entry(M, theta, c, nb, lo, len);
           app[int64_t(s) * MAX_NCI * MAX_NCI + (a - D.n_R) * MAX_NCI + (b - D.n_R)] = v;
@@ -363,8 +362,8 @@ __global__ void local_assemble_kernel(MeshDev M, const double* theta, const MatD
   if (a < D.n_R) {
     int k = avg_of[D.loc_off + a];
     if (k >= 0) {
-      int64_t t = tri_tile(D.T, a / NB);
-      mt[t * NB * NB + k * NB + (a % NB)] = T(avg_coef[D.loc_off + a] * da);
+      const int64_t t = env_tile(D, D.T, a / NB);
+      tiles[t * NB * NB + k * NB + (a % NB)] = T(avg_coef[D.loc_off + a] * da);
     }
   }
 }
@@ -375,7 +374,7 @@ __global__ void pad_identity_kernel(const MatDesc* mats, T* tiles) {
   const MatDesc D = mats[blockIdx.x];
   int r = D.n_R + threadIdx.x;
   if (D.T == 0 || r >= D.T * NB) return;
-  int64_t t = D.tile_off + tri_tile(D.T - 1, D.T - 1);
+  const int64_t t = env_tile(D, D.T - 1, D.T - 1);
   tiles[t * NB * NB + (r % NB) * NB + (r % NB)] = T(1);
 }
 
@@ -592,7 +591,7 @@ struct FactorArgs {
   const int32_t* tasks;   // (matrix, i, j) per ticket
   int ntasks;
   unsigned* ticket;
-  int* ready;             // per stored tile (tile_off + tri_tile(i, j)), zero before the launch
+  int* ready;             // per stored tile (env_tile(D, i, j)), zero before the launch
   int* err;
 };
 
@@ -622,6 +621,8 @@ __global__ __launch_bounds__(256, 2) void factor_persistent_kernel(FactorArgs F)
     const int64_t rbase = D.vec_off / NB;
     auto first_col = [&](int r) { return (F.fcol == nullptr || r >= D.T) ? 0 : F.fcol[rbase + r]; };
     const int kf = max(first_col(i), first_col(j));
+    // tiles (i, k) and (j, k), k >= kf, lie inside both rows' envelopes
+    const int64_t oi = row_origin(D, i), oj = row_origin(D, j);
     AccT acc[2][2];
     for (int p = 0; p < 2; ++p)
       for (int q = 0; q < 2; ++q) acc[p][q] = AccT(0);
@@ -632,10 +633,10 @@ __global__ __launch_bounds__(256, 2) void factor_persistent_kernel(FactorArgs F)
     constexpr int PER = NB * NB / 256;
     T ra[PER], rb[PER];
     auto fetch = [&](int k) {
-      wait_ready(F.ready + D.tile_off + tri_tile(i, k), F.err);
-      if (i != j) wait_ready(F.ready + D.tile_off + tri_tile(j, k), F.err);
-      const T* pa = tiles + (D.tile_off + tri_tile(i, k)) * int64_t(NB * NB);
-      const T* pb = tiles + (D.tile_off + tri_tile(j, k)) * int64_t(NB * NB);
+      wait_ready(F.ready + oi + k, F.err);
+      if (i != j) wait_ready(F.ready + oj + k, F.err);
+      const T* pa = tiles + (oi + k) * int64_t(NB * NB);
+      const T* pb = tiles + (oj + k) * int64_t(NB * NB);
       for (int q = 0; q < PER; ++q) ra[q] = load_agent(pa + tid + 256 * q);
       if (i != j)
         for (int q = 0; q < PER; ++q) rb[q] = load_agent(pb + tid + 256 * q);
@@ -654,7 +655,7 @@ __global__ __launch_bounds__(256, 2) void factor_persistent_kernel(FactorArgs F)
       __syncthreads();
     }
     // R = A_ij - P into LDS (sa)
-    T* tij = tiles + (D.tile_off + tri_tile(i, j)) * int64_t(NB * NB);
+    T* tij = tiles + (oi + j) * int64_t(NB * NB);
     for (int p = 0; p < 2; ++p)
       for (int q = 0; q < 2; ++q)
         for (int it = 0; it < 4; ++it) {
@@ -676,7 +677,7 @@ __global__ __launch_bounds__(256, 2) void factor_persistent_kernel(FactorArgs F)
       __syncthreads();
       for (int e = tid; e < NB * NB; e += 256) tij[e] = sa[(e / NB) * LDT + (e % NB)];
     } else {
-      wait_ready(F.ready + D.tile_off + tri_tile(j, j), F.err);
+      wait_ready(F.ready + oj + j, F.err);
       const T* dj = dinv + (D.dinv_off + j) * int64_t(NB * NB);
       for (int q = 0; q < PER; ++q) rb[q] = load_agent(dj + tid + 256 * q);
       for (int q = 0; q < PER; ++q) {
@@ -697,7 +698,7 @@ __global__ __launch_bounds__(256, 2) void factor_persistent_kernel(FactorArgs F)
     // every value of this tile has landed before its ready word is set
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (tid == 0) __hip_atomic_store(F.ready + D.tile_off + tri_tile(i, j), 1, __ATOMIC_RELAXED,
+    if (tid == 0) __hip_atomic_store(F.ready + oi + j, 1, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT);
     // end the body with a barrier: the thread-0 regions at the end of one task
     // and at the start of the next must not be merged into one region that
@@ -739,7 +740,7 @@ __global__ __launch_bounds__(256) void local_small_kernel(const MatDesc* mats, c
   __shared__ double X[MAX_NCI * MAX_NCI];
   __shared__ int bad;
   const int tid = threadIdx.x;
-  const T* bt = tiles + (D.tile_off + tri_tile(D.T, D.T)) * int64_t(NB * NB);
+  const T* bt = tiles + env_tile(D, D.T, D.T) * int64_t(NB * NB);
   for (int i = tid; i < MAX_NCI * MAX_NCI; i += 256) {
     int r = i / MAX_NCI, c = i % MAX_NCI;
     // the tile holds the lower triangle reliably; symmetrise from it
@@ -938,7 +939,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     if (MODE == TRSV_BWD_RR && D.n_ci > 0) {
       // rhs_k += W_k coef, W_k^T stored in the bordering tile row (rows = constraints)
       __syncthreads();
-      const T* bt = tiles + (tbase + tri_tile(D.T, k)) * int64_t(NB * NB);
+      const T* bt = tiles + env_tile(D, D.T, k) * int64_t(NB * NB);
       const double* cf = A.coef + int64_t(s) * MAX_NCI;
       if (tid < NB) {
         double v = 0.0;
@@ -970,11 +971,12 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     const int nt = FWD ? k - jlo : (list ? A.bptr[D.vec_off / NB + k + 1] - b0 : jhi - k);
     if (nt > 0) {
       auto sol_row = [&](int jj) -> int { return FWD ? jlo + jj : (list ? int(A.brows[b0 + jj]) : jhi - jj); };
+      const int64_t ok = FWD ? row_origin(D, k) : 0;
       auto tile_ptr = [&](int jj) -> const T* {
-        // forward: tile (k, jlo + jj), jj = 0..k-jlo-1; backward: tile (j, k) for the
-        // listed rows j (or j = jhi .. k+1)
-        int64_t t = FWD ? tri_tile(k, jlo + jj) : tri_tile(sol_row(jj), k);
-        return tiles + (tbase + t) * int64_t(NB * NB) + lane_off;
+        // forward: tile (k, jlo + jj), jj = 0..k-jlo-1, along the stored row; backward:
+        // tile (j, k) of the listed rows j (its index is listed too), or j = jhi .. k+1
+        const int64_t t = FWD ? ok + jlo + jj : (list ? D.tile_off + A.btile[b0 + jj] : env_tile(D, jhi - jj, k));
+        return tiles + t * int64_t(NB * NB) + lane_off;
       };
       V cur[NI], nxt[NI];
       {
@@ -1057,7 +1059,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     // ---------------- epilogue ----------------
     if (MODE == TRSV_FWD_RR && D.n_ci > 0) {
       // partial border products h_c = sum_r W^T[c][r] y_k[r] for this tile row
-      const T* bt = tiles + (tbase + tri_tile(D.T, k)) * int64_t(NB * NB);
+      const T* bt = tiles + env_tile(D, D.T, k) * int64_t(NB * NB);
       for (int c = w; c < D.n_ci; c += 4) {   // one wave per constraint row, coalesced
         double v = double(bt[c * NB + lane]) * double(s_out[lane]);
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -1144,10 +1146,17 @@ __global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
     T* my_sol = sol + D.vec_off;
     const int nr = FWD ? (k0 + 1 < TI ? 2 : 1) : (k0 >= 1 ? 2 : 1);
     const int kr0 = k0, kr1 = FWD ? k0 + 1 : k0 - 1;
+    // forward: the task's two rows are read along their stored rows (one origin
+    // each); backward: tile (j, k) of the rows j = k+1 .. lrow_ii[k], some of
+    // which lie left of row j's envelope (the interior numbering starts a new
+    // layer of rows that reach back to the first columns): those read the shared
+    // zero tile
+    const int64_t o0 = FWD ? row_origin(D, kr0) : 0;
+    const int64_t o1 = (FWD && nr == 2) ? row_origin(D, kr1) : 0;
     auto tptr = [&](int k, int j) -> const T* {
       // forward: tile (k, j), j < k; backward: tile (j, k), j > k
-      const int64_t t = FWD ? tri_tile(k, j) : tri_tile(j, k);
-      return tiles + (tbase + t) * int64_t(NB * NB) + lane_off;
+      const int64_t t = FWD ? (k == kr0 ? o0 : o1) + j : env_tile(D, j, k);
+      return tiles + t * int64_t(NB * NB) + lane_off;
     };
     auto load = [&](const T* p, V (&t)[NI]) {
       for (int i = 0; i < NI; ++i) t[i] = stream_load(reinterpret_cast<const V*>(p + i * STEP));
@@ -1828,7 +1837,7 @@ __global__ __launch_bounds__(256) void trailing_inverse_kernel(const MatDesc* ma
     for (int q = 0; q < 2; ++q) acc[p][q] = d4v(0);
   for (int kk = jj; kk < ii; ++kk) {
     __syncthreads();
-    const double* a = tiles + (D.tile_off + tri_tile(j0 + ii, j0 + kk)) * int64_t(NB * NB);
+    const double* a = tiles + env_tile(D, j0 + ii, j0 + kk) * int64_t(NB * NB);
     const double* b = xg + (D.xg_off + tri_tile(kk, jj)) * int64_t(NB * NB);
     for (int e = threadIdx.x; e < NB * NB; e += 256) {
       sa[(e / NB) * LDT + (e % NB)] = a[e];
@@ -2115,14 +2124,14 @@ __device__ void load_k_tile(double* dst, const MatDesc& D, const double* tiles, 
       if (r < nG) {
         const int a = D.n_I + r;
         if (MODE == SYM_OP) {
-          if (k <= r) v = tiles[(D.tile_off + tri_tile(a / NB, b / NB)) * (NB * NB) + (a % NB) * NB + b % NB];
+          if (k <= r) v = tiles[env_tile(D, a / NB, b / NB) * (NB * NB) + (a % NB) * NB + b % NB];
         } else {
           if (k >= r) v = xg[(D.xg_off + tri_tile(b / NB - j0, a / NB - j0)) * (NB * NB) + (b % NB) * NB + a % NB];
         }
       } else {
         const int c = r - nG;
         if (c < D.n_ci && (MODE == SYM_PC || c >= D.n_A))
-          v = tiles[(D.tile_off + tri_tile(D.T, b / NB)) * (NB * NB) + c * NB + b % NB];
+          v = tiles[env_tile(D, D.T, b / NB) * (NB * NB) + c * NB + b % NB];
       }
     }
     dst[rl * LDT + cl] = v;

@@ -243,7 +243,6 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
     D.tile_off = tile_off;
     D.dinv_off = dinv_off;
     D.vec_off = vec_off;
-    tile_off += tri_tile(D.Tx, 0);           // Tx (Tx+1) / 2
     dinv_off += D.T;
     vec_off += int64_t(D.T) * NB;
     if (lmap_off + nbox >= (int64_t(1) << 31)) { err = "box tables too large"; return BDDC_EINVAL; }
@@ -296,6 +295,18 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
         fc[la / NB] = std::min(fc[la / NB], fmin / NB);
         if (la < D.n_I) fi[la / NB] = std::min(fi[la / NB], fmin / NB);
       }
+      // envelope storage: row k keeps tiles fc[k] .. k, tile (k, j) at rd[k] + j
+      // from the matrix's first tile, then the dense border row
+      std::vector<int64_t> rd(D.T);
+      int64_t off = 0;
+      for (int k = 0; k < D.T; ++k) {
+        rd[k] = off - fc[k];
+        off += k - fc[k] + 1;
+      }
+      if (off >= (int64_t(1) << 31)) { err = "a local factor has too many tiles"; return BDDC_EINVAL; }
+      for (int k = 0; k < D.T; ++k) P.envrow.push_back(EnvRow{fc[k], int32_t(rd[k])});
+      D.tb = off;
+      tile_off += off + (D.Tx > D.T ? D.T + 1 : 0);
       for (int k = 0; k < D.T; ++k) {
         int32_t lr = k, li = k;
         for (int j = k + 1; j < D.T; ++j) {
@@ -306,8 +317,15 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
         P.lrow_ii.push_back(li);
         P.bptr.push_back(int32_t(P.brows.size()));
         for (int j = D.T - 1; j > k; --j)
-          if (fc[j] <= k) P.brows.push_back(j);
+          if (fc[j] <= k) {
+            P.brows.push_back(j);
+            P.btile.push_back(int32_t(rd[j] + k));
+          }
       }
+      // the forward interior pass reads each interior tile row k from fi[k] on
+      // along the stored row: inside the row's envelope (fi >= fc)
+      for (int k = 0; k < D.TI; ++k)
+        if (fi[k] < fc[k]) { err = "internal: interior envelope outside the factor envelope"; return BDDC_EINVAL; }
       P.fcol.insert(P.fcol.end(), fc.begin(), fc.end());
       P.fcol_ii.insert(P.fcol_ii.end(), fi.begin(), fi.end());
       {
@@ -379,7 +397,10 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
         P.padz[D.loc_off + D.n_R + c] = int32_t(int64_t(D.sym_row) * NB + nG + D.n_A + c);
     }
   }
-  P.n_tiles = tile_off;
+  // one all-zero tile after the last matrix: the tile read for any tile left of
+  // a row's envelope
+  P.n_tiles = tile_off + 1;
+  for (auto& D : P.subs) D.ztile = tile_off;
   P.bptr.push_back(int32_t(P.brows.size()));
   P.n_dinv = dinv_off;
   P.n_vec = vec_off;
@@ -480,6 +501,9 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
     }
   }
   if (int rc_ = make_factor_tasks(P.subs, &P.fcol, P.factor_tasks, err)) return rc_;
+  for (auto& D : P.subs) {
+    D.env = P.envrow.data() + D.vec_off / NB;
+  }
   return BDDC_OK;
 }
 

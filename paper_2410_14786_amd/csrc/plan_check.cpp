@@ -38,6 +38,29 @@ int main() {
     const int rc = bddc::make_plan(&mesh, &part, cons, P, err);
     int64_t sum_ni = 0;
     for (auto& D : P.subs) sum_ni += D.n_i;
+    // envelope storage: every stored tile (row i < T: columns fc[i] .. i; the
+    // border row: 0 .. T) has its own index, all indices together fill
+    // [0, n_tiles - 1), and every tile left of an envelope maps to the zero tile
+    if (rc == 0) {
+      std::vector<char> seen(P.n_tiles, 0);
+      bool ok = true;
+      for (auto& D : P.subs) {
+        for (int i = 0; i < D.Tx; ++i)
+          for (int j = 0; j <= i; ++j) {
+            const int64_t t = bddc::env_tile(D, i, j);
+            const bool inside = i >= D.T || j >= D.env[i].fc;
+            if (t < 0 || t >= P.n_tiles) { ok = false; continue; }
+            if (!inside) { ok = ok && t == P.n_tiles - 1; continue; }
+            if (t == P.n_tiles - 1 || seen[t]) ok = false;
+            seen[t] = 1;
+          }
+      }
+      for (int64_t t = 0; t + 1 < P.n_tiles; ++t) ok = ok && seen[t];
+      if (!ok) {
+        std::fprintf(stderr, "envelope storage check failed\n");
+        return 3;
+      }
+    }
     std::printf("%d %lld %d %d %lld %d %lld %lld\n", rc, (long long)P.n_free, P.nsubs, P.n_coarse,
                 (long long)sum_ni, P.max_nci, (long long)P.n_tiles, (long long)(P.factor_tasks.size() / 3));
     if (rc) std::fprintf(stderr, "case failed: %s\n", err.c_str());

@@ -81,6 +81,10 @@ CASES = {
     # and 3458 interface rows (55 tile rows of interface matrix), all six faces shared
     "3d_40_boxes_8_24_inclusions": lambda: W.make_workload("t", 3, (40, 40, 40), cuts=[[0, 8, 32, 40]] * 3,
                                                            theta="inclusions", seed=13),
+    # a box of 32^3 elements (32 768 dofs, 512 factor tile rows): the local
+    # factors are stored by envelope, a dense triangle would take 4.3 GB
+    "3d_40_box32_inclusions": lambda: W.make_workload("t", 3, (40, 40, 40), cuts=[[0, 32, 40]] * 3,
+                                                      theta="inclusions", seed=17),
     # 576 boxes of 3x3 elements: n_c = 1633, more coarse unknowns than the coarse CG keeps in LDS
     "2d_72_24x24_many": lambda: W.make_workload("t", 2, (72, 72), (24, 24), theta="lognormal", seed=5),
 }
@@ -124,7 +128,8 @@ def test_spmv_parity(name):
 
 @pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
 @pytest.mark.parametrize("name", ["2d_64_4x4_theta1", "3d_12x10x14_uneven", "3d_24_3x3x3_inclusions",
-                                  "2d_20x24_uneven", "3d_8_corners_only", "3d_40_boxes_8_24_inclusions"])
+                                  "2d_20x24_uneven", "3d_8_corners_only", "3d_40_boxes_8_24_inclusions",
+                                  "3d_40_box32_inclusions"])
 def test_pcg_iterates_match_oracle(name, full_space):
     """Same number K of iterations from the same x0 = P_I b: iterates agree, for
     the CG run on the whole space and the one restricted to interface dofs."""

@@ -109,3 +109,24 @@ def test_setup_stats_factor_flops_bounded_by_dense_count():
     assert 0 < flops <= dense
     assert ms > 0
     S.close()
+
+
+def test_factor_storage_follows_the_envelope():
+    """The local factors hold only the tiles inside each row's envelope: on the
+    64^3 workload (64 boxes of 16^3) the whole context needs less device memory
+    than the dense lower tile triangles of its factors alone."""
+    from paper_2410_14786_amd import bddc
+    import bench
+    w = W.cfg_3d_64()
+    S = bddc.solver_for(w)
+    dense = 0
+    for nR, nI, nci, nP in bench.sub_sizes(w):
+        T = (nR + 63) // 64
+        Tx = T + (1 if nci else 0)
+        dense += Tx * (Tx + 1) // 2 * 64 * 64 * 8
+    env = sum(bench.envelope_tiles(S.debug_read("envelope", i).astype(np.int64),
+                                   tuple(S.debug_read("sizes", i)[:2].astype(int)))[0] for i in range(S.n_sub))
+    print("64^3 device bytes", S.dev_bytes, "dense factor triangles", dense, "envelope tiles", env, flush=True)
+    assert S.dev_bytes < dense
+    assert env * 64 * 64 * 8 < dense / 2
+    S.close()
