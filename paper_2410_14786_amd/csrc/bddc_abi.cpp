@@ -148,6 +148,7 @@ struct bddc_ctx {
   double *ifc_dsc = nullptr, *ifc_wd = nullptr;
   int32_t *fcol = nullptr, *fcol_ii = nullptr, *lrow_rr = nullptr, *lrow_ii = nullptr;   // factor envelopes
   int32_t *bptr = nullptr, *brows = nullptr, *btile = nullptr;   // rows of each factor column in the envelope
+  int32_t *iptr = nullptr, *irows = nullptr, *itile0 = nullptr, *itile1 = nullptr;   // interior block
   EnvRow* envrow = nullptr;                     // envelope storage of each tile row
   std::vector<MatDesc> mats_dev;                // host image of the device descriptors
   double* xg = nullptr;                        // inverses of the trailing factor blocks
@@ -461,6 +462,10 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done, con
   a.done = done;
   a.tasks = c->t_bwd_ii;
   a.lrow = c->lrow_ii;
+  a.iptr = c->iptr;
+  a.irows = c->irows;
+  a.itile0 = c->itile0;
+  a.itile1 = c->itile1;
   a.ntasks = int(P.bwd_ii.size() / 2);
   a.ticket = W.tickets + 3;
   a.sol = slot(3);
@@ -619,6 +624,10 @@ void enqueue_interior_guess(bddc_ctx* c, const double* b, double* x, double* zer
   a = base_args(c);
   a.tasks = c->t_bwd_ii;
   a.lrow = c->lrow_ii;
+  a.iptr = c->iptr;
+  a.irows = c->irows;
+  a.itile0 = c->itile0;
+  a.itile1 = c->itile1;
   a.ntasks = int(P.bwd_ii.size() / 2);
   a.ticket = c->tickets + 3;
   a.sol = pub_slot(c, 3);
@@ -720,6 +729,10 @@ void enqueue_interior_complete(bddc_ctx* c, const double* b, const double* xt, d
   a = base_args(c);
   a.tasks = c->t_bwd_ii;
   a.lrow = c->lrow_ii;
+  a.iptr = c->iptr;
+  a.irows = c->irows;
+  a.itile0 = c->itile0;
+  a.itile1 = c->itile1;
   a.ntasks = int(P.bwd_ii.size() / 2);
   a.ticket = c->tickets + 3;
   a.sol = pub_slot(c, 3);
@@ -795,6 +808,10 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->upload(c->bptr, P.bptr))) return rc_;
   if ((rc_ = c->upload(c->brows, P.brows))) return rc_;
   if ((rc_ = c->upload(c->btile, P.btile))) return rc_;
+  if ((rc_ = c->upload(c->iptr, P.iptr))) return rc_;
+  if ((rc_ = c->upload(c->irows, P.irows))) return rc_;
+  if ((rc_ = c->upload(c->itile0, P.itile0))) return rc_;
+  if ((rc_ = c->upload(c->itile1, P.itile1))) return rc_;
   if ((rc_ = c->upload(c->lrow_ii, P.lrow_ii))) return rc_;
   if ((rc_ = c->upload(c->t_symfin, P.symfin))) return rc_;
 

@@ -108,6 +108,10 @@ struct Plan {
   // of L_RR whose envelope reaches column k, in descending order, and the index
   // of tile (j, k) counted from the matrix's tile_off
   std::vector<int32_t> bptr, brows, btile;
+  // the same for the interior block (tile columns k < TI, rows j <= lrow_ii[k]
+  // with fcol_ii[j] <= k; empty for k >= TI): row, tile (j, k) and tile (j, k-1)
+  // (-1 when left of row j's interior envelope), counted from tile_off
+  std::vector<int32_t> iptr, irows, itile0, itile1;
 
   // ticket-ordered task lists of the triangular solves, (matrix, tile row)
   std::vector<int32_t> fwd_rr, bwd_rr, fwd_ii, bwd_ii;

@@ -59,6 +59,10 @@ struct TrsvArgs {
   const int32_t* bptr;   // whole-space backward pass, per tile column k (vec_off / NB + k): its
   const int32_t* brows;  //   rows j > k inside the envelope, descending, brows[bptr[.]..bptr[.+1]) (null: range)
   const int32_t* btile;  //   and the tile (j, k) of each, counted from the matrix's tile_off
+  const int32_t* iptr;   // interior backward pass, per tile column k: rows j inside the interior
+  const int32_t* irows;  //   envelope, descending, and the tiles (j, k) and (j, k-1) (-1: zero),
+  const int32_t* itile0; //   counted from the matrix's tile_off (null: the range k+1 .. lrow)
+  const int32_t* itile1;
   int* werr;             // device status word: DEV_WAIT_GAVE_UP when a wait gives up
   int spin;              // polls of a published value before giving up (< 0: give up at once)
 };

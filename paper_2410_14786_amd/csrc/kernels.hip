@@ -1184,8 +1184,42 @@ __global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
     const bool inner = nr > 1 && kr0 >= lo[1] && kr0 <= hi[1];
     const int ext_lo = FWD ? min(lo[0], nr > 1 ? lo[1] : lo[0]) : kr0 + 1;
     const int ext_hi = FWD ? kr0 - 1 : max(hi[0], nr > 1 ? hi[1] : hi[0]);
-    const int nt = ext_hi - ext_lo + 1;
-    auto blk = [&](int jj) -> int { return FWD ? ext_lo + jj : ext_hi - jj; };
+    // backward with a row list: the rows j > kr0 inside column kr0's envelope
+    // (a superset of column kr1's rows beyond kr0), each with the tiles (j, kr0)
+    // and (j, kr1) (-1: zero); no zero tile is read and no row is looked up
+    const bool ilist = !FWD && A.iptr != nullptr;
+    const int il0 = ilist ? A.iptr[D.vec_off / NB + kr0] : 0;
+    const int nt = ilist ? A.iptr[D.vec_off / NB + kr0 + 1] - il0 : ext_hi - ext_lo + 1;
+    // the list (up to 4 x 64 entries) is read once into registers, lane l of
+    // register q holding entry 64 q + l, and each step takes its entry with a
+    // lane read: no memory access between the steps of the chain
+    constexpr int LREG = 4;
+    const bool lreg = ilist && nt <= 64 * LREG;
+    int erow[LREG], et0[LREG], et1[LREG];
+    for (int q = 0; q < LREG; ++q) {
+      const int e = 64 * q + lane;
+      const bool ok = lreg && e < nt;
+      erow[q] = ok ? A.irows[il0 + e] : 0;
+      et0[q] = ok ? A.itile0[il0 + e] : 0;
+      et1[q] = ok ? A.itile1[il0 + e] : -1;
+    }
+    auto ent = [&](const int (&a)[LREG], const int32_t* g, int jj) -> int {
+      if (!lreg) return int(g[il0 + jj]);
+      const int q = jj >> 6;
+      const int v = q == 0 ? a[0] : q == 1 ? a[1] : q == 2 ? a[2] : a[3];
+      return __builtin_amdgcn_readlane(v, jj & 63);
+    };
+    auto blk = [&](int jj) -> int { return ilist ? ent(erow, A.irows, jj) : (FWD ? ext_lo + jj : ext_hi - jj); };
+    auto in0 = [&](int jj, int j) -> bool { return ilist ? true : (j >= lo[0] && j <= hi[0]); };
+    auto in1 = [&](int jj, int j) -> bool {
+      return ilist ? (nr > 1 && ent(et1, A.itile1, jj) >= 0) : (j >= lo[1] && j <= hi[1]);
+    };
+    auto tile0 = [&](int jj, int j) -> const T* {
+      return ilist ? tiles + (D.tile_off + ent(et0, A.itile0, jj)) * int64_t(NB * NB) + lane_off : tptr(kr0, j);
+    };
+    auto tile1 = [&](int jj, int j) -> const T* {
+      return ilist ? tiles + (D.tile_off + ent(et1, A.itile1, jj)) * int64_t(NB * NB) + lane_off : tptr(kr1, j);
+    };
 
     // everything independent of other tasks first: both inverse diagonal tiles,
     // the coupling tile, the first external block's tiles
@@ -1195,8 +1229,8 @@ __global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
     if (inner) load(tptr(kr1, kr0), ti);
     if (nt > 0) {
       const int j = blk(0);
-      if (j >= lo[0] && j <= hi[0]) load(tptr(kr0, j), c0);
-      if (j >= lo[1] && j <= hi[1]) load(tptr(kr1, j), c1);
+      if (in0(0, j)) load(tile0(0, j), c0);
+      if (in1(0, j)) load(tile1(0, j), c1);
     }
 
     // right-hand sides of the task's rows
@@ -1250,8 +1284,8 @@ __global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
       const int j = blk(jj);
       if (jj + 1 < nt) {
         const int jn = blk(jj + 1);
-        if (jn >= lo[0] && jn <= hi[0]) load(tptr(kr0, jn), n0);
-        if (jn >= lo[1] && jn <= hi[1]) load(tptr(kr1, jn), n1);
+        if (in0(jj + 1, jn)) load(tile0(jj + 1, jn), n0);
+        if (in1(jj + 1, jn)) load(tile1(jj + 1, jn), n1);
       }
       const T* ys = my_sol + j * NB;
       T xv[FWD ? VEC : NI];
@@ -1260,8 +1294,8 @@ __global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
       } else {
         for (int i = 0; i < NI; ++i) xv[i] = poll_published(ys + 16 * w + RPI * i + lr, A.spin, A.werr);
       }
-      if (j >= lo[0] && j <= hi[0]) mac(acc0, c0, xv);
-      if (j >= lo[1] && j <= hi[1]) mac(acc1, c1, xv);
+      if (in0(jj, j)) mac(acc0, c0, xv);
+      if (in1(jj, j)) mac(acc1, c1, xv);
       for (int i = 0; i < NI; ++i) {
         c0[i] = n0[i];
         c1[i] = n1[i];

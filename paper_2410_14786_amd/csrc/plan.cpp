@@ -326,6 +326,17 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
       // along the stored row: inside the row's envelope (fi >= fc)
       for (int k = 0; k < D.TI; ++k)
         if (fi[k] < fc[k]) { err = "internal: interior envelope outside the factor envelope"; return BDDC_EINVAL; }
+      for (int k = 0; k < D.T; ++k) {
+        P.iptr.push_back(int32_t(P.irows.size()));
+        if (k >= D.TI) continue;
+        const int lr = P.lrow_ii[P.lrow_ii.size() - D.T + k];
+        for (int j = lr; j > k; --j)
+          if (fi[j] <= k) {
+            P.irows.push_back(j);
+            P.itile0.push_back(int32_t(rd[j] + k));
+            P.itile1.push_back(k >= 1 && fi[j] <= k - 1 ? int32_t(rd[j] + k - 1) : -1);
+          }
+      }
       P.fcol.insert(P.fcol.end(), fc.begin(), fc.end());
       P.fcol_ii.insert(P.fcol_ii.end(), fi.begin(), fi.end());
       {
@@ -400,6 +411,7 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
   // one all-zero tile after the last matrix: the tile read for any tile left of
   // a row's envelope
   P.n_tiles = tile_off + 1;
+  P.iptr.push_back(int32_t(P.irows.size()));
   for (auto& D : P.subs) D.ztile = tile_off;
   P.bptr.push_back(int32_t(P.brows.size()));
   P.n_dinv = dinv_off;
