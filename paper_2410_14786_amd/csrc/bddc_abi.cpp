@@ -34,7 +34,7 @@ int fail(int code, const std::string& msg) {
 // status of the device status word (bits DEV_*)
 int device_status_error(int w) {
   if (w & DEV_WAIT_GAVE_UP)
-    return fail(BDDC_EHIP, "a triangular-solve task gave up waiting for a published value (wait_polls limit)");
+    return fail(BDDC_EHIP, "a device-side wait (triangular-solve task or coarse-CG grid barrier) gave up (wait_polls limit)");
   return fail(BDDC_ENOCONV, "the coarse CG stopped at its iteration limit or broke down");
 }
 
@@ -409,7 +409,8 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done, con
     cf.spin = c->wait_polls;
     if (c->coarse_cg) {
       launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fval, c->ac_nfull, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
-                       c->gbuf, c->uc, c->ccg_work, COARSE_CG_TOL, c->coarse_maxit, done, c->err + 3, st);
+                       c->gbuf, c->uc, c->ccg_work, COARSE_CG_TOL, c->coarse_maxit, c->wait_polls, done,
+                       c->err + 3, st);
     } else {
       launch_trsv(TRSV_FWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
       cf.tasks = c->ctask_bwd;
@@ -419,8 +420,8 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done, con
       cf.uc = c->uc;
       launch_trsv(TRSV_BWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
     }
-    launch_coarse_coef(c->mats, P.nsubs, c->rc, c->uc, c->mu, c->sainv, c->sainve, c->wgt, c->coef, c->ww, done,
-                       st);
+    launch_coarse_coef(c->mats, P.nsubs, c->rc, c->uc, P.n_coarse, 1, c->mu, c->sainv, c->sainve, c->wgt, c->coef,
+                       c->ww, done, st);
   }
   // backward solve: D L^{-T} (t + W coef) = z_R + Phi_R u (weighted)
   a = base_args(c);
@@ -517,10 +518,6 @@ IfaceArgs iface_args(bddc_ctx* c) {
   a.wgt = c->wgt;
   a.sploc = c->sploc;
   a.ww = c->ww;
-  a.rc = c->rc;
-  a.mu = c->mu;
-  a.sainv = c->sainv;
-  a.sainve = c->sainve;
   return a;
 }
 
@@ -554,13 +551,14 @@ void enqueue_apply_iface(bddc_ctx* c, const double* r, double* z, double* part_r
                        c->rowp, a.ntiles, a.nwg, st);
     if (c->coarse_cg)
       launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fval, c->ac_nfull, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
-                       c->gbuf, c->upart, c->ccg_work, COARSE_CG_TOL, c->coarse_maxit, done, c->err + 3, st);
+                       c->gbuf, c->upart, c->ccg_work, COARSE_CG_TOL, c->coarse_maxit, c->wait_polls, done,
+                       c->err + 3, st);
     else
       launch_coarse_gemv(c->cainv, P.n_coarse, c->csplit, c->cinv_ptr, c->cinv, c->gbuf, c->upart, done, st);
+    launch_coarse_coef(c->mats, P.nsubs, c->rc, c->upart, P.n_coarse, c->csplit, c->mu, c->sainv, c->sainve,
+                       c->wgt, c->coef, c->ww, done, st);
   }
-  a.uc = c->upart;
-  a.nc = P.n_coarse;
-  a.nsplit = c->csplit;
+  a.coef = c->coef;
   a.tasks = c->t_symfin;
   a.ntasks = int(P.symfin.size() / 2);
   launch_pc_finish(a, st);
@@ -929,7 +927,7 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
     if ((rc_ = c->upload(c->ac_fsrc, fs))) return rc_;
     c->ac_nfull = int(fs.size());
     if ((rc_ = c->alloc(c->ac_fval, int64_t(fs.size())))) return rc_;
-    if ((rc_ = c->alloc(c->ccg_work, 7 * int64_t(nc) + 1))) return rc_;
+    if ((rc_ = c->alloc(c->ccg_work, 7 * int64_t(nc) + 3 * 64 + 8))) return rc_;
   }
   if ((rc_ = c->alloc(c->dc, nc))) return rc_;
   // (the coarse CG needs no dense coarse factor)

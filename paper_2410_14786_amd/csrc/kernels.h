@@ -109,13 +109,7 @@ struct IfaceArgs {
   const double* wgt;
   double* sploc;            // (S z) per local dof
   double* ww;               // weighted local preconditioner output
-  const double* uc;         // coarse solution as nsplit column-split partials of nc values
-  int nc;
-  int nsplit;
-  const int32_t* rc;
-  const double* mu;
-  const double* sainv;
-  const double* sainve;
+  const double* coef;       // coefficients of the coarse correction, MAX_NCI per subdomain
 };
 
 template <typename T> void launch_fill(T* p, T v, int64_t n, hipStream_t st);
@@ -155,9 +149,10 @@ void launch_coarse_prep(const MatDesc* mats, int nmats, const double* part, cons
                         const double* sainve, const int32_t* gmap, const double* wgt, const double* r,
                         double* gbuf, double* mu, const int* done, const double* rowp, int64_t ntiles, int nwg,
                         hipStream_t st);
-void launch_coarse_coef(const MatDesc* mats, int nmats, const int32_t* rc, const double* uc, const double* mu,
-                        const double* sainv, const double* sainve, const double* wgt, double* coef, double* ww,
-                        const int* done, hipStream_t st);
+// (uc: nsplit partial vectors of nc values, summed in order)
+void launch_coarse_coef(const MatDesc* mats, int nmats, const int32_t* rc, const double* uc, int nc, int nsplit,
+                        const double* mu, const double* sainv, const double* sainve, const double* wgt,
+                        double* coef, double* ww, const int* done, hipStream_t st);
 void launch_gather_v12(const int32_t* inv_ptr, const int32_t* inv, const double* ww, const uint8_t* kappa,
                        double* v12, double* z, int64_t n, const int* done, hipStream_t st);
 void launch_zero_interface(const uint8_t* kappa, double* x, int64_t n, hipStream_t st);
@@ -241,10 +236,14 @@ void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* c
 // relative residual tol); work: 3 nc doubles
 // full symmetric A_c in CSR for the coarse CG: fval[k] = val[fsrc[k]]
 void launch_coarse_cg_matrix(const int32_t* fsrc, const double* val, double* fval, int nnz, hipStream_t st);
-// (work: 7 nc doubles)
+// (work: 7 nc doubles, and at least nc + 3 * 64 doubles + 2 words for the
+// multi-workgroup variant used when A_c does not fit one workgroup's LDS; its
+// grid barrier gives up after `spin` polls and records DEV_WAIT_GAVE_UP)
+bool coarse_cg_grid_fits(int nc);
 void launch_coarse_cg(const int32_t* rowptr, const int32_t* col, const double* fval, int nnz, const double* dc,
                       int nc, const int32_t* cinv_ptr, const int32_t* cinv, const double* gbuf, double* u,
-                      double* work, double tol, int maxit, const int* done, int* werr, hipStream_t st);
+                      double* work, double tol, int maxit, int spin, const int* done, int* werr,
+                      hipStream_t st);
 // Size of the fixed device workspace of the allocation-free apply, and its
 // address on the current device (looked up once per device; 0 on success).
 constexpr size_t STATIC_SCRATCH_BYTES = size_t(64) << 20;

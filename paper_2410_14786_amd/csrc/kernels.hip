@@ -1103,9 +1103,12 @@ static void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t st, hipEve
 // tiles, the tile coupling the two rows, and both rows' tiles of the next
 // published block (double-buffered).  The register layouts, the envelope, the
 // published values and the right-hand sides are those of trsv_kernel.  The
-// kernel needs about 290 registers per lane: one workgroup per CU.
+// inverse diagonal tiles are parked in LDS as soon as they arrive (each thread
+// reads back only the entries it wrote, so no barrier guards them), which keeps
+// the kernel within 256 registers per lane: two workgroups per CU, twice the
+// tile loads in flight of a one-workgroup-per-CU kernel.
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
+__global__ __launch_bounds__(256, 2) void trsv2_kernel(TrsvArgs A) {
   using V = typename Traits<T>::V;
   constexpr int VEC = Traits<T>::VEC;
   constexpr int LPR = NB / VEC;
@@ -1120,6 +1123,7 @@ __global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
   __shared__ T s_v[NB];
   __shared__ T s_out[NB];
   __shared__ T s_red[4][NB];
+  __shared__ V s_dv[2][NI][256];   // inverse diagonal tiles: entry [q][i][tid] is thread tid's own
   __shared__ int s_task;
 
   if (A.done && *A.done) return;
@@ -1221,16 +1225,21 @@ __global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
       return ilist ? tiles + (D.tile_off + ent(et1, A.itile1, jj)) * int64_t(NB * NB) + lane_off : tptr(kr1, j);
     };
 
-    // everything independent of other tasks first: both inverse diagonal tiles,
-    // the coupling tile, the first external block's tiles
-    V dv0[NI], dv1[NI], ti[NI], c0[NI], c1[NI], n0[NI], n1[NI];
-    load(dinv + (D.dinv_off + kr0) * int64_t(NB * NB) + lane_off, dv0);
-    if (nr > 1) load(dinv + (D.dinv_off + kr1) * int64_t(NB * NB) + lane_off, dv1);
+    // everything independent of other tasks first: both inverse diagonal tiles
+    // (through the prefetch registers into LDS), the coupling tile, the first
+    // external block's tiles
+    V ti[NI], c0[NI], c1[NI], n0[NI], n1[NI];
+    load(dinv + (D.dinv_off + kr0) * int64_t(NB * NB) + lane_off, n0);
+    if (nr > 1) load(dinv + (D.dinv_off + kr1) * int64_t(NB * NB) + lane_off, n1);
     if (inner) load(tptr(kr1, kr0), ti);
     if (nt > 0) {
       const int j = blk(0);
       if (in0(0, j)) load(tile0(0, j), c0);
       if (in1(0, j)) load(tile1(0, j), c1);
+    }
+    for (int i = 0; i < NI; ++i) {
+      s_dv[0][i][tid] = n0[i];
+      if (nr > 1) s_dv[1][i][tid] = n1[i];
     }
 
     // right-hand sides of the task's rows
@@ -1304,7 +1313,8 @@ __global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
 
     // finish one row: reduce the partial sums, subtract from the right-hand
     // side, multiply by the inverse diagonal tile, publish, write the output
-    auto finish = [&](int q, int k, const T (&acc)[NACC], const V (&dvq)[NI]) {
+    auto finish = [&](int q, int k, const T (&acc)[NACC]) {
+      const V (&dvq)[NI][256] = s_dv[q];
       if (FWD) {
         for (int i = 0; i < NI; ++i) {
           T v = acc[i];
@@ -1327,15 +1337,18 @@ __global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
       if (FWD) {
         for (int i = 0; i < NI; ++i) {
           T v = T(0);
-          for (int e = 0; e < VEC; ++e) v += dvq[i][e] * s_v[16 * w + VEC * cp + e];
+          const V d = dvq[i][tid];
+          for (int e = 0; e < VEC; ++e) v += d[e] * s_v[16 * w + VEC * cp + e];
           for (int off = 1; off < CPL; off <<= 1) v += __shfl_xor(v, off, CPL);
           if (cp == 0) s_red[w][rg + RG * i] = v;
         }
       } else {
         T a2[VEC];
         for (int e = 0; e < VEC; ++e) a2[e] = T(0);
-        for (int i = 0; i < NI; ++i)
-          for (int e = 0; e < VEC; ++e) a2[e] += dvq[i][e] * s_v[16 * w + RPI * i + lr];
+        for (int i = 0; i < NI; ++i) {
+          const V d = dvq[i][tid];
+          for (int e = 0; e < VEC; ++e) a2[e] += d[e] * s_v[16 * w + RPI * i + lr];
+        }
         for (int e = 0; e < VEC; ++e) {
           T v = a2[e];
           for (int off = LPR; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
@@ -1360,7 +1373,7 @@ __global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
       __syncthreads();
     };
 
-    finish(0, kr0, acc0, dv0);
+    finish(0, kr0, acc0);
     if (nr > 1) {
       if (inner) {
         // the first row's block, from LDS
@@ -1373,7 +1386,7 @@ __global__ __launch_bounds__(256) void trsv2_kernel(TrsvArgs A) {
         mac(acc1, ti, xv);
       }
       __syncthreads();   // s_out is overwritten by the second row
-      finish(1, kr1, acc1, dv1);
+      finish(1, kr1, acc1);
     }
   }
 }
@@ -1486,9 +1499,10 @@ __global__ __launch_bounds__(64) void coarse_prep_kernel(const MatDesc* mats, co
 }
 
 // per subdomain: u = R_ci u_c; coef_A = -mu + S_A^{-1} u_A + S_A^{-1} E u_Pi;
-// coef_Pi = -u_Pi; corner outputs w_Pi = u_Pi (weighted)
+// coef_Pi = -u_Pi; corner outputs w_Pi = u_Pi (weighted).  u_c is given as
+// nsplit partial vectors of nc values (their sum, in order).
 __global__ __launch_bounds__(64) void coarse_coef_kernel(const MatDesc* mats, const int32_t* rc, const double* uc,
-                                                         const double* mu, const double* sainv,
+                                                         int nc, int nsplit, const double* mu, const double* sainv,
                                                          const double* sainve, const double* wgt, double* coef,
                                                          double* ww, const int* done) {
   if (done && *done) return;
@@ -1497,7 +1511,12 @@ __global__ __launch_bounds__(64) void coarse_coef_kernel(const MatDesc* mats, co
   const int tid = threadIdx.x;
   __shared__ double u[MAX_NCI];
   if (D.n_ci == 0) return;
-  if (tid < D.n_ci) u[tid] = uc[rc[D.coarse_off + tid]];
+  if (tid < D.n_ci) {
+    const int pc = rc[D.coarse_off + tid];
+    double v = 0.0;
+    for (int q = 0; q < nsplit; ++q) v += uc[int64_t(q) * nc + pc];
+    u[tid] = v;
+  }
   __syncthreads();
   const double* so = sainv + int64_t(s) * MAX_NCI * MAX_NCI;
   const double* se = sainve + int64_t(s) * MAX_NCI * MAX_NCI;
@@ -1525,11 +1544,11 @@ void launch_coarse_prep(const MatDesc* mats, int nmats, const double* part, cons
                      gbuf, mu, done, rowp, ntiles, nwg);
 }
 
-void launch_coarse_coef(const MatDesc* mats, int nmats, const int32_t* rc, const double* uc, const double* mu,
-                        const double* sainv, const double* sainve, const double* wgt, double* coef, double* ww,
-                        const int* done, hipStream_t st) {
-  hipLaunchKernelGGL(coarse_coef_kernel, dim3(nmats), dim3(64), 0, st, mats, rc, uc, mu, sainv, sainve, wgt, coef,
-                     ww, done);
+void launch_coarse_coef(const MatDesc* mats, int nmats, const int32_t* rc, const double* uc, int nc, int nsplit,
+                        const double* mu, const double* sainv, const double* sainve, const double* wgt,
+                        double* coef, double* ww, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(coarse_coef_kernel, dim3(nmats), dim3(64), 0, st, mats, rc, uc, nc, nsplit, mu, sainv, sainve,
+                     wgt, coef, ww, done);
 }
 
 // v12[g] = sum over the subdomains holding g of W_i w_i (gather through the inverse
@@ -1929,8 +1948,9 @@ void launch_coarse_inverse(const double* xg, const double* dc, int nc, double* a
   hipLaunchKernelGGL(coarse_inverse_kernel, dim3((nc + 255) / 256, nc), dim3(256), 0, st, xg, dc, nc, ainv);
 }
 
+constexpr int CG_RW = 8;   // rows of A_c^{-1} per wave of the coarse GEMV
 // u_c = A_c^{-1} r_c with r_c = sum_i R_ci^T g_i gathered per column block; block
-// (four rows, column split s) writes its partial u into upart[s*nc + i]
+// (4 CG_RW rows, column split s) writes its partial u into upart[s*nc + i]
 __global__ __launch_bounds__(256) void coarse_gemv_kernel(const double* ainv, int nc, int cs,
                                                           const int32_t* cinv_ptr, const int32_t* cinv,
                                                           const double* gbuf, double* upart, const int* done) {
@@ -1938,17 +1958,18 @@ __global__ __launch_bounds__(256) void coarse_gemv_kernel(const double* ainv, in
   const int dn = done ? *done : 0;   // tested once the loads are in flight
   const int s = blockIdx.y;
   const int j0 = s * cs, j1 = min(nc, j0 + cs);
-  // one row per wave (the rows are independent, so many short chains in flight);
-  // the row is loaded while the coarse residual is assembled
+  // CG_RW rows per wave, loaded while the coarse residual is assembled (the
+  // assembly of a column slice is repeated by every block of the slice, so a
+  // block takes many rows)
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + w;
+  const int i0 = (blockIdx.x * 4 + w) * CG_RW;
   constexpr int PER_LANE = COARSE_SPLIT_COLS / 64;
-  double rv[PER_LANE];
-  {
-    const double* row = ainv + int64_t(min(i, nc - 1)) * nc;
+  double rv[CG_RW][PER_LANE];
+  for (int k = 0; k < CG_RW; ++k) {
+    const double* row = ainv + int64_t(min(i0 + k, nc - 1)) * nc;
     for (int q = 0; q < PER_LANE; ++q) {
       const int j = j0 + lane + 64 * q;
-      rv[q] = j < j1 ? row[j] : 0.0;
+      rv[k][q] = j < j1 ? row[j] : 0.0;
     }
   }
   for (int j = j0 + threadIdx.x; j < j1; j += 256) {
@@ -1958,19 +1979,23 @@ __global__ __launch_bounds__(256) void coarse_gemv_kernel(const double* ainv, in
   }
   if (dn) return;
   __syncthreads();
-  if (i >= nc) return;
-  double v = 0.0;
-  for (int q = 0; q < PER_LANE; ++q)
-    if (j0 + lane + 64 * q < j1) v += rv[q] * rcs[lane + 64 * q];
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  if (lane == 0) upart[int64_t(s) * nc + i] = v;
+  for (int k = 0; k < CG_RW; ++k) {
+    const int i = i0 + k;
+    if (i >= nc) break;
+    double v = 0.0;
+    for (int q = 0; q < PER_LANE; ++q)
+      if (j0 + lane + 64 * q < j1) v += rv[k][q] * rcs[lane + 64 * q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) upart[int64_t(s) * nc + i] = v;
+  }
 }
 
 void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* cinv_ptr, const int32_t* cinv,
                         const double* gbuf, double* upart, const int* done, hipStream_t st) {
   if (nc <= 0) return;
   const int cs = (nc + nsplit - 1) / nsplit;
-  hipLaunchKernelGGL(coarse_gemv_kernel, dim3((nc + 3) / 4, nsplit), dim3(256), 0, st, ainv, nc, cs, cinv_ptr,
+  hipLaunchKernelGGL(coarse_gemv_kernel, dim3((nc + 4 * CG_RW - 1) / (4 * CG_RW), nsplit), dim3(256), 0, st, ainv,
+                     nc, cs, cinv_ptr,
                      cinv, gbuf, upart, done);
 }
 
@@ -2109,6 +2134,196 @@ __global__ __launch_bounds__(CCG_BLK) void coarse_cg_kernel(const int32_t* rowpt
     for (int i = g; i < nc; i += CCG_NG) uc[i] = x[i];
 }
 
+// The same CG spread over CCG_GRID workgroups when A_c does not fit one
+// workgroup's LDS: workgroup g owns a contiguous block of rows, keeps that
+// block's CSR and its rows of r, p, s, w, dc^2 and x in LDS, and copies the
+// shared vector u into LDS for each mat-vec.  An iteration meets twice at a
+// grid-wide barrier: after the partial sums of (gamma, delta, ||r||^2) are
+// written (every workgroup then adds all partials in the same order, so all
+// take the same decisions), and after every workgroup has written its rows of
+// the new u.  u and the partial sums are written and read with device-scope
+// atomic accesses.  A barrier wait gives up after `spin` polls, marks the
+// status word and ends the workgroup's iteration, so that the kernel finishes
+// instead of hanging; the 64 workgroups, one per compute unit by their LDS
+// size, are normally co-resident, and otherwise the late ones start as the
+// earlier kernels on the device drain.
+constexpr int CCG_GRID = 64;          // workgroups
+constexpr int CCG_GBLK = 256;         // threads per workgroup
+constexpr int CCG_GG = 4;             // lanes per row of the mat-vec
+constexpr int CCG_GROWS = 256;        // rows per workgroup held in LDS
+constexpr int CCG_GLDS_DBL = 12000;   // LDS doubles for u, the block's CSR values and columns
+static_assert(CCG_GRID <= 64, "one lane per workgroup in the reduction of the partial sums");
+
+__device__ __forceinline__ bool ccg_grid_barrier(unsigned* bar, unsigned& gen, int spin, int* werr) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  __shared__ int s_ok;
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned g = gen;
+    const unsigned n = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    if (n == gridDim.x) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar[1], g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      int n = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (n++ >= spin) {
+          atomicOr(werr, DEV_WAIT_GAVE_UP);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    gen = g + 1;
+    s_ok = ok;
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(s_ok) != 0;
+}
+
+__global__ __launch_bounds__(CCG_GBLK) void coarse_cg_grid_kernel(const int32_t* rowptr, const int32_t* col,
+                                                                 const double* fval, const double* dc, int nc,
+                                                                 const int32_t* cinv_ptr, const int32_t* cinv,
+                                                                 const double* gbuf, double* uc, double* work,
+                                                                 unsigned* bar, double tol2, int maxit,
+                                                                 int spin, const int* done, int* werr) {
+  __shared__ double sh[3 * (CCG_GBLK / 64)];
+  __shared__ double sv[CCG_GLDS_DBL];
+  __shared__ double rv[6 * CCG_GROWS];
+  if (done && *done) return;
+  const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x;
+  const int r0 = int(int64_t(nc) * b / G), r1 = int(int64_t(nc) * (b + 1) / G);
+  const int nr = r1 - r0;
+  const int k0 = rowptr[r0], nk = rowptr[r1] - k0;
+  // LDS: u (nc), then the block's CSR values and columns when they fit
+  const bool csr_lds = nc + nk + (nk + 1) / 2 <= CCG_GLDS_DBL;
+  double* us = sv;
+  double* fs = sv + nc;
+  int32_t* cs = reinterpret_cast<int32_t*>(sv + nc + nk);
+  if (csr_lds)
+    for (int k = t; k < nk; k += CCG_GBLK) {
+      fs[k] = fval[k0 + k];
+      cs[k] = col[k0 + k];
+    }
+  double* r = rv;
+  double* p = rv + CCG_GROWS;
+  double* s = rv + 2 * CCG_GROWS;
+  double* w = rv + 3 * CCG_GROWS;
+  double* dd = rv + 4 * CCG_GROWS;
+  double* x = rv + 5 * CCG_GROWS;
+  double* ug = work;                 // shared u (nc)
+  double* part = work + nc;          // 3 partial sums per workgroup
+  for (int i = t; i < nr; i += CCG_GBLK) {
+    double v = 0.0;
+    for (int k = cinv_ptr[r0 + i]; k < cinv_ptr[r0 + i + 1]; ++k) v += gbuf[cinv[k]];
+    const double d2 = dc[r0 + i] * dc[r0 + i];
+    r[i] = v;
+    dd[i] = d2;
+    x[i] = 0.0;
+    store_agent(ug + r0 + i, d2 * v);
+  }
+  unsigned gen = 0;
+  bool ok = ccg_grid_barrier(bar, gen, spin, werr);
+  const int g = t / CCG_GG, l = t % CCG_GG;
+  constexpr int NG = CCG_GBLK / CCG_GG;
+  double bb = 0.0, gam_old = 1.0, alpha = 1.0;
+  for (int it = 0; ok && it <= maxit; ++it) {
+    // u into LDS, eight loads in flight per thread
+    constexpr int UB = 8;
+    for (int i0 = t; i0 < nc; i0 += UB * CCG_GBLK) {
+      double v[UB];
+#pragma unroll
+      for (int q = 0; q < UB; ++q) {
+        v[q] = load_agent(ug + min(i0 + q * CCG_GBLK, nc - 1));   // unconditional: no branch between the loads
+      }
+#pragma unroll
+      for (int q = 0; q < UB; ++q) {
+        const int i = i0 + q * CCG_GBLK;
+        if (i < nc) us[i] = v[q];
+      }
+    }
+    __syncthreads();
+    double gam = 0.0, del = 0.0, rr = 0.0;
+    for (int i = g; i < nr; i += NG) {
+      double v = 0.0;
+      const int a = rowptr[r0 + i] - k0, e = rowptr[r0 + i + 1] - k0;
+      if (csr_lds)
+        for (int k = a + l; k < e; k += CCG_GG) v += fs[k] * us[cs[k]];
+      else
+        for (int k = a + l; k < e; k += CCG_GG) v += fval[k0 + k] * us[col[k0 + k]];
+      for (int o = CCG_GG / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, CCG_GG);
+      if (l == 0) {
+        w[i] = v;
+        const double ui = us[r0 + i], ri = r[i];
+        gam += ri * ui;
+        del += v * ui;
+        rr += ri * ri;
+      }
+    }
+    // block partial sums, in a fixed order
+    for (int off = 32; off > 0; off >>= 1) {
+      gam += __shfl_xor(gam, off, 64);
+      del += __shfl_xor(del, off, 64);
+      rr += __shfl_xor(rr, off, 64);
+    }
+    if ((t & 63) == 0) {
+      sh[3 * (t >> 6)] = gam;
+      sh[3 * (t >> 6) + 1] = del;
+      sh[3 * (t >> 6) + 2] = rr;
+    }
+    __syncthreads();
+    if (t < 3) {
+      double v = 0.0;
+      for (int q = 0; q < CCG_GBLK / 64; ++q) v += sh[3 * q + t];
+      store_agent(part + 3 * b + t, v);
+    }
+    if (!ccg_grid_barrier(bar, gen, spin, werr)) break;
+    // every wave reads the G partial sums (lane q those of workgroup q) and adds
+    // them by a butterfly: IEEE addition is commutative, so every lane of every
+    // wave of every workgroup ends with the same bits
+    {
+      const int q = t & 63, qc = min(q, G - 1);
+      const double g0 = load_agent(part + 3 * qc), d0 = load_agent(part + 3 * qc + 1),
+                   r0v = load_agent(part + 3 * qc + 2);
+      gam = q < G ? g0 : 0.0;
+      del = q < G ? d0 : 0.0;
+      rr = q < G ? r0v : 0.0;
+      for (int off = 32; off > 0; off >>= 1) {
+        gam += __shfl_xor(gam, off, 64);
+        del += __shfl_xor(del, off, 64);
+        rr += __shfl_xor(rr, off, 64);
+      }
+    }
+    if (it == 0) bb = rr;
+    // every lane holds the same sums; the decisions are read as scalars so that
+    // the compiler keeps the loop and its barriers uniform
+    if (__builtin_amdgcn_readfirstlane(int(!(bb > 0.0) || rr <= tol2 * bb))) break;
+    const double beta = it == 0 ? 0.0 : gam / gam_old;
+    const double den = del - beta * gam / alpha;
+    if (__builtin_amdgcn_readfirstlane(int(it == maxit || !(gam > 0.0) || !(den > 0.0)))) {
+      if (b == 0 && t == 0) atomicOr(werr, DEV_COARSE_NOCONV);
+      break;
+    }
+    alpha = gam / den;
+    gam_old = gam;
+    for (int i = t; i < nr; i += CCG_GBLK) {
+      const double ui = us[r0 + i];
+      const double pi = it == 0 ? ui : ui + beta * p[i];
+      const double si = it == 0 ? w[i] : w[i] + beta * s[i];
+      p[i] = pi;
+      s[i] = si;
+      x[i] += alpha * pi;
+      const double ri = r[i] - alpha * si;
+      r[i] = ri;
+      store_agent(ug + r0 + i, dd[i] * ri);
+    }
+    ok = ccg_grid_barrier(bar, gen, spin, werr);
+  }
+  for (int i = t; i < nr; i += CCG_GBLK) uc[r0 + i] = x[i];
+}
+
 __global__ void coarse_cg_matrix_kernel(const int32_t* fsrc, const double* val, double* fval, int n) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) fval[k] = val[fsrc[k]];
@@ -2121,16 +2336,29 @@ void launch_coarse_cg_matrix(const int32_t* fsrc, const double* val, double* fva
 
 void launch_coarse_cg(const int32_t* rowptr, const int32_t* col, const double* fval, int nnz, const double* dc,
                       int nc, const int32_t* cinv_ptr, const int32_t* cinv, const double* gbuf, double* u,
-                      double* work, double tol, int maxit, const int* done, int* werr, hipStream_t st) {
+                      double* work, double tol, int maxit, int spin, const int* done, int* werr,
+                      hipStream_t st) {
   if (nc <= 0) return;
   // LDS bytes of the resident variant: 7 nc + nnz doubles, nnz + nc + 1 ints
   const int64_t need = 8 * (7 * int64_t(nc) + nnz) + 4 * (int64_t(nnz) + nc + 1);
-  if (need <= 8 * int64_t(CCG_LDS_DBL))
+  if (need <= 8 * int64_t(CCG_LDS_DBL)) {
     hipLaunchKernelGGL(coarse_cg_kernel<true>, dim3(1), dim3(CCG_BLK), 0, st, rowptr, col, fval, nnz, dc, nc,
                        cinv_ptr, cinv, gbuf, u, work, tol * tol, maxit, done, werr);
-  else
+  } else if (coarse_cg_grid_fits(nc)) {
+    // the grid variant's barrier words sit after its shared vectors
+    unsigned* bar = reinterpret_cast<unsigned*>(work + nc + 3 * CCG_GRID);
+    launch_fill<unsigned>(bar, 0u, 2, st);
+    hipLaunchKernelGGL(coarse_cg_grid_kernel, dim3(CCG_GRID), dim3(CCG_GBLK), 0, st, rowptr, col, fval, dc, nc,
+                       cinv_ptr, cinv, gbuf, u, work, bar, tol * tol, maxit, spin, done, werr);
+  } else {
     hipLaunchKernelGGL(coarse_cg_kernel<false>, dim3(1), dim3(CCG_BLK), 0, st, rowptr, col, fval, nnz, dc, nc,
                        cinv_ptr, cinv, gbuf, u, work, tol * tol, maxit, done, werr);
+  }
+}
+
+bool coarse_cg_grid_fits(int nc) {
+  // every workgroup holds u and at most CCG_GROWS rows of the six row vectors
+  return nc < CCG_GLDS_DBL && (nc + CCG_GRID - 1) / CCG_GRID <= CCG_GROWS;
 }
 
 // Symmetric interface matrices of a subdomain, lower tile triangle over
@@ -2492,12 +2720,10 @@ __global__ __launch_bounds__(256) void op_finish_kernel(IfaceArgs A) {
 
 // Preconditioner output on the interface rows of tile row ii:
 //   x = (X^T X f)_r + sum_c (W^T X)(c, r) coef_c,  ww = W D x,
-// with the coefficients of the coarse correction computed in place:
-//   u = R_ci u_c, coef_A = -mu + S_A^{-1} u_A + S_A^{-1} E u_Pi, coef_Pi = -u_Pi;
-// the task ii = 0 also writes the corner outputs W_Pi u_Pi.  (Products with the
-// constraint rows vanish: their input is zero.)
+// with the coefficients of the coarse correction from coarse_coef_kernel
+// (which also writes the corner outputs).  (Products with the constraint rows
+// vanish: their input is zero.)
 __global__ __launch_bounds__(256) void pc_finish_kernel(IfaceArgs A) {
-  __shared__ double u[MAX_NCI];
   __shared__ double cf[MAX_NCI];
   __shared__ double s_red[4][NB];
   const int dn = A.sc->done;   // tested once the loads are in flight
@@ -2505,72 +2731,30 @@ __global__ __launch_bounds__(256) void pc_finish_kernel(IfaceArgs A) {
   const MatDesc D = A.mats[s];
   const int TS = sym_tile_rows(D), nG = D.n_R - D.n_I, tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
-  const bool rows = ii * NB < nG;   // uniform: this tile row holds interface rows
-  if (!rows && ii != 0) return;
-  const int nA = D.n_A, nP = D.n_P, nci = D.n_ci;
-  // Everything that does not depend on the coarse solution is loaded first: the
-  // partial sums of the output row, the constraint rows M(n_G + c, r) for
+  if (ii * NB >= nG) return;   // a tile row of constraint rows only: no output
+  const int nci = D.n_ci;
+  // the partial sums of the output row, the constraint rows M(n_G + c, r) for
   // c = w, w + 4, ... (M(n_G + c, r) lies in tile ((n_G + c) / 64, ii)), the
-  // output weight.
+  // output weight and the coefficients, all loaded before the first barrier
   constexpr int CPW = MAX_NCI / 4;
   double mc[CPW];
   double wdr = 0.0;
   const int r_out = ii * NB + lane;
-  if (rows) {
-    sum_row(A, D, ii, TS, s_red);
-    for (int q = 0; q < CPW; ++q) {
-      const int c = w + 4 * q;
-      double m = 0.0;
-      if (c < nci) {
-        const int R = nG + c;
-        const int64_t t = (D.sg_off + tri_tile(R / NB, ii)) * int64_t(NB * NB);
-        m = A.m32 ? double(static_cast<const float*>(A.m)[t + sym_f32_off(R % NB, lane)])
-                  : static_cast<const double*>(A.m)[t + (R % NB) * NB + lane];
-      }
-      mc[q] = m;
+  sum_row(A, D, ii, TS, s_red);
+  for (int q = 0; q < CPW; ++q) {
+    const int c = w + 4 * q;
+    double m = 0.0;
+    if (c < nci) {
+      const int R = nG + c;
+      const int64_t t = (D.sg_off + tri_tile(R / NB, ii)) * int64_t(NB * NB);
+      m = A.m32 ? double(static_cast<const float*>(A.m)[t + sym_f32_off(R % NB, lane)])
+                : static_cast<const double*>(A.m)[t + (R % NB) * NB + lane];
     }
-    if (w == 0 && r_out < nG) wdr = A.wd[D.loc_off + D.n_I + r_out];
+    mc[q] = m;
   }
-  if (tid < nci) {
-    const int pc = A.rc[D.coarse_off + tid];
-    double v = 0.0;
-    for (int q = 0; q < A.nsplit; ++q) v += A.uc[int64_t(q) * A.nc + pc];
-    u[tid] = v;
-  }
-  // the first terms of the coefficient rows (S_A^{-1} and S_A^{-1} E, coefficient
-  // c = tid / 4, lanes tid % 4 split its terms) do not depend on u either
-  constexpr int SPO = 8, SPE = 2;
-  const int c = tid >> 2, l4 = tid & 3;
-  const double* so = A.sainv + int64_t(s) * MAX_NCI * MAX_NCI + c * MAX_NCI;
-  const double* se = A.sainve + int64_t(s) * MAX_NCI * MAX_NCI + c * MAX_NCI;
-  double sov[SPO], sev[SPE];
-#pragma unroll
-  for (int k = 0; k < SPO; ++k) sov[k] = (c < nA && l4 + 4 * k < nA) ? so[l4 + 4 * k] : 0.0;
-#pragma unroll
-  for (int k = 0; k < SPE; ++k) sev[k] = (c < nA && l4 + 4 * k < nP) ? se[l4 + 4 * k] : 0.0;
+  if (w == 0 && r_out < nG) wdr = A.wd[D.loc_off + D.n_I + r_out];
+  if (tid < nci) cf[tid] = A.coef[int64_t(s) * MAX_NCI + tid];
   if (dn) return;
-  __syncthreads();
-  {
-    double v = 0.0;
-    if (c < nA) {
-#pragma unroll
-      for (int k = 0; k < SPO; ++k)
-        if (l4 + 4 * k < nA) v += sov[k] * u[l4 + 4 * k];
-      for (int t = l4 + 4 * SPO; t < nA; t += 4) v += so[t] * u[t];
-#pragma unroll
-      for (int k = 0; k < SPE; ++k)
-        if (l4 + 4 * k < nP) v += sev[k] * u[nA + l4 + 4 * k];
-      for (int q = l4 + 4 * SPE; q < nP; q += 4) v += se[q] * u[nA + q];
-    }
-    v += __shfl_xor(v, 1, 4);
-    v += __shfl_xor(v, 2, 4);
-    if (l4 == 0 && c < nci) cf[c] = c < nA ? v - A.mu[int64_t(s) * MAX_NCI + c] : -u[c];
-    if (ii == 0 && tid >= nA && tid < nci) {
-      const int64_t l = D.loc_off + D.n_R + (tid - nA);
-      A.ww[l] = A.wgt[l] * u[tid];
-    }
-  }
-  if (!rows) return;
   __syncthreads();
   // constraint rows: wave w takes c = w, w+4, ...
   {
