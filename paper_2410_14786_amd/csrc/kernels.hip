@@ -1616,26 +1616,70 @@ __device__ __forceinline__ double reduce_partials(const double* part, int np, do
   return block_sum(v, sh);
 }
 
-// CSR row times x by a group of ROW_LANES consecutive lanes (a Q1 row has at most
-// 27 entries in 3D): many rows in flight per wave, short reductions
+// CSR rows times x, each row by a group of ROW_LANES consecutive lanes.  A Q1
+// row has at most 27 entries (3D), so every lane takes ROW_STEPS entries of each
+// of its U rows with unconditional loads (addresses clamped into the row, the
+// surplus terms dropped by a select): the loads of all U rows are in flight at
+// once, where a loop over the entries waits for every trip's loads.  Longer rows
+// (not produced by Q1 assembly) finish in a loop.  Rows >= n give 0.  Every row
+// of the matrix is non-empty (it holds its diagonal), so clamped addresses stay
+// inside the arrays.
 constexpr int ROW_LANES = 4;
-__device__ __forceinline__ double row_dot(const int32_t* rowptr, const int32_t* col, const double* val,
-                                          const double* x, int64_t row, int sl) {
-  const int b = rowptr[row], e = rowptr[row + 1];
-  double v = 0.0;
-  for (int j = b + sl; j < e; j += ROW_LANES) v += val[j] * x[col[j]];
-  for (int off = ROW_LANES / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, ROW_LANES);
-  return v;
+constexpr int ROW_STEPS = 7;
+template <int U>
+__device__ __forceinline__ void rows_dot(const int32_t* rowptr, const int32_t* col, const double* val,
+                                         const double* x, const int64_t (&row)[U], int64_t n, int sl,
+                                         double (&v)[U]) {
+  int b[U], e[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t rw = row[u] < n ? row[u] : n - 1;
+    b[u] = rowptr[rw];
+    e[u] = row[u] < n ? rowptr[rw + 1] : b[u];
+  }
+  int cc[U][ROW_STEPS];
+  double cv[U][ROW_STEPS];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int k = 0; k < ROW_STEPS; ++k) {
+      const int j = min(b[u] + sl + ROW_LANES * k, max(e[u] - 1, b[u]));
+      cc[u][k] = col[j];
+      cv[u][k] = val[j];
+    }
+  double xv[U][ROW_STEPS];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int k = 0; k < ROW_STEPS; ++k) xv[u][k] = x[cc[u][k]];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < ROW_STEPS; ++k) {
+      const double t = cv[u][k] * xv[u][k];
+      s += b[u] + sl + ROW_LANES * k < e[u] ? t : 0.0;
+    }
+    for (int j = b[u] + sl + ROW_LANES * ROW_STEPS; j < e[u]; j += ROW_LANES) s += val[j] * x[col[j]];
+    for (int off = ROW_LANES / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, ROW_LANES);
+    v[u] = s;
+  }
 }
+constexpr int ROW_U = 2;   // rows per lane group and step of the SpMV loops
 
 __global__ __launch_bounds__(VBLK) void spmv_kernel(const int32_t* rowptr, const int32_t* col, const double* val,
                                                     const double* x, double* y, int64_t n) {
   const int sl = threadIdx.x % ROW_LANES;
   const int64_t hw = (blockIdx.x * int64_t(VBLK) + threadIdx.x) / ROW_LANES;
   const int64_t nhw = (int64_t(gridDim.x) * VBLK) / ROW_LANES;
-  for (int64_t row = hw; row < n; row += nhw) {
-    double v = row_dot(rowptr, col, val, x, row, sl);
-    if (sl == 0) y[row] = v;
+  for (int64_t row0 = hw; row0 < n; row0 += ROW_U * nhw) {
+    int64_t rows[ROW_U];
+    double v[ROW_U];
+    for (int u = 0; u < ROW_U; ++u) rows[u] = row0 + u * nhw;
+    rows_dot<ROW_U>(rowptr, col, val, x, rows, n, sl, v);
+    if (sl == 0)
+      for (int u = 0; u < ROW_U; ++u)
+        if (rows[u] < n) y[rows[u]] = v[u];
   }
 }
 
@@ -1656,14 +1700,20 @@ __global__ __launch_bounds__(VBLK) void residual_kernel(const int32_t* rowptr, c
   const int64_t hw = (blockIdx.x * int64_t(VBLK) + threadIdx.x) / ROW_LANES;
   const int64_t nhw = (int64_t(gridDim.x) * VBLK) / ROW_LANES;
   double rr = 0.0, bb = 0.0;
-  for (int64_t row = hw; row < n; row += nhw) {
-    double v = row_dot(rowptr, col, val, x, row, sl);
-    if (sl == 0) {
-      double rv = (iface_only && iface_only[row] < 2) ? 0.0 : b[row] - v;
-      r[row] = rv;
-      rr += rv * rv;
-      bb += b[row] * b[row];
-    }
+  for (int64_t row0 = hw; row0 < n; row0 += ROW_U * nhw) {
+    int64_t rows[ROW_U];
+    double v[ROW_U];
+    for (int u = 0; u < ROW_U; ++u) rows[u] = row0 + u * nhw;
+    rows_dot<ROW_U>(rowptr, col, val, x, rows, n, sl, v);
+    if (sl == 0)
+      for (int u = 0; u < ROW_U; ++u) {
+        const int64_t row = rows[u];
+        if (row >= n) break;
+        double rv = (iface_only && iface_only[row] < 2) ? 0.0 : b[row] - v[u];
+        r[row] = rv;
+        rr += rv * rv;
+        bb += b[row] * b[row];
+      }
   }
   double t = block_sum(rr, sh);
   double u = block_sum(bb, sh);
@@ -1700,15 +1750,21 @@ __global__ __launch_bounds__(VBLK) void pcg_dir_kernel(const int32_t* rowptr, co
   const int64_t hw = (blockIdx.x * int64_t(VBLK) + threadIdx.x) / ROW_LANES;
   const int64_t nhw = (int64_t(gridDim.x) * VBLK) / ROW_LANES;
   double pq = 0.0;
-  for (int64_t row = hw; row < n; row += nhw) {
-    double az = row_dot(rowptr, col, val, z, row, sl);
-    if (sl == 0) {
-      double pv = z[row] + (fresh ? 0.0 : beta * p[row]);
-      double qv = az + (fresh ? 0.0 : beta * q[row]);
-      p[row] = pv;
-      q[row] = qv;
-      pq += pv * qv;
-    }
+  for (int64_t row0 = hw; row0 < n; row0 += ROW_U * nhw) {
+    int64_t rows[ROW_U];
+    double az[ROW_U];
+    for (int u = 0; u < ROW_U; ++u) rows[u] = row0 + u * nhw;
+    rows_dot<ROW_U>(rowptr, col, val, z, rows, n, sl, az);
+    if (sl == 0)
+      for (int u = 0; u < ROW_U; ++u) {
+        const int64_t row = rows[u];
+        if (row >= n) break;
+        double pv = z[row] + (fresh ? 0.0 : beta * p[row]);
+        double qv = az[u] + (fresh ? 0.0 : beta * q[row]);
+        p[row] = pv;
+        q[row] = qv;
+        pq += pv * qv;
+      }
   }
   double t = block_sum(pq, sh);
   if (threadIdx.x == 0) part_pq[blockIdx.x] = t;

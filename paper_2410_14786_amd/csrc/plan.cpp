@@ -485,17 +485,29 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
   }
 
   // ---- task lists: forward passes by tile row, backward passes from the bottom ----
-  // (interior passes: two tile rows per task, the task names the first)
+  // (interior passes: two tile rows per task, the task names the first).  The
+  // chains of the subdomains are aligned at their ends: a chain of n tasks
+  // enters n levels before the last level, so the longest chains (the critical
+  // paths) start first, while the workgroups are shared by few chains and can
+  // take their later tasks early.  Each chain keeps its own order, so tickets
+  // stay in dependency order.
   auto make_tasks = [&](std::vector<int32_t>& out, bool interior_only, bool backward) {
-    int maxT = interior_only ? P.maxTI : P.maxT;
     const int step = interior_only ? 2 : 1;
-    for (int d = 0; d < maxT; d += step)
+    std::vector<int> nt(P.nsubs);
+    int maxN = 0;
+    for (int s = 0; s < P.nsubs; ++s) {
+      const int T = interior_only ? P.subs[s].TI : P.subs[s].T;
+      nt[s] = (T + step - 1) / step;
+      maxN = std::max(maxN, nt[s]);
+    }
+    for (int e = 0; e < maxN; ++e)
       for (int s = 0; s < P.nsubs; ++s) {
-        int T = interior_only ? P.subs[s].TI : P.subs[s].T;
-        if (d < T) {
-          out.push_back(s);
-          out.push_back(backward ? T - 1 - d : d);
-        }
+        const int i = e - (maxN - nt[s]);
+        if (i < 0) continue;
+        const int T = interior_only ? P.subs[s].TI : P.subs[s].T;
+        const int d = i * step;
+        out.push_back(s);
+        out.push_back(backward ? T - 1 - d : d);
       }
   };
   make_tasks(P.fwd_rr, false, false);
