@@ -182,14 +182,14 @@ int bddc_pcg_solve(bddc_ctx* ctx, const double* b, double* x, double rtol,
  * HIP graph capture, tight serving loops, harnesses that forbid allocation.
  * It calls no hipMalloc, hipFree or other allocating routine and records no
  * timing event.  The buffers that one application starts afresh (published
- * triangular-solve values, coarse solution values, ticket counters) live in a
+ * triangular-solve values and ticket counters) live in a
  * fixed device workspace of 64 MiB that the library holds on every GPU it runs
  * on until the process ends, instead of in the ctx.  Every call on one GPU
  * uses that GPU's workspace, whatever the ctx: calls that overlap on one GPU
  * (different streams, or different host threads) race and must be ordered by
  * the caller.  Each call re-initialises the part it uses before reading it.
  * Errors: EINVAL (NULL or aliased vectors, or a problem whose apply workspace
- * 4 * n_vec * (4 or 8 bytes) + the coarse and ticket buffers exceeds 64 MiB; the
+ * 4 * n_vec * (4 or 8 bytes) + the ticket counters exceeds 64 MiB; the
  * message gives both sizes), EHIP (no workspace address on this device).
  * Asynchronous on the ctx stream. */
 int bddc_apply_noalloc(bddc_ctx* ctx, const double* r, double* z);

@@ -140,7 +140,6 @@ struct bddc_ctx {
   double *ctiles = nullptr, *cdinv = nullptr;
   MatDesc* cmat = nullptr;
   MatDesc cmat_host{};
-  int32_t *ctask_fwd = nullptr, *ctask_bwd = nullptr;
   int Tc = 0;
   int32_t *t_fwd_rr = nullptr, *t_bwd_rr = nullptr, *t_fwd_ii = nullptr, *t_bwd_ii = nullptr;
   int32_t *t_symfin = nullptr, *tinfo = nullptr, *trows_op = nullptr, *trows_pc = nullptr;
@@ -156,20 +155,19 @@ struct bddc_ctx {
   float* hg32 = nullptr;                       // X^T X (+ border rows) in FP32 (pc32, instead of hg)
   double *symp = nullptr, *rowp = nullptr;     // their column / row partial products
   double *zpad = nullptr, *fpad = nullptr;     // D^{-1} z (+ corners) and W D r in padded rows
-  double *cxg = nullptr, *cainv = nullptr, *upart = nullptr;   // explicit coarse inverse (interface form)
+  double *cxg = nullptr, *cainv = nullptr;   // explicit coarse inverse
+  double* upart = nullptr;   // u_c as csplit column-split partials (the coarse CG: one vector)
   int csplit = 1;
   double *sploc = nullptr, *cpp = nullptr;
   int max_loclen = 1;
   void* pub_local = nullptr;   // 4 * n_vec entries of the local precision
-  double* pub_coarse = nullptr;
   unsigned* tickets = nullptr;
   int* fready = nullptr;            // per tile ready words of the persistent factorisation
   int wait_polls = 1 << 22;         // polls of a published value before a solve task gives up
   int coarse_maxit = COARSE_CG_MAXIT;
   unsigned* fticket = nullptr;
   void* static_scratch = nullptr;   // this device's fixed workspace (bddc_apply_noalloc)
-  double *part = nullptr, *gbuf = nullptr, *mu = nullptr, *coef = nullptr, *ww = nullptr, *v12 = nullptr,
-         *uc = nullptr;
+  double *part = nullptr, *gbuf = nullptr, *mu = nullptr, *coef = nullptr, *ww = nullptr, *v12 = nullptr;
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *tmp = nullptr;
   double *part_a = nullptr, *part_b = nullptr, *part_c = nullptr, *scal = nullptr;
   PcgScalars* sc = nullptr;
@@ -338,7 +336,6 @@ void* pub_slot(bddc_ctx* c, int i) {
 // Buffers of one preconditioner application that start over at every call.
 struct ApplyWs {
   void* pub_local;      // 4 * n_vec entries of the local precision
-  double* pub_coarse;   // 2 * Tc * NB doubles
   unsigned* tickets;    // 8 counters
 };
 
@@ -354,12 +351,12 @@ int trsv_grid_ii(bddc_ctx* c, int ntasks) {
 
 // z = M^{-1} r (paper Sec. 2): v1 + v2 through the forward solve, the coarse
 // problem and the backward solve, then v3 on subdomain interiors.
-// ws: where the per-application buffers live (published solutions, coarse
-// solutions, tickets); NULL: the ctx's own.  With ws no event is recorded.
+// ws: where the per-application buffers live (published solutions, tickets);
+// NULL: the ctx's own.  With ws no event is recorded.
 void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done, const ApplyWs* ws = nullptr) {
   const Plan& P = c->plan;
   hipStream_t st = c->st;
-  ApplyWs own{c->pub_local, c->pub_coarse, c->tickets};
+  ApplyWs own{c->pub_local, c->tickets};
   const ApplyWs& W = ws ? *ws : own;
   const bool events = ws == nullptr;
   auto slot = [&](int i) -> void* {
@@ -369,7 +366,6 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done, con
   hipEvent_t ea = events ? c->begin("apply") : nullptr;
   if (c->fp32) launch_fill_sentinel<float>(static_cast<float*>(W.pub_local), 4 * P.n_vec, st);
   else launch_fill_sentinel<double>(static_cast<double*>(W.pub_local), 4 * P.n_vec, st);
-  if (c->Tc > 0) launch_fill_sentinel<double>(W.pub_coarse, 2 * int64_t(c->Tc) * NB, st);
   launch_fill<unsigned>(W.tickets, 0u, 8, st);
 
   // forward solve with A_RR: t = L^{-1} D W_i R_i r, border partials W^T t
@@ -391,37 +387,15 @@ void enqueue_apply(bddc_ctx* c, const double* r, double* z, const int* done, con
   if (P.n_coarse > 0) {
     launch_coarse_prep(c->mats, P.nsubs, c->part, c->sainv, c->sainve, c->gmap, c->wgt, r, c->gbuf, c->mu, done, nullptr,
                        0, 0, st);
-    TrsvArgs cf;
-    std::memset(&cf, 0, sizeof(cf));
-    cf.mats = c->cmat;
-    cf.tiles = c->ctiles;
-    cf.dinv = c->cdinv;
-    cf.done = done;
-    cf.tasks = c->ctask_fwd;
-    cf.ntasks = c->Tc;
-    cf.ticket = W.tickets + 4;
-    cf.sol = W.pub_coarse;
-    cf.cinv_ptr = c->cinv_ptr;
-    cf.cinv = c->cinv;
-    cf.gbuf = c->gbuf;
-    cf.dc = c->dc;
-    cf.werr = c->err + 3;
-    cf.spin = c->wait_polls;
-    if (c->coarse_cg) {
+    // u_c = A_c^{-1} r_c: the explicit inverse (column-split partials), or the coarse CG
+    if (c->coarse_cg)
       launch_coarse_cg(c->ac_rowptr, c->ac_fcol, c->ac_fval, c->ac_nfull, c->dc, P.n_coarse, c->cinv_ptr, c->cinv,
-                       c->gbuf, c->uc, c->ccg_work, COARSE_CG_TOL, c->coarse_maxit, c->wait_polls, done,
+                       c->gbuf, c->upart, c->ccg_work, COARSE_CG_TOL, c->coarse_maxit, c->wait_polls, done,
                        c->err + 3, st);
-    } else {
-      launch_trsv(TRSV_FWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
-      cf.tasks = c->ctask_bwd;
-      cf.ticket = W.tickets + 5;
-      cf.src = W.pub_coarse;
-      cf.sol = W.pub_coarse + int64_t(c->Tc) * NB;
-      cf.uc = c->uc;
-      launch_trsv(TRSV_BWD_C, false, cf, trsv_grid(c, cf.ntasks), st);
-    }
-    launch_coarse_coef(c->mats, P.nsubs, c->rc, c->uc, P.n_coarse, 1, c->mu, c->sainv, c->sainve, c->wgt, c->coef,
-                       c->ww, done, st);
+    else
+      launch_coarse_gemv(c->cainv, P.n_coarse, c->csplit, c->cinv_ptr, c->cinv, c->gbuf, c->upart, done, st);
+    launch_coarse_coef(c->mats, P.nsubs, c->rc, c->upart, P.n_coarse, c->csplit, c->mu, c->sainv, c->sainve,
+                       c->wgt, c->coef, c->ww, done, st);
   }
   // backward solve: D L^{-T} (t + W coef) = z_R + Phi_R u (weighted)
   a = base_args(c);
@@ -933,21 +907,11 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   // (the coarse CG needs no dense coarse factor)
   if ((rc_ = c->alloc(c->ctiles, c->coarse_cg ? 1 : tri_tile(c->Tc, 0) * NB * NB))) return rc_;
   if ((rc_ = c->alloc(c->cdinv, c->coarse_cg ? 1 : int64_t(c->Tc) * NB * NB))) return rc_;
-  if ((rc_ = c->alloc(c->pub_coarse, 2 * int64_t(c->Tc) * NB))) return rc_;
-  std::vector<int32_t> cf, cb;
-  for (int k = 0; k < c->Tc; ++k) {
-    cf.push_back(0);
-    cf.push_back(k);
-    cb.push_back(0);
-    cb.push_back(c->Tc - 1 - k);
-  }
-  if ((rc_ = c->upload(c->ctask_fwd, cf))) return rc_;
-  if ((rc_ = c->upload(c->ctask_bwd, cb))) return rc_;
   if (nc > 0 && c->coarse_cg) {
     launch_coarse_assembly(c->ac_src_ptr, c->ac_src, c->ac_row, c->ac_col, c->ac_diag, int(P.ac_row.size()), nc,
                            c->aci, c->ac_val, c->dc, nullptr, c->err + 2, st);
     launch_coarse_cg_matrix(c->ac_fsrc, c->ac_val, c->ac_fval, c->ac_nfull, st);
-    if (c->iface && (rc_ = c->alloc(c->upart, nc))) return rc_;
+    if ((rc_ = c->alloc(c->upart, nc))) return rc_;
   } else if (nc > 0) {
     launch_fill<double>(c->ctiles, 0.0, tri_tile(c->Tc, 0) * NB * NB, st);
     launch_pad_identity(c->cmat, 1, c->ctiles, false, st);
@@ -964,7 +928,7 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
       launch_factor_persistent(c->cmat, c->ctiles, c->cdinv, false, nullptr, ctasks, int(ct.size() / 3), c->fticket,
                                cready, tri_tile(c->Tc, 0), 2 * c->cus, c->err + 2, st);
     }
-    if (c->iface) {
+    {
       // A_c^{-1} = D X^T X D, X = inverse of the coarse Cholesky factor
       if ((rc_ = c->alloc(c->cxg, tri_tile(c->Tc, 0) * NB * NB))) return rc_;
       if ((rc_ = c->alloc(c->cainv, int64_t(nc) * nc))) return rc_;
@@ -983,7 +947,6 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
   if ((rc_ = c->alloc(c->coef, int64_t(P.nsubs) * MAX_NCI))) return rc_;
   if ((rc_ = c->alloc(c->ww, P.n_loc))) return rc_;
   if ((rc_ = c->alloc(c->v12, P.n_free))) return rc_;
-  if ((rc_ = c->alloc(c->uc, nc + 1))) return rc_;
   launch_fill<double>(c->coef, 0.0, int64_t(P.nsubs) * MAX_NCI, st);
   if ((rc_ = c->alloc(c->r, P.n_free))) return rc_;
   if ((rc_ = c->alloc(c->z, P.n_free))) return rc_;
@@ -1146,13 +1109,12 @@ int bddc_apply_noalloc(bddc_ctx* c, const double* r, double* z) {
   auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t es = c->fp32 ? sizeof(float) : sizeof(double);
   const size_t b_pub = up(size_t(4) * size_t(P.n_vec) * es);
-  const size_t b_coarse = up(size_t(2) * size_t(std::max(c->Tc, 0)) * NB * sizeof(double));
-  const size_t need = b_pub + b_coarse + up(8 * sizeof(unsigned));
+  const size_t need = b_pub + up(8 * sizeof(unsigned));
   if (need > STATIC_SCRATCH_BYTES)
     return fail(BDDC_EINVAL, "this problem needs " + std::to_string(need) + " bytes of apply workspace; the fixed "
                              "workspace of bddc_apply_noalloc holds " + std::to_string(STATIC_SCRATCH_BYTES));
   char* base = static_cast<char*>(c->static_scratch);
-  ApplyWs ws{base, reinterpret_cast<double*>(base + b_pub), reinterpret_cast<unsigned*>(base + b_pub + b_coarse)};
+  ApplyWs ws{base, reinterpret_cast<unsigned*>(base + b_pub)};
   enqueue_apply(c, r, z, nullptr, &ws);
   HIP_TRY(hipGetLastError());
   return BDDC_OK;
@@ -1227,7 +1189,7 @@ int bddc_pcg_solve(bddc_ctx* c, const double* b, double* x, double rtol, int32_t
     *hdone = 0;   // nothing of this ctx is in flight here
     // (re)start: z = M^{-1} r, rz
     if (iface) {
-      launch_reset(false, nullptr, 0, c->pub_coarse, 2 * int64_t(c->Tc) * NB, c->tickets, done, st);
+      launch_reset(false, nullptr, 0, nullptr, 0, c->tickets, done, st);
       launch_scatter_f_ifc(ifc_args(c), st);
       enqueue_apply_iface(c, c->r, c->z, c->part_c, done);
     } else {

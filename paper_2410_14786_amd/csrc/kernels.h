@@ -21,9 +21,7 @@ enum {
   TRSV_FWD_RR = 0,  // L y = D W_i R_i r on the whole A_RR factor (+ border partials)
   TRSV_BWD_RR = 1,  // L^T x = y + W coef on the whole factor (-> weighted local output)
   TRSV_FWD_II = 2,  // interior block, rhs = D (r - A v12) on interior rows
-  TRSV_BWD_II = 3,  // interior block, z = v12 + D x on interior rows
-  TRSV_FWD_C = 4,   // coarse factor, rhs gathered from the subdomain coarse residuals
-  TRSV_BWD_C = 5    // coarse factor, u_c = D x
+  TRSV_BWD_II = 3   // interior block, z = v12 + D x on interior rows
 };
 
 struct TrsvArgs {
@@ -49,11 +47,6 @@ struct TrsvArgs {
   double* ww;            // BWD_RR weighted local output
   double* zout;          // BWD_II output
   const double* base;    // BWD_II: added to the output (may be null)
-  const int32_t* cinv_ptr;
-  const int32_t* cinv;
-  const double* gbuf;
-  const double* dc;
-  double* uc;
   const int32_t* fcol;   // per tile row: first nonzero tile column (null: dense)
   const int32_t* lrow;   // backward passes, per tile column k: last tile row to read (null: dense)
   const int32_t* bptr;   // whole-space backward pass, per tile column k (vec_off / NB + k): its

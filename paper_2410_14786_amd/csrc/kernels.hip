@@ -876,7 +876,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
   constexpr int LPR = NB / VEC;      // lanes per tile row
   constexpr int RPI = 64 / LPR;      // tile rows per wave instruction
   constexpr int NI = 16 / RPI;       // instructions per 16-row slab
-  constexpr bool FWD = (MODE == TRSV_FWD_RR || MODE == TRSV_FWD_C);
+  constexpr bool FWD = MODE == TRSV_FWD_RR;
   static_assert(MODE != TRSV_FWD_II && MODE != TRSV_BWD_II, "interior passes: trsv2_kernel");
 
   __shared__ T s_rhs[NB];
@@ -926,10 +926,6 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
         if (MODE == TRSV_FWD_RR) {
           const int64_t l = D.loc_off + a;
           rhs = A.wd[l] * A.rin[A.gmap[l]];
-        } else if (MODE == TRSV_FWD_C) {
-          double v = 0.0;
-          for (int j = A.cinv_ptr[a]; j < A.cinv_ptr[a + 1]; ++j) v += A.gbuf[A.cinv[j]];
-          rhs = A.dc[a] * v;
         } else {
           rhs = double(src[D.vec_off + a]);   // backward: the forward solution
         }
@@ -1072,11 +1068,6 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
           const int64_t l = D.loc_off + a;
           A.ww[l] = A.wd[l] * double(s_out[tid]);
         }
-      }
-    } else if (MODE == TRSV_BWD_C) {
-      if (tid < NB) {
-        const int a = k * NB + tid;
-        if (a < D.n_R) A.uc[a] = A.dc[a] * double(s_out[tid]);
       }
     }
     __syncthreads();
@@ -1410,8 +1401,6 @@ static void launch_trsv_t(int mode, const TrsvArgs& a, int grid, hipStream_t st,
   switch (mode) {
     case TRSV_FWD_RR: launch_timed(trsv_kernel<T, TRSV_FWD_RR>, g, b, st, t0, t1, a); break;
     case TRSV_BWD_RR: launch_timed(trsv_kernel<T, TRSV_BWD_RR>, g, b, st, t0, t1, a); break;
-    case TRSV_FWD_C: launch_timed(trsv_kernel<T, TRSV_FWD_C>, g, b, st, t0, t1, a); break;
-    case TRSV_BWD_C: launch_timed(trsv_kernel<T, TRSV_BWD_C>, g, b, st, t0, t1, a); break;
   }
 }
 
@@ -1421,7 +1410,7 @@ void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t s
     launch_trsv2(mode, fp32, a, grid, st, t0, t1);
     return;
   }
-  if (fp32 && mode != TRSV_FWD_C && mode != TRSV_BWD_C)
+  if (fp32)
     launch_trsv_t<float>(mode, a, grid, st, t0, t1);
   else
     launch_trsv_t<double>(mode, a, grid, st, t0, t1);
@@ -1452,7 +1441,7 @@ __device__ double sym_row_product(const double* rowp, int64_t tr0, int len, int6
 //   g[A]  = S_A^{-1} h_A                        (also mu, the average multipliers)
 //   g[Pi] = -h_Pi + (S_A^{-1} E)^T h_A + W_Pi r_Pi
 // g = Phi_i^T W_i R_i r, the subdomain's share of the coarse residual r_c.
-__global__ __launch_bounds__(64) void coarse_prep_kernel(const MatDesc* mats, const double* part,
+__global__ __launch_bounds__(256) void coarse_prep_kernel(const MatDesc* mats, const double* part,
                                                          const double* sainv, const double* sainve,
                                                          const int32_t* gmap, const double* wgt, const double* r,
                                                          double* gbuf, double* mu, const int* done,
@@ -1462,21 +1451,39 @@ __global__ __launch_bounds__(64) void coarse_prep_kernel(const MatDesc* mats, co
   const MatDesc D = mats[s];
   const int tid = threadIdx.x;
   __shared__ double h[MAX_NCI];
+  __shared__ double hq[4][MAX_NCI];
   if (D.n_ci == 0) return;
-  if (tid < D.n_ci) {
+  // constraint c = tid % 64; the whole-space partial products of the T tile
+  // rows are split over the four waves (rows k = q, q + 4, ..., four loads in
+  // flight each) and added in wave order
+  const int c = tid & 63, q = tid >> 6;
+  if (c < D.n_ci) {
     double v = 0.0;
     if (rowp) {
-      // interface form: W^T t is the row product of constraint row n_G + tid,
+      // interface form: W^T t is the row product of constraint row n_G + c,
       // (W_G^T X) f
-      const int R = D.n_R - D.n_I + tid;
-      v = sym_row_product(rowp, D.sg_off + tri_tile(R / NB, 0), R / NB + 1, ntiles, nwg, R % NB);
+      if (q == 0) {
+        const int R = D.n_R - D.n_I + c;
+        v = sym_row_product(rowp, D.sg_off + tri_tile(R / NB, 0), R / NB + 1, ntiles, nwg, R % NB);
+      }
     } else {
-      const int64_t base = (D.vec_off / NB) * MAX_NCI;
-      for (int k = 0; k < D.T; ++k) v += part[base + int64_t(k) * MAX_NCI + tid];
+      const double* pp = part + (D.vec_off / NB) * MAX_NCI + c;
+      int k = q;
+      for (; k + 12 < D.T; k += 16) {
+        const double a0 = pp[int64_t(k) * MAX_NCI], a1 = pp[int64_t(k + 4) * MAX_NCI],
+                     a2 = pp[int64_t(k + 8) * MAX_NCI], a3 = pp[int64_t(k + 12) * MAX_NCI];
+        v += a0;
+        v += a1;
+        v += a2;
+        v += a3;
+      }
+      for (; k < D.T; k += 4) v += pp[int64_t(k) * MAX_NCI];
     }
-    h[tid] = v;
+    hq[q][c] = v;
   }
   if (dn) return;
+  __syncthreads();
+  if (tid < D.n_ci) h[tid] = hq[0][tid] + hq[1][tid] + hq[2][tid] + hq[3][tid];
   __syncthreads();
   const double* so = sainv + int64_t(s) * MAX_NCI * MAX_NCI;
   const double* se = sainve + int64_t(s) * MAX_NCI * MAX_NCI;
@@ -1540,7 +1547,7 @@ void launch_coarse_prep(const MatDesc* mats, int nmats, const double* part, cons
                         const double* sainve, const int32_t* gmap, const double* wgt, const double* r,
                         double* gbuf, double* mu, const int* done, const double* rowp, int64_t ntiles, int nwg,
                         hipStream_t st) {
-  hipLaunchKernelGGL(coarse_prep_kernel, dim3(nmats), dim3(64), 0, st, mats, part, sainv, sainve, gmap, wgt, r,
+  hipLaunchKernelGGL(coarse_prep_kernel, dim3(nmats), dim3(256), 0, st, mats, part, sainv, sainve, gmap, wgt, r,
                      gbuf, mu, done, rowp, ntiles, nwg);
 }
 
