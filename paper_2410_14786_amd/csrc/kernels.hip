@@ -877,6 +877,10 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
   constexpr int RPI = 64 / LPR;      // tile rows per wave instruction
   constexpr int NI = 16 / RPI;       // instructions per 16-row slab
   constexpr bool FWD = MODE == TRSV_FWD_RR;
+  // FP32 forward passes take the backward layout (a wave owns 16 whole rows):
+  // with a wave on 16 columns an FP32 tile row gives each wave 64 bytes of a
+  // 128-byte line, and the streamed tiles are fetched about 1.4 times over
+  constexpr bool ROWL = FWD && sizeof(T) == 4;
   static_assert(MODE != TRSV_FWD_II && MODE != TRSV_BWD_II, "interior passes: trsv2_kernel");
 
   __shared__ T s_rhs[NB];
@@ -894,11 +898,15 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
   // Backward passes (column products) let wave w own rows 16w..16w+15: lane =
   // LPR * lr + lc holds rows 16w + RPI i + lr, columns VEC lc + e, so a column sum
   // reduces over RPI lanes, then the four waves.  Both take NI loads per lane.
+  // (ROWL: forward row sums in the backward layout reduce over LPR lanes and are
+  // complete in the wave that owns the row.)
   constexpr int CPL = 16 / VEC, RG = 64 / CPL;
   static_assert(64 / RG == NI, "layouts differ in loads per lane");
   const int rg = lane / CPL, cp = lane % CPL;
-  const int64_t lane_off = FWD ? (int64_t(rg) * NB + 16 * w + VEC * cp) : (int64_t(16 * w + lr) * NB + VEC * lc);
-  constexpr int64_t STEP = FWD ? RG * NB : RPI * NB;   // between a lane's consecutive loads
+  const int64_t lane_off =
+      (FWD && !ROWL) ? (int64_t(rg) * NB + 16 * w + VEC * cp) : (int64_t(16 * w + lr) * NB + VEC * lc);
+  constexpr int64_t STEP = (FWD && !ROWL) ? RG * NB : RPI * NB;   // between a lane's consecutive loads
+  const int xcol = ROWL ? VEC * lc : 16 * w + VEC * cp;             // forward: first column of a lane's x values
   const T* tiles = reinterpret_cast<const T*>(A.tiles);
   const T* dinv = reinterpret_cast<const T*>(A.dinv);
   T* sol = reinterpret_cast<T*>(A.sol);
@@ -983,7 +991,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
         const T* ys = my_sol + sol_row(jj) * NB;
         T xv[FWD ? VEC : NI];
         if (FWD) {
-          for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + 16 * w + VEC * cp + e, A.spin, A.werr);
+          for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + xcol + e, A.spin, A.werr);
         } else {
           for (int i = 0; i < NI; ++i) xv[i] = poll_published(ys + 16 * w + RPI * i + lr, A.spin, A.werr);
         }
@@ -1002,7 +1010,13 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
       }
     }
     // reduce partial sums into s_red
-    if (FWD) {
+    if (ROWL) {
+      for (int i = 0; i < NI; ++i) {
+        T v = acc[i];
+        for (int off = 1; off < LPR; off <<= 1) v += __shfl_xor(v, off, LPR);
+        if (lc == 0) s_red[w][16 * w + RPI * i + lr] = v;
+      }
+    } else if (FWD) {
       for (int i = 0; i < NI; ++i) {
         T v = acc[i];
         for (int off = 1; off < CPL; off <<= 1) v += __shfl_xor(v, off, CPL);
@@ -1017,14 +1031,21 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     }
     __syncthreads();
     if (tid < NB) {
-      T red = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
+      T red = ROWL ? s_red[tid >> 4][tid] : s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
       s_v[tid] = (k * NB + tid >= nlo && k * NB + tid < nlim) ? (s_rhs[tid] - red) : T(0);
     }
     __syncthreads();
 
     // ---------------- diagonal block: multiply by the inverse tile ----------------
     {
-      if (FWD) {
+      if (ROWL) {
+        for (int i = 0; i < NI; ++i) {
+          T v = T(0);
+          for (int e = 0; e < VEC; ++e) v += dv[i][e] * s_v[VEC * lc + e];
+          for (int off = 1; off < LPR; off <<= 1) v += __shfl_xor(v, off, LPR);
+          if (lc == 0) s_red[w][16 * w + RPI * i + lr] = v;
+        }
+      } else if (FWD) {
         for (int i = 0; i < NI; ++i) {
           T v = T(0);
           for (int e = 0; e < VEC; ++e) v += dv[i][e] * s_v[16 * w + VEC * cp + e];
@@ -1044,7 +1065,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
       }
       __syncthreads();
       if (tid < NB) {
-        T o = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
+        T o = ROWL ? s_red[tid >> 4][tid] : s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
         if (k * NB + tid >= nlim || k * NB + tid < nlo) o = T(0);
         s_out[tid] = o;
         store_published(my_sol + k * NB + tid, o);
@@ -1106,6 +1127,7 @@ __global__ __launch_bounds__(256, 2) void trsv2_kernel(TrsvArgs A) {
   constexpr int RPI = 64 / LPR;
   constexpr int NI = 16 / RPI;
   constexpr bool FWD = MODE == TRSV_FWD_II;
+  constexpr bool ROWL = FWD && sizeof(T) == 4;   // FP32 forward: a wave owns 16 whole rows, as in trsv_kernel
   static_assert(MODE == TRSV_FWD_II || MODE == TRSV_BWD_II, "interior passes only");
   constexpr int CPL = 16 / VEC, RG = 64 / CPL;
   constexpr int NACC = FWD ? NI : VEC;
@@ -1121,8 +1143,10 @@ __global__ __launch_bounds__(256, 2) void trsv2_kernel(TrsvArgs A) {
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int lr = lane / LPR, lc = lane % LPR;
   const int rg = lane / CPL, cp = lane % CPL;
-  const int64_t lane_off = FWD ? (int64_t(rg) * NB + 16 * w + VEC * cp) : (int64_t(16 * w + lr) * NB + VEC * lc);
-  constexpr int64_t STEP = FWD ? RG * NB : RPI * NB;
+  const int64_t lane_off =
+      (FWD && !ROWL) ? (int64_t(rg) * NB + 16 * w + VEC * cp) : (int64_t(16 * w + lr) * NB + VEC * lc);
+  constexpr int64_t STEP = (FWD && !ROWL) ? RG * NB : RPI * NB;
+  const int xcol = ROWL ? VEC * lc : 16 * w + VEC * cp;   // forward: first column of a lane's x values
   const T* tiles = reinterpret_cast<const T*>(A.tiles);
   const T* dinv = reinterpret_cast<const T*>(A.dinv);
   T* sol = reinterpret_cast<T*>(A.sol);
@@ -1290,7 +1314,7 @@ __global__ __launch_bounds__(256, 2) void trsv2_kernel(TrsvArgs A) {
       const T* ys = my_sol + j * NB;
       T xv[FWD ? VEC : NI];
       if (FWD) {
-        for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + 16 * w + VEC * cp + e, A.spin, A.werr);
+        for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + xcol + e, A.spin, A.werr);
       } else {
         for (int i = 0; i < NI; ++i) xv[i] = poll_published(ys + 16 * w + RPI * i + lr, A.spin, A.werr);
       }
@@ -1306,7 +1330,13 @@ __global__ __launch_bounds__(256, 2) void trsv2_kernel(TrsvArgs A) {
     // side, multiply by the inverse diagonal tile, publish, write the output
     auto finish = [&](int q, int k, const T (&acc)[NACC]) {
       const V (&dvq)[NI][256] = s_dv[q];
-      if (FWD) {
+      if (ROWL) {
+        for (int i = 0; i < NI; ++i) {
+          T v = acc[i];
+          for (int off = 1; off < LPR; off <<= 1) v += __shfl_xor(v, off, LPR);
+          if (lc == 0) s_red[w][16 * w + RPI * i + lr] = v;
+        }
+      } else if (FWD) {
         for (int i = 0; i < NI; ++i) {
           T v = acc[i];
           for (int off = 1; off < CPL; off <<= 1) v += __shfl_xor(v, off, CPL);
@@ -1321,11 +1351,19 @@ __global__ __launch_bounds__(256, 2) void trsv2_kernel(TrsvArgs A) {
       }
       __syncthreads();
       if (tid < NB) {
-        const T red = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
+        const T red = ROWL ? s_red[tid >> 4][tid] : s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
         s_v[tid] = k * NB + tid < nlim ? (s_rhs[q][tid] - red) : T(0);
       }
       __syncthreads();
-      if (FWD) {
+      if (ROWL) {
+        for (int i = 0; i < NI; ++i) {
+          const V d = dvq[i][tid];
+          T v = T(0);
+          for (int e = 0; e < VEC; ++e) v += d[e] * s_v[VEC * lc + e];
+          for (int off = 1; off < LPR; off <<= 1) v += __shfl_xor(v, off, LPR);
+          if (lc == 0) s_red[w][16 * w + RPI * i + lr] = v;
+        }
+      } else if (FWD) {
         for (int i = 0; i < NI; ++i) {
           T v = T(0);
           const V d = dvq[i][tid];
@@ -1348,7 +1386,7 @@ __global__ __launch_bounds__(256, 2) void trsv2_kernel(TrsvArgs A) {
       }
       __syncthreads();
       if (tid < NB) {
-        T o = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
+        T o = ROWL ? s_red[tid >> 4][tid] : s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
         if (k * NB + tid >= nlim) o = T(0);
         s_out[tid] = o;
         store_published(my_sol + k * NB + tid, o);
@@ -1370,7 +1408,7 @@ __global__ __launch_bounds__(256, 2) void trsv2_kernel(TrsvArgs A) {
         // the first row's block, from LDS
         T xv[FWD ? VEC : NI];
         if (FWD) {
-          for (int e = 0; e < VEC; ++e) xv[e] = s_out[16 * w + VEC * cp + e];
+          for (int e = 0; e < VEC; ++e) xv[e] = s_out[xcol + e];
         } else {
           for (int i = 0; i < NI; ++i) xv[i] = s_out[16 * w + RPI * i + lr];
         }
