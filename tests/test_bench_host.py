@@ -64,3 +64,22 @@ def test_envelope_bytes_never_exceed_dense_tiles():
         e = bench.algorithmic_bytes(w, lb)
         for f in bench.FULL_FAMILIES:
             assert d[f] >= e[f] - sum(nR * 64 * lb for nR, _, _, _ in sizes)
+
+
+def test_traffic_records_are_consistent():
+    """profiles/traffic.txt: every record's calibrated bytes follow from its two
+    counter readings and factors, and bench.py finds a record only when it was
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    rows = [ln.split() for ln in open(path).read().splitlines() if ln and not ln.startswith("#")]
+    assert rows
+    keys = set()
+    for key, sha, b, fk, wk, ff, wf in rows:
+        assert key not in keys
+        keys.add(key)
+        assert len(sha) == 16 and all(c in "0123456789abcdef" for c in sha)
+        assert abs(int(b) - (float(fk) * 1024 * float(ff) + float(wk) * 1024 * float(wf))) <= 2e-4 * int(b) + 1024
+        assert 1.9 < float(ff) < 2.1 and 0.95 < float(wf) < 1.05
+        workload, bits, kernel = key.split("/")
+        got = bench.load_traffic(kernel, workload, int(bits))
+        assert got == (int(b) if sha == bench.kernel_hash() else None)
