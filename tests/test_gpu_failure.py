@@ -5,6 +5,8 @@ still finishes normally:
   the kernels use 0 for the missing value and mark the ctx's device status
   word; bddc_sync and bddc_pcg_solve report BDDC_EHIP and clear the word, and
   with the default limit the same ctx gives oracle-exact results again;
+* a grid barrier of the coarse CG over 64 workgroups that gives up (same limit,
+  on a case whose triangular passes have no waits): BDDC_EHIP, then recovery;
 * a coarse CG that stops at its iteration limit: BDDC_ENOCONV from the solve;
 * a non-positive or non-finite conductivity given in device memory (the host
   cannot check it): the device check makes bddc_setup return BDDC_ENOTSPD, and
@@ -81,6 +83,25 @@ def test_wait_give_up_is_reported(oracle8, full_space):
     assert np.abs(z.cpu().numpy() - zo).max() <= 1e-10 * np.abs(zo).max()
     x, info = S.solve(dev(w.b), w.rtol)
     assert info["relres_true"] <= w.rtol
+    S.close()
+
+
+def test_coarse_cg_grid_barrier_give_up_is_reported():
+    # 8x8x8 boxes of 3^3 elements: one tile row per factor and interior (no
+    # published-value waits), n_c = 2863 (the coarse CG runs over 64 workgroups)
+    w = W.make_workload("t", 3, (24, 24, 24), (8, 8, 8), theta="lognormal", seed=19)
+    P = O.BDDC(w.dim, w.nel, w.cuts, w.theta, w.constraints)
+    assert P.n_coarse == 2863
+    bddc = bd()
+    S = bddc.solver_for(w, coarse_cg=True)
+    S.set_limit("wait_polls", -1)
+    with pytest.raises(bddc.BDDCError) as e:
+        S.solve(dev(w.b), w.rtol)
+    assert e.value.code == EHIP
+    S.set_limit("wait_polls", 1 << 22)
+    x, info = S.solve(dev(w.b), w.rtol)
+    ref = O.bddc_pcg(P, w.b, w.rtol)
+    assert abs(info["iters"] - ref.iters) <= 1 and info["relres_true"] <= w.rtol
     S.close()
 
 

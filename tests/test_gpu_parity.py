@@ -87,6 +87,10 @@ CASES = {
                                                       theta="inclusions", seed=17),
     # 576 boxes of 3x3 elements: n_c = 1633, more coarse unknowns than the coarse CG keeps in LDS
     "2d_72_24x24_many": lambda: W.make_workload("t", 2, (72, 72), (24, 24), theta="lognormal", seed=5),
+    # 8x8x8 boxes of 3^3 elements: the coarse space of the 128^3 workload (n_c = 2863, the
+    # coarse CG split over 64 workgroups) on a mesh the oracle solves in seconds
+    "3d_24_8x8x8_boxes_of_3": lambda: W.make_workload("t", 3, (24, 24, 24), (8, 8, 8), theta="lognormal",
+                                                      seed=19),
 }
 
 _oracles = {}
@@ -422,7 +426,7 @@ def test_rho_scaling_matches_oracle(name, full_space):
 
 @pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
 @pytest.mark.parametrize("name", ["2d_64_4x4_theta1", "3d_12x10x14_uneven", "3d_24_3x3x3_inclusions",
-                                  "2d_72_24x24_many"])
+                                  "2d_72_24x24_many", "3d_24_8x8x8_boxes_of_3"])
 def test_coarse_cg_matches_oracle(name, full_space):
     """The coarse problem by CG (the paper's choice) to a relative residual of
     1e-13: the oracle's preconditioner (exact coarse solve) to 1e-10, the same
