@@ -344,6 +344,25 @@ def test_graph_replays_match_eager(full_space):
     Sg.close()
 
 
+@pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
+def test_graph_replays_match_eager_with_coarse_cg_grid(full_space):
+    """The coarse CG over 64 workgroups (n_c = 2863) inside captured graphs: its
+    barrier words are reset by a fill kernel in every replay, and every replay
+    gives the bits of the eager solve."""
+    w, P = oracle_for("3d_24_8x8x8_boxes_of_3")
+    Se = bd().solver_for(w, full_space=full_space, coarse_cg=True)
+    Sg = bd().solver_for(w, full_space=full_space, coarse_cg=True, use_graph=True)
+    x, info = Se.solve(dev(w.b), w.rtol)
+    xr, itr = host(x), info["iters"]
+    for rep in range(3):
+        x, info = Sg.solve(dev(w.b), w.rtol)
+        Se.apply(dev(w.b))                        # eager work between replays
+        assert info["iters"] == itr
+        assert np.array_equal(host(x), xr), rep
+    Se.close()
+    Sg.close()
+
+
 def test_kernel_timing_with_graph_solver():
     """Timing switches a graph-replaying solver to eager launches."""
     w, P = oracle_for("3d_16_2x2x2")
