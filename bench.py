@@ -359,6 +359,33 @@ def cpu_baseline(w_full, full_iters, workers=None):
                       f"for iterations"}
 
 
+def copy_bandwidth(torch):
+    """HBM bandwidth of plain streams on this GPU (GB/s), measured ceilings
+    beside the datasheet peak: a device copy (bytes read plus bytes written)
+    and a read-only sum (bytes read)."""
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+
+    def timed(fn):
+        fn()
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        return float(np.median(ts))
+
+    copy = 2 * n * 8 / timed(lambda: dst.copy_(src)) / 1e9
+    read = n * 8 / timed(lambda: src.sum()) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return copy, read
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -399,6 +426,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    # (not in counter runs, whose calibration copy must be the only large copy)
+    copy_gbs, read_gbs = (None, None) if args.copy_calibration else copy_bandwidth(torch)
     w = W.WORKLOADS[args.workload]()
     golden = load_golden(args.workload)
     print(f"[bench] workload {w.name}: n_free {w.n_free}, {int(np.prod(w.nsub))} subdomains", file=sys.stderr,
@@ -469,6 +498,8 @@ def main():
         achieved = algo[dom] / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None,
+                "frac_of_read": round(achieved / read_gbs, 4) if read_gbs else None,
                 "traffic": load_traffic(dom, args.workload, bits),
                 "bytes_per_launch": algo[dom], "avg_launch_ms": round(avg_s * 1e3, 4), "launches": n_l}
         # bytes every family streams per solve (launch counts of the timed run)
@@ -509,6 +540,11 @@ def main():
         out[k] = m[k]
     out["timed"] = timed = summarize(runs["timed"], main_bits)
     out["roofline_measured_in"] = "timed run: the same solves with dispatch-recorded events around the kernels"
+    out["stream_bandwidth"] = None if copy_gbs is None else {
+        "copy_GBps": round(copy_gbs, 1), "read_GBps": round(read_gbs, 1),
+        "how": "1 GiB FP64 device-to-device copy (bytes read plus written per second) and read-only sum "
+               "(bytes read per second), median of 5 each; roofline.frac_of_copy and frac_of_read are "
+               "achieved over these"}
     for k in ["applies_per_s", "kernel_ms", "kernel_hbm_frac", "bytes_per_solve", "solve_hbm_frac"]:
         out[k] = timed[k]
     out["roofline"] = timed["roofline"]

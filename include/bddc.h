@@ -90,14 +90,16 @@ enum { BDDC_SETUP_FULL_SPACE = 2 };
 enum { BDDC_SETUP_RHO_SCALING = 4 };
 
 /* Setup option flag: solve the coarse problem of eq. (2) by CG, as the paper
- * does (Sec. 2), instead of the dense FP64 Cholesky factor (whole space) or its
- * explicit inverse (interface form): CG on the assembled A_c with its diagonal
- * as preconditioner (the paper's CG is unpreconditioned), from zero to a
- * relative residual of 1e-13 (at most 2000 iterations), in one workgroup at
- * every application of the preconditioner.  No dense coarse factor or inverse
- * is formed; A_c is checked for a positive diagonal only, and a coarse matrix
- * that is not positive definite ends that inner CG early instead of failing
- * setup.  The explicit forms are faster on one GPU. */
+ * does (Sec. 2), instead of the explicit inverse of its dense FP64 Cholesky
+ * factor: CG on the assembled A_c with its diagonal as preconditioner (the
+ * paper's CG is unpreconditioned), from zero to a relative residual of 1e-13
+ * (at most 2000 iterations) at every application of the preconditioner, in one
+ * workgroup when A_c and the CG vectors fit its LDS, else with the rows of A_c
+ * split over 64 workgroups that meet at grid barriers (their waits are bounded
+ * by the "wait_polls" limit of bddc_set_limit).  No dense coarse factor or
+ * inverse is formed; A_c is checked for a positive diagonal only, and a coarse
+ * matrix that is not positive definite ends that inner CG early instead of
+ * failing setup.  The explicit inverse is faster on one GPU. */
 enum { BDDC_SETUP_COARSE_CG = 8 };
 
 /* Solve flags. */
@@ -259,9 +261,11 @@ int64_t bddc_debug_read(bddc_ctx* ctx, const char* what, int32_t sub, double* ho
 
 /* Device-side limits, mainly for tests of the failure paths:
  *   "wait_polls"      polls of a published value before a triangular-solve task
- *                     gives up (default 4194304, about a second); the task then
- *                     uses 0, finishes normally and marks the ctx's device status
- *                     word; a negative value makes every wait give up at once;
+ *                     gives up, and polls of a grid barrier of the coarse CG
+ *                     over 64 workgroups (default 4194304, about a second); the
+ *                     task then uses 0 (the coarse CG stops), finishes normally
+ *                     and marks the ctx's device status word; a negative value
+ *                     makes every wait give up at once;
  *   "coarse_cg_maxit" iteration limit of the coarse CG (BDDC_SETUP_COARSE_CG,
  *                     default 2000); a coarse CG that stops at it (or breaks
  *                     down) marks the device status word.
@@ -272,9 +276,9 @@ int64_t bddc_debug_read(bddc_ctx* ctx, const char* what, int32_t sub, double* ho
 int bddc_set_limit(bddc_ctx* ctx, const char* what, int32_t value);
 
 /* Waits for all work queued on the ctx stream and reports the device status
- * word since it was last reported: OK, EHIP (a triangular-solve wait gave up,
- * e.g. in an asynchronous bddc_apply) or ENOCONV (the coarse CG did not
- * converge); the word is cleared. */
+ * word since it was last reported: OK, EHIP (a triangular-solve wait or a
+ * coarse-CG grid barrier gave up, e.g. in an asynchronous bddc_apply) or
+ * ENOCONV (the coarse CG did not converge); the word is cleared. */
 int bddc_sync(bddc_ctx* ctx);
 
 /* Launch shape of the persistent kernels (triangular solves and tile

@@ -163,7 +163,7 @@ struct bddc_ctx {
   void* pub_local = nullptr;   // 4 * n_vec entries of the local precision
   unsigned* tickets = nullptr;
   int* fready = nullptr;            // per tile ready words of the persistent factorisation
-  int wait_polls = 1 << 22;         // polls of a published value before a solve task gives up
+  int wait_polls = 1 << 22;         // polls of a published value (or a coarse-CG grid barrier) before a wait gives up
   int coarse_maxit = COARSE_CG_MAXIT;
   unsigned* fticket = nullptr;
   void* static_scratch = nullptr;   // this device's fixed workspace (bddc_apply_noalloc)
