@@ -135,7 +135,7 @@ void launch_coarse_assembly(const int32_t* src_ptr, const int32_t* src, const in
 void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st, hipEvent_t t0 = nullptr,
                  hipEvent_t t1 = nullptr);
 // interior passes (TRSV_FWD_II, TRSV_BWD_II; launch_trsv routes them here): two
-// tile rows per task, one workgroup per CU
+// tile rows per task, two workgroups per CU
 void launch_trsv2(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t st, hipEvent_t t0 = nullptr,
                   hipEvent_t t1 = nullptr);
 void launch_coarse_prep(const MatDesc* mats, int nmats, const double* part, const double* sainv,
