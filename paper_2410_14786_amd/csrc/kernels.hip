@@ -2029,24 +2029,45 @@ void launch_trailing_inverse(const MatDesc* mats, int nmats, int maxTG, const do
     hipLaunchKernelGGL(trailing_inverse_kernel, dim3(ii + 1, nmats), dim3(256), 0, st, mats, tiles, dinv, xg, ii);
 }
 
-// Explicit coarse inverse for the interface iteration: A_c^{-1} = D X^T X D with
-// X = L_c^{-1} (L_c the Cholesky factor of the equilibrated D A_c D), row-major dense.
-__global__ void coarse_inverse_kernel(const double* xg, const double* dc, int nc, double* ainv) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  if (j >= nc) return;
-  double v = 0.0;
-  for (int k = max(i, j); k < nc; ++k) {
-    const double* ti = xg + (tri_tile(k / NB, i / NB)) * int64_t(NB * NB) + (k % NB) * NB;
-    const double* tj = xg + (tri_tile(k / NB, j / NB)) * int64_t(NB * NB) + (k % NB) * NB;
-    v += ti[i % NB] * tj[j % NB];
+// Explicit coarse inverse: A_c^{-1} = D X^T X D with X = L_c^{-1} (L_c the
+// Cholesky factor of the equilibrated D A_c D, X lower triangular in tiles, the
+// diagonal tiles with zeros above the diagonal), row-major dense.  One workgroup
+// per output tile (I, J): the sum over K >= max(I, J) of X(K, I)^T X(K, J) on
+// MFMA, both tiles transposed into LDS.
+__global__ __launch_bounds__(256) void coarse_inverse_kernel(const double* xg, const double* dc, int nc,
+                                                             double* ainv) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  const int Tc = (nc + NB - 1) / NB;
+  __shared__ double sa[NB * LDT];
+  __shared__ double sb[NB * LDT];
+  d4v acc[2][2];
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q) acc[p][q] = d4v(0);
+  for (int K = max(I, J); K < Tc; ++K) {
+    __syncthreads();
+    const double* a = xg + tri_tile(K, I) * int64_t(NB * NB);
+    const double* b = xg + tri_tile(K, J) * int64_t(NB * NB);
+    for (int e = threadIdx.x; e < NB * NB; e += 256) {
+      sa[(e % NB) * LDT + (e / NB)] = a[e];   // X(K, I)^T
+      sb[(e % NB) * LDT + (e / NB)] = b[e];   // X(K, J)^T: gemm_nt gives X(K, I)^T X(K, J)
+    }
+    __syncthreads();
+    gemm_nt_tile<double>(sa, sb, acc);
   }
-  ainv[int64_t(i) * nc + j] = dc[i] * v * dc[j];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q)
+      for (int it = 0; it < 4; ++it) {
+        const int i = I * NB + r0 + 16 * p + Acc4<double>::row(lane, it), j = J * NB + c0 + 16 * q + (lane & 15);
+        if (i < nc && j < nc) ainv[int64_t(i) * nc + j] = dc[i] * acc[p][q][it] * dc[j];
+      }
 }
 
 void launch_coarse_inverse(const double* xg, const double* dc, int nc, double* ainv, hipStream_t st) {
   if (nc <= 0) return;
-  hipLaunchKernelGGL(coarse_inverse_kernel, dim3((nc + 255) / 256, nc), dim3(256), 0, st, xg, dc, nc, ainv);
+  const int Tc = (nc + NB - 1) / NB;
+  hipLaunchKernelGGL(coarse_inverse_kernel, dim3(Tc, Tc), dim3(256), 0, st, xg, dc, nc, ainv);
 }
 
 constexpr int CG_RW = 8;   // rows of A_c^{-1} per wave of the coarse GEMV
