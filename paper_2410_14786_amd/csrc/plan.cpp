@@ -342,15 +342,18 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
       {
         // the tile operations the factorisation runs: tile (i, k) is zero when
         // k < fc[i] (the bordering row T, if any, is dense)
+        // (per column k: a panel solve for every nonzero tile (i, k), a diagonal
+        // update of (i, i) and an off-diagonal update of (i, j) for every nonzero
+        // (j, k) with k < j < i, counted by a running total over i)
         const double b3 = double(NB) * NB * NB;
         auto nz = [&](int i, int k) { return i >= D.T || fc[i] <= k; };
         for (int k = 0; k < D.T; ++k) {
           P.factor_flops += b3 / 3.0;
+          int64_t above = 0;   // nonzero tiles (j, k), k < j < i
           for (int i = k + 1; i < D.Tx; ++i) {
             if (!nz(i, k)) continue;
-            P.factor_flops += b3;
-            for (int j = k + 1; j <= i; ++j)
-              if (nz(j, k)) P.factor_flops += j == i ? b3 : 2.0 * b3;
+            P.factor_flops += b3 + b3 + 2.0 * b3 * double(above);
+            ++above;
           }
         }
       }

@@ -7,6 +7,7 @@
 // stdin, one case per line:  dim nel0 nel1 nel2 constraints n0 cuts0... n1 cuts1... n2 cuts2...
 //   (n_a cut positions per axis, 0 ... nel_a; nel2 = 1 and n2 = 2 "0 1" in 2D)
 // stdout, per case: status n_free n_sub n_coarse sum_ni max_nci n_tiles factor_tasks
+#include <cmath>
 #include <cstdio>
 #include <iostream>
 #include <sstream>
@@ -59,6 +60,29 @@ int main() {
       if (!ok) {
         std::fprintf(stderr, "envelope storage check failed\n");
         return 3;
+      }
+      // the factorisation flop count, by enumerating every tile update: for
+      // each column k, a diagonal factorisation, then for every nonzero (i, k)
+      // a panel solve and, for every nonzero (j, k) with k < j <= i, the update
+      // of tile (i, j) (diagonal: one tile product, off-diagonal: two)
+      double flops = 0.0;
+      const double b3 = double(bddc::NB) * bddc::NB * bddc::NB;
+      for (auto& D : P.subs) {
+        auto nz = [&](int i, int k) { return i >= D.T || D.env[i].fc <= k; };
+        for (int k = 0; k < D.T; ++k) {
+          flops += b3 / 3.0;
+          for (int i = k + 1; i < D.Tx; ++i) {
+            if (!nz(i, k)) continue;
+            flops += b3;
+            for (int j = k + 1; j <= i; ++j)
+              if (nz(j, k)) flops += j == i ? b3 : 2.0 * b3;
+          }
+        }
+      }
+      if (std::abs(flops - P.factor_flops) > 1e-12 * flops) {
+        std::fprintf(stderr, "factorisation flop count %.17g differs from the enumeration %.17g\n",
+                     P.factor_flops, flops);
+        return 4;
       }
     }
     std::printf("%d %lld %d %d %lld %d %lld %lld\n", rc, (long long)P.n_free, P.nsubs, P.n_coarse,
