@@ -44,8 +44,10 @@ extern "C" {
 typedef enum {
   BDDC_OK = 0,
   BDDC_EINVAL = -1,      /* bad dimension, sizes, cuts, pointers or options      */
-  BDDC_ENOTSPD = -2,     /* theta <= 0, or a non-positive pivot in a local or
-                            the coarse Cholesky factor                            */
+  BDDC_ENOTSPD = -2,     /* theta <= 0, a non-positive pivot in a local or the
+                            coarse Cholesky factor, or a box that touches no
+                            Dirichlet boundary while corner constraints are off
+                            (its A_RR is singular; found by the planner)          */
   BDDC_ENOMEM = -3,      /* device or host allocation failed                      */
   BDDC_EHIP = -4,        /* a HIP runtime call failed                             */
   BDDC_ENOCONV = -5,     /* maxit reached; x and info are still filled            */

@@ -233,6 +233,19 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
       err = "a subdomain has more than 64 constraints";
       return BDDC_ENOTIMPL;
     }
+    // A_RR is factored by Cholesky.  For a box that touches no Dirichlet
+    // boundary (every face an interior cut) it is the Neumann matrix of the box
+    // minus its corner nodes: singular when no corner is a primal constraint
+    // (and SPD otherwise, or when any box node is a Dirichlet node)
+    {
+      bool floating = true;
+      for (int a = 0; a < dim; ++a) floating = floating && lo[a] > 0 && lo[a] + len[a] < P.nel[a];
+      if (floating && D.n_P == 0) {
+        err = "subdomain " + std::to_string(s) + " touches no Dirichlet boundary and has no corner constraints, so "
+              "its A_RR is singular (add BDDC_CORNERS)";
+        return BDDC_ENOTSPD;
+      }
+    }
     P.max_nci = std::max(P.max_nci, int(D.n_ci));
     D.loc_off = loc_off;
     D.lmap_off = int32_t(lmap_off);

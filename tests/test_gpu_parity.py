@@ -76,6 +76,11 @@ CASES = {
                                                   constraints=W.CORNERS | W.EDGES),
     "3d_8_corners_only": lambda: W.make_workload("t", 3, (8, 8, 8), (2, 2, 2), theta="lognormal", seed=8,
                                                  constraints=W.CORNERS),
+    # no corner constraints (every box touches the Dirichlet boundary, so A_RR is
+    # SPD): the centre node is an interface dof of R, the coarse space holds
+    # only edge and face averages
+    "3d_8_edges_faces": lambda: W.make_workload("t", 3, (8, 8, 8), (2, 2, 2), theta="lognormal", seed=9,
+                                                constraints=W.EDGES | W.FACES),
     # boxes of 8 and 24 elements per side (the extremes of the 128^3 workload's box
     # lengths), inclusions; the middle box has 15 625 dofs, 216 factor tile rows
     # and 3458 interface rows (55 tile rows of interface matrix), all six faces shared

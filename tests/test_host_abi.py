@@ -137,3 +137,22 @@ def test_too_many_constraints_not_implemented(lib):
     with pytest.raises(bddc.BDDCError) as e:
         bddc.plan_stats(3, (16, 16, 16), [[0, 8, 16]] * 3, W.ALL_PRIMAL)
     assert e.value.code == bddc.ENOTIMPL
+
+
+def test_floating_box_without_corners_is_rejected(lib):
+    """A box that touches no Dirichlet boundary needs corner constraints: its
+    A_RR (the box's Neumann matrix minus the corner nodes) is singular otherwise.
+    The planner rejects it before any device work; partitions in which every
+    box touches the boundary plan without corners."""
+    with pytest.raises(bddc.BDDCError) as e:
+        bddc.plan_stats(3, (12, 12, 12), [[0, 4, 8, 12]] * 3, W.EDGES | W.FACES)
+    assert e.value.code == bddc.ENOTSPD and "corner" in str(e.value)
+    with pytest.raises(bddc.BDDCError) as e:
+        bddc.plan_stats(2, (12, 12), [[0, 4, 8, 12]] * 2, W.EDGES)
+    assert e.value.code == bddc.ENOTSPD
+    # no floating box: every box of a 2x2x2 partition touches the boundary
+    st = bddc.plan_stats(3, (8, 8, 8), [[0, 4, 8]] * 3, W.EDGES | W.FACES)
+    assert st["n_sub"] == 8 and st["corners"] == 1
+    # corners present: the middle box of 3x3x3 is fine
+    st = bddc.plan_stats(3, (12, 12, 12), [[0, 4, 8, 12]] * 3, W.CORNERS | W.EDGES | W.FACES)
+    assert st["n_sub"] == 27
