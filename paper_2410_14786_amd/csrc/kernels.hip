@@ -41,6 +41,17 @@ __device__ __forceinline__ V stream_load(const V* p) {
 // 16 columns, each 64 rows x 16 columns row-major (64 bytes per row).
 __host__ __device__ __forceinline__ int sym_f32_off(int r, int c) { return (c >> 4) * (NB * 16) + r * 16 + (c & 15); }
 
+// read-only data that is uniform per wave: scalar loads
+typedef __attribute__((address_space(4))) const int32_t cint32_t;
+// env_tile with the row's envelope entry (fc, rd) read by scalar loads (i uniform)
+__device__ __forceinline__ int64_t env_tile_s(const MatDesc& D, int i, int j) {
+  if (i >= D.T) return D.tile_off + D.tb + j;
+  if (D.env == nullptr) return D.tile_off + tri_tile(i, j);
+  static_assert(sizeof(EnvRow) == 2 * sizeof(int32_t), "EnvRow is (fc, rd)");
+  const cint32_t* e = (const cint32_t*)(D.env + i);
+  return j < e[0] ? D.ztile : D.tile_off + e[1] + j;
+}
+
 template <typename T> struct Traits;
 template <> struct Traits<double> {
   using U = unsigned long long;
@@ -82,6 +93,24 @@ __device__ __forceinline__ T poll_published(const T* p, int spin, int* werr) {
   }
   atomicOr(werr, DEV_WAIT_GAVE_UP);
   return T(0);
+}
+
+// A lane's N published values v[i] = p[base + i * stride] in two steps, so that
+// their round trips overlap each other and the loads issued in between (the
+// next tile): issue_published sends every load, resolve_published then tests
+// them all and waits, one at a time, only for values still holding the
+// sentinel (with poll_published's bound and give-up).
+template <typename T, int N>
+__device__ __forceinline__ void issue_published(T (&v)[N], const T* base, int stride) {
+  for (int i = 0; i < N; ++i) v[i] = load_published(base + i * stride);
+}
+template <typename T, int N>
+__device__ __forceinline__ void resolve_published(T (&v)[N], const T* base, int stride, int spin, int* werr) {
+  bool miss = spin < 0;
+  for (int i = 0; i < N; ++i) miss |= is_sentinel(v[i]);
+  if (miss)
+    for (int i = 0; i < N; ++i)
+      if (spin < 0 || is_sentinel(v[i])) v[i] = poll_published(base + i * stride, spin, werr);
 }
 
 template <typename T>
@@ -974,12 +1003,18 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
     const int b0 = list ? A.bptr[D.vec_off / NB + k] : 0;
     const int nt = FWD ? k - jlo : (list ? A.bptr[D.vec_off / NB + k + 1] - b0 : jhi - k);
     if (nt > 0) {
-      auto sol_row = [&](int jj) -> int { return FWD ? jlo + jj : (list ? int(A.brows[b0 + jj]) : jhi - jj); };
+      // the backward row list is uniform per wave and read-only: scalar loads
+      // (constant address space), which a wait for the polled values or the
+      // tiles in flight does not include
+      const cint32_t* lrow = (const cint32_t*)(A.brows) + b0;
+      const cint32_t* ltil = (const cint32_t*)(A.btile) + b0;
+      auto sol_row = [&](int jj) -> int { return FWD ? jlo + jj : (list ? int(lrow[jj]) : jhi - jj); };
       const int64_t ok = FWD ? row_origin(D, k) : 0;
       auto tile_ptr = [&](int jj) -> const T* {
         // forward: tile (k, jlo + jj), jj = 0..k-jlo-1, along the stored row; backward:
         // tile (j, k) of the listed rows j (its index is listed too), or j = jhi .. k+1
-        const int64_t t = FWD ? ok + jlo + jj : (list ? D.tile_off + A.btile[b0 + jj] : env_tile(D, jhi - jj, k));
+        const int64_t t =
+            FWD ? ok + jlo + jj : (list ? D.tile_off + ltil[jj] : env_tile_s(D, jhi - jj, k));
         return tiles + t * int64_t(NB * NB) + lane_off;
       };
       V cur[NI], nxt[NI];
@@ -988,17 +1023,23 @@ __global__ __launch_bounds__(256) void trsv_kernel(TrsvArgs A) {
         for (int i = 0; i < NI; ++i) cur[i] = stream_load(reinterpret_cast<const V*>(p + i * STEP));
       }
       for (int jj = 0; jj < nt; ++jj) {
+        // the block's values are requested first, then the next tile; the wait
+        // for the values leaves the next tile's loads in flight
         const T* ys = my_sol + sol_row(jj) * NB;
-        T xv[FWD ? VEC : NI];
-        if (FWD) {
-          for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + xcol + e, A.spin, A.werr);
-        } else {
-          for (int i = 0; i < NI; ++i) xv[i] = poll_published(ys + 16 * w + RPI * i + lr, A.spin, A.werr);
+        const T* xs = FWD ? ys + xcol : ys + 16 * w + lr;
+        constexpr int NX = FWD ? VEC : NI, XS = FWD ? 1 : RPI;
+        T xv[NX];
+        issue_published(xv, xs, XS);
+        {
+          // past the last tile the loads go to one shared address (a single
+          // line), so that every step has the same loads in flight and the
+          // wait for the values below never includes the next tile
+          const bool more = jj + 1 < nt;
+          const T* p = tile_ptr(more ? jj + 1 : jj);
+          for (int i = 0; i < NI; ++i) nxt[i] = stream_load(reinterpret_cast<const V*>(more ? p + i * STEP : tiles));
         }
-        if (jj + 1 < nt) {
-          const T* p = tile_ptr(jj + 1);
-          for (int i = 0; i < NI; ++i) nxt[i] = stream_load(reinterpret_cast<const V*>(p + i * STEP));
-        }
+        __builtin_amdgcn_sched_barrier(0);   // every load above issues before the first test
+        resolve_published(xv, xs, XS, A.spin, A.werr);
         if (FWD) {
           for (int i = 0; i < NI; ++i)
             for (int e = 0; e < VEC; ++e) acc[i] += cur[i][e] * xv[e];
@@ -1174,7 +1215,7 @@ __global__ __launch_bounds__(256, 2) void trsv2_kernel(TrsvArgs A) {
     const int64_t o1 = (FWD && nr == 2) ? row_origin(D, kr1) : 0;
     auto tptr = [&](int k, int j) -> const T* {
       // forward: tile (k, j), j < k; backward: tile (j, k), j > k
-      const int64_t t = FWD ? (k == kr0 ? o0 : o1) + j : env_tile(D, j, k);
+      const int64_t t = FWD ? (k == kr0 ? o0 : o1) + j : env_tile_s(D, j, k);
       return tiles + t * int64_t(NB * NB) + lane_off;
     };
     auto load = [&](const T* p, V (&t)[NI]) {
@@ -1223,7 +1264,7 @@ __global__ __launch_bounds__(256, 2) void trsv2_kernel(TrsvArgs A) {
       et1[q] = ok ? A.itile1[il0 + e] : -1;
     }
     auto ent = [&](const int (&a)[LREG], const int32_t* g, int jj) -> int {
-      if (!lreg) return int(g[il0 + jj]);
+      if (!lreg) return int(((const cint32_t*)g)[il0 + jj]);   // scalar load
       const int q = jj >> 6;
       const int v = q == 0 ? a[0] : q == 1 ? a[1] : q == 2 ? a[2] : a[3];
       return __builtin_amdgcn_readlane(v, jj & 63);
@@ -1306,18 +1347,29 @@ __global__ __launch_bounds__(256, 2) void trsv2_kernel(TrsvArgs A) {
     };
     for (int jj = 0; jj < nt; ++jj) {
       const int j = blk(jj);
-      if (jj + 1 < nt) {
-        const int jn = blk(jj + 1);
-        if (in0(jj + 1, jn)) load(tile0(jj + 1, jn), n0);
-        if (in1(jj + 1, jn)) load(tile1(jj + 1, jn), n1);
-      }
+      // the block's values are requested before the next tiles, so that the
+      // wait for them leaves those loads in flight
       const T* ys = my_sol + j * NB;
-      T xv[FWD ? VEC : NI];
-      if (FWD) {
-        for (int e = 0; e < VEC; ++e) xv[e] = poll_published(ys + xcol + e, A.spin, A.werr);
-      } else {
-        for (int i = 0; i < NI; ++i) xv[i] = poll_published(ys + 16 * w + RPI * i + lr, A.spin, A.werr);
+      const T* xs = FWD ? ys + xcol : ys + 16 * w + lr;
+      constexpr int NX = FWD ? VEC : NI, XS = FWD ? 1 : RPI;
+      T xv[NX];
+      issue_published(xv, xs, XS);
+      {
+        // a tile that is not needed (past the last block, or outside a row's
+        // range) is replaced by loads of one shared address (a single line),
+        // so that every step has the same loads in flight and the wait for the
+        // values below never includes the next tiles
+        const bool more = jj + 1 < nt;
+        const int jm = more ? jj + 1 : jj;
+        const int jn = blk(jm);
+        const bool m0 = more && in0(jm, jn), m1 = more && in1(jm, jn);
+        const T* p0 = m0 ? tile0(jm, jn) : tiles;
+        const T* p1 = m1 ? tile1(jm, jn) : tiles;
+        for (int i = 0; i < NI; ++i) n0[i] = stream_load(reinterpret_cast<const V*>(m0 ? p0 + i * STEP : tiles));
+        for (int i = 0; i < NI; ++i) n1[i] = stream_load(reinterpret_cast<const V*>(m1 ? p1 + i * STEP : tiles));
       }
+      __builtin_amdgcn_sched_barrier(0);   // every load above issues before the first test
+      resolve_published(xv, xs, XS, A.spin, A.werr);
       if (in0(jj, j)) mac(acc0, c0, xv);
       if (in1(jj, j)) mac(acc1, c1, xv);
       for (int i = 0; i < NI; ++i) {
@@ -2677,7 +2729,6 @@ template <> struct SymLayout<float> {
 // operator), and in a diagonal tile the row blocks above wave w's columns.
 // Tile descriptors are uniform per wave and read-only: scalar loads (constant
 // address space), which complete independently of the vector memory counter.
-typedef __attribute__((address_space(4))) const int32_t cint32_t;
 template <typename T>
 __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   using L = SymLayout<T>;
