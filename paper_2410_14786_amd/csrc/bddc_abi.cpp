@@ -1061,8 +1061,9 @@ int bddc_setup(const bddc_mesh* mesh, const bddc_partition* part, const bddc_coe
   c->rho_scaling = (opts->flags & BDDC_SETUP_RHO_SCALING) != 0;
   c->coarse_cg = (opts->flags & BDDC_SETUP_COARSE_CG) != 0;
   c->iface = !(opts->flags & BDDC_SETUP_FULL_SPACE);
-  // the interface mat-vec packs a tile's row distance into 8 bits: at most
-  // IFACE_MAX_TS tile rows per subdomain; larger boxes iterate on the whole space
+  // the interface mat-vec packs a tile's row distance and its column into 8
+  // bits each: at most IFACE_MAX_TS tile rows per subdomain; larger boxes
+  // iterate on the whole space
   for (auto& D : c->plan.subs)
     if (sym_tile_rows(D) > IFACE_MAX_TS) c->iface = false;
   // FP32 local solves: on the whole space the local factors and triangular

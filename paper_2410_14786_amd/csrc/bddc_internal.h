@@ -124,8 +124,9 @@ struct Plan {
   // (64 per row) of the operator (interface and corner dofs) and of the
   // preconditioner (interface dofs), -1 elsewhere
   std::vector<int32_t> symfin, tinfo, padz, padf;
-  // per tile, the rows the mat-vec reads: h | z0 << 8 | z1 << 16 (rows below h
-  // outside [z0, z1)); the operator skips its zero average-constraint rows
+  // per tile, the rows the mat-vec reads and the tile's column jj:
+  // h | z0 << 8 | z1 << 16 | jj << 24 (rows below h outside [z0, z1)); the
+  // operator skips its zero average-constraint rows
   std::vector<int32_t> trows_op, trows_pc;
   int64_t n_symrows = 0;
   // floating-point operations of the batched tile Cholesky inside the envelope

@@ -84,7 +84,8 @@ struct IfaceArgs {
   const void* m;            // symmetric interface matrices, one stream of ntiles tiles
   int m32;                  // their elements: 0 double, 1 float (applied with FP32 accumulation)
   const int32_t* tinfo;     // per tile: (global row << 8) | (ii - jj)
-  const int32_t* trows;     // per tile: rows to read, h | z0 << 8 | z1 << 16 (rows r < h outside [z0, z1))
+  const int32_t* trows;     // per tile: rows to read and column, h | z0 << 8 | z1 << 16 | jj << 24
+                            //   (rows r < h outside [z0, z1))
   int64_t ntiles;
   int nwg;                  // workgroups of the mat-vec launch (its range split)
   const int32_t* tasks;     // finishers: (matrix, row ii)
@@ -222,6 +223,7 @@ void launch_op_finish(const IfaceArgs& a, hipStream_t st);
 void launch_pc_finish(const IfaceArgs& a, hipStream_t st);
 constexpr int COARSE_SPLIT_COLS = 512;   // columns of A_c^{-1} per coarse GEMV block
 constexpr int IFACE_MAX_TS = 255;        // interface form: tile rows of a symmetric interface matrix
+constexpr int SYM_LDS_COLS = 64;         // interface mat-vec: columns whose products a workgroup sums in LDS
 void launch_coarse_inverse(const double* xg, const double* dc, int nc, double* ainv, hipStream_t st);
 void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* cinv_ptr, const int32_t* cinv,
                         const double* gbuf, double* upart, const int* done, hipStream_t st);

@@ -1512,6 +1512,19 @@ void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t s
 // product of every row piece it covers (a piece starts at a row's first tile or
 // at a range start) in rowp[(start tile * 4 + wave) * 64 + row].  This sums the
 // pieces of the row whose len tiles start at tr0, in a fixed order.
+// Workgroup of a mat-vec launch whose range holds tile p: the g with
+// g ntiles / nwg <= p < (g+1) ntiles / nwg (integer division).
+__device__ __forceinline__ int64_t sym_wg(int64_t p, int64_t ntiles, int64_t nwg) {
+  return ((p + 1) * nwg - 1) / ntiles;
+}
+// Whether the slot of tile (i2, jj) holds a column product: for jj <
+// SYM_LDS_COLS only the column's first tile in each workgroup range does (it
+// holds the sum over the range's rows), for the other columns every tile.
+__device__ __forceinline__ bool sym_col_first(const MatDesc& D, int i2, int jj, int64_t ntiles, int64_t nwg) {
+  if (jj >= SYM_LDS_COLS || i2 == jj) return true;
+  return sym_wg(D.sg_off + tri_tile(i2, jj), ntiles, nwg) != sym_wg(D.sg_off + tri_tile(i2 - 1, jj), ntiles, nwg);
+}
+
 __device__ double sym_row_product(const double* rowp, int64_t tr0, int len, int64_t ntiles, int64_t nwg, int lane) {
   double v = 0.0;
   for (int w = 0; w < 4; ++w) v += rowp[(tr0 * 4 + w) * NB + lane];
@@ -2717,16 +2730,22 @@ template <> struct SymLayout<float> {
 // barriers, nothing staged): every tile (ii, jj) is read once and used twice,
 // for the row product sum_jj M(ii, jj) v_jj (kept in registers along a row
 // piece and stored per piece and wave, see sym_row_product) and the column
-// product M(ii, jj)^T v_ii (stored at the tile's slot in part).  A diagonal tile
-// counts its lower triangle in the row product and its strict lower triangle in
-// the column product.  Output row k of a subdomain is then its row product plus
-// the column products of the tiles (i, k), i >= k.  Inputs come from padded
-// per-row vectors (zero where a row has no interface dof).
+// product M(ii, jj)^T v_ii (stored in part at a tile's slot, see below).  A
+// diagonal tile counts its lower triangle in the row product and its strict
+// lower triangle in the column product.  Output row k of a subdomain is then its
+// row product plus the column products of the tiles (i, k), i >= k.  Inputs
+// come from padded per-row vectors (zero where a row has no interface dof).
 // Wave w owns columns 16w..16w+15 of every tile (lane layout: SymLayout), so a
 // column product reduces over the RG row-group lanes of one wave and a row
-// product over the CPL column lanes.  Rows that hold nothing are not read: past
-// the matrix's last row, in a zero row range (the average-constraint rows of the
-// operator), and in a diagonal tile the row blocks above wave w's columns.
+// product over the CPL column lanes.  The column products of a column jj <
+// SYM_LDS_COLS are summed in LDS over the rows of a workgroup's range and stored
+// once, at the column's first tile in the range (sym_col_first tells those
+// slots apart); the other columns store one product per tile.  The partial
+// products are a write stream beside the tile reads, and on MI355X such writes
+// cost the reads far more than their share of the bytes.  Rows that hold
+// nothing are not read: past the matrix's last row, in a zero row range (the
+// average-constraint rows of the operator), and in a diagonal tile the row
+// blocks above wave w's columns.
 // Tile descriptors are uniform per wave and read-only: scalar loads (constant
 // address space), which complete independently of the vector memory counter.
 template <typename T>
@@ -2757,6 +2776,13 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rg = lane / CPL, cp = lane % CPL;
   const int col = 16 * w + VEC * cp;
+  // column sums of this range (wave w keeps its own 16 columns, so the waves
+  // share nothing), the first tile of each column in the range (per wave), and
+  // the columns touched since the range or the subdomain started
+  __shared__ double s_col[SYM_LDS_COLS][NB];
+  __shared__ int64_t s_first[4][SYM_LDS_COLS];
+  uint64_t touched = 0;
+  static_assert(SYM_LDS_COLS <= 64, "one bit per column");
   const int64_t N = A.ntiles, G = gridDim.x;
   const int64_t t0 = blockIdx.x * N / G, t1 = (blockIdx.x + 1) * N / G;
   if (t0 >= t1) return;
@@ -2778,12 +2804,28 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
       racc[t] = T(0);
     }
   };
+  auto flush_cols = [&]() {
+    for (uint64_t m = touched; m != 0; m &= m - 1) {
+      const int jj = __builtin_ctzll(m);
+      const int64_t slot = s_first[w][jj];
+      if (rg == 0)
+        for (int j = 0; j < VEC; j += 2) {
+          d2v o2;
+          o2[0] = s_col[jj][col + j];
+          o2[1] = s_col[jj][col + j + 1];
+          *reinterpret_cast<d2v*>(A.part + slot * NB + col + j) = o2;
+        }
+    }
+    touched = 0;
+  };
   // the tile descriptors run one tile ahead, so that every load of a tile (its
   // elements, its inputs, the inputs of a row that starts at it) issues at once
   int inf_next = tinfo[t0], rws_next = trows[t0];
   for (int64_t t = t0; t < t1; ++t) {
     const int inf = inf_next, rws = rws_next;
     const int row = inf >> 8, d = inf & 255;
+    const int jt = int(unsigned(rws) >> 24);   // the tile's column in its subdomain
+    if (jt == 0 && d == 0) flush_cols();        // tile (0, 0): a new subdomain
     V b[KR];
     {
       // FP64 tiles are row-major (a wave's 16 columns of a row: one 128-byte
@@ -2792,7 +2834,7 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
       constexpr int RS = sizeof(T) == 4 ? 16 : NB;   // row stride
       const T* p = mat + t * (NB * NB) + (sizeof(T) == 4 ? sym_f32_off(0, 16 * w) + VEC * cp : col) + rg * RS;
       // rows kept: r < h, outside [z0, z1), and (diagonal tile) r >= 16 w
-      const int h = rws & 255, z0 = (rws >> 8) & 255, z1 = rws >> 16;
+      const int h = rws & 255, z0 = (rws >> 8) & 255, z1 = (rws >> 16) & 255;
       const int rmin = d == 0 ? 16 * w : 0;
       for (int k = 0; k < KR; ++k) {
         const int r = rg + RG * k;
@@ -2807,9 +2849,16 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
       xx[j] = T(x2[0]);
       xx[j + 1] = T(x2[1]);
     }
-    double xn[KR];
+    // a new row's inputs (the old ones are dead once the row changes: the
+    // flush reads only the row sums); FP32 takes them through FP64 registers
+    constexpr bool XD = sizeof(T) == sizeof(double);
+    double xn[XD ? 1 : KR];
     if (row != cur_row)
-      for (int k = 0; k < KR; ++k) xn[k] = xv[int64_t(row) * NB + rg + RG * k];
+      for (int k = 0; k < KR; ++k) {
+        const double v = xv[int64_t(row) * NB + rg + RG * k];
+        if constexpr (XD) xi[k] = v;
+        else xn[k] = v;
+      }
     {
       const int64_t tn = min(t + 1, t1 - 1);
       inf_next = tinfo[tn];
@@ -2819,7 +2868,8 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
       flush();
       pstart = t;
       cur_row = row;
-      for (int k = 0; k < KR; ++k) xi[k] = T(xn[k]);
+      if constexpr (!XD)
+        for (int k = 0; k < KR; ++k) xi[k] = T(xn[k]);
     }
     T c[VEC];
     for (int j = 0; j < VEC; ++j) c[j] = T(0);
@@ -2845,15 +2895,23 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
     }
     double o[VEC];
     for (int j = 0; j < VEC; ++j) o[j] = double(sum_rg(c[j]));
-    if (rg == 0)
+    if (jt < SYM_LDS_COLS) {
+      const bool first = !((touched >> jt) & 1);
+      touched |= uint64_t(1) << jt;
+      if (rg == 0)
+        for (int j = 0; j < VEC; ++j) s_col[jt][col + j] = first ? o[j] : s_col[jt][col + j] + o[j];
+      if (first && lane == 0) s_first[w][jt] = t;
+    } else if (rg == 0) {
       for (int j = 0; j < VEC; j += 2) {
         d2v o2;
         o2[0] = o[j];
         o2[1] = o[j + 1];
         *reinterpret_cast<d2v*>(A.part + t * NB + col + j) = o2;
       }
+    }
   }
   flush();
+  flush_cols();
 }
 
 // Output row ii of a subdomain's symmetric matrix: the row product (over its
@@ -2865,7 +2923,8 @@ __device__ __forceinline__ void sum_row(const IfaceArgs& A, const MatDesc& D, in
   double y = 0.0;
   if (w == 0) y = sym_row_product(A.rowp, D.sg_off + tri_tile(ii, 0), ii + 1, A.ntiles, A.nwg, lane);
   const double* pp = A.part + D.sg_off * NB + lane;
-  for (int i2 = ii + w; i2 < TS; i2 += 4) y += pp[tri_tile(i2, ii) * NB];
+  for (int i2 = ii + w; i2 < TS; i2 += 4)
+    if (sym_col_first(D, i2, ii, A.ntiles, A.nwg)) y += pp[tri_tile(i2, ii) * NB];
   s_red[w][lane] = y;
 }
 

@@ -396,8 +396,9 @@ int make_plan(const bddc_mesh* mesh, const bddc_partition* part, uint32_t constr
         const int z0 = clamp64(nG - ii * NB), z1 = clamp64(nG + D.n_A - ii * NB);
         for (int jj = 0; jj <= ii; ++jj) {
           P.tinfo.push_back(int32_t(((rows + ii) << 8) | (ii - jj)));
-          P.trows_op.push_back(h | (z0 << 8) | (z1 << 16));
-          P.trows_pc.push_back(h);
+          const uint32_t col = uint32_t(jj & 255) << 24;   // the interface form has TS <= IFACE_MAX_TS
+          P.trows_op.push_back(int32_t(uint32_t(h | (z0 << 8) | (z1 << 16)) | col));
+          P.trows_pc.push_back(int32_t(uint32_t(h) | col));
         }
       }
       xg += tri_tile(TG, 0);
