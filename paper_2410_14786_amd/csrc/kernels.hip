@@ -1512,10 +1512,16 @@ void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t s
 // product of every row piece it covers (a piece starts at a row's first tile or
 // at a range start) in rowp[(start tile * 4 + wave) * 64 + row].  This sums the
 // pieces of the row whose len tiles start at tr0, in a fixed order.
+// floor(a / b) for integers 0 <= a, 0 < b with a + b < 2^53, by one FP64
+// division (a 64-bit integer division is a long instruction sequence here):
+// a and b are exact doubles, and a quotient k + f that is not an integer lies
+// at least 1/b below k + 1, while rounding moves it by less than (k + 1) 2^-53
+// <= (a + b) / b 2^-53 < 1/b.
+__device__ __forceinline__ int64_t small_div(int64_t a, int64_t b) { return int64_t(double(a) / double(b)); }
 // Workgroup of a mat-vec launch whose range holds tile p: the g with
 // g ntiles / nwg <= p < (g+1) ntiles / nwg (integer division).
 __device__ __forceinline__ int64_t sym_wg(int64_t p, int64_t ntiles, int64_t nwg) {
-  return ((p + 1) * nwg - 1) / ntiles;
+  return small_div((p + 1) * nwg - 1, ntiles);
 }
 // Whether the slot of tile (i2, jj) holds a column product: for jj <
 // SYM_LDS_COLS only the column's first tile in each workgroup range does (it
@@ -1528,8 +1534,8 @@ __device__ __forceinline__ bool sym_col_first(const MatDesc& D, int i2, int jj, 
 __device__ double sym_row_product(const double* rowp, int64_t tr0, int len, int64_t ntiles, int64_t nwg, int lane) {
   double v = 0.0;
   for (int w = 0; w < 4; ++w) v += rowp[(tr0 * 4 + w) * NB + lane];
-  for (int64_t g = (tr0 * nwg) / ntiles; g < nwg; ++g) {
-    const int64_t b = (g * ntiles) / nwg;
+  for (int64_t g = small_div(tr0 * nwg, ntiles); g < nwg; ++g) {
+    const int64_t b = small_div(g * ntiles, nwg);
     if (b <= tr0) continue;
     if (b >= tr0 + len) break;
     for (int w = 0; w < 4; ++w) v += rowp[(b * 4 + w) * NB + lane];
