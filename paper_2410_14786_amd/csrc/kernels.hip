@@ -2748,7 +2748,8 @@ template <> struct SymLayout<float> {
 // once, at the column's first tile in the range (sym_col_first tells those
 // slots apart); the other columns store one product per tile.  The partial
 // products are a write stream beside the tile reads, and on MI355X such writes
-// cost the reads far more than their share of the bytes.  Rows that hold
+// cost the reads far more than their share of the bytes; so the row pieces too
+// are kept in LDS and stored as whole lines once the range is done.  Rows that hold
 // nothing are not read: past the matrix's last row, in a zero row range (the
 // average-constraint rows of the operator), and in a diagonal tile the row
 // blocks above wave w's columns.
@@ -2789,6 +2790,11 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   __shared__ int64_t s_first[4][SYM_LDS_COLS];
   uint64_t touched = 0;
   static_assert(SYM_LDS_COLS <= 64, "one bit per column");
+  // the range's first SYM_ROW_PIECES row pieces, per wave, stored as whole
+  // lines when the range is done (later pieces are stored at once)
+  __shared__ double s_row[SYM_ROW_PIECES][4][NB];
+  __shared__ int64_t s_pstart[4][SYM_ROW_PIECES];
+  int npieces = 0;
   const int64_t N = A.ntiles, G = gridDim.x;
   const int64_t t0 = blockIdx.x * N / G, t1 = (blockIdx.x + 1) * N / G;
   if (t0 >= t1) return;
@@ -2804,10 +2810,18 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
     racc[t] = T(0);
   }
   auto flush = [&]() {
+    const bool keep = npieces < SYM_ROW_PIECES;
     for (int t = 0; t < KR; ++t) {
       const T v = sum_cp(racc[t]);
-      if (cp == 0) A.rowp[(pstart * 4 + w) * NB + rg + RG * t] = double(v);
+      if (cp == 0) {
+        if (keep) s_row[npieces][w][rg + RG * t] = double(v);
+        else A.rowp[(pstart * 4 + w) * NB + rg + RG * t] = double(v);
+      }
       racc[t] = T(0);
+    }
+    if (keep) {
+      if (lane == 0) s_pstart[w][npieces] = pstart;
+      ++npieces;
     }
   };
   auto flush_cols = [&]() {
@@ -2918,6 +2932,7 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   }
   flush();
   flush_cols();
+  for (int q = 0; q < npieces; ++q) A.rowp[(s_pstart[w][q] * 4 + w) * NB + lane] = s_row[q][w][lane];
 }
 
 // Output row ii of a subdomain's symmetric matrix: the row product (over its
