@@ -863,7 +863,7 @@ int do_setup(bddc_ctx* c, const bddc_coefficients* coef) {
       return rc_;
     }
     if ((rc_ = c->alloc(c->symp, P.n_sg * NB))) return rc_;
-    if ((rc_ = c->alloc(c->rowp, P.n_sg * 4 * NB))) return rc_;
+    if ((rc_ = c->alloc(c->rowp, P.n_sg * NB))) return rc_;
     launch_sym_build(SYM_OP, c->mats, P.nsubs, P.maxTS, static_cast<const double*>(c->tiles), c->xg, c->cpp, c->sg,
                      false, st);
     launch_sym_build(SYM_PC, c->mats, P.nsubs, P.maxTS, static_cast<const double*>(c->tiles), c->xg, c->cpp,

@@ -97,7 +97,7 @@ struct IfaceArgs {
   const double* part_rr;    // its partial sums of r.r
   int nparts_rr;            // their count
   double* part;             // column products, 64 per tile
-  double* rowp;             // row products per piece and wave, 4 x 64 per piece start tile
+  double* rowp;             // row products per row piece, 64 per piece start tile
   const double* dsc;
   const double* wd;
   const double* wgt;
@@ -224,7 +224,7 @@ void launch_pc_finish(const IfaceArgs& a, hipStream_t st);
 constexpr int COARSE_SPLIT_COLS = 512;   // columns of A_c^{-1} per coarse GEMV block
 constexpr int IFACE_MAX_TS = 255;        // interface form: tile rows of a symmetric interface matrix
 constexpr int SYM_LDS_COLS = 64;         // interface mat-vec: columns whose products a workgroup sums in LDS
-constexpr int SYM_ROW_PIECES = 8;        // interface mat-vec: row pieces a workgroup keeps in LDS until its end
+constexpr int SYM_ROW_PIECES = 28;       // interface mat-vec: row pieces a workgroup keeps in LDS until its end
 void launch_coarse_inverse(const double* xg, const double* dc, int nc, double* ainv, hipStream_t st);
 void launch_coarse_gemv(const double* ainv, int nc, int nsplit, const int32_t* cinv_ptr, const int32_t* cinv,
                         const double* gbuf, double* upart, const int* done, hipStream_t st);

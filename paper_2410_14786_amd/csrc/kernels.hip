@@ -1508,10 +1508,10 @@ void launch_trsv(int mode, bool fp32, const TrsvArgs& a, int grid, hipStream_t s
 
 // The symmetric interface matrices of all subdomains form one stream of ntiles
 // tiles; workgroup g of a mat-vec launch with nwg workgroups takes the tiles
-// [g ntiles / nwg, (g+1) ntiles / nwg).  Each of its four waves stores the row
-// product of every row piece it covers (a piece starts at a row's first tile or
-// at a range start) in rowp[(start tile * 4 + wave) * 64 + row].  This sums the
-// pieces of the row whose len tiles start at tr0, in a fixed order.
+// [g ntiles / nwg, (g+1) ntiles / nwg).  It stores the row product of every row
+// piece it covers (a piece starts at a row's first tile or at a range start) in
+// rowp[start tile * 64 + row].  This sums the pieces of the row whose len tiles
+// start at tr0, in a fixed order.
 // floor(a / b) for integers 0 <= a, 0 < b with a + b < 2^53, by one FP64
 // division (a 64-bit integer division is a long instruction sequence here):
 // a and b are exact doubles, and a quotient k + f that is not an integer lies
@@ -1533,12 +1533,12 @@ __device__ __forceinline__ bool sym_col_first(const MatDesc& D, int i2, int jj, 
 
 __device__ double sym_row_product(const double* rowp, int64_t tr0, int len, int64_t ntiles, int64_t nwg, int lane) {
   double v = 0.0;
-  for (int w = 0; w < 4; ++w) v += rowp[(tr0 * 4 + w) * NB + lane];
+  v += rowp[tr0 * NB + lane];
   for (int64_t g = small_div(tr0 * nwg, ntiles); g < nwg; ++g) {
     const int64_t b = small_div(g * ntiles, nwg);
     if (b <= tr0) continue;
     if (b >= tr0 + len) break;
-    for (int w = 0; w < 4; ++w) v += rowp[(b * 4 + w) * NB + lane];
+    v += rowp[b * NB + lane];
   }
   return v;
 }
@@ -2749,7 +2749,8 @@ template <> struct SymLayout<float> {
 // slots apart); the other columns store one product per tile.  The partial
 // products are a write stream beside the tile reads, and on MI355X such writes
 // cost the reads far more than their share of the bytes; so the row pieces too
-// are kept in LDS and stored as whole lines once the range is done.  Rows that hold
+// are summed over the waves and kept in LDS, and stored as whole lines once the
+// range is done.  Rows that hold
 // nothing are not read: past the matrix's last row, in a zero row range (the
 // average-constraint rows of the operator), and in a diagonal tile the row
 // blocks above wave w's columns.
@@ -2787,13 +2788,15 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   // share nothing), the first tile of each column in the range (per wave), and
   // the columns touched since the range or the subdomain started
   __shared__ double s_col[SYM_LDS_COLS][NB];
-  __shared__ int64_t s_first[4][SYM_LDS_COLS];
+  __shared__ int32_t s_first[4][SYM_LDS_COLS];
   uint64_t touched = 0;
   static_assert(SYM_LDS_COLS <= 64, "one bit per column");
-  // the range's first SYM_ROW_PIECES row pieces, per wave, stored as whole
-  // lines when the range is done (later pieces are stored at once)
-  __shared__ double s_row[SYM_ROW_PIECES][4][NB];
-  __shared__ int64_t s_pstart[4][SYM_ROW_PIECES];
+  // a row piece's sums: the four waves' partial sums (double-buffered) are added
+  // in a fixed order after a barrier; the range's first SYM_ROW_PIECES pieces
+  // are stored as whole lines when the range is done, later ones at once
+  __shared__ double s_rpart[2][4][NB];
+  __shared__ double s_row[SYM_ROW_PIECES][NB];
+  __shared__ int32_t s_pstart[SYM_ROW_PIECES];
   int npieces = 0;
   const int64_t N = A.ntiles, G = gridDim.x;
   const int64_t t0 = blockIdx.x * N / G, t1 = (blockIdx.x + 1) * N / G;
@@ -2809,20 +2812,27 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
     xi[t] = T(xv[int64_t(cur_row) * NB + rg + RG * t]);
     racc[t] = T(0);
   }
+  // (every wave of the workgroup meets the same row changes: the barrier is
+  // uniform.  A buffer of s_rpart is written again two pieces later, after the
+  // next barrier, which wave 0 reaches only once it has read the buffer.)
   auto flush = [&]() {
-    const bool keep = npieces < SYM_ROW_PIECES;
+    const int b = npieces & 1;
     for (int t = 0; t < KR; ++t) {
       const T v = sum_cp(racc[t]);
-      if (cp == 0) {
-        if (keep) s_row[npieces][w][rg + RG * t] = double(v);
-        else A.rowp[(pstart * 4 + w) * NB + rg + RG * t] = double(v);
-      }
+      if (cp == 0) s_rpart[b][w][rg + RG * t] = double(v);
       racc[t] = T(0);
     }
-    if (keep) {
-      if (lane == 0) s_pstart[w][npieces] = pstart;
-      ++npieces;
+    __syncthreads();
+    if (w == 0) {
+      const double y = ((s_rpart[b][0][lane] + s_rpart[b][1][lane]) + s_rpart[b][2][lane]) + s_rpart[b][3][lane];
+      if (npieces < SYM_ROW_PIECES) {
+        s_row[npieces][lane] = y;
+        if (lane == 0) s_pstart[npieces] = int32_t(pstart);
+      } else {
+        A.rowp[pstart * NB + lane] = y;
+      }
     }
+    ++npieces;
   };
   auto flush_cols = [&]() {
     for (uint64_t m = touched; m != 0; m &= m - 1) {
@@ -2920,7 +2930,7 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
       touched |= uint64_t(1) << jt;
       if (rg == 0)
         for (int j = 0; j < VEC; ++j) s_col[jt][col + j] = first ? o[j] : s_col[jt][col + j] + o[j];
-      if (first && lane == 0) s_first[w][jt] = t;
+      if (first && lane == 0) s_first[w][jt] = int32_t(t);
     } else if (rg == 0) {
       for (int j = 0; j < VEC; j += 2) {
         d2v o2;
@@ -2932,7 +2942,8 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   }
   flush();
   flush_cols();
-  for (int q = 0; q < npieces; ++q) A.rowp[(s_pstart[w][q] * 4 + w) * NB + lane] = s_row[q][w][lane];
+  if (w == 0)
+    for (int q = 0; q < min(npieces, SYM_ROW_PIECES); ++q) A.rowp[int64_t(s_pstart[q]) * NB + lane] = s_row[q][lane];
 }
 
 // Output row ii of a subdomain's symmetric matrix: the row product (over its
