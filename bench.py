@@ -360,9 +360,11 @@ def cpu_baseline(w_full, full_iters, workers=None):
 
 
 def copy_bandwidth(torch):
-    """HBM bandwidth of plain streams on this GPU (GB/s), measured ceilings
-    beside the datasheet peak: a device copy (bytes read plus bytes written)
-    and a read-only sum (bytes read)."""
+    """HBM bandwidth of two plain streams on this GPU (GB/s), reference points
+    beside the datasheet peak: PyTorch's device copy (bytes read plus bytes
+    written) and its sum of a vector (bytes read).  They are not ceilings: a
+    read stream written for the purpose (non-temporal 16-byte loads, whole
+    tiles per workgroup) moves more."""
     n = (1 << 30) // 8
     src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
@@ -542,9 +544,9 @@ def main():
     out["roofline_measured_in"] = "timed run: the same solves with dispatch-recorded events around the kernels"
     out["stream_bandwidth"] = None if copy_gbs is None else {
         "copy_GBps": round(copy_gbs, 1), "read_GBps": round(read_gbs, 1),
-        "how": "1 GiB FP64 device-to-device copy (bytes read plus written per second) and read-only sum "
-               "(bytes read per second), median of 5 each; roofline.frac_of_copy and frac_of_read are "
-               "achieved over these"}
+        "how": "PyTorch's 1 GiB FP64 device-to-device copy (bytes read plus written per second) and its sum "
+               "of the same vector (bytes read per second), median of 5 each: reference points, not ceilings; "
+               "roofline.frac_of_copy and frac_of_read are achieved over these"}
     for k in ["applies_per_s", "kernel_ms", "kernel_hbm_frac", "bytes_per_solve", "solve_hbm_frac"]:
         out[k] = timed[k]
     out["roofline"] = timed["roofline"]
