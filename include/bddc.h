@@ -270,11 +270,19 @@ int64_t bddc_debug_read(bddc_ctx* ctx, const char* what, int32_t sub, double* ho
  *                     makes every wait give up at once;
  *   "coarse_cg_maxit" iteration limit of the coarse CG (BDDC_SETUP_COARSE_CG,
  *                     default 2000); a coarse CG that stops at it (or breaks
- *                     down) marks the device status word.
+ *                     down) marks the device status word;
+ *   "sym_lds_cols"    interface form: the tile columns (0..64, default 64)
+ *                     whose partial products a mat-vec workgroup sums over its
+ *                     rows before storing them; the others store one per tile
+ *                     (results agree to rounding);
+ *   "sym_row_pieces"  interface form: row pieces (0..28, default 28) a mat-vec
+ *                     workgroup keeps until its range is done; the others are
+ *                     stored at once (results are bitwise the same).
+ * The last two select code paths for tests; they are not tuning knobs.
  * A marked status word is reported, and cleared, by the next bddc_pcg_solve
  * (EHIP for a wait that gave up, ENOCONV for the coarse CG; x and info are
  * still filled) or bddc_sync.  Captured graphs are dropped.
- * Errors: EINVAL (unknown name, negative coarse_cg_maxit). */
+ * Errors: EINVAL (unknown name, negative coarse_cg_maxit, sym_* out of range). */
 int bddc_set_limit(bddc_ctx* ctx, const char* what, int32_t value);
 
 /* Waits for all work queued on the ctx stream and reports the device status

@@ -165,6 +165,8 @@ struct bddc_ctx {
   int* fready = nullptr;            // per tile ready words of the persistent factorisation
   int wait_polls = 1 << 22;         // polls of a published value (or a coarse-CG grid barrier) before a wait gives up
   int coarse_maxit = COARSE_CG_MAXIT;
+  int sym_lds_cols = SYM_LDS_COLS;     // interface mat-vec: columns summed in LDS (test limit)
+  int sym_row_pieces = SYM_ROW_PIECES; // interface mat-vec: row pieces kept in LDS (test limit)
   unsigned* fticket = nullptr;
   void* static_scratch = nullptr;   // this device's fixed workspace (bddc_apply_noalloc)
   double *part = nullptr, *gbuf = nullptr, *mu = nullptr, *coef = nullptr, *ww = nullptr, *v12 = nullptr;
@@ -492,6 +494,8 @@ IfaceArgs iface_args(bddc_ctx* c) {
   a.wgt = c->wgt;
   a.sploc = c->sploc;
   a.ww = c->ww;
+  a.lds_cols = c->sym_lds_cols;
+  a.row_pieces = c->sym_row_pieces;
   return a;
 }
 
@@ -1436,8 +1440,16 @@ int bddc_set_limit(bddc_ctx* c, const char* what, int32_t value) {
     if (value < 0) return fail(BDDC_EINVAL, "coarse_cg_maxit must be >= 0");
     drop_graphs(c);
     c->coarse_maxit = value;
+  } else if (w == "sym_lds_cols") {
+    if (value < 0 || value > SYM_LDS_COLS) return fail(BDDC_EINVAL, "sym_lds_cols must be in [0, 64]");
+    drop_graphs(c);
+    c->sym_lds_cols = value;
+  } else if (w == "sym_row_pieces") {
+    if (value < 0 || value > SYM_ROW_PIECES) return fail(BDDC_EINVAL, "sym_row_pieces must be in [0, 28]");
+    drop_graphs(c);
+    c->sym_row_pieces = value;
   } else {
-    return fail(BDDC_EINVAL, "unknown limit (wait_polls, coarse_cg_maxit)");
+    return fail(BDDC_EINVAL, "unknown limit (wait_polls, coarse_cg_maxit, sym_lds_cols, sym_row_pieces)");
   }
   return BDDC_OK;
 }

@@ -104,6 +104,8 @@ struct IfaceArgs {
   double* sploc;            // (S z) per local dof
   double* ww;               // weighted local preconditioner output
   const double* coef;       // coefficients of the coarse correction, MAX_NCI per subdomain
+  int lds_cols;             // columns jj < lds_cols (<= SYM_LDS_COLS) have their products summed in LDS
+  int row_pieces;           // row pieces (<= SYM_ROW_PIECES) a workgroup keeps in LDS until its end
 };
 
 template <typename T> void launch_fill(T* p, T v, int64_t n, hipStream_t st);

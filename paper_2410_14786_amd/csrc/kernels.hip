@@ -1523,11 +1523,12 @@ __device__ __forceinline__ int64_t small_div(int64_t a, int64_t b) { return int6
 __device__ __forceinline__ int64_t sym_wg(int64_t p, int64_t ntiles, int64_t nwg) {
   return small_div((p + 1) * nwg - 1, ntiles);
 }
-// Whether the slot of tile (i2, jj) holds a column product: for jj <
-// SYM_LDS_COLS only the column's first tile in each workgroup range does (it
-// holds the sum over the range's rows), for the other columns every tile.
-__device__ __forceinline__ bool sym_col_first(const MatDesc& D, int i2, int jj, int64_t ntiles, int64_t nwg) {
-  if (jj >= SYM_LDS_COLS || i2 == jj) return true;
+// Whether the slot of tile (i2, jj) holds a column product: for jj < lds_cols
+// only the column's first tile in each workgroup range does (it holds the sum
+// over the range's rows), for the other columns every tile.
+__device__ __forceinline__ bool sym_col_first(const MatDesc& D, int i2, int jj, int64_t ntiles, int64_t nwg,
+                                              int lds_cols) {
+  if (jj >= lds_cols || i2 == jj) return true;
   return sym_wg(D.sg_off + tri_tile(i2, jj), ntiles, nwg) != sym_wg(D.sg_off + tri_tile(i2 - 1, jj), ntiles, nwg);
 }
 
@@ -2732,28 +2733,28 @@ template <> struct SymLayout<float> {
 };
 
 // y = M v for the symmetric interface matrices, all subdomains at once.  The
-// launch splits the tile stream into equal contiguous ranges (no tickets, no
-// barriers, nothing staged): every tile (ii, jj) is read once and used twice,
-// for the row product sum_jj M(ii, jj) v_jj (kept in registers along a row
-// piece and stored per piece and wave, see sym_row_product) and the column
-// product M(ii, jj)^T v_ii (stored in part at a tile's slot, see below).  A
-// diagonal tile counts its lower triangle in the row product and its strict
-// lower triangle in the column product.  Output row k of a subdomain is then its
-// row product plus the column products of the tiles (i, k), i >= k.  Inputs
-// come from padded per-row vectors (zero where a row has no interface dof).
+// launch splits the tile stream into equal contiguous ranges (no tickets):
+// every tile (ii, jj) is read once and used twice, for the row product
+// sum_jj M(ii, jj) v_jj (kept in registers along a row piece, see
+// sym_row_product) and the column product M(ii, jj)^T v_ii.  A diagonal tile
+// counts its lower triangle in the row product and its strict lower triangle in
+// the column product.  Output row k of a subdomain is then its row product plus
+// the column products of the tiles (i, k), i >= k.  Inputs come from padded
+// per-row vectors (zero where a row has no interface dof).
 // Wave w owns columns 16w..16w+15 of every tile (lane layout: SymLayout), so a
 // column product reduces over the RG row-group lanes of one wave and a row
-// product over the CPL column lanes.  The column products of a column jj <
-// SYM_LDS_COLS are summed in LDS over the rows of a workgroup's range and stored
-// once, at the column's first tile in the range (sym_col_first tells those
-// slots apart); the other columns store one product per tile.  The partial
-// products are a write stream beside the tile reads, and on MI355X such writes
-// cost the reads far more than their share of the bytes; so the row pieces too
-// are summed over the waves and kept in LDS, and stored as whole lines once the
-// range is done.  Rows that hold
-// nothing are not read: past the matrix's last row, in a zero row range (the
-// average-constraint rows of the operator), and in a diagonal tile the row
-// blocks above wave w's columns.
+// product over the CPL column lanes.  The partial products are a write stream
+// beside the tile reads, and on MI355X such writes cost the reads far more than
+// their share of the bytes, so they are staged in LDS:
+//  - the column products of a column jj < A.lds_cols (at most SYM_LDS_COLS) are
+//    summed over the rows of the range and stored once, at the column's first
+//    tile in the range (sym_col_first tells those slots apart); the other
+//    columns store one product per tile;
+//  - a row piece's sums are added over the four waves (one barrier per piece)
+//    and the range's first pieces are stored as whole lines when it is done.
+// Rows that hold nothing are not read: past the matrix's last row, in a zero
+// row range (the average-constraint rows of the operator), and in a diagonal
+// tile the row blocks above wave w's columns.
 // Tile descriptors are uniform per wave and read-only: scalar loads (constant
 // address space), which complete independently of the vector memory counter.
 template <typename T>
@@ -2792,8 +2793,9 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   uint64_t touched = 0;
   static_assert(SYM_LDS_COLS <= 64, "one bit per column");
   // a row piece's sums: the four waves' partial sums (double-buffered) are added
-  // in a fixed order after a barrier; the range's first SYM_ROW_PIECES pieces
-  // are stored as whole lines when the range is done, later ones at once
+  // in a fixed order after a barrier; the range's first A.row_pieces pieces
+  // (at most SYM_ROW_PIECES) are stored as whole lines when the range is done,
+  // later ones at once
   __shared__ double s_rpart[2][4][NB];
   __shared__ double s_row[SYM_ROW_PIECES][NB];
   __shared__ int32_t s_pstart[SYM_ROW_PIECES];
@@ -2825,7 +2827,7 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
     __syncthreads();
     if (w == 0) {
       const double y = ((s_rpart[b][0][lane] + s_rpart[b][1][lane]) + s_rpart[b][2][lane]) + s_rpart[b][3][lane];
-      if (npieces < SYM_ROW_PIECES) {
+      if (npieces < A.row_pieces) {
         s_row[npieces][lane] = y;
         if (lane == 0) s_pstart[npieces] = int32_t(pstart);
       } else {
@@ -2925,7 +2927,7 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
     }
     double o[VEC];
     for (int j = 0; j < VEC; ++j) o[j] = double(sum_rg(c[j]));
-    if (jt < SYM_LDS_COLS) {
+    if (jt < A.lds_cols) {
       const bool first = !((touched >> jt) & 1);
       touched |= uint64_t(1) << jt;
       if (rg == 0)
@@ -2943,7 +2945,7 @@ __global__ __launch_bounds__(256) void sym_mv_kernel(IfaceArgs A) {
   flush();
   flush_cols();
   if (w == 0)
-    for (int q = 0; q < min(npieces, SYM_ROW_PIECES); ++q) A.rowp[int64_t(s_pstart[q]) * NB + lane] = s_row[q][lane];
+    for (int q = 0; q < min(npieces, A.row_pieces); ++q) A.rowp[int64_t(s_pstart[q]) * NB + lane] = s_row[q][lane];
 }
 
 // Output row ii of a subdomain's symmetric matrix: the row product (over its
@@ -2956,7 +2958,7 @@ __device__ __forceinline__ void sum_row(const IfaceArgs& A, const MatDesc& D, in
   if (w == 0) y = sym_row_product(A.rowp, D.sg_off + tri_tile(ii, 0), ii + 1, A.ntiles, A.nwg, lane);
   const double* pp = A.part + D.sg_off * NB + lane;
   for (int i2 = ii + w; i2 < TS; i2 += 4)
-    if (sym_col_first(D, i2, ii, A.ntiles, A.nwg)) y += pp[tri_tile(i2, ii) * NB];
+    if (sym_col_first(D, i2, ii, A.ntiles, A.nwg, A.lds_cols)) y += pp[tri_tile(i2, ii) * NB];
   s_red[w][lane] = y;
 }
 

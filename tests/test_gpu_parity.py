@@ -160,6 +160,39 @@ def test_pcg_iterates_match_oracle(name, full_space):
     S.close()
 
 
+@pytest.mark.parametrize("name", ["3d_40_boxes_8_24_inclusions", "3d_24_8x8x8_boxes_of_3"])
+def test_mat_vec_store_paths(name):
+    """The interface mat-vec stages its partial products in LDS before storing
+    them.  Every staging path gives the oracle's K-step iterate: fewer row
+    pieces kept (the rest stored at once) changes nothing, bitwise; fewer
+    columns summed (the rest stored per tile) regroups sums (rounding only)."""
+    w, P = oracle_for(name)
+    ref = O.bddc_pcg(P, w.b, w.rtol)
+    K = max(ref.iters - 2, 1)
+    refK = O.bddc_pcg(P, w.b, 1e-300, maxit=K)
+    S = bd().solver_for(w)
+    S.set_tuning(1)   # few workgroups: several row pieces and columns per range
+    x0, i0 = S.solve(dev(w.b), 1e-15, maxit=K, raise_on_noconv=False)
+    x0 = host(x0)
+    assert i0["iters"] == K
+    close(x0, refK.x, 1e-10)
+    for pieces in (0, 1, 5):
+        S.set_limit("sym_row_pieces", pieces)
+        x1, _ = S.solve(dev(w.b), 1e-15, maxit=K, raise_on_noconv=False)
+        assert np.array_equal(host(x1), x0), pieces
+    S.set_limit("sym_row_pieces", 28)
+    for cols in (0, 3):
+        S.set_limit("sym_lds_cols", cols)
+        x2, _ = S.solve(dev(w.b), 1e-15, maxit=K, raise_on_noconv=False)
+        x2 = host(x2)
+        assert np.allclose(x2, x0, rtol=1e-12, atol=1e-12 * np.abs(x0).max()), cols
+        en, ee = close(x2, refK.x, 1e-10)
+        say(name, "lds_cols", cols, "iterate rel err", en, "entry-wise", ee)
+    with pytest.raises(RuntimeError):
+        S.set_limit("sym_row_pieces", 29)
+    S.close()
+
+
 @pytest.mark.parametrize("full_space", [False, True], ids=["interface", "full_space"])
 @pytest.mark.parametrize("name", ["2d_20x24_uneven", "3d_16_2x2x2"])
 def test_solution_matches_sparse_direct(name, full_space):
